@@ -1,0 +1,144 @@
+/*
+ * libwlra: the sWLR alternating sweep on one AMD Instinct MI355X (gfx950).
+ *
+ * Solves problem (5) of Dutta & Li, "A Fast Algorithm for a Weighted Low Rank
+ * Approximation" (arXiv 1703.06303):
+ *
+ *     min over X1, X2 with rank([X1 X2]) <= r of
+ *         || (A1 - X1) o W1 ||_F^2 + || A2 - X2 ||_F^2
+ *
+ * A = [A1 A2] is m x n, A1 its first k columns, W1 (m x k) has entries > 0,
+ * and o is the entrywise product.  Each sweep is Algorithm 1 (Section 3): the
+ * Golub-Hoffman-Stewart closed form of Theorem 1 gives C_p and
+ * D_p = H_{r-k}((I - Q_p Q_p^T) A2) from X1_p = Q_p R_p, and the row update
+ * below eq. (9) gives X1_{p+1}(i,:) = E_p(i,:) (diag(W1(i,:)^2) + C_p C_p^T)^-1
+ * with E_p = A1 o W1 o W1 + (A2 - D_p) C_p^T.  The stopping rule is the one of
+ * Section 4.1: with Error_p = ||X_p - X_{p-1}||_F, stop when Error_p < tol or
+ * Error_p / ||X_{p-1}||_F < tol, or after max_sweeps X1 updates.
+ *
+ * Every call takes plain pointers and sizes.  Matrices are column-major
+ * (a video frame is one contiguous column).  Device pointers are HIP device
+ * memory on the handle's device; the caller owns every buffer it passes and
+ * the library owns only its workspace.  No exception crosses this interface:
+ * every entry point returns a status code (wlra_status below).
+ */
+#ifndef WLRA_H
+#define WLRA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  0 and 1 mean a valid result is in the outputs. */
+enum wlra_status {
+  WLRA_OK = 0,            /* converged under the Section 4.1 rule             */
+  WLRA_MAX_SWEEPS = 1,    /* max_sweeps X1 updates done; result is X_p        */
+  WLRA_E_ARG = -1,        /* bad dimension, leading dimension or pointer      */
+  WLRA_E_WEIGHT = -2,     /* a W1 entry is not > 0 or not finite (Theorem 2
+                             assumes (W1)_ij > 0)                             */
+  WLRA_E_NONFINITE = -3,  /* A or X1_init has a NaN or Inf                     */
+  WLRA_E_RANK = -4,       /* X1_p is numerically rank deficient: the paper
+                             assumes rank(X1) = k (Section 3)                 */
+  WLRA_E_NOMEM = -5,      /* workspace allocation failed                      */
+  WLRA_E_HIP = -6,        /* a HIP runtime call failed                        */
+  WLRA_E_NODEVICE = -7    /* no usable gfx950 device                          */
+};
+
+/* Arithmetic of a handle.  The storage type of A, W1, X1_init, X1_out and
+ * X2_out is double for WLRA_FP64 and float otherwise.  Sums over the m rows
+ * (the Grams X1^T X1, X1^T A2, A2^T A2 and the objective) and all k x k,
+ * k x (n-k), (n-k) x (n-k) steps run in double in every mode. */
+typedef enum {
+  WLRA_FP64 = 0,
+  WLRA_FP32 = 1,
+  WLRA_MIXED_BF16 = 2    /* A2 products in bf16 with fp32 accumulate, then one
+                            exact FP32 refinement sweep                       */
+} wlra_precision;
+
+/* Start X1_0 (Algorithm 1 leaves it open; Section 4.1 recommends a random
+ * matrix). */
+typedef enum {
+  WLRA_INIT_RANDOM = 0,  /* iid N(0,1) from Philox4x32-10 keyed by `seed`     */
+  WLRA_INIT_GIVEN = 1,   /* X1_init (device, m x k, ld ldx0)                  */
+  WLRA_INIT_A1 = 2,      /* X1_0 = A1                                         */
+  WLRA_INIT_LEARNED = 3  /* reserved for the learned warm start              */
+} wlra_init;
+
+typedef struct {
+  int64_t m, n, k, r;      /* 0 <= k <= r <= min(m, n); A1 = first k columns    */
+  const void *A;           /* device, m x n, column-major                       */
+  int64_t lda;             /* >= m                                              */
+  const void *W1;          /* device m x k, entries > 0 and finite; NULL means
+                              every entry equals w1_const                       */
+  int64_t ldw;             /* >= m when W1 != NULL                              */
+  double w1_const;         /* > 0, used when W1 == NULL                         */
+  double tol;              /* epsilon of Section 4.1 (the paper uses 1e-7);
+                              tol <= 0 runs exactly max_sweeps X1 updates        */
+  int32_t max_sweeps;      /* >= 0                                              */
+  int32_t init;            /* wlra_init                                         */
+  uint64_t seed;           /* WLRA_INIT_RANDOM key                              */
+  const void *X1_init;     /* device m x k when init == WLRA_INIT_GIVEN         */
+  int64_t ldx0;            /* >= m when X1_init is used                         */
+  void *X1_out;            /* device m x k, required                            */
+  int64_t ldx1;            /* >= m                                              */
+  void *X2_out;            /* device m x (n-k) = X1 C + D, optional (NULL)      */
+  int64_t ldx2;            /* >= m when X2_out != NULL                          */
+  double *trace;           /* host, optional: 2*(max_sweeps+1) doubles; trace[p]
+                              = F(X_p), trace[max_sweeps+1+p] = Error_p (p>=1)  */
+  double eig_tol;          /* relative residual target of the H_{r-k} eigen
+                              step; <= 0 selects the default for the precision  */
+} wlra_problem;
+
+typedef struct {
+  int32_t status;          /* wlra_status                                       */
+  int32_t sweeps;          /* X1 updates done (p of the returned X_p)           */
+  double objective;        /* F(X_p) of problem (5), accumulated in double      */
+  double abs_change;       /* Error_p = ||X_p - X_{p-1}||_F (0 when p = 0)      */
+  double rel_change;       /* Error_p / ||X_{p-1}||_F                           */
+  double gap;              /* sigma_{r-k} - sigma_{r-k+1} of P^perp A2 (a lower
+                              estimate; +inf when r = k)                        */
+  float ms;                /* wall time of the call on the handle's stream      */
+  int32_t eig_iters;       /* filter iterations of the eigen step, summed        */
+} wlra_result;
+
+typedef struct wlra_ctx *wlra_handle;
+
+/* Create a handle bound to `device` and `hip_stream` (a hipStream_t; NULL is
+ * the null stream).  The handle owns a workspace that grows on demand before
+ * the kernels of a solve are enqueued; wlra_reserve grows it ahead of time.
+ * Returns WLRA_E_NODEVICE when the device is absent or not gfx950. */
+int wlra_create(wlra_handle *out, int device, void *hip_stream, int precision,
+                uint32_t flags);
+
+/* Grow the workspace for problems up to the given sizes (optional). */
+int wlra_reserve(wlra_handle h, int64_t m, int64_t n, int64_t k, int64_t r);
+
+/* Solve one instance of problem (5) with Algorithm 1.  Blocks until the
+ * result is on the host.  Writes X1_out (and X2_out when given) with the
+ * returned X_p.  Inputs are only read. */
+int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res);
+
+/* Solve `count` independent instances (uneven m, n, k, r allowed).  Returns
+ * WLRA_E_ARG if any instance fails argument checks (nothing is run), else 0;
+ * the status of each instance is in res[i].status. */
+int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs,
+                       wlra_result *res);
+
+int wlra_destroy(wlra_handle h);
+
+/* Host-only argument check of one problem for a precision (no device access):
+ * returns WLRA_OK or WLRA_E_ARG. */
+int wlra_validate(const wlra_problem *prob, int precision);
+
+const char *wlra_strerror(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int wlra_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WLRA_H */

@@ -1,0 +1,338 @@
+// Small-step kernels of the sWLR sweep, all in double on the device:
+//   k_coef   Cholesky R of X1^T X1 (the R of X1 = QR, Algorithm 1 step 4),
+//            B = R^-T X1^T A2 = Q^T A2 and C = R^-1 B (step 5)
+//   k_formM  M = A2^T A2 - B^T B = (P^perp A2)^T (P^perp A2), whose top r-k
+//            eigenpairs give D = H_{r-k}(P^perp A2) (steps 4 and 6)
+//   k_post   S = C C^T, T = (CV)(CV)^T, Z = (I - VV^T) C^T for the row pass
+//            (step 7) and the objective F(X_p)
+//   k_decide Error_p of Section 4.1 (from the exact row pass k_change) and
+//            the stopping decision.
+// One workgroup each except k_formM.
+#include "common.h"
+#include "launch.h"
+
+// -----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gastats(int n2, const double *__restrict__ GA,
+                                                 SmallState *st) {
+  __shared__ double red[4];
+  double tr = 0, f = 0;
+  for (int e = threadIdx.x; e < n2 * n2; e += 256) {
+    const double v = GA[e];
+    f += v * v;
+    if (e % n2 == e / n2) tr += v;
+  }
+  tr = block_sum(tr, red);
+  f = block_sum(f, red);
+  if (threadIdx.x == 0) {
+    st->trGA = tr;
+    st->nrmGA = sqrt(f);
+    st->eig_floor *= sqrt(f);  // relative target -> absolute residual
+  }
+}
+
+// -----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
+  SmallState *st = a.st;
+  if (st->done) return;
+  __shared__ double sR[64 * 64];
+  __shared__ double sW[64 * 64];
+  __shared__ double red[4];
+  __shared__ int fail;
+  const int k = a.k, n2 = a.n2, t = threadIdx.x;
+
+  double f1 = 0, dx = 0;
+  for (int i = t; i < a.nparts; i += 256) {
+    f1 += a.upd_part[2 * i];
+    dx += a.upd_part[2 * i + 1];
+  }
+  f1 = block_sum(f1, red);
+  dx = block_sum(dx, red);
+  if (t == 0) {
+    st->f1 = f1;
+    st->dx1 = dx;
+    fail = 0;
+  }
+  for (int e = t; e < k * k; e += 256) sR[(e % k) + (e / k) * 64] = a.G1[e];
+  __syncthreads();
+  double gmax = 0, tr = 0;
+  for (int i = 0; i < k; ++i) {
+    gmax = fmax(gmax, sR[i + i * 64]);
+    tr += sR[i + i * 64];
+  }
+  // A pivot below k * eps * max diag(X1^T X1) means X1 is numerically
+  // rank deficient (cond(X1) > 1 / sqrt(k eps)).
+  const double thr = (double)k * 2.220446049250313e-16 * gmax;
+  for (int j = 0; j < k; ++j) {
+    if (t == 0) {
+      double p = sR[j + j * 64];
+      if (!(p > thr)) {
+        fail = 1;
+        p = gmax > 0 ? gmax : 1.0;
+      }
+      sR[j + j * 64] = sqrt(p);
+    }
+    __syncthreads();
+    const double rjj = sR[j + j * 64];
+    for (int c = j + 1 + t; c < k; c += 256) sR[j + c * 64] /= rjj;
+    __syncthreads();
+    const int rem = k - j - 1;
+    for (int e = t; e < rem * rem; e += 256) {
+      const int aa = j + 1 + e % rem, cc = j + 1 + e / rem;
+      if (aa <= cc) sR[aa + cc * 64] -= sR[j + aa * 64] * sR[j + cc * 64];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (t == 0) {
+      atomicOr(a.flags, DEV_RANK);
+      st->done = 1;
+    }
+    return;
+  }
+  for (int e = t; e < k * k; e += 256) {
+    const int r = e % k, c = e / k;
+    a.R[e] = (r <= c) ? sR[r + c * 64] : 0.0;
+  }
+  // B = R^-T P (forward substitution per column), C = R^-1 B (backward).
+  for (int j = t; j < n2; j += 256) {
+    const double *p = a.P + (int64_t)j * k;
+    double *bb = a.B + (int64_t)j * k;
+    double *cc = a.C + (int64_t)j * k;
+    for (int i = 0; i < k; ++i) {
+      double s = p[i];
+      for (int q = 0; q < i; ++q) s -= sR[q + i * 64] * bb[q];
+      bb[i] = s / sR[i + i * 64];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = bb[i];
+      for (int q = i + 1; q < k; ++q) s -= sR[i + q * 64] * cc[q];
+      cc[i] = s / sR[i + i * 64];
+    }
+  }
+  __syncthreads();
+  double nb2 = 0;
+  for (int e = t; e < k * n2; e += 256) nb2 += a.B[e] * a.B[e];
+  nb2 = block_sum(nb2, red);
+  if (t == 0) {
+    st->nB2 = nb2;
+    st->trG1 = tr;
+  }
+}
+
+// -----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_formM(int n2, int k, const double *__restrict__ GA,
+                                               const double *__restrict__ B,
+                                               double *__restrict__ M, const SmallState *st) {
+  if (st->done) return;
+  const int64_t total = (int64_t)n2 * n2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n2), j = (int)(e / n2);
+    const double *bi = B + (int64_t)i * k, *bj = B + (int64_t)j * k;
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s = fma(bi[c], bj[c], s);
+    M[e] = GA[e] - s;
+  }
+}
+
+// -----------------------------------------------------------------------------
+// Helpers for k_post (1024 threads).  All small matrices column-major.
+
+// out (r x c) with out(a, b) = sum_i X[a + i*ldx] * Y[b + i*ldy]: products
+// of two short-and-wide matrices over their long index; one thread per
+// entry, sequential (deterministic) sums.
+__device__ void gram_rows(int n, const double *X, int ldx, int r, const double *Y, int ldy, int c,
+                          double *out) {
+  for (int e = threadIdx.x; e < r * c; e += blockDim.x) {
+    const int a = e % r, b = e / r;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s = fma(X[a + (int64_t)i * ldx], Y[b + (int64_t)i * ldy], s);
+    out[e] = s;
+  }
+}
+
+// In-place Cholesky (upper, K = R^T R) of a k x k matrix in LDS (ld 64).
+__device__ int small_chol64(double *K, int k, int *fail) {
+  if (threadIdx.x == 0) *fail = 0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x == 0) {
+      double p = K[j + j * 64];
+      if (!(p > 0)) {
+        *fail = 1;
+        p = 1.0;
+      }
+      K[j + j * 64] = sqrt(p);
+    }
+    __syncthreads();
+    const double rjj = K[j + j * 64];
+    for (int c = j + 1 + threadIdx.x; c < k; c += blockDim.x) K[j + c * 64] /= rjj;
+    __syncthreads();
+    const int rem = k - j - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+      const int aa = j + 1 + e % rem, cc = j + 1 + e / rem;
+      if (aa <= cc) K[aa + cc * 64] -= K[j + aa * 64] * K[j + cc * 64];
+    }
+    __syncthreads();
+  }
+  return *fail;
+}
+
+// x <- x K^-1 for a row vector x (stride sx) with K = R^T R symmetric:
+// solve R^T y = x^T, then R z = y.
+__device__ void row_solve(double *x, int sx, const double *R, int k) {
+  for (int i = 0; i < k; ++i) {
+    double s = x[i * sx];
+    for (int q = 0; q < i; ++q) s -= R[q + i * 64] * x[q * sx];
+    x[i * sx] = s / R[i + i * 64];
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    double s = x[i * sx];
+    for (int q = i + 1; q < k; ++q) s -= R[i + q * 64] * x[q * sx];
+    x[i * sx] = s / R[i + i * 64];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
+  SmallState *st = a.st;
+  if (st->done) return;
+  __shared__ double sK[64 * 64];
+  __shared__ int fail;
+  const int k = a.k, n2 = a.n2, l = a.l, b = a.b, t = threadIdx.x;
+  const double *V = a.Y;  // first l columns, ld n2
+  double *ws = a.scratch;
+  double *CV = ws;                       // k x l
+  double *S = CV + 64 * 32;              // k x k
+  double *Tm = S + 64 * 64;              // k x k
+  double *Zk = Tm + 64 * 64;             // n2 x k row-major, K^-1 folded in
+  double *Zd = a.Zcur;                   // n2 x k row-major, plain Z
+  // CV = C V, S = C C^T (sums over n2, C is k x n2 col-major)
+  for (int e = t; e < k * l; e += 1024) {
+    const int c = e % k, q = e / k;
+    double s = 0.0;
+    for (int j = 0; j < n2; ++j) s = fma(a.C[c + (int64_t)j * k], V[j + (int64_t)q * n2], s);
+    CV[e] = s;
+  }
+  gram_rows(n2, a.C, k, k, a.C, k, k, S);
+  __syncthreads();
+  for (int e = t; e < k * k; e += 1024) {
+    const int c = e % k, d = e / k;
+    double s = 0.0;
+    for (int q = 0; q < l; ++q) s = fma(CV[c + q * k], CV[d + q * k], s);
+    Tm[e] = s;
+  }
+  for (int j = t; j < n2; j += 1024) {
+    for (int c = 0; c < k; ++c) {
+      double s = a.C[c + (int64_t)j * k];
+      for (int q = 0; q < l; ++q) s -= V[j + (int64_t)q * n2] * CV[c + q * k];
+      Zd[(int64_t)j * k + c] = s;
+      Zk[(int64_t)j * k + c] = s;
+    }
+    for (int q = 0; q < l; ++q) a.Vcur[(int64_t)j * l + q] = V[j + (int64_t)q * n2];
+  }
+  __syncthreads();
+  for (int e = t; e < n2 * k; e += 1024) o.Zx[e] = (T)Zd[e];
+  const bool constw = a.wconst > 0;
+  if (constw) {
+    const double w2 = a.wconst * a.wconst;
+    for (int e = t; e < k * k; e += 1024) {
+      const int r = e % k, c = e / k;
+      sK[r + c * 64] = S[e] + (r == c ? w2 : 0.0);
+    }
+    __syncthreads();
+    small_chol64(sK, k, &fail);
+    // rows of S, of T and of Z, each times K^-1 (K = w^2 I + S)
+    for (int r = t; r < 2 * k + n2; r += 1024) {
+      if (r < k) row_solve(S + r, k, sK, k);
+      else if (r < 2 * k) row_solve(Tm + (r - k), k, sK, k);
+      else row_solve(Zk + (int64_t)(r - 2 * k) * k, 1, sK, k);
+    }
+    __syncthreads();
+  }
+  // typed copies for the row pass (row-major, input index first)
+  for (int e = t; e < k * k; e += 1024) {
+    const int r = e % k, c = e / k;  // S, Tm are col-major; store [r][c] row-major
+    o.St[r * k + c] = (T)S[e];
+    o.Tt[r * k + c] = (T)Tm[e];
+  }
+  for (int e = t; e < n2 * k; e += 1024) o.Zt[e] = (T)Zk[e];
+  for (int e = t; e < n2 * l; e += 1024) o.Vr[e] = (T)a.Vcur[e];
+  if (t == 0) {
+    // F(X_p) = ||(A1 - X1) o W1||^2 + ||P^perp A2||^2 - sum of the top r-k
+    // eigenvalues of M, with ||P^perp A2||^2 = ||A2||^2 - ||B||^2.
+    double sth = 0.0;
+    for (int q = 0; q < l; ++q) sth += a.theta[q];
+    st->F = st->f1 + st->trGA - st->nB2 - sth;
+    st->nrmX2sq = st->nB2 + sth;
+    st->nrmX = sqrt(st->trG1 + st->nB2 + sth);
+    if (l == 0 || b <= l)
+      st->gap = __builtin_inf();
+    else
+      st->gap = sqrt(fmax(a.theta[l - 1], 0.0)) - sqrt(fmax(a.theta[l], 0.0));
+  }
+}
+
+// Error_p and the stopping rule of Section 4.1:
+//   Error_p = ||X_p - X_{p-1}||_F,  stop when Error_p < tol or
+//   Error_p / ||X_{p-1}||_F < tol, or when p = max_sweeps.
+// ||X1_p - X1_{p-1}||^2 comes from the row update (dx1), ||X2_p - X2_{p-1}||^2
+// from the row pass k_change (partials in chg_part).
+__global__ __launch_bounds__(256) void k_decide(SmallArgs a) {
+  SmallState *st = a.st;
+  if (st->done) return;
+  __shared__ double red[4];
+  double d2 = 0.0;
+  if (st->have_prev)
+    for (int i = threadIdx.x; i < a.nchg; i += 256) d2 += a.chg_part[i];
+  d2 = block_sum(d2, red);
+  if (threadIdx.x == 0) {
+    int done = 0;
+    if (st->have_prev) {
+      const double err = sqrt(st->dx1 + d2);
+      st->err = err;
+      st->rel = st->nrmX_q > 0 ? err / st->nrmX_q : __builtin_inf();
+      if (st->tol > 0 && (err < st->tol || st->rel < st->tol)) {
+        done = 1;
+        st->status = 0;
+      }
+    } else {
+      st->err = 0.0;
+      st->rel = 0.0;
+    }
+    if (!done && st->sweep >= st->max_sweeps) {
+      done = 1;
+      st->status = 1;
+    }
+    st->nrmX_q = st->nrmX;
+    st->done = done;
+    st->have_prev = 1;
+    if (!done) st->sweep += 1;
+  }
+}
+
+// -----------------------------------------------------------------------------
+void launch_gastats(hipStream_t s, int n2, const double *GA, SmallState *st) {
+  hipLaunchKernelGGL(k_gastats, dim3(1), dim3(256), 0, s, n2, GA, st);
+}
+
+void launch_coef(hipStream_t s, const SmallArgs &a) {
+  hipLaunchKernelGGL(k_coef, dim3(1), dim3(256), 0, s, a);
+}
+
+void launch_formM(hipStream_t s, const SmallArgs &a) {
+  const int64_t total = (int64_t)a.n2 * a.n2;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_formM, dim3(g), dim3(256), 0, s, a.n2, a.k, a.GA, a.B, a.M, a.st);
+}
+
+void launch_decide(hipStream_t s, const SmallArgs &a) {
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, a);
+}
+
+template <typename T>
+void launch_post(hipStream_t s, const SmallArgs &a, const SmallOut<T> &o) {
+  hipLaunchKernelGGL(k_post<T>, dim3(1), dim3(1024), 0, s, a, o);
+}
+template void launch_post<float>(hipStream_t, const SmallArgs &, const SmallOut<float> &);
+template void launch_post<double>(hipStream_t, const SmallArgs &, const SmallOut<double> &);

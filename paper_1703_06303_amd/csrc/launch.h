@@ -1,0 +1,85 @@
+// Host-side launcher prototypes shared by the kernel files and the API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+template <typename T>
+struct UpdateArgs {
+  int64_t m;
+  int k, n2;
+  const T *A;
+  int64_t lda;
+  const T *W1;
+  int64_t ldw;
+  T wc;
+  bool constw;
+  const T *X1o;
+  T *X1n;
+  const T *Zt, *Tt, *St;
+  double *part;
+  int nl;
+  const SmallState *st;
+  int *flags;
+};
+
+template <typename T>
+void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t lda, int64_t k,
+                     const T *W1, int64_t ldw, int *flags);
+template <typename T>
+void launch_init_x1(hipStream_t s, int64_t m, int64_t k, int mode, uint64_t seed, const T *src,
+                    int64_t lds, T *X1, int *flags);
+template <typename TX, typename TY>
+void launch_tsgemm(hipStream_t s, int64_t m, const TX *X, int64_t ldx, int k1, const TY *Y,
+                   int64_t ldy, int k2, int sym, int splits, int64_t rows_per_split, double *part,
+                   double *out, const int *skip);
+template <typename T>
+void launch_f1(hipStream_t s, int64_t m, int k, const T *A, int64_t lda, const T *W1, int64_t ldw,
+               double wc, const T *X1, double *part, int nwg);
+template <typename T>
+void launch_update(hipStream_t s, const UpdateArgs<T> &a);
+template <typename T>
+void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
+               const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2);
+template <typename T>
+void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, int64_t ld);
+
+// Small-step kernels (k_small.hip, k_eig.hip).
+struct SmallArgs {
+  int k, n2, l, b;
+  int nparts;              // workgroups of the last row pass (f1, dx1 pairs)
+  const double *upd_part;  // [nparts][2]
+  int nchg;                // workgroups of the last change pass
+  const double *chg_part;  // [nchg]
+  const double *G1, *P, *GA;
+  double *R, *B, *C, *M;
+  double *Y, *Wb, *F0, *F1, *F2, *theta;
+  double *Zcur, *Vcur;     // this sweep's Z (n2 x k) and V (n2 x l), row-major double
+  double *scratch;         // k_post workspace
+  SmallState *st;
+  int *flags;
+  double wconst;           // > 0: constant W1
+  int eig_maxit, eig_deg;
+};
+
+template <typename T>
+struct SmallOut {
+  T *Zt, *Tt, *St, *Vr;  // row-pass operands (K^-1 folded in when W1 is constant)
+  T *Zx;                 // plain Z = (I - V V^T) C^T for the dense X2 output
+};
+
+void launch_coef(hipStream_t s, const SmallArgs &a);
+void launch_formM(hipStream_t s, const SmallArgs &a);
+void launch_eig(hipStream_t s, const SmallArgs &a);
+template <typename T>
+void launch_post(hipStream_t s, const SmallArgs &a, const SmallOut<T> &o);
+void launch_gastats(hipStream_t s, int n2, const double *GA, SmallState *st);
+void launch_decide(hipStream_t s, const SmallArgs &a);
+template <typename T>
+void launch_change(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
+                   const T *X1p, const T *X1q, const double *Zp, const double *Zq,
+                   const double *Vp, const double *Vq, double *part, const SmallState *st);

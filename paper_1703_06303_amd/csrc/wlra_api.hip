@@ -1,0 +1,417 @@
+// C-ABI of libwlra: argument checks, workspace, and the sweep loop of
+// Algorithm 1 driven from the host with one small device-to-host read of the
+// sweep state per sweep.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/wlra.h"
+#include "common.h"
+#include "launch.h"
+
+#define WLRA_VERSION 100
+#define EIG_GUARD 3
+#define EIG_DEG 12
+#define EIG_MAXIT 60
+#define UPD_LDS_BUDGET 65536
+
+struct wlra_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int precision = 0;
+  uint32_t flags = 0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  SmallState *st_host = nullptr;  // pinned
+  int *flags_host = nullptr;      // pinned
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+struct Layout {
+  size_t off[40];
+  size_t total;
+  int n = 0;
+  size_t add(size_t bytes) {
+    const size_t o = total;
+    total += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct Sizes {
+  int64_t m, n, k, r, n2, l, b;
+  int splits_ga, splits_p;
+  int64_t rows_ga, rows_p;
+  int nwg_upd, nwg_f1;
+  size_t elt;
+};
+
+struct Ptrs {
+  void *X1[2];
+  double *part, *GA, *P, *G1, *R, *B, *C, *M;
+  double *Y, *Wb, *F0, *F1, *F2, *theta, *scratch, *upd_part, *chg_part;
+  double *Zd[2], *Vd[2];
+  void *Zt, *Tt, *St, *Vr, *Zx;
+  SmallState *st;
+  int *flags;
+};
+
+int choose_splits(int64_t m, int tiles, int64_t *rows) {
+  int s = (int)std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, (m + 255) / 256));
+  int64_t r = (m + s - 1) / s;
+  r = (r + 31) / 32 * 32;
+  s = (int)((m + r - 1) / r);
+  *rows = r;
+  return std::max(1, s);
+}
+
+Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt) {
+  Sizes z;
+  z.m = m; z.n = n; z.k = k; z.r = r; z.n2 = n - k; z.l = r - k;
+  z.b = z.l > 0 ? std::min<int64_t>(z.n2, z.l + EIG_GUARD) : 0;
+  const int tga = (int)(((z.n2 + 31) / 32) * ((z.n2 + 31) / 32 + 1) / 2);
+  z.splits_ga = choose_splits(m, std::max(1, tga), &z.rows_ga);
+  const int tp = (int)(((std::max<int64_t>(k, 1) + 31) / 32) * ((z.n2 + 31) / 32));
+  z.splits_p = choose_splits(m, std::max(1, tp), &z.rows_p);
+  z.nwg_upd = (int)((m + 63) / 64);
+  z.nwg_f1 = 256;
+  z.elt = elt;
+  return z;
+}
+
+// Device workspace of one solve, in allocation order (256-byte aligned).
+Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
+  Layout L{};
+  L.total = 0;
+  const size_t d = sizeof(double);
+  const int64_t m = z.m, k = z.k, n2 = z.n2, l = z.l;
+  const int64_t kk = std::max<int64_t>(k, 1), ll = std::max<int64_t>(l, 1);
+  const size_t part = std::max<size_t>((size_t)z.splits_ga * n2 * n2,
+                                       (size_t)z.splits_p * std::max<int64_t>(kk * n2, kk * kk));
+  struct Item { void **dst; size_t bytes; };
+  Ptrs p{};
+  Item items[] = {
+      {&p.X1[0], (size_t)(m * kk) * z.elt},
+      {&p.X1[1], (size_t)(m * kk) * z.elt},
+      {(void **)&p.part, part * d},
+      {(void **)&p.GA, (size_t)(n2 * n2) * d},
+      {(void **)&p.P, (size_t)(kk * n2) * d},
+      {(void **)&p.G1, (size_t)(kk * kk) * d},
+      {(void **)&p.R, (size_t)(kk * kk) * d},
+      {(void **)&p.B, (size_t)(kk * n2) * d},
+      {(void **)&p.C, (size_t)(kk * n2) * d},
+      {(void **)&p.M, (size_t)(n2 * n2) * d},
+      {(void **)&p.Y, (size_t)(n2 * WLRA_BMAX) * d},
+      {(void **)&p.Wb, (size_t)(n2 * WLRA_BMAX) * d},
+      {(void **)&p.F0, (size_t)(n2 * WLRA_BMAX) * d},
+      {(void **)&p.F1, (size_t)(n2 * WLRA_BMAX) * d},
+      {(void **)&p.F2, (size_t)(n2 * WLRA_BMAX) * d},
+      {(void **)&p.theta, (size_t)WLRA_BMAX * d},
+      {(void **)&p.scratch, (size_t)(2048 + 2 * 4096 + 64 * n2) * d},
+      {(void **)&p.upd_part, (size_t)2 * std::max(z.nwg_upd, z.nwg_f1) * d},
+      {(void **)&p.chg_part, (size_t)z.nwg_upd * d},
+      {(void **)&p.Zd[0], (size_t)(n2 * kk) * d},
+      {(void **)&p.Zd[1], (size_t)(n2 * kk) * d},
+      {(void **)&p.Vd[0], (size_t)(n2 * ll) * d},
+      {(void **)&p.Vd[1], (size_t)(n2 * ll) * d},
+      {&p.Zt, (size_t)(n2 * kk) * z.elt},
+      {&p.Tt, (size_t)(kk * kk) * z.elt},
+      {&p.St, (size_t)(kk * kk) * z.elt},
+      {&p.Vr, (size_t)(n2 * ll) * z.elt},
+      {&p.Zx, (size_t)(n2 * kk) * z.elt},
+      {(void **)&p.st, sizeof(SmallState)},
+      {(void **)&p.flags, 64},
+  };
+  for (auto &it : items) {
+    const size_t off = L.add(it.bytes);
+    *it.dst = base ? (void *)(base + off) : nullptr;
+  }
+  if (P) *P = p;
+  return L;
+}
+
+int ensure_ws(wlra_ctx *h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return WLRA_OK;
+  if (h->ws) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return WLRA_E_HIP;
+    hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  const size_t want = bytes + bytes / 4;
+  if (hipMalloc(&h->ws, want) != hipSuccess) {
+    h->ws = nullptr;
+    return WLRA_E_NOMEM;
+  }
+  h->ws_bytes = want;
+  return WLRA_OK;
+}
+
+int check_problem(const wlra_problem *p, int precision) {
+  if (p == nullptr) return WLRA_E_ARG;
+  if (precision < WLRA_FP64 || precision > WLRA_MIXED_BF16) return WLRA_E_ARG;
+  const int64_t m = p->m, n = p->n, k = p->k, r = p->r;
+  if (m < 1 || n < 1 || k < 0 || r < k || r > std::min(m, n)) return WLRA_E_ARG;
+  if (k > WLRA_KMAX) return WLRA_E_ARG;
+  const int64_t l = r - k, n2 = n - k;
+  if (l > WLRA_BMAX - EIG_GUARD) return WLRA_E_ARG;
+  if (l > 0 && n2 > 1024) return WLRA_E_ARG;
+  if (n2 > WLRA_NMAX) return WLRA_E_ARG;
+  if (p->A == nullptr || p->lda < m) return WLRA_E_ARG;
+  if (k > 0 && p->W1 != nullptr && p->ldw < m) return WLRA_E_ARG;
+  if (k > 0 && p->W1 == nullptr && !(p->w1_const > 0 && isfinite(p->w1_const))) return WLRA_E_WEIGHT;
+  if (p->max_sweeps < 0) return WLRA_E_ARG;
+  if (k > 0 && (p->X1_out == nullptr || p->ldx1 < m)) return WLRA_E_ARG;
+  if (p->X2_out != nullptr && p->ldx2 < m) return WLRA_E_ARG;
+  if (p->init < WLRA_INIT_RANDOM || p->init > WLRA_INIT_A1) return WLRA_E_ARG;
+  if (k > 0 && p->init == WLRA_INIT_GIVEN && (p->X1_init == nullptr || p->ldx0 < m)) return WLRA_E_ARG;
+  if (!(p->tol == p->tol)) return WLRA_E_ARG;
+  return WLRA_OK;
+}
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    if ((x) != hipSuccess) return WLRA_E_HIP; \
+  } while (0)
+
+template <typename T>
+int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
+  const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T));
+  int rc = ensure_ws(h, make_layout(z, nullptr, nullptr).total);
+  if (rc != WLRA_OK) return rc;
+  Ptrs P;
+  make_layout(z, &P, h->ws);
+  hipStream_t s = h->stream;
+  const int64_t m = z.m, k = z.k, n2 = z.n2, l = z.l, b = z.b;
+  const T *A = static_cast<const T *>(pr->A);
+  const T *A2 = A + k * pr->lda;
+  const T *W1 = (k > 0) ? static_cast<const T *>(pr->W1) : nullptr;
+  const bool constw = (k > 0 && W1 == nullptr);
+  const double wc = constw ? pr->w1_const : 0.0;
+
+  HIPCHK(hipEventRecord(h->ev0, s));
+  HIPCHK(hipMemsetAsync(P.flags, 0, 64, s));
+  SmallState &sh = *h->st_host;
+  memset(&sh, 0, sizeof(SmallState));
+  sh.tol = pr->tol;
+  sh.max_sweeps = (k > 0) ? pr->max_sweeps : 0;
+  sh.eig_first = 1;
+  const double eig_tol = pr->eig_tol > 0 ? pr->eig_tol
+                         : (h->precision == WLRA_FP64 ? 64.0 * 2.220446049250313e-16 : 1e-10);
+  sh.eig_floor = eig_tol;
+  HIPCHK(hipMemcpyAsync(P.st, &sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
+
+  launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags);
+  T *X1c = static_cast<T *>(P.X1[0]);
+  if (k > 0) {
+    const int mode = pr->init == WLRA_INIT_RANDOM ? 0 : 1;
+    const T *src = pr->init == WLRA_INIT_GIVEN ? static_cast<const T *>(pr->X1_init) : A;
+    const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : pr->lda;
+    launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags);
+  }
+  // One-time Gram of the unweighted block: A2^T A2.
+  launch_tsgemm<T, T>(s, m, A2, pr->lda, (int)n2, A2, pr->lda, (int)n2, 1, z.splits_ga, z.rows_ga,
+                      P.part, P.GA, nullptr);
+  // eig_floor is relative to ||A2^T A2||_F; k_gastats scales it.
+  launch_gastats(s, (int)n2, P.GA, P.st);
+  int nparts = 0;
+  if (k > 0) {
+    launch_tsgemm<T, T>(s, m, X1c, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p, z.rows_p,
+                        P.part, P.P, nullptr);
+    launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_p, z.rows_p, P.part,
+                        P.G1, nullptr);
+    launch_f1<T>(s, m, (int)k, A, pr->lda, W1, pr->ldw, wc, X1c, P.upd_part, z.nwg_f1);
+    nparts = z.nwg_f1;
+  }
+  HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (*h->flags_host & DEV_BAD_W) return WLRA_E_WEIGHT;
+  if (*h->flags_host & DEV_BAD_A) return WLRA_E_NONFINITE;
+
+  SmallArgs sa{};
+  sa.k = (int)k; sa.n2 = (int)n2; sa.l = (int)l; sa.b = (int)b;
+  sa.G1 = P.G1; sa.P = P.P; sa.GA = P.GA;
+  sa.R = P.R; sa.B = P.B; sa.C = P.C; sa.M = P.M;
+  sa.Y = P.Y; sa.Wb = P.Wb; sa.F0 = P.F0; sa.F1 = P.F1; sa.F2 = P.F2; sa.theta = P.theta;
+  sa.scratch = P.scratch; sa.st = P.st; sa.flags = P.flags; sa.wconst = constw ? wc : 0.0;
+  sa.eig_maxit = EIG_MAXIT; sa.eig_deg = EIG_DEG;
+  sa.upd_part = P.upd_part; sa.chg_part = P.chg_part; sa.nchg = z.nwg_upd;
+  SmallOut<T> so{static_cast<T *>(P.Zt), static_cast<T *>(P.Tt), static_cast<T *>(P.St),
+                 static_cast<T *>(P.Vr), static_cast<T *>(P.Zx)};
+
+  int cur = 0;
+  for (int p = 0;; ++p) {
+    // Small step for sweep p: R, B, C from the Grams of X1_p; the top r-k
+    // eigenpairs of (P^perp A2)^T (P^perp A2); Z, T, S and F(X_p).
+    sa.nparts = nparts;
+    sa.Zcur = P.Zd[p & 1];
+    sa.Vcur = P.Vd[p & 1];
+    launch_coef(s, sa);
+    if (l > 0) {
+      launch_formM(s, sa);
+      launch_eig(s, sa);
+    }
+    launch_post<T>(s, sa, so);
+    if (p > 0)
+      launch_change<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c,
+                       static_cast<const T *>(P.X1[cur ^ 1]), P.Zd[p & 1], P.Zd[(p & 1) ^ 1],
+                       P.Vd[p & 1], P.Vd[(p & 1) ^ 1], P.chg_part, P.st);
+    launch_decide(s, sa);
+    HIPCHK(hipMemcpyAsync(h->st_host, P.st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (pr->trace && p <= pr->max_sweeps) {
+      pr->trace[p] = sh.F;
+      pr->trace[pr->max_sweeps + 1 + p] = sh.err;
+    }
+    if (sh.done) break;
+    // X1_{p+1} from X1_p (Algorithm 1 steps 7-9), then the sums for p+1.
+    T *X1n = static_cast<T *>(P.X1[cur ^ 1]);
+    UpdateArgs<T> ua{};
+    ua.m = m; ua.k = (int)k; ua.n2 = (int)n2; ua.A = A; ua.lda = pr->lda; ua.W1 = W1;
+    ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1c; ua.X1n = X1n;
+    ua.Zt = so.Zt; ua.Tt = so.Tt; ua.St = so.St; ua.part = P.upd_part; ua.st = P.st;
+    ua.flags = P.flags;
+    {
+      const size_t per = (size_t)(k * (k + 1) / 2 + k) * sizeof(T);
+      int nl = 64;
+      while (nl > 1 && per * nl > UPD_LDS_BUDGET) nl >>= 1;
+      ua.nl = nl;
+    }
+    launch_update<T>(s, ua);
+    launch_tsgemm<T, T>(s, m, X1n, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p, z.rows_p,
+                        P.part, P.P, nullptr);
+    launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_p, z.rows_p, P.part,
+                        P.G1, nullptr);
+    nparts = z.nwg_upd;
+    cur ^= 1;
+    X1c = X1n;
+  }
+  HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int dflags = *h->flags_host;
+  if (dflags & DEV_RANK) return WLRA_E_RANK;
+  if (k > 0) launch_copy_out<T>(s, m, k, X1c, static_cast<T *>(pr->X1_out), pr->ldx1);
+  if (pr->X2_out != nullptr)
+    launch_x2<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c, so.Zx, so.Vr,
+                 static_cast<T *>(pr->X2_out), pr->ldx2);
+  HIPCHK(hipEventRecord(h->ev1, s));
+  HIPCHK(hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  if (res) {
+    res->status = (k == 0) ? WLRA_OK : sh.status;
+    res->sweeps = sh.sweep;
+    res->objective = sh.F;
+    res->abs_change = sh.err;
+    res->rel_change = sh.rel;
+    res->gap = sh.gap;
+    res->ms = ms;
+    res->eig_iters = sh.eig_iters;
+  }
+  return (k == 0) ? WLRA_OK : sh.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wlra_version(void) { return WLRA_VERSION; }
+
+const char *wlra_strerror(int status) {
+  switch (status) {
+    case WLRA_OK: return "converged";
+    case WLRA_MAX_SWEEPS: return "maximum number of sweeps reached";
+    case WLRA_E_ARG: return "invalid argument";
+    case WLRA_E_WEIGHT: return "W1 entry not positive or not finite";
+    case WLRA_E_NONFINITE: return "non-finite entry in A or X1_init";
+    case WLRA_E_RANK: return "X1 numerically rank deficient";
+    case WLRA_E_NOMEM: return "out of device memory";
+    case WLRA_E_HIP: return "HIP runtime error";
+    case WLRA_E_NODEVICE: return "no usable gfx950 device";
+    default: return "unknown status";
+  }
+}
+
+int wlra_validate(const wlra_problem *prob, int precision) {
+  const int rc = check_problem(prob, precision);
+  return rc == WLRA_E_WEIGHT ? WLRA_E_ARG : rc;
+}
+
+int wlra_create(wlra_handle *out, int device, void *hip_stream, int precision, uint32_t flags) {
+  if (out == nullptr) return WLRA_E_ARG;
+  *out = nullptr;
+  if (precision < WLRA_FP64 || precision > WLRA_MIXED_BF16) return WLRA_E_ARG;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return WLRA_E_NODEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return WLRA_E_NODEVICE;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return WLRA_E_NODEVICE;
+  if (hipSetDevice(device) != hipSuccess) return WLRA_E_HIP;
+  wlra_ctx *h = new (std::nothrow) wlra_ctx();
+  if (h == nullptr) return WLRA_E_NOMEM;
+  h->device = device;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->precision = precision;
+  h->flags = flags;
+  if (hipHostMalloc((void **)&h->st_host, sizeof(SmallState), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&h->flags_host, 64, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+    wlra_destroy(h);
+    return WLRA_E_HIP;
+  }
+  *out = h;
+  return WLRA_OK;
+}
+
+int wlra_reserve(wlra_handle h, int64_t m, int64_t n, int64_t k, int64_t r) {
+  if (h == nullptr || m < 1 || n < 1 || k < 0 || r < k || r > std::min(m, n)) return WLRA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+  const Sizes z = make_sizes(m, n, k, r, h->precision == WLRA_FP64 ? 8 : 4);
+  return ensure_ws(h, make_layout(z, nullptr, nullptr).total);
+}
+
+int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res) {
+  if (h == nullptr) return WLRA_E_ARG;
+  int rc = check_problem(prob, h->precision);
+  if (rc != WLRA_OK) {
+    if (res) { memset(res, 0, sizeof(*res)); res->status = rc; }
+    return rc;
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+  if (h->precision == WLRA_FP64)
+    rc = solve_impl<double>(h, prob, res);
+  else
+    rc = solve_impl<float>(h, prob, res);
+  if (rc < 0 && res) res->status = rc;
+  return rc;
+}
+
+int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs, wlra_result *res) {
+  if (h == nullptr || count < 0 || (count > 0 && (probs == nullptr || res == nullptr)))
+    return WLRA_E_ARG;
+  for (int i = 0; i < count; ++i)
+    if (check_problem(&probs[i], h->precision) == WLRA_E_ARG) return WLRA_E_ARG;
+  for (int i = 0; i < count; ++i) wlra_solve(h, &probs[i], &res[i]);
+  return WLRA_OK;
+}
+
+int wlra_destroy(wlra_handle h) {
+  if (h == nullptr) return WLRA_OK;
+  if (h->ws) hipFree(h->ws);
+  if (h->st_host) hipHostFree(h->st_host);
+  if (h->flags_host) hipHostFree(h->flags_host);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  delete h;
+  return WLRA_OK;
+}
+
+}  // extern "C"

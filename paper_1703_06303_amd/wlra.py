@@ -1,0 +1,200 @@
+"""ctypes binding of libwlra (the C ABI declared in include/wlra.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  Matrices
+are column-major on the device; `colmajor(t)` gives a tensor whose storage is
+column-major (stride (1, m)).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwlra.so")
+
+OK, MAX_SWEEPS = 0, 1
+E_ARG, E_WEIGHT, E_NONFINITE, E_RANK, E_NOMEM, E_HIP, E_NODEVICE = -1, -2, -3, -4, -5, -6, -7
+FP64, FP32, MIXED_BF16 = 0, 1, 2
+INIT_RANDOM, INIT_GIVEN, INIT_A1, INIT_LEARNED = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16}
+INITS = {"random": INIT_RANDOM, "given": INIT_GIVEN, "a1": INIT_A1}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64), ("r", ctypes.c_int64),
+        ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+        ("W1", ctypes.c_void_p), ("ldw", ctypes.c_int64),
+        ("w1_const", ctypes.c_double), ("tol", ctypes.c_double),
+        ("max_sweeps", ctypes.c_int32), ("init", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("X1_init", ctypes.c_void_p), ("ldx0", ctypes.c_int64),
+        ("X1_out", ctypes.c_void_p), ("ldx1", ctypes.c_int64),
+        ("X2_out", ctypes.c_void_p), ("ldx2", ctypes.c_int64),
+        ("trace", ctypes.POINTER(ctypes.c_double)),
+        ("eig_tol", ctypes.c_double),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+        ("objective", ctypes.c_double), ("abs_change", ctypes.c_double),
+        ("rel_change", ctypes.c_double), ("gap", ctypes.c_double),
+        ("ms", ctypes.c_float), ("eig_iters", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+SYMBOLS = ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched", "wlra_destroy",
+           "wlra_validate", "wlra_strerror", "wlra_version")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libwlra.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libwlra.so not found at {path}; run paper_1703_06303_amd/build.py")
+    lib = ctypes.CDLL(path)
+    lib.wlra_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p,
+                                ctypes.c_int, ctypes.c_uint32]
+    lib.wlra_reserve.argtypes = [ctypes.c_void_p] + [ctypes.c_int64] * 4
+    lib.wlra_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Result)]
+    lib.wlra_solve_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
+                                       ctypes.POINTER(Result)]
+    lib.wlra_destroy.argtypes = [ctypes.c_void_p]
+    lib.wlra_validate.argtypes = [ctypes.POINTER(Problem), ctypes.c_int]
+    lib.wlra_strerror.argtypes = [ctypes.c_int]
+    lib.wlra_strerror.restype = ctypes.c_char_p
+    lib.wlra_version.argtypes = []
+    for name in ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
+                 "wlra_destroy", "wlra_validate", "wlra_version"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().wlra_strerror(code).decode()
+
+
+class WlraError(RuntimeError):
+    def __init__(self, code):
+        super().__init__(f"libwlra status {code}: {strerror(code)}")
+        self.code = code
+
+
+def colmajor(t):
+    """Column-major copy of a 2-D tensor (stride (1, rows))."""
+    return t.t().contiguous().t()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def make_problem(A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init="random",
+                 seed=0, X1_init=None, X1_out=None, X2_out=None, trace=None, eig_tol=0.0):
+    """Fill a Problem from tensors (column-major device tensors or None)."""
+    m, n = A.shape
+    p = Problem()
+    p.m, p.n, p.k, p.r = m, n, k, r
+    p.A, p.lda = _ptr(A), A.stride(1) if n > 1 else m
+    p.W1 = _ptr(W1)
+    p.ldw = W1.stride(1) if (W1 is not None and W1.shape[1] > 1) else m
+    p.w1_const = float(w1_const)
+    p.tol = float(tol)
+    p.max_sweeps = int(max_sweeps)
+    p.init = INITS[init] if isinstance(init, str) else int(init)
+    p.seed = int(seed)
+    p.X1_init = _ptr(X1_init)
+    p.ldx0 = X1_init.stride(1) if (X1_init is not None and X1_init.shape[1] > 1) else m
+    p.X1_out = _ptr(X1_out)
+    p.ldx1 = X1_out.stride(1) if (X1_out is not None and X1_out.shape[1] > 1) else m
+    p.X2_out = _ptr(X2_out)
+    p.ldx2 = X2_out.stride(1) if (X2_out is not None and X2_out.shape[1] > 1) else m
+    p.trace = trace if trace is not None else ctypes.POINTER(ctypes.c_double)()
+    p.eig_tol = float(eig_tol)
+    return p
+
+
+def validate(problem: Problem, precision: int) -> int:
+    """Host-only argument check (no device access)."""
+    return load().wlra_validate(ctypes.byref(problem), int(precision))
+
+
+class Solver:
+    """One libwlra handle bound to a device and a stream."""
+
+    def __init__(self, precision="fp32", device=0, stream=None):
+        import torch
+        lib = load()
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.dtype = torch.float64 if self.precision == FP64 else torch.float32
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib.wlra_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream),
+                             self.precision, 0)
+        if rc != OK:
+            raise WlraError(rc)
+        self.h = h
+        self.lib = lib
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.wlra_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, m, n, k, r):
+        rc = self.lib.wlra_reserve(self.h, m, n, k, r)
+        if rc != OK:
+            raise WlraError(rc)
+
+    def solve(self, A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init="random",
+              seed=0, X1_init=None, want_x2=False, want_trace=False, eig_tol=0.0, raise_on_error=True):
+        """Solve problem (5).  A, W1, X1_init: column-major device tensors of
+        the handle's dtype.  Returns (X1, X2 or None, result dict)."""
+        import torch
+        m, n = A.shape
+        X1 = colmajor(torch.empty((m, k), dtype=self.dtype, device=A.device))
+        X2 = colmajor(torch.empty((m, n - k), dtype=self.dtype, device=A.device)) if want_x2 else None
+        tr = (ctypes.c_double * (2 * (max_sweeps + 1)))() if want_trace else None
+        p = make_problem(A, k, r, W1=W1, w1_const=w1_const, tol=tol, max_sweeps=max_sweeps,
+                         init=init, seed=seed, X1_init=X1_init, X1_out=X1, X2_out=X2,
+                         trace=ctypes.cast(tr, ctypes.POINTER(ctypes.c_double)) if tr is not None else None,
+                         eig_tol=eig_tol)
+        res = Result()
+        rc = self.lib.wlra_solve(self.h, ctypes.byref(p), ctypes.byref(res))
+        if rc < 0 and raise_on_error:
+            raise WlraError(rc)
+        out = res.as_dict()
+        out["rc"] = rc
+        if tr is not None:
+            out["trace_F"] = list(tr[:max_sweeps + 1])
+            out["trace_err"] = list(tr[max_sweeps + 1:])
+        return X1, X2, out
+
+    def solve_batched(self, problems):
+        """Solve a list of Problem structs (already filled with pointers)."""
+        cnt = len(problems)
+        arr = (Problem * cnt)(*problems)
+        res = (Result * cnt)()
+        rc = self.lib.wlra_solve_batched(self.h, cnt, arr, res)
+        if rc < 0:
+            raise WlraError(rc)
+        return [r.as_dict() for r in res]

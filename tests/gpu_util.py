@@ -1,0 +1,35 @@
+"""Helpers shared by the GPU tests: move seeded inputs to the device in the
+column-major layout libwlra expects and bring results back."""
+import numpy as np
+
+
+def dev(x, dtype):
+    import torch
+    from paper_1703_06303_amd.wlra import colmajor
+    return colmajor(torch.tensor(np.asarray(x), dtype=dtype, device="cuda"))
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel(X, Y):
+    return float(np.linalg.norm(X - Y) / np.linalg.norm(Y))
+
+
+def gpu_solve(solver, inst, tol, max_sweeps, init="given", dense_w=None, want_x2=True,
+              want_trace=False, eig_tol=0.0, A=None):
+    """Run one instance through the C ABI.  dense_w: pass W1 as a matrix
+    (default: a matrix unless the instance has a constant weight)."""
+    dt = solver.dtype
+    Ah = inst.A if A is None else A
+    Ad = dev(Ah, dt)
+    if dense_w is None:
+        dense_w = inst.W1 is not None
+    W1 = dev(inst.W1_dense(), dt) if (dense_w and inst.k > 0) else None
+    X0 = dev(inst.X1_0, dt) if (init == "given" and inst.k > 0) else None
+    X1, X2, res = solver.solve(Ad, inst.k, inst.r, W1=W1, w1_const=inst.w1_const or 1.0,
+                               tol=tol, max_sweeps=max_sweeps, init=init, X1_init=X0,
+                               want_x2=want_x2, want_trace=want_trace, eig_tol=eig_tol,
+                               raise_on_error=False)
+    return host(X1), (host(X2) if X2 is not None else None), res

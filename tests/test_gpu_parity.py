@@ -1,0 +1,167 @@
+"""GPU parity of libwlra (called through its C ABI) against the FP64 oracle.
+
+Bars: relative Frobenius error of X = [X1 X2] <= 1e-10 in FP64 mode and
+<= 1e-5 in FP32 mode, at the same start X1_0 and the same number of sweeps
+(the X iterates of Algorithm 1 are compared, not only the fixed point).
+"""
+import numpy as np
+import pytest
+
+from gen import video
+from oracle import swlr as O
+
+from .gpu_util import gpu_solve, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def s64():
+    from paper_1703_06303_amd.wlra import Solver
+    return Solver("fp64")
+
+
+@pytest.fixture(scope="module")
+def s32():
+    from paper_1703_06303_amd.wlra import Solver
+    return Solver("fp32")
+
+
+def _oracle(inst, tol, sweeps):
+    w = inst.W1 if inst.W1 is not None else inst.w1_const
+    return O.swlr(inst.A, w, inst.k, inst.r, tol=tol, max_sweeps=sweeps, X1_0=inst.X1_0)
+
+
+@pytest.mark.parametrize("sweeps", [0, 1, 3, 6])
+def test_config1_fp64_same_sweeps(s64, sweeps):
+    inst = video.config1()
+    ref = _oracle(inst, 0.0, sweeps)
+    X1, X2, res = gpu_solve(s64, inst, 0.0, sweeps)
+    print("config1 fp64 sweeps", sweeps, res, flush=True)
+    assert res["rc"] == 1 and res["sweeps"] == sweeps
+    assert rel(np.hstack([X1, X2]), ref.X) <= 1e-10
+    assert abs(res["objective"] - ref.F[-1]) <= 1e-12 * ref.F[-1]
+
+
+def test_config1_fp64_converged(s64):
+    inst = video.config1()
+    ref = _oracle(inst, 1e-7, 100)
+    X1, X2, res = gpu_solve(s64, inst, 1e-7, 100, want_trace=True)
+    assert res["rc"] == 0
+    assert res["sweeps"] == ref.sweeps
+    assert rel(np.hstack([X1, X2]), ref.X) <= 1e-10
+    assert res["rel_change"] == pytest.approx(ref.rel[-1], rel=1e-3, abs=1e-12)
+    F = np.array(res["trace_F"][:res["sweeps"] + 1])
+    assert np.all(np.diff(F) <= 1e-13 * F[0])
+
+
+def test_config1_constant_vs_dense_weight(s64):
+    inst = video.config1()
+    X1a, X2a, ra = gpu_solve(s64, inst, 0.0, 4, dense_w=False)
+    X1b, X2b, rb = gpu_solve(s64, inst, 0.0, 4, dense_w=True)
+    assert rel(np.hstack([X1a, X2a]), np.hstack([X1b, X2b])) <= 1e-11
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return video.config2()
+
+
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_config2_fp32_same_sweeps(s32, c2, sweeps):
+    ref = _oracle(c2, 0.0, sweeps)
+    X1, X2, res = gpu_solve(s32, c2, 0.0, sweeps)
+    err = rel(np.hstack([X1, X2]), ref.X)
+    print("config2 fp32 sweeps", sweeps, "relX", err, res, flush=True)
+    assert err <= 1e-5
+    assert abs(res["objective"] - ref.F[-1]) <= 1e-6 * ref.F[-1]
+
+
+def test_config2_fp32_converged_objective(s32, c2):
+    ref = _oracle(c2, 1e-13, 60)
+    X1, X2, res = gpu_solve(s32, c2, 1e-7, 100)
+    print("config2 fp32 converged", res, "F*", ref.F[-1], flush=True)
+    assert res["rc"] == 0
+    assert abs(res["objective"] - ref.F[-1]) <= 1e-6 * ref.F[-1]
+    # the reported objective is the objective of the returned X
+    F_true = O.objective(c2.A, c2.W1, np.hstack([X1, X2]), c2.k)
+    assert abs(res["objective"] - F_true) <= 1e-6 * F_true
+    assert rel(np.hstack([X1, X2]), ref.X) <= 1e-5
+
+
+# ragged sizes: rows not a multiple of 64, columns not of 32, k across the
+# register-tile templates, r = k (no D term), k = 0 (Eckart-Young), a block
+# that covers all of n - k.
+SHAPES = [
+    (10, 10, 13, 3, 5, True),
+    (257, 1, 40, 17, 20, False),
+    (13, 10, 70, 33, 36, False),
+    (8, 8, 9, 1, 2, True),
+    (9, 10, 20, 5, 5, False),
+    (15, 5, 12, 0, 4, False),
+    (10, 5, 8, 2, 7, False),
+    (20, 30, 150, 60, 64, False),
+]
+
+
+@pytest.mark.parametrize("h,w,n,k,r,const", SHAPES)
+def test_ragged_shapes_fp64(s64, h, w, n, k, r, const):
+    wspec = ("const", 7.5) if const else ("loguniform", 0.0, 2.5)
+    inst = video.make_instance(h, w, n, k, r, 2, fg="bernoulli", fg_p=0.1, fg_lo=0.5, fg_hi=1.0,
+                               noise=0.05, w1=wspec, seed=1000 + h * w + n + k)
+    for sweeps in (2, 5):
+        ref = _oracle(inst, 0.0, sweeps)
+        X1, X2, res = gpu_solve(s64, inst, 0.0, sweeps)
+        print("shape", (h * w, n, k, r), sweeps, res, flush=True)
+        assert res["rc"] in (0, 1)
+        X = np.hstack([X1, X2]) if k > 0 else X2
+        assert rel(X, ref.X) <= 1e-10
+        assert abs(res["objective"] - ref.F[-1]) <= 1e-11 * ref.F[-1]
+
+
+def test_fp32_ragged(s32):
+    inst = video.make_instance(17, 11, 45, 7, 10, 2, fg="blobs", noise=0.02,
+                               w1=("loguniform", 1.0, 4.0), seed=77, dtype=np.float32)
+    ref = _oracle(inst, 0.0, 4)
+    X1, X2, res = gpu_solve(s32, inst, 0.0, 4)
+    assert rel(np.hstack([X1, X2]), ref.X) <= 1e-5
+
+
+def test_deterministic(s32, c2):
+    a = gpu_solve(s32, c2, 0.0, 2)
+    b = gpu_solve(s32, c2, 0.0, 2)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2]["objective"] == b[2]["objective"]
+
+
+def test_theorem2_on_gpu_output(s64):
+    inst = video.small(m_hw=(12, 10), n=24, k=4, r=7, seed=9)
+    X1, X2, res = gpu_solve(s64, inst, 1e-12, 300)
+    assert rel(X2, O.ghs(X1, inst.A[:, inst.k:], inst.r)) <= 1e-10
+
+
+@pytest.mark.parametrize("init", ["random", "a1"])
+def test_other_starts_reach_same_objective(s64, init):
+    inst = video.config1()
+    ref = _oracle(inst, 1e-13, 200)
+    X1, X2, res = gpu_solve(s64, inst, 1e-9, 200, init=init)
+    assert res["rc"] == 0
+    assert abs(res["objective"] - ref.F[-1]) <= 1e-11 * ref.F[-1]
+
+
+def test_error_codes(s64):
+    from paper_1703_06303_amd import wlra
+    inst = video.small(seed=5)
+    bad = inst.W1.copy(); bad[3, 1] = 0.0
+    inst_w = video.Instance(A=inst.A, k=inst.k, r=inst.r, W1=bad, w1_const=0.0, X1_0=inst.X1_0,
+                            frame_hw=inst.frame_hw, seed=0)
+    assert gpu_solve(s64, inst_w, 1e-7, 10)[2]["rc"] == wlra.E_WEIGHT
+    A = inst.A.copy(); A[7, 2] = np.nan
+    assert gpu_solve(s64, inst, 1e-7, 10, A=A)[2]["rc"] == wlra.E_NONFINITE
+    X0 = inst.X1_0.copy(); X0[:, 1] = X0[:, 0]
+    inst_r = video.Instance(A=inst.A, k=inst.k, r=inst.r, W1=inst.W1, w1_const=0.0, X1_0=X0,
+                            frame_hw=inst.frame_hw, seed=0)
+    assert gpu_solve(s64, inst_r, 1e-7, 10)[2]["rc"] == wlra.E_RANK
+    inst_k = video.Instance(A=inst.A, k=inst.k, r=inst.k - 1, W1=inst.W1, w1_const=0.0,
+                            X1_0=inst.X1_0, frame_hw=inst.frame_hw, seed=0)
+    assert gpu_solve(s64, inst_k, 1e-7, 10)[2]["rc"] == wlra.E_ARG
