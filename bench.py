@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Throughput of the sWLR solve (Dutta & Li, arXiv 1703.06303) on one MI355X.
+
+One step = one complete solve of problem (5) with Algorithm 1 (random start,
+the Section 4.1 stopping rule with tol = 1e-7) on a seeded synthetic video
+matrix resident in HBM: 120 x 160 frames (m = 19200), n = 200, rank-3
+background, 10% 8x8 blob foreground, N(0, 0.02^2) noise, k = 20 background
+frames with W1 = 10**U(1, 4), r = 25, FP32 storage.  Every solve's objective
+is checked against the FP64 oracle's converged objective F* (relative 1e-6).
+
+Prints one JSON line (see the keys below).  `roofline` is for the kernel with
+the largest device time, from HIP events bracketing each launch on the
+library's stream in a profiled repeat of the timed steps.  `cpu_baseline` is
+the FP64 oracle (NumPy/LAPACK) on the host cores, on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def workload(name):
+    import numpy as np
+    from gen import video
+    if name == "config2":
+        inst = video.config2()
+        return inst, "fp32", np.float32
+    if name == "config1":
+        return video.config1(), "fp64", np.float64
+    if name == "config3":
+        return video.config3(), "fp32", np.float32
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_work(name, inst, res_list, elt):
+    """Algorithmic bytes and flops of one launch of kernel `name`."""
+    m, n, k, r = inst.m, inst.n, inst.k, inst.r
+    n2, l = n - k, r - k
+    wbytes = 0 if inst.W1 is None else m * k * elt
+    if name == "update":
+        bytes_ = m * n * elt + wbytes + 2 * m * k * elt
+        flops = 2 * m * n2 * k + 4 * m * k * k + (0 if inst.W1 is None else m * (k ** 3 / 3 + 2 * k * k))
+        return bytes_, flops, "hbm"
+    if name == "gram_X1A2":
+        return m * (n2 + k) * elt, 2 * m * k * n2, "hbm"
+    if name == "gram_A2":
+        return m * n2 * elt, m * n2 * n2, "fp64"
+    if name == "change":
+        return m * (n2 + 2 * k) * elt, 2 * m * n2 * (2 * l + 2 * k), "hbm"
+    if name == "eig":
+        mv = sum(x["eig_matvecs"] for x in res_list)
+        launches = sum(x["sweeps"] + 1 for x in res_list)
+        return 0, 2.0 * n2 * n2 * mv / max(launches, 1), "fp64"
+    return 0, 0, "latency"
+
+
+def cpu_baseline(inst, sample_solves, tol):
+    import numpy as np
+    from oracle import swlr as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    w = inst.W1 if inst.W1 is not None else inst.w1_const
+    t0 = time.perf_counter()
+    sweeps = []
+    for _ in range(sample_solves):
+        res = O.swlr(inst.A, w, inst.k, inst.r, tol=tol, max_sweeps=200, X1_0=inst.X1_0)
+        sweeps.append(res.sweeps)
+    dt = time.perf_counter() - t0
+    return {"value": sample_solves / dt, "unit": "solves/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{sample_solves} full solves of the same workload (tol {tol}, "
+                      f"{sweeps} sweeps), FP64 NumPy/LAPACK, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-solves", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from oracle import swlr as O
+    from paper_1703_06303_amd import wlra
+
+    inst, prec, npdt = workload(args.workload)
+    elt = 8 if prec == "fp64" else 4
+    # F* = the oracle's objective converged far below the paper's threshold.
+    w = inst.W1 if inst.W1 is not None else inst.w1_const
+    t0 = time.perf_counter()
+    ref = O.swlr(inst.A, w, inst.k, inst.r, tol=1e-13, max_sweeps=500, X1_0=inst.X1_0)
+    fstar = ref.F[-1]
+    t_ref = time.perf_counter() - t0
+    print(f"# oracle F* = {fstar!r} ({ref.sweeps} sweeps, {t_ref:.1f} s)", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    A = wlra.colmajor(torch.tensor(inst.A, dtype=tdt, device=dev))
+    W1 = wlra.colmajor(torch.tensor(inst.W1, dtype=tdt, device=dev)) if inst.W1 is not None else None
+    solver = wlra.Solver(prec)
+    solver.reserve(inst.m, inst.n, inst.k, inst.r)
+
+    def run(s, step):
+        return s.solve(A, inst.k, inst.r, W1=W1, w1_const=inst.w1_const or 1.0, tol=args.tol,
+                       max_sweeps=200, init="random", seed=1000 + step)
+
+    for i in range(args.warmup):
+        run(solver, i)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, _, res = run(solver, i)
+        results.append(res)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"# timed {args.steps} solves in {dt:.4f} s", file=sys.stderr, flush=True)
+
+    # profiled repeat of the same steps: per-kernel device time from events
+    psolver = wlra.Solver(prec, profile=True)
+    psolver.reserve(inst.m, inst.n, inst.k, inst.r)
+    run(psolver, 0)
+    psolver.profile(reset=True)
+    presults = []
+    for i in range(args.steps):
+        _, _, res = run(psolver, i)
+        presults.append(res)
+    torch.cuda.synchronize()
+    prof = psolver.profile()
+    total_ms = sum(v[1] for v in prof.values())
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    dname, (dlaunch, dms) = dom
+    avg_s = dms / dlaunch / 1e3
+    bytes_, flops, bound = kernel_work(dname, inst, presults, elt)
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    elif bound == "fp64":
+        roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "alu", "achieved": 0.0, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dname
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["share_of_device_time"] = dms / total_ms if total_ms else None
+
+    objs = np.array([r["objective"] for r in results])
+    relF = np.abs(objs - fstar) / fstar
+    sweeps = np.array([r["sweeps"] for r in results])
+    ok = int(np.sum((relF <= 1e-6) & (np.array([r["status"] for r in results]) == 0)))
+    value = args.steps / dt
+    line = {
+        "metric": "WLRA solves/s to rel. objective 1e-6 vs FP64 oracle; learned+mixed vs plain",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: m={inst.m} ({inst.frame_hw[0]}x{inst.frame_hw[1]}) "
+                               f"n={inst.n} k={inst.k} r={inst.r}, plain {prec} solve, random start, "
+                               f"tol {args.tol}",
+                   "m": inst.m, "n": inst.n, "k": inst.k, "r": inst.r, "precision": prec,
+                   "variant": "plain"},
+        "roofline": roof,
+        "solves_meeting_1e-6": f"{ok}/{args.steps}",
+        "max_rel_objective_err": float(relF.max()),
+        "sweeps_per_solve": float(sweeps.mean()),
+        "sweeps_per_s": float(sweeps.sum() / dt),
+        "kernel_ms_per_solve": {k_: v[1] / args.steps for k_, v in sorted(prof.items())},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(inst, args.cpu_solves, args.tol)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,13 +97,28 @@ typedef struct {
   double objective;        /* F(X_p) of problem (5), accumulated in double      */
   double abs_change;       /* Error_p = ||X_p - X_{p-1}||_F (0 when p = 0)      */
   double rel_change;       /* Error_p / ||X_{p-1}||_F                           */
-  double gap;              /* sigma_{r-k} - sigma_{r-k+1} of P^perp A2 (a lower
-                              estimate; +inf when r = k)                        */
+  double gap;              /* sigma_{r-k} - sigma_{r-k+1} of P^perp A2, with
+                              sigma_{r-k+1} from the first guard Ritz value of
+                              the eigen block; +inf when r = k                  */
   float ms;                /* wall time of the call on the handle's stream      */
-  int32_t eig_iters;       /* filter iterations of the eigen step, summed        */
+  int32_t eig_iters;       /* filter rounds of the eigen step, summed            */
+  int32_t eig_matvecs;     /* products of M = (P^perp A2)^T P^perp A2 with one
+                              vector done by the eigen step, summed             */
 } wlra_result;
 
 typedef struct wlra_ctx *wlra_handle;
+
+/* wlra_create flags. */
+#define WLRA_FLAG_PROFILE 1u  /* bracket every kernel launch with HIP events on
+                                 the handle's stream and keep per-kernel totals
+                                 (read with wlra_profile); adds event overhead */
+
+/* Per-kernel timing totals of a profiling handle. */
+typedef struct {
+  char name[24];           /* kernel name                                       */
+  int64_t launches;        /* launches since create or the last reset           */
+  double ms;               /* summed device time between the bracketing events  */
+} wlra_kstat;
 
 /* Create a handle bound to `device` and `hip_stream` (a hipStream_t; NULL is
  * the null stream).  The handle owns a workspace that grows on demand before
@@ -127,6 +142,11 @@ int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs,
                        wlra_result *res);
 
 int wlra_destroy(wlra_handle h);
+
+/* Copy up to `max` per-kernel totals into `out` (host) and return how many
+ * kernels have totals (0 when the handle was created without
+ * WLRA_FLAG_PROFILE).  reset != 0 clears the totals afterwards. */
+int wlra_profile(wlra_handle h, int32_t max, wlra_kstat *out, int32_t reset);
 
 /* Host-only argument check of one problem for a precision (no device access):
  * returns WLRA_OK or WLRA_E_ARG. */

@@ -41,7 +41,7 @@ struct SmallState {
   int32_t eig_iters;  // filter rounds, summed over sweeps
   int32_t have_prev;  // 1 when the (p-1) quantities are valid
   int32_t eig_first;  // 1 until the eigen block holds a warm start
-  int32_t pad;
+  int32_t eig_matvecs;  // products M y (single vectors), summed over sweeps
 };
 
 __device__ __forceinline__ void wave_sync() {

@@ -378,7 +378,7 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
   blk_rot(n2, Y, b, s.S);
   blk_rot(n2, W, b, s.S);
 
-  int locked = 0, it = 0;
+  int locked = 0, it = 0, nmv = b;
   while (true) {
     // residuals ||W_q - th_q Y_q|| for q in [locked, l)
     const int nq = l - locked;
@@ -432,6 +432,7 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
     blk_op(s, M, n2, F0, act, F1, Y, s.th, locked);
     for (int e = t; e < n2 * act; e += ET) F1[e] = (F1[e] - e0 * F0[e]) * (s1 / h);
     __syncthreads();
+    nmv += act * (d + 1);
     for (int j = 2; j <= d; ++j) {
       const double s2 = 1.0 / (tau - s1);
       blk_op(s, M, n2, F1, act, F2, Y, s.th, locked);
@@ -465,6 +466,7 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
   for (int q = t; q < b; q += ET) a.theta[q] = s.th[q];
   if (t == 0) {
     st->eig_iters += it;
+    st->eig_matvecs += nmv;
     st->eig_first = 0;
     if (it >= a.eig_maxit && locked < l) atomicOr(a.flags, DEV_EIG_MAXIT);
   }

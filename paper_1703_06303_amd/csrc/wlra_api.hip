@@ -20,6 +20,19 @@
 #define EIG_MAXIT 60
 #define UPD_LDS_BUDGET 65536
 
+enum KernelKind {
+  KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_XTX, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
+  KK_POST, KK_CHANGE, KK_DECIDE, KK_UPDATE, KK_X2, KK_COPY, KK_COUNT
+};
+static const char *kKernelNames[KK_COUNT] = {
+    "validate", "init_x1", "gram_A2", "gram_stats", "gram_X1A2", "gram_X1X1", "objective_f1",
+    "coef", "form_M", "eig", "post", "change", "decide", "update", "x2_out", "copy_out"};
+
+struct ProfEvent {
+  int kind;
+  hipEvent_t e0, e1;
+};
+
 struct wlra_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -30,7 +43,53 @@ struct wlra_ctx {
   SmallState *st_host = nullptr;  // pinned
   int *flags_host = nullptr;      // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // profiling (WLRA_FLAG_PROFILE)
+  std::vector<hipEvent_t> pool;
+  std::vector<ProfEvent> pending;
+  int64_t launches[KK_COUNT] = {};
+  double ms[KK_COUNT] = {};
 };
+
+static hipEvent_t prof_event(wlra_ctx *h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Fold finished event pairs into the totals (call after a stream sync).
+static void prof_collect(wlra_ctx *h) {
+  for (auto &pe : h->pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pe.e0, pe.e1) == hipSuccess) {
+      h->ms[pe.kind] += t;
+      h->launches[pe.kind] += 1;
+    }
+    h->pool.push_back(pe.e0);
+    h->pool.push_back(pe.e1);
+  }
+  h->pending.clear();
+}
+
+// Run `stmt` (one kernel launch) between two events when profiling.
+#define PROF(h, kind, stmt)                                        \
+  do {                                                             \
+    if ((h)->flags & WLRA_FLAG_PROFILE) {                          \
+      ProfEvent pe{kind, prof_event(h), prof_event(h)};            \
+      if (pe.e0 && pe.e1) hipEventRecord(pe.e0, (h)->stream);       \
+      stmt;                                                        \
+      if (pe.e0 && pe.e1) {                                        \
+        hipEventRecord(pe.e1, (h)->stream);                        \
+        (h)->pending.push_back(pe);                                \
+      }                                                            \
+    } else {                                                       \
+      stmt;                                                        \
+    }                                                              \
+  } while (0)
 
 namespace {
 
@@ -208,26 +267,30 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   sh.eig_floor = eig_tol;
   HIPCHK(hipMemcpyAsync(P.st, &sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
 
-  launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags);
+  PROF(h, KK_VALIDATE, launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags));
   T *X1c = static_cast<T *>(P.X1[0]);
   if (k > 0) {
     const int mode = pr->init == WLRA_INIT_RANDOM ? 0 : 1;
     const T *src = pr->init == WLRA_INIT_GIVEN ? static_cast<const T *>(pr->X1_init) : A;
     const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : pr->lda;
-    launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags);
+    PROF(h, KK_INIT, launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags));
   }
   // One-time Gram of the unweighted block: A2^T A2.
-  launch_tsgemm<T, T>(s, m, A2, pr->lda, (int)n2, A2, pr->lda, (int)n2, 1, z.splits_ga, z.rows_ga,
-                      P.part, P.GA, nullptr);
+  PROF(h, KK_GRAM,
+       (launch_tsgemm<T, T>(s, m, A2, pr->lda, (int)n2, A2, pr->lda, (int)n2, 1, z.splits_ga,
+                            z.rows_ga, P.part, P.GA, nullptr)));
   // eig_floor is relative to ||A2^T A2||_F; k_gastats scales it.
-  launch_gastats(s, (int)n2, P.GA, P.st);
+  PROF(h, KK_GAST, launch_gastats(s, (int)n2, P.GA, P.st));
   int nparts = 0;
   if (k > 0) {
-    launch_tsgemm<T, T>(s, m, X1c, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p, z.rows_p,
-                        P.part, P.P, nullptr);
-    launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_p, z.rows_p, P.part,
-                        P.G1, nullptr);
-    launch_f1<T>(s, m, (int)k, A, pr->lda, W1, pr->ldw, wc, X1c, P.upd_part, z.nwg_f1);
+    PROF(h, KK_XTA,
+         (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p,
+                              z.rows_p, P.part, P.P, nullptr)));
+    PROF(h, KK_XTX,
+         (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_p, z.rows_p,
+                              P.part, P.G1, nullptr)));
+    PROF(h, KK_F1, launch_f1<T>(s, m, (int)k, A, pr->lda, W1, pr->ldw, wc, X1c, P.upd_part,
+                                z.nwg_f1));
     nparts = z.nwg_f1;
   }
   HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -253,19 +316,21 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     sa.nparts = nparts;
     sa.Zcur = P.Zd[p & 1];
     sa.Vcur = P.Vd[p & 1];
-    launch_coef(s, sa);
+    PROF(h, KK_COEF, launch_coef(s, sa));
     if (l > 0) {
-      launch_formM(s, sa);
-      launch_eig(s, sa);
+      PROF(h, KK_FORMM, launch_formM(s, sa));
+      PROF(h, KK_EIG, launch_eig(s, sa));
     }
-    launch_post<T>(s, sa, so);
+    PROF(h, KK_POST, launch_post<T>(s, sa, so));
     if (p > 0)
-      launch_change<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c,
-                       static_cast<const T *>(P.X1[cur ^ 1]), P.Zd[p & 1], P.Zd[(p & 1) ^ 1],
-                       P.Vd[p & 1], P.Vd[(p & 1) ^ 1], P.chg_part, P.st);
-    launch_decide(s, sa);
+      PROF(h, KK_CHANGE,
+           launch_change<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c,
+                            static_cast<const T *>(P.X1[cur ^ 1]), P.Zd[p & 1],
+                            P.Zd[(p & 1) ^ 1], P.Vd[p & 1], P.Vd[(p & 1) ^ 1], P.chg_part, P.st));
+    PROF(h, KK_DECIDE, launch_decide(s, sa));
     HIPCHK(hipMemcpyAsync(h->st_host, P.st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    prof_collect(h);
     if (pr->trace && p <= pr->max_sweeps) {
       pr->trace[p] = sh.F;
       pr->trace[pr->max_sweeps + 1 + p] = sh.err;
@@ -284,11 +349,13 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
       while (nl > 1 && per * nl > UPD_LDS_BUDGET) nl >>= 1;
       ua.nl = nl;
     }
-    launch_update<T>(s, ua);
-    launch_tsgemm<T, T>(s, m, X1n, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p, z.rows_p,
-                        P.part, P.P, nullptr);
-    launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_p, z.rows_p, P.part,
-                        P.G1, nullptr);
+    PROF(h, KK_UPDATE, launch_update<T>(s, ua));
+    PROF(h, KK_XTA,
+         (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p,
+                              z.rows_p, P.part, P.P, nullptr)));
+    PROF(h, KK_XTX,
+         (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_p, z.rows_p,
+                              P.part, P.G1, nullptr)));
     nparts = z.nwg_upd;
     cur ^= 1;
     X1c = X1n;
@@ -297,12 +364,15 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   HIPCHK(hipStreamSynchronize(s));
   const int dflags = *h->flags_host;
   if (dflags & DEV_RANK) return WLRA_E_RANK;
-  if (k > 0) launch_copy_out<T>(s, m, k, X1c, static_cast<T *>(pr->X1_out), pr->ldx1);
+  if (k > 0)
+    PROF(h, KK_COPY, launch_copy_out<T>(s, m, k, X1c, static_cast<T *>(pr->X1_out), pr->ldx1));
   if (pr->X2_out != nullptr)
-    launch_x2<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c, so.Zx, so.Vr,
-                 static_cast<T *>(pr->X2_out), pr->ldx2);
+    PROF(h, KK_X2,
+         launch_x2<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c, so.Zx, so.Vr,
+                      static_cast<T *>(pr->X2_out), pr->ldx2));
   HIPCHK(hipEventRecord(h->ev1, s));
   HIPCHK(hipEventSynchronize(h->ev1));
+  prof_collect(h);
   float ms = 0.f;
   hipEventElapsedTime(&ms, h->ev0, h->ev1);
   if (res) {
@@ -314,6 +384,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     res->gap = sh.gap;
     res->ms = ms;
     res->eig_iters = sh.eig_iters;
+    res->eig_matvecs = sh.eig_matvecs;
   }
   return (k == 0) ? WLRA_OK : sh.status;
 }
@@ -403,8 +474,36 @@ int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs, 
   return WLRA_OK;
 }
 
+int wlra_profile(wlra_handle h, int32_t max, wlra_kstat *out, int32_t reset) {
+  if (h == nullptr || max < 0 || (max > 0 && out == nullptr)) return WLRA_E_ARG;
+  if (!(h->flags & WLRA_FLAG_PROFILE)) return 0;
+  int n = 0;
+  for (int i = 0; i < KK_COUNT; ++i) {
+    if (h->launches[i] == 0) continue;
+    if (n < max) {
+      memset(out[n].name, 0, sizeof(out[n].name));
+      strncpy(out[n].name, kKernelNames[i], sizeof(out[n].name) - 1);
+      out[n].launches = h->launches[i];
+      out[n].ms = h->ms[i];
+    }
+    ++n;
+  }
+  if (reset)
+    for (int i = 0; i < KK_COUNT; ++i) {
+      h->launches[i] = 0;
+      h->ms[i] = 0.0;
+    }
+  return n;
+}
+
 int wlra_destroy(wlra_handle h) {
   if (h == nullptr) return WLRA_OK;
+  for (auto &pe : h->pending) {
+    h->pool.push_back(pe.e0);
+    h->pool.push_back(pe.e1);
+  }
+  for (hipEvent_t e : h->pool)
+    if (e) hipEventDestroy(e);
   if (h->ws) hipFree(h->ws);
   if (h->st_host) hipHostFree(h->st_host);
   if (h->flags_host) hipHostFree(h->flags_host);

@@ -41,15 +41,21 @@ class Result(ctypes.Structure):
         ("status", ctypes.c_int32), ("sweeps", ctypes.c_int32),
         ("objective", ctypes.c_double), ("abs_change", ctypes.c_double),
         ("rel_change", ctypes.c_double), ("gap", ctypes.c_double),
-        ("ms", ctypes.c_float), ("eig_iters", ctypes.c_int32),
+        ("ms", ctypes.c_float), ("eig_iters", ctypes.c_int32), ("eig_matvecs", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
+FLAG_PROFILE = 1
+
 SYMBOLS = ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched", "wlra_destroy",
-           "wlra_validate", "wlra_strerror", "wlra_version")
+           "wlra_profile", "wlra_validate", "wlra_strerror", "wlra_version")
 
 _lib = None
 
@@ -69,12 +75,14 @@ def load(path: str = LIB_PATH):
     lib.wlra_solve_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
                                        ctypes.POINTER(Result)]
     lib.wlra_destroy.argtypes = [ctypes.c_void_p]
+    lib.wlra_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(KStat),
+                                 ctypes.c_int32]
     lib.wlra_validate.argtypes = [ctypes.POINTER(Problem), ctypes.c_int]
     lib.wlra_strerror.argtypes = [ctypes.c_int]
     lib.wlra_strerror.restype = ctypes.c_char_p
     lib.wlra_version.argtypes = []
     for name in ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
-                 "wlra_destroy", "wlra_validate", "wlra_version"):
+                 "wlra_destroy", "wlra_profile", "wlra_validate", "wlra_version"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -132,7 +140,7 @@ def validate(problem: Problem, precision: int) -> int:
 class Solver:
     """One libwlra handle bound to a device and a stream."""
 
-    def __init__(self, precision="fp32", device=0, stream=None):
+    def __init__(self, precision="fp32", device=0, stream=None, profile=False):
         import torch
         lib = load()
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -143,7 +151,7 @@ class Solver:
         self.stream = stream
         h = ctypes.c_void_p()
         rc = lib.wlra_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream),
-                             self.precision, 0)
+                             self.precision, FLAG_PROFILE if profile else 0)
         if rc != OK:
             raise WlraError(rc)
         self.h = h
@@ -159,6 +167,14 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+    def profile(self, reset=False):
+        """Per-kernel totals {name: (launches, ms)} of a profiling handle."""
+        buf = (KStat * 32)()
+        n = self.lib.wlra_profile(self.h, 32, buf, 1 if reset else 0)
+        if n < 0:
+            raise WlraError(n)
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].ms) for i in range(min(n, 32))}
 
     def reserve(self, m, n, k, r):
         rc = self.lib.wlra_reserve(self.h, m, n, k, r)
