@@ -15,126 +15,207 @@
 // Rayleigh-Ritz step solved by parallel cyclic Jacobi.  A Ritz pair is
 // converged when ||M y - theta y|| <= eig_floor.
 //
-// One workgroup of 1024 threads; vectors live in global memory (L2
-// resident); the block being multiplied is staged through LDS.
+// One workgroup of 1024 threads.  Every filter step is a barrier-separated
+// sequence of short phases, so the design keeps data on chip: M is read from
+// L2 with 8 loads in flight per thread, and the blocks Y (basis), W = M Y and
+// the three filter blocks live in LDS when they fit (W shares storage with a
+// filter block: it is only needed between the Rayleigh-Ritz step and the next
+// filter), else in global memory with LDS staging.  Blocks are addressed
+// through a handle that is either an offset into the LDS pool or a global
+// pointer, fixed at compile time, so LDS blocks compile to ds_* accesses.
 #include "common.h"
 #include "launch.h"
 
-#define ET 1024
+#define ET 512
 #define B_ WLRA_BMAX
+#define EIG_POOL 17152     // doubles of LDS for blocks / staging / partial sums
+#define EIG_PART 4096      // doubles reserved for matvec partial sums
 
 struct EigLDS {
-  double sx[8192];      // staged block (n2 x 8) for M * X
-  double sp[8192];      // partial sums
+  double pool[EIG_POOL];
   double H[B_ * B_];    // Gram / Rayleigh quotient / Cholesky factor
   double S[B_ * B_];    // Jacobi rotations (eigenvectors of H)
-  double G[B_ * B_];    // L^T X for projections
+  double G[B_ * B_];    // L^T X, R^-1
   double th[B_];
   double res[B_];
-  double red[16];
   double rc[32], rs[32];
   int rp[32], rq[32];
   int ints[4];
 };
 
-// Out[:, 0:nc] = M X[:, 0:nc] - L diag(thL) (L^T X)   (L = first `locked`
-// columns of Lb); all blocks n2 x *, ld n2.
-__device__ void blk_op(EigLDS &s, const double *__restrict__ M, int n2, const double *X, int nc,
-                       double *Out, const double *Lb, const double *thL, int locked) {
-  const int t = threadIdx.x;
-  const int S = max(1, min(8, ET / n2));
-  for (int c0 = 0; c0 < nc; c0 += 8) {
-    const int cw = min(8, nc - c0);
-    for (int e = t; e < n2 * 8; e += ET) {
-      const int l = e >> 3, q = e & 7;
-      s.sx[e] = (q < cw) ? X[l + (int64_t)(c0 + q) * n2] : 0.0;
+// Block handle: an offset into the LDS pool (RES) or a global pointer.
+template <bool RES>
+struct Blk;
+template <>
+struct Blk<true> {
+  int off;
+  __device__ __forceinline__ double &at(EigLDS &s, int i) const { return s.pool[off + i]; }
+  __device__ __forceinline__ Blk<true> plus(int d) const { return Blk<true>{off + d}; }
+  __device__ __forceinline__ bool same(const Blk<true> &o) const { return off == o.off; }
+};
+template <>
+struct Blk<false> {
+  double *p;
+  __device__ __forceinline__ double &at(EigLDS &, int i) const { return p[i]; }
+  __device__ __forceinline__ Blk<false> plus(int d) const { return Blk<false>{p + d}; }
+  __device__ __forceinline__ bool same(const Blk<false> &o) const { return p == o.p; }
+};
+
+#define STAGE_OFF 0                      // staging (global mode), 8192 doubles
+#define PART_OFF (EIG_POOL - EIG_PART)   // partial sums / row scratch
+
+struct EigCtx {
+  int n2, S, sl, row;    // slices of the matvec, this thread's slice and row
+  int l0, l1;            // column range of M owned by this thread
+  const double *M;
+};
+
+template <bool RES>
+__device__ __forceinline__ void blk_gram(EigLDS &s, const EigCtx &cx, Blk<RES> X, int p, Blk<RES> Y,
+                                         int q, double *G, bool diag = false);
+
+// Out[:, 0:nc] = M X[:, 0:nc] - L diag(thL) (L^T X), blocks n2 x * (ld n2).
+// On the FP64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16 x 4 slab
+// of M by a 4 x 16 slab of X.  Each wavefront owns whole 16-row tiles of the
+// output and runs over all of the inner index, so no cross-lane reduction is
+// needed.  Fragment layouts (lane l): A[l % 16][l / 16], B[l / 16][l % 16],
+// accumulator v holds D[l / 16 + 4 v][l % 16].
+typedef double eig_d4 __attribute__((ext_vector_type(4)));
+template <bool RES>
+__device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, int nc,
+                                       Blk<RES> Out, Blk<RES> Lb, const double *thL, int locked) {
+  const int t = threadIdx.x, n2 = cx.n2;
+  const int lane = t & 63, wv = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int cwmax = RES ? 16 : min(16, 8192 / n2);
+  const int rtiles = (n2 + 15) / 16;
+  for (int c0 = 0; c0 < nc; c0 += cwmax) {
+    const int cw = min(cwmax, nc - c0);
+    int xoff;  // X columns c0.. as an LDS offset (column-major, ld n2)
+    if (RES) {
+      xoff = reinterpret_cast<const Blk<true> &>(X).off + c0 * n2;
+    } else {
+      const Blk<RES> Xs = X.plus(c0 * n2);
+      for (int e = t; e < n2 * cw; e += ET) s.pool[STAGE_OFF + e] = Xs.at(s, e);
+      __syncthreads();
+      xoff = STAGE_OFF;
     }
-    __syncthreads();
-    if (t < S * n2) {
-      const int i = t % n2, sl = t / n2;
-      const int l0 = sl * n2 / S, l1 = (sl + 1) * n2 / S;
-      double acc[8];
+    const bool colok = li < cw;
+    for (int rt = wv; rt < rtiles; rt += ET / 64) {
+      const int r = rt * 16 + li;
+      const bool rowok = r < n2;
+      eig_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      int k = 0;
+      for (; k + 16 <= n2; k += 16) {
+        double a[4], bb[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-      for (int l = l0; l < l1; ++l) {
-        const double mv = M[i + (int64_t)l * n2];
-        const double *xr = s.sx + l * 8;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = fma(mv, xr[q], acc[q]);
-      }
-      if (S == 1) {
-        for (int q = 0; q < cw; ++q) Out[i + (int64_t)(c0 + q) * n2] = acc[q];
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s.sp[(sl * n2 + i) * 8 + q] = acc[q];
-      }
-    }
-    __syncthreads();
-    if (S > 1) {
-      for (int i = t; i < n2; i += ET)
-        for (int q = 0; q < cw; ++q) {
-          double v = 0.0;
-          for (int sl = 0; sl < S; ++sl) v += s.sp[(sl * n2 + i) * 8 + q];
-          Out[i + (int64_t)(c0 + q) * n2] = v;
+        for (int u = 0; u < 4; ++u) {
+          const int kk = k + 4 * u + lk;
+          a[u] = rowok ? cx.M[r + (int64_t)kk * n2] : 0.0;
+          bb[u] = colok ? s.pool[xoff + kk + li * n2] : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc, 0, 0, 0);
+      }
+      for (; k < n2; k += 4) {
+        const int kk = k + lk;
+        const bool kok = kk < n2;
+        const double a = (rowok && kok) ? cx.M[r + (int64_t)kk * n2] : 0.0;
+        const double bb = (colok && kok) ? s.pool[xoff + kk + li * n2] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+      }
+      if (colok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = rt * 16 + lk + 4 * v;
+          if (row < n2) Out.at(s, row + (c0 + li) * n2) = acc[v];
+        }
+      }
     }
     __syncthreads();
   }
   if (locked > 0) {
-    // G = L^T X  (locked x nc)
-    const int pairs = locked * nc;
-    const int Sg = max(1, min(8, ET / pairs));
-    for (int e = t; e < pairs * Sg; e += ET) {
-      const int pr = e % pairs, sl = e / pairs;
-      const int a = pr % locked, c = pr / locked;
-      const int i0 = sl * n2 / Sg, i1 = (sl + 1) * n2 / Sg;
-      double acc = 0.0;
-      for (int i = i0; i < i1; ++i) acc = fma(Lb[i + (int64_t)a * n2], X[i + (int64_t)c * n2], acc);
-      s.sp[e] = acc;
-    }
+    // Out -= L (diag(thL) L^T X)
+    blk_gram<RES>(s, cx, Lb, locked, X, nc, s.G);
+    for (int e = t; e < locked * nc; e += ET) s.G[(e % locked) + (e / locked) * B_] *= thL[e % locked];
     __syncthreads();
-    for (int pr = t; pr < pairs; pr += ET) {
-      double v = 0.0;
-      for (int sl = 0; sl < Sg; ++sl) v += s.sp[sl * pairs + pr];
-      s.G[(pr % locked) + (pr / locked) * B_] = v * thL[pr % locked];
+    for (int e = t; e < n2 * nc; e += ET) {
+      const int i = e % n2, c = e / n2;
+      double v = Out.at(s, e);
+      for (int a = 0; a < locked; ++a) v -= Lb.at(s, i + a * n2) * s.G[a + c * B_];
+      Out.at(s, e) = v;
     }
-    __syncthreads();
-    for (int i = t; i < n2; i += ET)
-      for (int c = 0; c < nc; ++c) {
-        double v = Out[i + (int64_t)c * n2];
-        for (int a = 0; a < locked; ++a) v -= Lb[i + (int64_t)a * n2] * s.G[a + c * B_];
-        Out[i + (int64_t)c * n2] = v;
-      }
     __syncthreads();
   }
 }
 
-// G (p x q, ld B_) = X^T Y over n2 rows; fixed-order sums.
-__device__ void blk_gram(EigLDS &s, int n2, const double *X, int p, const double *Y, int q,
-                         double *G) {
-  const int t = threadIdx.x;
-  const int pairs = p * q;
-  const int Sg = max(1, min(8, ET / pairs));
-  for (int e = t; e < pairs * Sg; e += ET) {
-    const int pr = e % pairs, sl = e / pairs;
-    const int a = pr % p, c = pr / p;
-    const int i0 = sl * n2 / Sg, i1 = (sl + 1) * n2 / Sg;
+// G (p x q, ld B_) = X^T Y over n2 rows.  Global blocks are staged through
+// LDS first when they fit.  Each wavefront takes whole (a, c) pairs, lanes
+// stride over the rows and a fixed xor tree sums them (deterministic).
+// `diag` computes only a == c (p == q).
+__device__ __forceinline__ void gram_pairs(EigLDS &s, int n2, int xoff, int p, int yoff, int q,
+                                           double *G, bool diag) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int pairs = diag ? p : p * q;
+  for (int pr = wv; pr < pairs; pr += ET / 64) {
+    const int a = diag ? pr : pr % p, c = diag ? pr : pr / p;
+    const int xa = xoff + a * n2, yc = yoff + c * n2;
     double acc = 0.0;
-    for (int i = i0; i < i1; ++i) acc = fma(X[i + (int64_t)a * n2], Y[i + (int64_t)c * n2], acc);
-    s.sp[e] = acc;
-  }
-  __syncthreads();
-  for (int pr = t; pr < pairs; pr += ET) {
-    double v = 0.0;
-    for (int sl = 0; sl < Sg; ++sl) v += s.sp[sl * pairs + pr];
-    G[(pr % p) + (pr / p) * B_] = v;
+    for (int i = lane; i < n2; i += 64) acc = fma(s.pool[xa + i], s.pool[yc + i], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) G[a + c * B_] = acc;
   }
   __syncthreads();
 }
 
+template <bool RES>
+__device__ __forceinline__ void blk_gram(EigLDS &s, const EigCtx &cx, Blk<RES> X, int p, Blk<RES> Y,
+                                         int q, double *G, bool diag) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, n2 = cx.n2;
+  if (RES) {
+    gram_pairs(s, n2, reinterpret_cast<const Blk<true> &>(X).off, p,
+               reinterpret_cast<const Blk<true> &>(Y).off, q, G, diag);
+    return;
+  }
+  const bool same = X.same(Y) && (p == q);
+  if ((int64_t)n2 * (same ? p : p + q) <= 8192) {
+    for (int e = t; e < n2 * p; e += ET) s.pool[STAGE_OFF + e] = X.at(s, e);
+    if (!same)
+      for (int e = t; e < n2 * q; e += ET) s.pool[STAGE_OFF + n2 * p + e] = Y.at(s, e);
+    __syncthreads();
+    gram_pairs(s, n2, STAGE_OFF, p, same ? STAGE_OFF : STAGE_OFF + n2 * p, q, G, diag);
+    return;
+  }
+  const int pairs = diag ? p : p * q;
+  for (int pr = wv; pr < pairs; pr += ET / 64) {
+    const int a = diag ? pr : pr % p, c = diag ? pr : pr / p;
+    double acc = 0.0;
+    for (int i = lane; i < n2; i += 64) acc = fma(X.at(s, i + a * n2), Y.at(s, i + c * n2), acc);
+    acc = wave_sum(acc);
+    if (lane == 0) G[a + c * B_] = acc;
+  }
+  __syncthreads();
+}
+
+// res[q - q0] = ||W_q - th_q Y_q|| for q in [q0, q1): wave per column.
+template <bool RES>
+__device__ __forceinline__ void blk_resid(EigLDS &s, int n2, Blk<RES> W, Blk<RES> Y, int q0, int q1) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int q = q0 + wv; q < q1; q += ET / 64) {
+    const double th = s.th[q];
+    double acc = 0.0;
+    for (int i = lane; i < n2; i += 64) {
+      const double r = W.at(s, i + q * n2) - th * Y.at(s, i + q * n2);
+      acc = fma(r, r, acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) s.res[q - q0] = sqrt(acc);
+  }
+  __syncthreads();
+}
 // Upper Cholesky in place of G (nb x nb, ld B_) by wavefront 0, with an
 // optional diagonal shift.  Returns nonzero on a non-positive pivot.
-__device__ int blk_chol(EigLDS &s, double *G, int nb, double shift) {
+__device__ __forceinline__ int blk_chol(EigLDS &s, double *G, int nb, double shift) {
   const int t = threadIdx.x;
   if (t < 64) {
     if (t == 0) s.ints[0] = 0;
@@ -166,49 +247,58 @@ __device__ int blk_chol(EigLDS &s, double *G, int nb, double shift) {
   return s.ints[0];
 }
 
-// X (n2 x nb) <- X R^-1, R upper in LDS; one row per thread.
-__device__ void blk_trsm(int n2, double *X, int nb, const double *R) {
-  for (int i = threadIdx.x; i < n2; i += ET) {
-    double x[B_];
-#pragma unroll
-    for (int c = 0; c < B_; ++c) x[c] = (c < nb) ? X[i + (int64_t)c * n2] : 0.0;
-#pragma unroll
-    for (int c = 0; c < B_; ++c) {
-      if (c < nb) {
-        double v = x[c];
-#pragma unroll
-        for (int a = 0; a < c; ++a) v -= x[a] * R[a + c * B_];
-        x[c] = v / R[c + c * B_];
-      }
+
+// X (n2 x nb) <- X S (S nb x nb in LDS, ld B_).  Rows are copied to LDS
+// scratch in chunks, then each thread forms one output entry.
+template <bool RES>
+__device__ __forceinline__ void blk_rot(EigLDS &s, int n2, Blk<RES> X, int nb, const double *S) {
+  const int t = threadIdx.x;
+  const int tmp = RES ? PART_OFF : STAGE_OFF;
+  const int cap = RES ? EIG_PART : 8192;
+  const int rows = max(1, cap / nb);
+  for (int r0 = 0; r0 < n2; r0 += rows) {
+    const int nr = min(rows, n2 - r0);
+    for (int e = t; e < nr * nb; e += ET) {
+      const int i = e % nr, c = e / nr;
+      s.pool[tmp + i * nb + c] = X.at(s, r0 + i + c * n2);
     }
-#pragma unroll
-    for (int c = 0; c < B_; ++c)
-      if (c < nb) X[i + (int64_t)c * n2] = x[c];
+    __syncthreads();
+    for (int e = t; e < nr * nb; e += ET) {
+      const int i = e % nr, c = e / nr;
+      double v = 0.0;
+      for (int a = 0; a < nb; ++a) v = fma(s.pool[tmp + i * nb + a], S[a + c * B_], v);
+      X.at(s, r0 + i + c * n2) = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// X (n2 x nb) <- X S (S nb x nb in LDS, ld B_); one row per thread.
-__device__ void blk_rot(int n2, double *X, int nb, const double *S) {
-  for (int i = threadIdx.x; i < n2; i += ET) {
-    double x[B_];
-#pragma unroll
-    for (int c = 0; c < B_; ++c) x[c] = (c < nb) ? X[i + (int64_t)c * n2] : 0.0;
-    for (int c = 0; c < nb; ++c) {
-      double v = 0.0;
-#pragma unroll
-      for (int a = 0; a < B_; ++a)
-        if (a < nb) v = fma(x[a], S[a + c * B_], v);
-      X[i + (int64_t)c * n2] = v;
+// X (n2 x nb) <- X R^-1 with R upper triangular in LDS: wavefront 0 forms
+// R^-1 (column c of R^-1 by back substitution on lane c), then blk_rot.
+template <bool RES>
+__device__ __forceinline__ void blk_trsm(EigLDS &s, int n2, Blk<RES> X, int nb, const double *R) {
+  const int t = threadIdx.x;
+  double *Ri = s.G;
+  if (t < 64) {
+    for (int e = t; e < B_ * B_; e += 64) Ri[e] = 0.0;
+    wave_sync();
+    if (t < nb) {
+      const int c = t;
+      for (int a = c; a >= 0; --a) {
+        double v = (a == c) ? 1.0 : 0.0;
+        for (int q = a + 1; q <= c; ++q) v -= R[a + q * B_] * Ri[q + c * B_];
+        Ri[a + c * B_] = v / R[a + a * B_];
+      }
     }
   }
   __syncthreads();
+  blk_rot<RES>(s, n2, X, nb, Ri);
 }
 
 // Symmetric eigendecomposition of H (nb x nb) by parallel cyclic Jacobi on
 // wavefront 0 (round-robin pairing, nb/2 disjoint rotations per round).
 // On return th[0..nb) is descending and S holds the eigenvectors.
-__device__ void blk_jacobi(EigLDS &s, int nb) {
+__device__ __forceinline__ void blk_jacobi(EigLDS &s, int nb) {
   const int t = threadIdx.x;
   if (t < 64) {
     double *H = s.H, *S = s.S;
@@ -226,7 +316,8 @@ __device__ void blk_jacobi(EigLDS &s, int nb) {
       }
       off = wave_sum(off);
       tot = wave_sum(tot);
-      if (!(off > 1e-32 * tot)) break;
+      // converged once the off-diagonal mass is at the rounding level of H
+      if (!(off > 1e-28 * tot)) break;
       for (int round = 0; round < nbp - 1; ++round) {
         if (t < half) {
           const int x0 = t, x1 = nbp - 1 - t;
@@ -315,35 +406,35 @@ __device__ void blk_jacobi(EigLDS &s, int nb) {
 // Orthonormalise the nb columns of X against the `locked` columns of L and
 // among themselves: CholeskyQR2, shifted CholeskyQR3 if the Gram is not
 // numerically positive definite.
-__device__ void blk_orth(EigLDS &s, int n2, double *X, int nb, const double *L, int locked,
-                         int *flags) {
-  const int t = threadIdx.x;
+template <bool RES>
+__device__ __forceinline__ void blk_orth(EigLDS &s, const EigCtx &cx, Blk<RES> X, int nb,
+                                         Blk<RES> L, int locked, int *flags) {
+  const int t = threadIdx.x, n2 = cx.n2;
   int shifted = 0;
   for (int rep = 0; rep < 3; ++rep) {
     if (rep == 2 && !shifted) break;
     if (locked > 0) {
-      blk_gram(s, n2, L, locked, X, nb, s.G);
-      for (int i = t; i < n2; i += ET)
-        for (int c = 0; c < nb; ++c) {
-          double v = X[i + (int64_t)c * n2];
-          for (int a = 0; a < locked; ++a) v -= L[i + (int64_t)a * n2] * s.G[a + c * B_];
-          X[i + (int64_t)c * n2] = v;
-        }
+      blk_gram<RES>(s, cx, L, locked, X, nb, s.G);
+      for (int e = t; e < n2 * nb; e += ET) {
+        const int i = e % n2, c = e / n2;
+        double v = X.at(s, e);
+        for (int a = 0; a < locked; ++a) v -= L.at(s, i + a * n2) * s.G[a + c * B_];
+        X.at(s, e) = v;
+      }
       __syncthreads();
     }
     // normalise columns
-    blk_gram(s, n2, X, nb, X, nb, s.H);
+    blk_gram<RES>(s, cx, X, nb, X, nb, s.H, true);
     for (int c = t; c < nb; c += ET) s.res[c] = s.H[c + c * B_];
     __syncthreads();
-    for (int i = t; i < n2; i += ET)
-      for (int c = 0; c < nb; ++c) {
-        const double d = s.res[c];
-        X[i + (int64_t)c * n2] *= (d > 0 ? 1.0 / sqrt(d) : 0.0);
-      }
+    for (int e = t; e < n2 * nb; e += ET) {
+      const double d = s.res[e / n2];
+      X.at(s, e) *= (d > 0 ? 1.0 / sqrt(d) : 0.0);
+    }
     __syncthreads();
-    blk_gram(s, n2, X, nb, X, nb, s.H);
+    blk_gram<RES>(s, cx, X, nb, X, nb, s.H);
     if (blk_chol(s, s.H, nb, 0.0)) {
-      blk_gram(s, n2, X, nb, X, nb, s.H);
+      blk_gram<RES>(s, cx, X, nb, X, nb, s.H);
       double fro = 0.0;
       for (int e = 0; e < nb * nb; ++e) fro += s.H[(e % nb) + (e / nb) * B_] * s.H[(e % nb) + (e / nb) * B_];
       const double sh = 11.0 * ((double)n2 * nb + (double)nb * (nb + 1)) * 2.220446049250313e-16 * sqrt(fro);
@@ -353,56 +444,38 @@ __device__ void blk_orth(EigLDS &s, int n2, double *X, int nb, const double *L, 
         return;
       }
     }
-    blk_trsm(n2, X, nb, s.H);
+    blk_trsm<RES>(s, n2, X, nb, s.H);
   }
 }
 
-__global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
+template <bool RES>
+__device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const EigCtx &cx,
+                                         Blk<RES> Y, Blk<RES> F0, Blk<RES> F1, Blk<RES> F2) {
   SmallState *st = a.st;
-  if (st->done) return;
-  __shared__ EigLDS s;
   const int n2 = a.n2, l = a.l, b = a.b, t = threadIdx.x;
-  const double *M = a.M;
-  double *Y = a.Y, *W = a.Wb;
   const double floor_ = st->eig_floor;
   const double maxamp = 1e6;
-
+  Blk<RES> W = F0;
   if (st->eig_first) {
-    for (int e = t; e < n2 * b; e += ET) Y[e] = hash_unit((uint32_t)(e % n2), (uint32_t)(e / n2));
-    __syncthreads();
+    for (int e = t; e < n2 * b; e += ET) Y.at(s, e) = hash_unit((uint32_t)(e % n2), (uint32_t)(e / n2));
+  } else if (RES) {
+    for (int e = t; e < n2 * b; e += ET) Y.at(s, e) = a.Y[e];
   }
-  blk_orth(s, n2, Y, b, Y, 0, a.flags);
-  blk_op(s, M, n2, Y, b, W, Y, s.th, 0);
-  blk_gram(s, n2, Y, b, W, b, s.H);
+  __syncthreads();
+  blk_orth<RES>(s, cx, Y, b, Y, 0, a.flags);
+  blk_op<RES>(s, cx, Y, b, W, Y, s.th, 0);
+  blk_gram<RES>(s, cx, Y, b, W, b, s.H);
   blk_jacobi(s, b);
-  blk_rot(n2, Y, b, s.S);
-  blk_rot(n2, W, b, s.S);
+  blk_rot<RES>(s, n2, Y, b, s.S);
+  blk_rot<RES>(s, n2, W, b, s.S);
 
   int locked = 0, it = 0, nmv = b;
   while (true) {
-    // residuals ||W_q - th_q Y_q|| for q in [locked, l)
-    const int nq = l - locked;
-    const int Sg = max(1, min(8, ET / max(nq, 1)));
-    for (int e = t; e < nq * Sg; e += ET) {
-      const int q = locked + e % nq, sl = e / nq;
-      const int i0 = sl * n2 / Sg, i1 = (sl + 1) * n2 / Sg;
-      const double th = s.th[q];
-      double acc = 0.0;
-      for (int i = i0; i < i1; ++i) {
-        const double r = W[i + (int64_t)q * n2] - th * Y[i + (int64_t)q * n2];
-        acc = fma(r, r, acc);
-      }
-      s.sp[e] = acc;
-    }
-    __syncthreads();
+    // residuals ||W_q - th_q Y_q|| for q in [locked, l); lock the converged prefix
+    blk_resid<RES>(s, n2, W, Y, locked, l);
     if (t == 0) {
       int lk = locked;
-      while (lk < l) {
-        double v = 0.0;
-        for (int sl = 0; sl < Sg; ++sl) v += s.sp[sl * nq + (lk - locked)];
-        if (sqrt(v) <= floor_) ++lk;
-        else break;
-      }
+      while (lk < l && s.res[lk - locked] <= floor_) ++lk;
       s.ints[2] = lk;
     }
     __syncthreads();
@@ -410,8 +483,7 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
     if (locked >= l || it >= a.eig_maxit) break;
 
     const int act = b - locked;
-    double *Ya = Y + (int64_t)locked * n2;
-    double *Wa = W + (int64_t)locked * n2;
+    const Blk<RES> Ya = Y.plus(locked * n2);
     // filter interval [0, c] damped; normalised at th[locked]
     const double cc = s.th[b - 1];
     const double e0 = 0.5 * cc;
@@ -426,36 +498,38 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
     }
     const double sigma = h / (top - e0), tau = 2.0 / sigma;
     double s1 = sigma;
-    double *F0 = a.F0, *F1 = a.F1, *F2 = a.F2;
-    for (int e = t; e < n2 * act; e += ET) F0[e] = Ya[e];
+    Blk<RES> P0 = F0, P1 = F1, P2 = F2;
+    for (int e = t; e < n2 * act; e += ET) P0.at(s, e) = Ya.at(s, e);
     __syncthreads();
-    blk_op(s, M, n2, F0, act, F1, Y, s.th, locked);
-    for (int e = t; e < n2 * act; e += ET) F1[e] = (F1[e] - e0 * F0[e]) * (s1 / h);
+    blk_op<RES>(s, cx, P0, act, P1, Y, s.th, locked);
+    for (int e = t; e < n2 * act; e += ET) P1.at(s, e) = (P1.at(s, e) - e0 * P0.at(s, e)) * (s1 / h);
     __syncthreads();
     nmv += act * (d + 1);
     for (int j = 2; j <= d; ++j) {
       const double s2 = 1.0 / (tau - s1);
-      blk_op(s, M, n2, F1, act, F2, Y, s.th, locked);
+      blk_op<RES>(s, cx, P1, act, P2, Y, s.th, locked);
       for (int e = t; e < n2 * act; e += ET)
-        F2[e] = 2.0 * (s2 / h) * (F2[e] - e0 * F1[e]) - (s1 * s2) * F0[e];
+        P2.at(s, e) = 2.0 * (s2 / h) * (P2.at(s, e) - e0 * P1.at(s, e)) - (s1 * s2) * P0.at(s, e);
       __syncthreads();
-      double *tmp = F0;
-      F0 = F1;
-      F1 = F2;
-      F2 = tmp;
+      const Blk<RES> tmp = P0;
+      P0 = P1;
+      P1 = P2;
+      P2 = tmp;
       s1 = s2;
     }
-    for (int e = t; e < n2 * act; e += ET) Ya[e] = F1[e];
+    for (int e = t; e < n2 * act; e += ET) Ya.at(s, e) = P1.at(s, e);
     __syncthreads();
-    blk_orth(s, n2, Ya, act, Y, locked, a.flags);
-    blk_op(s, M, n2, Ya, act, Wa, Y, s.th, 0);
-    blk_gram(s, n2, Ya, act, Wa, act, s.H);
+    blk_orth<RES>(s, cx, Ya, act, Y, locked, a.flags);
+    // W (active columns) in F0: free once the filter is done
+    const Blk<RES> Wa = W.plus(locked * n2);
+    blk_op<RES>(s, cx, Ya, act, Wa, Y, s.th, 0);
+    blk_gram<RES>(s, cx, Ya, act, Wa, act, s.H);
     // keep the locked Ritz values while Jacobi overwrites th[0..act)
     for (int q = t; q < locked; q += ET) s.res[q] = s.th[q];
     __syncthreads();
     blk_jacobi(s, act);
-    blk_rot(n2, Ya, act, s.S);
-    blk_rot(n2, Wa, act, s.S);
+    blk_rot<RES>(s, n2, Ya, act, s.S);
+    blk_rot<RES>(s, n2, Wa, act, s.S);
     if (t == 0) {
       for (int q = act - 1; q >= 0; --q) s.th[locked + q] = s.th[q];
       for (int q = 0; q < locked; ++q) s.th[q] = s.res[q];
@@ -463,12 +537,35 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
     __syncthreads();
     ++it;
   }
+  if (RES)
+    for (int e = t; e < n2 * b; e += ET) a.Y[e] = Y.at(s, e);
   for (int q = t; q < b; q += ET) a.theta[q] = s.th[q];
   if (t == 0) {
     st->eig_iters += it;
     st->eig_matvecs += nmv;
     st->eig_first = 0;
     if (it >= a.eig_maxit && locked < l) atomicOr(a.flags, DEV_EIG_MAXIT);
+  }
+}
+
+__global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
+  if (a.st->done) return;
+  __shared__ EigLDS s;
+  const int n2 = a.n2, b = a.b, t = threadIdx.x;
+  EigCtx cx;
+  cx.n2 = n2;
+  cx.M = a.M;
+  cx.S = max(1, min(8, ET / n2));
+  cx.sl = t / n2;
+  cx.row = (t < cx.S * n2) ? t % n2 : -1;
+  cx.l0 = cx.sl * n2 / cx.S;
+  cx.l1 = (cx.sl + 1) * n2 / cx.S;
+  if (4 * n2 * b <= PART_OFF) {
+    eig_body<true>(s, a, cx, Blk<true>{0}, Blk<true>{n2 * b}, Blk<true>{2 * n2 * b},
+                   Blk<true>{3 * n2 * b});
+  } else {
+    eig_body<false>(s, a, cx, Blk<false>{a.Y}, Blk<false>{a.F0}, Blk<false>{a.F1},
+                    Blk<false>{a.F2});
   }
 }
 

@@ -31,11 +31,15 @@ __global__ __launch_bounds__(256) void k_gastats(int n2, const double *__restric
 }
 
 // -----------------------------------------------------------------------------
+// Columns of P are staged through LDS (stride k+1) in chunks; one thread
+// solves one column in place: forward with R^T gives B, backward with R
+// gives C.
+#define COEF_STAGE 12288
 __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
   SmallState *st = a.st;
   if (st->done) return;
   __shared__ double sR[64 * 64];
-  __shared__ double sW[64 * 64];
+  __shared__ double sP[COEF_STAGE];
   __shared__ double red[4];
   __shared__ int fail;
   const int k = a.k, n2 = a.n2, t = threadIdx.x;
@@ -93,25 +97,40 @@ __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
     const int r = e % k, c = e / k;
     a.R[e] = (r <= c) ? sR[r + c * 64] : 0.0;
   }
-  // B = R^-T P (forward substitution per column), C = R^-1 B (backward).
-  for (int j = t; j < n2; j += 256) {
-    const double *p = a.P + (int64_t)j * k;
-    double *bb = a.B + (int64_t)j * k;
-    double *cc = a.C + (int64_t)j * k;
-    for (int i = 0; i < k; ++i) {
-      double s = p[i];
-      for (int q = 0; q < i; ++q) s -= sR[q + i * 64] * bb[q];
-      bb[i] = s / sR[i + i * 64];
+  const int ld = k + 1;
+  const int cw = max(1, COEF_STAGE / max(ld, 1));
+  double nb2 = 0.0;
+  for (int j0 = 0; j0 < n2; j0 += cw) {
+    const int nc = min(cw, n2 - j0);
+    for (int e = t; e < nc * k; e += 256) sP[(e % k) + (e / k) * ld] = a.P[(int64_t)j0 * k + e];
+    __syncthreads();
+    for (int jj = t; jj < nc; jj += 256) {  // B = R^-T P
+      double *x = sP + jj * ld;
+      for (int i = 0; i < k; ++i) {
+        double s = x[i];
+        for (int q = 0; q < i; ++q) s -= sR[q + i * 64] * x[q];
+        x[i] = s / sR[i + i * 64];
+      }
     }
-    for (int i = k - 1; i >= 0; --i) {
-      double s = bb[i];
-      for (int q = i + 1; q < k; ++q) s -= sR[i + q * 64] * cc[q];
-      cc[i] = s / sR[i + i * 64];
+    __syncthreads();
+    for (int e = t; e < nc * k; e += 256) {
+      const double v = sP[(e % k) + (e / k) * ld];
+      a.B[(int64_t)j0 * k + e] = v;
+      nb2 += v * v;
     }
+    __syncthreads();
+    for (int jj = t; jj < nc; jj += 256) {  // C = R^-1 B
+      double *x = sP + jj * ld;
+      for (int i = k - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int q = i + 1; q < k; ++q) s -= sR[i + q * 64] * x[q];
+        x[i] = s / sR[i + i * 64];
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < nc * k; e += 256) a.C[(int64_t)j0 * k + e] = sP[(e % k) + (e / k) * ld];
+    __syncthreads();
   }
-  __syncthreads();
-  double nb2 = 0;
-  for (int e = t; e < k * n2; e += 256) nb2 += a.B[e] * a.B[e];
   nb2 = block_sum(nb2, red);
   if (t == 0) {
     st->nB2 = nb2;
@@ -136,20 +155,10 @@ __global__ __launch_bounds__(256) void k_formM(int n2, int k, const double *__re
 }
 
 // -----------------------------------------------------------------------------
-// Helpers for k_post (1024 threads).  All small matrices column-major.
-
-// out (r x c) with out(a, b) = sum_i X[a + i*ldx] * Y[b + i*ldy]: products
-// of two short-and-wide matrices over their long index; one thread per
-// entry, sequential (deterministic) sums.
-__device__ void gram_rows(int n, const double *X, int ldx, int r, const double *Y, int ldy, int c,
-                          double *out) {
-  for (int e = threadIdx.x; e < r * c; e += blockDim.x) {
-    const int a = e % r, b = e / r;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s = fma(X[a + (int64_t)i * ldx], Y[b + (int64_t)i * ldy], s);
-    out[e] = s;
-  }
-}
+// k_post (1024 threads).  The two long sums over n2 (CV = C V and S = C C^T)
+// stage column chunks of C and row chunks of V through LDS, each thread
+// owning fixed output entries; everything else is elementwise with short
+// inner products.  Small matrices are column-major in the global scratch.
 
 // In-place Cholesky (upper, K = R^T R) of a k x k matrix in LDS (ld 64).
 __device__ int small_chol64(double *K, int k, int *fail) {
@@ -178,26 +187,15 @@ __device__ int small_chol64(double *K, int k, int *fail) {
   return *fail;
 }
 
-// x <- x K^-1 for a row vector x (stride sx) with K = R^T R symmetric:
-// solve R^T y = x^T, then R z = y.
-__device__ void row_solve(double *x, int sx, const double *R, int k) {
-  for (int i = 0; i < k; ++i) {
-    double s = x[i * sx];
-    for (int q = 0; q < i; ++q) s -= R[q + i * 64] * x[q * sx];
-    x[i * sx] = s / R[i + i * 64];
-  }
-  for (int i = k - 1; i >= 0; --i) {
-    double s = x[i * sx];
-    for (int q = i + 1; q < k; ++q) s -= R[i + q * 64] * x[q * sx];
-    x[i * sx] = s / R[i + i * 64];
-  }
-}
-
+#define POST_CH 7680
 template <typename T>
 __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
   SmallState *st = a.st;
   if (st->done) return;
-  __shared__ double sK[64 * 64];
+  __shared__ double sC[POST_CH];     // C chunk, k x cw (ld k)
+  __shared__ double sV[4096];        // V chunk, cw x l (row-major)
+  __shared__ double sK[64 * 64];     // K = w^2 I + S, then its Cholesky factor
+  __shared__ double sKi[64 * 64];    // R^-1, then K^-1
   __shared__ int fail;
   const int k = a.k, n2 = a.n2, l = a.l, b = a.b, t = threadIdx.x;
   const double *V = a.Y;  // first l columns, ld n2
@@ -207,34 +205,69 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
   double *Tm = S + 64 * 64;              // k x k
   double *Zk = Tm + 64 * 64;             // n2 x k row-major, K^-1 folded in
   double *Zd = a.Zcur;                   // n2 x k row-major, plain Z
-  // CV = C V, S = C C^T (sums over n2, C is k x n2 col-major)
-  for (int e = t; e < k * l; e += 1024) {
-    const int c = e % k, q = e / k;
-    double s = 0.0;
-    for (int j = 0; j < n2; ++j) s = fma(a.C[c + (int64_t)j * k], V[j + (int64_t)q * n2], s);
-    CV[e] = s;
+
+  // ---- CV = C V and S = C C^T ----------------------------------------------
+  const int ncv = k * l, nss = k * k, nout = ncv + nss;
+  double acc[6];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) acc[u] = 0.0;
+  const int cw = max(1, min(POST_CH / max(k, 1), 4096 / max(l, 1)));
+  for (int j0 = 0; j0 < n2; j0 += cw) {
+    const int nc = min(cw, n2 - j0);
+    __syncthreads();
+    for (int e = t; e < nc * k; e += 1024) sC[e] = a.C[(int64_t)j0 * k + e];
+    for (int e = t; e < nc * l; e += 1024) {
+      const int jj = e / l, q = e - jj * l;
+      sV[e] = V[(j0 + jj) + (int64_t)q * n2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int o_ = t + 1024 * u;
+      if (o_ < nout) {
+        double s_ = acc[u];
+        if (o_ < ncv) {
+          const int c = o_ % k, q = o_ / k;
+          for (int jj = 0; jj < nc; ++jj) s_ = fma(sC[c + jj * k], sV[jj * l + q], s_);
+        } else {
+          const int e = o_ - ncv, c = e % k, d = e / k;
+          for (int jj = 0; jj < nc; ++jj) s_ = fma(sC[c + jj * k], sC[d + jj * k], s_);
+        }
+        acc[u] = s_;
+      }
+    }
   }
-  gram_rows(n2, a.C, k, k, a.C, k, k, S);
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int o_ = t + 1024 * u;
+    if (o_ < ncv) CV[o_] = acc[u];
+    else if (o_ < nout) S[o_ - ncv] = acc[u];
+  }
   __syncthreads();
+  // ---- T = (CV)(CV)^T, Z = C^T - V (CV)^T --------------------------------------
   for (int e = t; e < k * k; e += 1024) {
     const int c = e % k, d = e / k;
-    double s = 0.0;
-    for (int q = 0; q < l; ++q) s = fma(CV[c + q * k], CV[d + q * k], s);
-    Tm[e] = s;
+    double s_ = 0.0;
+    for (int q = 0; q < l; ++q) s_ = fma(CV[c + q * k], CV[d + q * k], s_);
+    Tm[e] = s_;
   }
-  for (int j = t; j < n2; j += 1024) {
-    for (int c = 0; c < k; ++c) {
-      double s = a.C[c + (int64_t)j * k];
-      for (int q = 0; q < l; ++q) s -= V[j + (int64_t)q * n2] * CV[c + q * k];
-      Zd[(int64_t)j * k + c] = s;
-      Zk[(int64_t)j * k + c] = s;
-    }
-    for (int q = 0; q < l; ++q) a.Vcur[(int64_t)j * l + q] = V[j + (int64_t)q * n2];
+  for (int e = t; e < n2 * k; e += 1024) {
+    const int j = e / k, c = e - j * k;
+    double s_ = a.C[(int64_t)j * k + c];
+    for (int q = 0; q < l; ++q) s_ -= V[j + (int64_t)q * n2] * CV[c + q * k];
+    Zd[e] = s_;
+    o.Zx[e] = (T)s_;
+  }
+  for (int e = t; e < n2 * l; e += 1024) {
+    const int j = e / l, q = e - j * l;
+    const double v = V[j + (int64_t)q * n2];
+    a.Vcur[e] = v;
+    o.Vr[e] = (T)v;
   }
   __syncthreads();
-  for (int e = t; e < n2 * k; e += 1024) o.Zx[e] = (T)Zd[e];
   const bool constw = a.wconst > 0;
   if (constw) {
+    // K^-1 = R^-1 R^-T with K = w^2 I + S = R^T R
     const double w2 = a.wconst * a.wconst;
     for (int e = t; e < k * k; e += 1024) {
       const int r = e % k, c = e / k;
@@ -242,12 +275,50 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
     }
     __syncthreads();
     small_chol64(sK, k, &fail);
-    // rows of S, of T and of Z, each times K^-1 (K = w^2 I + S)
-    for (int r = t; r < 2 * k + n2; r += 1024) {
-      if (r < k) row_solve(S + r, k, sK, k);
-      else if (r < 2 * k) row_solve(Tm + (r - k), k, sK, k);
-      else row_solve(Zk + (int64_t)(r - 2 * k) * k, 1, sK, k);
+    if (t < k) {
+      const int c = t;
+      for (int r = 0; r < k; ++r) sKi[r + c * 64] = 0.0;
+      for (int r = c; r >= 0; --r) {
+        double v = (r == c) ? 1.0 : 0.0;
+        for (int q = r + 1; q <= c; ++q) v -= sK[r + q * 64] * sKi[q + c * 64];
+        sKi[r + c * 64] = v / sK[r + r * 64];
+      }
     }
+    __syncthreads();
+    for (int e = t; e < k * k; e += 1024) {  // K^-1 into sK (symmetric)
+      const int r = e % k, c = e / k;
+      double v = 0.0;
+      for (int q = max(r, c); q < k; ++q) v = fma(sKi[r + q * 64], sKi[c + q * 64], v);
+      sK[r + c * 64] = v;
+    }
+    __syncthreads();
+    // S K^-1, T K^-1 (col-major k x k) and Z K^-1 (row-major n2 x k)
+    for (int e = t; e < k * k; e += 1024) {
+      const int r = e % k, c = e / k;
+      double vs = 0.0, vt = 0.0;
+      for (int q = 0; q < k; ++q) {
+        vs = fma(S[r + q * k], sK[q + c * 64], vs);
+        vt = fma(Tm[r + q * k], sK[q + c * 64], vt);
+      }
+      sKi[r + c * 64] = vs;      // S K^-1
+      sV[r + c * 64] = vt;       // T K^-1 (sV is free now; k*k <= 4096)
+    }
+    for (int e = t; e < n2 * k; e += 1024) {
+      const int j = e / k, c = e - j * k;
+      const double *zr = Zd + (int64_t)j * k;
+      double v = 0.0;
+      for (int q = 0; q < k; ++q) v = fma(zr[q], sK[q + c * 64], v);
+      Zk[e] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < k * k; e += 1024) {
+      const int r = e % k, c = e / k;
+      S[e] = sKi[r + c * 64];
+      Tm[e] = sV[r + c * 64];
+    }
+    __syncthreads();
+  } else {
+    for (int e = t; e < n2 * k; e += 1024) Zk[e] = Zd[e];
     __syncthreads();
   }
   // typed copies for the row pass (row-major, input index first)
@@ -255,9 +326,9 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
     const int r = e % k, c = e / k;  // S, Tm are col-major; store [r][c] row-major
     o.St[r * k + c] = (T)S[e];
     o.Tt[r * k + c] = (T)Tm[e];
+    o.Gt[r * k + c] = (T)(-S[e]);
   }
-  for (int e = t; e < n2 * k; e += 1024) o.Zt[e] = (T)Zk[e];
-  for (int e = t; e < n2 * l; e += 1024) o.Vr[e] = (T)a.Vcur[e];
+  for (int e = t; e < n2 * k; e += 1024) o.Gt[(int64_t)k * k + e] = (T)Zk[e];
   if (t == 0) {
     // F(X_p) = ||(A1 - X1) o W1||^2 + ||P^perp A2||^2 - sum of the top r-k
     // eigenvalues of M, with ||P^perp A2||^2 = ||A2||^2 - ||B||^2.

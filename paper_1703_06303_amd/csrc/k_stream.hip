@@ -79,15 +79,30 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
   const int64_t r0 = (int64_t)s * rows_per_split;
   const int64_t r1 = min(m, r0 + rows_per_split);
   double a00 = 0, a01 = 0, a10 = 0, a11 = 0;
-  for (int64_t rb = r0; rb < r1; rb += 32) {
-    for (int e = threadIdx.x; e < 1024; e += 256) {
+  // each thread moves 4 + 4 elements per 32-row chunk; the next chunk is
+  // loaded into registers while the current one is multiplied
+  double px[4], py[4];
+  auto fetch = [&](int64_t rb) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
       const int rr = e & 31, cc = e >> 5;
       const int64_t row = rb + rr;
       const bool rin = row < r1;
-      sX[cc][rr] = (rin && i0 + cc < k1) ? (double)X[row + (int64_t)(i0 + cc) * ldx] : 0.0;
-      sY[cc][rr] = (rin && j0 + cc < k2) ? (double)Y[row + (int64_t)(j0 + cc) * ldy] : 0.0;
+      px[u] = (rin && i0 + cc < k1) ? (double)X[row + (int64_t)(i0 + cc) * ldx] : 0.0;
+      py[u] = (rin && j0 + cc < k2) ? (double)Y[row + (int64_t)(j0 + cc) * ldy] : 0.0;
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int64_t rb = r0; rb < r1; rb += 32) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      sX[e >> 5][e & 31] = px[u];
+      sY[e >> 5][e & 31] = py[u];
     }
     __syncthreads();
+    if (rb + 32 < r1) fetch(rb + 32);
 #pragma unroll 8
     for (int rr = 0; rr < 32; ++rr) {
       const double x0 = sX[2 * tx][rr], x1 = sX[2 * tx + 1][rr];
@@ -150,8 +165,7 @@ __global__ __launch_bounds__(256) void k_f1(int64_t m, int k, const T *__restric
 }
 
 // ---------------------------------------------------------------------------
-// The X1 update of Algorithm 1 (steps 7-9), one row per lane, 64 rows per
-// workgroup (one wavefront).  Row i of X1_{p+1} is E_p(i,:) K_i^-1 with
+// The X1 update of Algorithm 1 (steps 7-9), one row per lane.  Row i of X1_{p+1} is E_p(i,:) K_i^-1 with
 // K_i = diag(W1(i,:)^2) + C C^T and E_p = A1 o W1 o W1 + (A2 - D_p) C_p^T.
 // Since D_p = (A2 - X1 C) V V^T,  (A2 - D_p) C^T = A2 Z + X1 T  with
 // Z = (I - V V^T) C^T and T = (CV)(CV)^T.  The kernel solves for the
@@ -162,103 +176,295 @@ __global__ __launch_bounds__(256) void k_f1(int64_t m, int k, const T *__restric
 // of x1' once the objective weighs it again by w^2.
 // When W1 is one constant w, K = w^2 I + S is shared: the small step
 // pre-multiplies Z, T and S by K^-1 and no per-row solve is needed.
-// Layouts (row-major, input index first): Zt[j*k + c], Tt[c'*k + c],
-// St[c'*k + c] (S, or S K^-1 when CONSTW).
-// Per-row Cholesky factors live in LDS, lane-interleaved (element e of lane l
-// at [e*nl + l]), for `nl` lanes at a time.
+//
+// Work split: a workgroup owns 64 rows (one per lane); its UPD_NW wavefronts
+// each take a contiguous slice of the n columns of A = [A1 A2] against
+// G = [-S; Z] (n x k, row-major, input index first) and wavefront 0 adds
+// x1 T; the slices are summed in a fixed order through LDS.  With a constant
+// weight wavefront 0 writes X1' = A1 + e directly; otherwise it stores the
+// right-hand sides e for k_rowsolve.
 // Partials per workgroup: (||(A1 - X1') o W1||^2, ||X1' - X1||^2).
+#define UPD_NW 4
 template <typename T, int KMAX, bool CONSTW>
-__global__ __launch_bounds__(64) void k_update(int64_t m, int k, int n2, const T *__restrict__ A,
-                                               int64_t lda, const T *__restrict__ W1, int64_t ldw,
-                                               T wc, const T *__restrict__ X1o,
-                                               T *__restrict__ X1n, const T *__restrict__ Zt,
-                                               const T *__restrict__ Tt, const T *__restrict__ St,
-                                               double *__restrict__ part, int nl,
-                                               const SmallState *__restrict__ st, int *flags) {
+__global__ __launch_bounds__(64 * UPD_NW) void k_update(
+    int64_t m, int k, int n, const T *__restrict__ A, int64_t lda, const T *__restrict__ W1,
+    int64_t ldw, T wc, const T *__restrict__ X1o, T *__restrict__ X1n, const T *__restrict__ Gt,
+    const T *__restrict__ Tt, const T *__restrict__ St, double *__restrict__ part,
+    T *__restrict__ Eb, int grows, const SmallState *__restrict__ st) {
   if (st->done) return;
+  // LDS: [staged rows of G (grows elements) | reused as the k x 64 slice sum]
+  //      [T k x k] [S k x k]
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *sm = reinterpret_cast<T *>(smem_raw);
-  const int lane = threadIdx.x;
+  T *sG = reinterpret_cast<T *>(smem_raw);
+  T *red = sG;
+  T *sT = sG + grows;
+  T *sS = sT + k * k;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const bool act = i < m;
   const int64_t ir = act ? i : (m - 1);
 
+  for (int e = threadIdx.x; e < k * k; e += 64 * UPD_NW) {
+    sT[e] = Tt[e];
+    sS[e] = St[e];
+  }
   T e[KMAX];
 #pragma unroll
   for (int c = 0; c < KMAX; ++c) e[c] = T(0);
+  __syncthreads();
+  if (w == 0) {
+    T xo[KMAX];
+#pragma unroll
+    for (int cp = 0; cp < KMAX; ++cp) xo[cp] = (cp < k) ? X1o[ir + (int64_t)cp * m] : T(0);
+#pragma unroll
+    for (int cp = 0; cp < KMAX; ++cp)
+      if (cp < k) {
+        const T *row = sT + cp * k;
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c)
+          if (c < k) e[c] = fma(xo[cp], row[c], e[c]);
+      }
+  }
+  // A = [A1 A2] times G = [-S; Z], rows of G staged through LDS in chunks.
+  const int rows_per = grows / k;
+  for (int c0 = 0; c0 < n; c0 += rows_per) {
+    const int c1 = min(n, c0 + rows_per);
+    __syncthreads();
+    for (int e2 = threadIdx.x; e2 < (c1 - c0) * k; e2 += 64 * UPD_NW)
+      sG[e2] = Gt[(int64_t)c0 * k + e2];
+    __syncthreads();
+    const int len = c1 - c0;
+    const int j0 = c0 + w * len / UPD_NW, j1 = c0 + (w + 1) * len / UPD_NW;
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = A[ir + (int64_t)(j + u) * lda];
+      const T *g = sG + (j - c0) * k;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c)
+          if (c < k) e[c] = fma(v[u], g[u * k + c], e[c]);
+      }
+    }
+    for (; j < j1; ++j) {
+      const T v0 = A[ir + (int64_t)j * lda];
+      const T *g = sG + (j - c0) * k;
+#pragma unroll
+      for (int c = 0; c < KMAX; ++c)
+        if (c < k) e[c] = fma(v0, g[c], e[c]);
+    }
+  }
+  // fixed-order sum of the wavefront slices into wavefront 0
+  for (int q = 1; q < UPD_NW; ++q) {
+    __syncthreads();
+    if (w == q) {
+#pragma unroll
+      for (int c = 0; c < KMAX; ++c)
+        if (c < k) red[c * 64 + lane] = e[c];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int c = 0; c < KMAX; ++c)
+        if (c < k) e[c] += red[c * 64 + lane];
+    }
+  }
+  if (w > 0) return;
 
-  for (int cp = 0; cp < k; ++cp) {
-    const T xv = X1o[ir + (int64_t)cp * m];
-    const T *row = Tt + cp * k;
+  if (!CONSTW) {
+    // right-hand sides for the per-row solve (k_rowsolve)
+    if (act) {
 #pragma unroll
-    for (int c = 0; c < KMAX; ++c)
-      if (c < k) e[c] = fma(xv, row[c], e[c]);
+      for (int c = 0; c < KMAX; ++c)
+        if (c < k) Eb[i + (int64_t)c * m] = e[c];
+    }
+    return;
   }
-  for (int cp = 0; cp < k; ++cp) {
-    const T av = A[ir + (int64_t)cp * lda];
-    const T *row = St + cp * k;
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c)
-      if (c < k) e[c] = fma(-av, row[c], e[c]);
-  }
-  const T *A2 = A + (int64_t)k * lda;
-  int j = 0;
-  for (; j + 4 <= n2; j += 4) {
-    const T v0 = A2[ir + (int64_t)j * lda];
-    const T v1 = A2[ir + (int64_t)(j + 1) * lda];
-    const T v2 = A2[ir + (int64_t)(j + 2) * lda];
-    const T v3 = A2[ir + (int64_t)(j + 3) * lda];
-    const T *z0 = Zt + (int64_t)j * k;
+  double f1 = 0.0, dx = 0.0;
+  if (act) {
 #pragma unroll
     for (int c = 0; c < KMAX; ++c)
       if (c < k) {
-        T t = e[c];
-        t = fma(v0, z0[c], t);
-        t = fma(v1, z0[k + c], t);
-        t = fma(v2, z0[2 * k + c], t);
-        t = fma(v3, z0[3 * k + c], t);
-        e[c] = t;
+        const T x = A[i + (int64_t)c * lda] + e[c];
+        X1n[i + (int64_t)c * m] = x;
+        const double wd = CONSTW ? (double)wc : (double)W1[i + (int64_t)c * ldw];
+        const double d = (double)A[i + (int64_t)c * lda] - (double)x;
+        f1 += d * d * wd * wd;
+        const double dd = (double)x - (double)X1o[i + (int64_t)c * m];
+        dx += dd * dd;
       }
   }
-  for (; j < n2; ++j) {
-    const T v0 = A2[ir + (int64_t)j * lda];
-    const T *z0 = Zt + (int64_t)j * k;
+  f1 = wave_sum(f1);
+  dx = wave_sum(dx);
+  if (lane == 0) {
+    part[2 * blockIdx.x] = f1;
+    part[2 * blockIdx.x + 1] = dx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-row solve of the X1 update: x1_i' = a1_i + e_i (diag(w_i^2) + S)^-1,
+// one row per lane.  Register version: the lower Cholesky factor of the
+// row's k x k matrix lives in registers (all indices compile-time after
+// unrolling; k <= KMAX), S is read through uniform (scalar) loads.
+template <typename T, int KMAX>
+__global__ __launch_bounds__(64) void k_rowsolve_reg(
+    int64_t m, int k, const T *__restrict__ A, int64_t lda, const T *__restrict__ W1, int64_t ldw,
+    const T *__restrict__ X1o, T *__restrict__ X1n, const T *__restrict__ Eb,
+    const T *__restrict__ St, double *__restrict__ part, const SmallState *__restrict__ st,
+    int *flags) {
+  if (st->done) return;
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool act = i < m;
+  const int64_t ir = act ? i : (m - 1);
+  T e[KMAX], q[KMAX], L[KMAX * (KMAX + 1) / 2];
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) {
+    e[c] = (c < k) ? Eb[ir + (int64_t)c * m] : T(0);
+    const T wv = (c < k) ? W1[ir + (int64_t)c * ldw] : T(1);
+    q[c] = wv * wv;
+  }
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < k) {
+      T sv = q[j] + St[j * k + j];
+#pragma unroll
+      for (int p = 0; p < j; ++p) sv -= L[j * (j + 1) / 2 + p] * L[j * (j + 1) / 2 + p];
+      if (!(sv > T(0))) {
+        bad = 1;
+        sv = T(1);
+      }
+      const T ljj = sqrt(sv);
+      L[j * (j + 1) / 2 + j] = ljj;
+      const T inv = T(1) / ljj;
+#pragma unroll
+      for (int r = j + 1; r < KMAX; ++r) {
+        if (r < k) {
+          T t = St[r * k + j];
+#pragma unroll
+          for (int p = 0; p < j; ++p) t -= L[r * (r + 1) / 2 + p] * L[j * (j + 1) / 2 + p];
+          L[r * (r + 1) / 2 + j] = t * inv;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < KMAX; ++r)
+    if (r < k) {
+      T t = e[r];
+#pragma unroll
+      for (int p = 0; p < r; ++p) t -= L[r * (r + 1) / 2 + p] * e[p];
+      e[r] = t / L[r * (r + 1) / 2 + r];
+    }
+#pragma unroll
+  for (int r = KMAX - 1; r >= 0; --r)
+    if (r < k) {
+      T t = e[r];
+#pragma unroll
+      for (int p = r + 1; p < KMAX; ++p)
+        if (p < k) t -= L[p * (p + 1) / 2 + r] * e[p];
+      e[r] = t / L[r * (r + 1) / 2 + r];
+    }
+  double f1 = 0.0, dx = 0.0;
+  if (act) {
 #pragma unroll
     for (int c = 0; c < KMAX; ++c)
-      if (c < k) e[c] = fma(v0, z0[c], e[c]);
+      if (c < k) {
+        const T a1 = A[i + (int64_t)c * lda];
+        const T x = a1 + e[c];
+        X1n[i + (int64_t)c * m] = x;
+        const double d = (double)a1 - (double)x;
+        f1 += d * d * (double)q[c];
+        const double dd = (double)x - (double)X1o[i + (int64_t)c * m];
+        dx += dd * dd;
+      }
   }
+  f1 = wave_sum(f1);
+  dx = wave_sum(dx);
+  if (lane == 0) {
+    part[2 * blockIdx.x] = f1;
+    part[2 * blockIdx.x + 1] = dx;
+  }
+  if (bad) atomicOr(flags, DEV_ROWSOLVE);
+}
 
+// LDS version for any k <= WLRA_KMAX: the factor of each lane's matrix is
+// lane-interleaved in LDS (element e of lane l at [e*nl + l]), `nl` lanes at
+// a time.
+template <typename T, int KMAX>
+__global__ __launch_bounds__(64) void k_rowsolve_lds(
+    int64_t m, int k, const T *__restrict__ A, int64_t lda, const T *__restrict__ W1, int64_t ldw,
+    const T *__restrict__ X1o, T *__restrict__ X1n, const T *__restrict__ Eb,
+    const T *__restrict__ St, double *__restrict__ part, int nl,
+    const SmallState *__restrict__ st, int *flags) {
+  if (st->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sS = reinterpret_cast<T *>(smem_raw);  // k x k
+  T *sm = sS + k * k;
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool act = i < m;
+  const int64_t ir = act ? i : (m - 1);
+  for (int e2 = lane; e2 < k * k; e2 += 64) sS[e2] = St[e2];
+  T e[KMAX];
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) e[c] = (c < k) ? Eb[ir + (int64_t)c * m] : T(0);
+  __syncthreads();
   int bad = 0;
-  if (!CONSTW) {
+  {
     const int tri = k * (k + 1) / 2;
     for (int round = 0; round < 64; round += nl) {
       const int sl = lane - round;
       if (sl >= 0 && sl < nl) {
         T *L = sm + sl;
         T *E = sm + (int64_t)tri * nl + sl;
+        T *Q = E + (int64_t)k * nl;  // w^2 of this row
 #pragma unroll
         for (int c = 0; c < KMAX; ++c)
-          if (c < k) E[c * nl] = e[c];
+          if (c < k) {
+            E[c * nl] = e[c];
+            const T wv = W1[ir + (int64_t)c * ldw];
+            Q[c * nl] = wv * wv;
+          }
         for (int jj = 0; jj < k; ++jj) {
           const int bj = jj * (jj + 1) / 2;
-          const T w = W1[ir + (int64_t)jj * ldw];
-          T s = fma(w, w, St[jj * k + jj]);
-          for (int p = 0; p < jj; ++p) {
-            const T l = L[(bj + p) * nl];
-            s -= l * l;
+          T sv = Q[jj * nl] + sS[jj * k + jj];
+          {
+            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int p = 0;
+            for (; p + 4 <= jj; p += 4) {
+              const T l0 = L[(bj + p) * nl], l1 = L[(bj + p + 1) * nl];
+              const T l2 = L[(bj + p + 2) * nl], l3 = L[(bj + p + 3) * nl];
+              a0 = fma(l0, l0, a0); a1 = fma(l1, l1, a1);
+              a2 = fma(l2, l2, a2); a3 = fma(l3, l3, a3);
+            }
+            for (; p < jj; ++p) { const T l0 = L[(bj + p) * nl]; a0 = fma(l0, l0, a0); }
+            sv -= (a0 + a1) + (a2 + a3);
           }
-          if (!(s > T(0))) {
+          if (!(sv > T(0))) {
             bad = 1;
-            s = T(1);
+            sv = T(1);
           }
-          const T ljj = sqrt(s);
+          const T ljj = sqrt(sv);
           L[(bj + jj) * nl] = ljj;
           const T inv = T(1) / ljj;
           for (int ii = jj + 1; ii < k; ++ii) {
             const int bi = ii * (ii + 1) / 2;
-            T t = St[ii * k + jj];
-            for (int p = 0; p < jj; ++p) t -= L[(bi + p) * nl] * L[(bj + p) * nl];
-            L[(bi + jj) * nl] = t * inv;
+            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int p = 0;
+            for (; p + 4 <= jj; p += 4) {
+              a0 = fma(L[(bi + p) * nl], L[(bj + p) * nl], a0);
+              a1 = fma(L[(bi + p + 1) * nl], L[(bj + p + 1) * nl], a1);
+              a2 = fma(L[(bi + p + 2) * nl], L[(bj + p + 2) * nl], a2);
+              a3 = fma(L[(bi + p + 3) * nl], L[(bj + p + 3) * nl], a3);
+            }
+            for (; p < jj; ++p) a0 = fma(L[(bi + p) * nl], L[(bj + p) * nl], a0);
+            L[(bi + jj) * nl] = (sS[ii * k + jj] - ((a0 + a1) + (a2 + a3))) * inv;
           }
         }
         for (int ii = 0; ii < k; ++ii) {
@@ -284,11 +490,12 @@ __global__ __launch_bounds__(64) void k_update(int64_t m, int k, int n2, const T
 #pragma unroll
     for (int c = 0; c < KMAX; ++c)
       if (c < k) {
-        const T x = A[i + (int64_t)c * lda] + e[c];
+        const T a1 = A[i + (int64_t)c * lda];
+        const T x = a1 + e[c];
         X1n[i + (int64_t)c * m] = x;
-        const double w = CONSTW ? (double)wc : (double)W1[i + (int64_t)c * ldw];
-        const double d = (double)A[i + (int64_t)c * lda] - (double)x;
-        f1 += d * d * w * w;
+        const double wd = (double)W1[i + (int64_t)c * ldw];
+        const double d = (double)a1 - (double)x;
+        f1 += d * d * wd * wd;
         const double dd = (double)x - (double)X1o[i + (int64_t)c * m];
         dx += dd * dd;
       }
@@ -347,56 +554,132 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
 // Error_p of Section 4.1, unweighted block: ||X2_p - X2_{p-1}||_F^2 summed
 // row by row in double, with x2_i = a2_i V V^T + x1_i Z^T for both sweeps.
 // Each row difference is formed directly, so no large Gram terms cancel and
-// changes far below sqrt(eps) ||X|| stay resolved.  One partial per
-// workgroup.  Zp/Zq: n2 x k, Vp/Vq: n2 x l, all row-major double.
+// changes far below sqrt(eps) ||X|| stay resolved.  Zp/Zq: n2 x k, Vp/Vq:
+// n2 x l, all row-major double.  A workgroup owns 64 rows; its CHG_NW
+// wavefronts first split the n2 columns to form u = a2 [V_p V_q] (summed
+// through LDS), then split them again for the row differences.  One partial
+// per workgroup.
+#define CHG_NW 4
+#define CHG_STAGE 12288  // doubles of [V_p V_q Z_p Z_q] rows staged per chunk
 template <typename T, int KMAX, int LMAX>
-__global__ __launch_bounds__(64) void k_change(int64_t m, int k, int n2, int l,
-                                               const T *__restrict__ A, int64_t lda,
-                                               const T *__restrict__ X1p, const T *__restrict__ X1q,
-                                               const double *__restrict__ Zp,
-                                               const double *__restrict__ Zq,
-                                               const double *__restrict__ Vp,
-                                               const double *__restrict__ Vq,
-                                               double *__restrict__ part,
-                                               const SmallState *__restrict__ st) {
+__global__ __launch_bounds__(64 * CHG_NW) void k_change(
+    int64_t m, int k, int n2, int l, const T *__restrict__ A, int64_t lda,
+    const T *__restrict__ X1p, const T *__restrict__ X1q, const double *__restrict__ Zp,
+    const double *__restrict__ Zq, const double *__restrict__ Vp, const double *__restrict__ Vq,
+    double *__restrict__ part, const SmallState *__restrict__ st) {
   if (st->done) return;
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  __shared__ double sR[CHG_STAGE];
+  __shared__ double su[2 * LMAX * 64];
+  __shared__ double sacc[CHG_NW];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const bool act = i < m;
   const int64_t ir = act ? i : (m - 1);
   const T *A2 = A + (int64_t)k * lda;
-  double up[LMAX], uq[LMAX], xp[KMAX], xq[KMAX];
+  const int rw = 2 * l + 2 * k;                 // staged row: [vp | vq | zp | zq]
+  const int crow = max(1, CHG_STAGE / max(rw, 1));
+  auto stage = [&](int c0, int c1) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < (c1 - c0) * rw; e += 64 * CHG_NW) {
+      const int r = e / rw, q = e - r * rw, j = c0 + r;
+      double v;
+      if (q < l) v = Vp[(int64_t)j * l + q];
+      else if (q < 2 * l) v = Vq[(int64_t)j * l + (q - l)];
+      else if (q < 2 * l + k) v = Zp[(int64_t)j * k + (q - 2 * l)];
+      else v = Zq[(int64_t)j * k + (q - 2 * l - k)];
+      sR[e] = v;
+    }
+    __syncthreads();
+  };
+  // phase 1: u = a2 [V_p V_q], slices of the columns per wavefront
+  double up[LMAX], uq[LMAX];
 #pragma unroll
   for (int q = 0; q < LMAX; ++q) up[q] = uq[q] = 0.0;
-  for (int j = 0; j < n2; ++j) {
-    const double v = (double)A2[ir + (int64_t)j * lda];
-    const double *vp = Vp + (int64_t)j * l, *vq = Vq + (int64_t)j * l;
+  for (int c0 = 0; c0 < n2; c0 += crow) {
+    const int c1 = min(n2, c0 + crow), len = c1 - c0;
+    stage(c0, c1);
+    const int j0 = c0 + w * len / CHG_NW, j1 = c0 + (w + 1) * len / CHG_NW;
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+      double v[8];
 #pragma unroll
-    for (int q = 0; q < LMAX; ++q)
-      if (q < l) {
-        up[q] = fma(v, vp[q], up[q]);
-        uq[q] = fma(v, vq[q], uq[q]);
+      for (int u = 0; u < 8; ++u) v[u] = (double)A2[ir + (int64_t)(j + u) * lda];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double *rr = sR + (j + u - c0) * rw;
+#pragma unroll
+        for (int q = 0; q < LMAX; ++q)
+          if (q < l) {
+            up[q] = fma(v[u], rr[q], up[q]);
+            uq[q] = fma(v[u], rr[l + q], uq[q]);
+          }
       }
+    }
+    for (; j < j1; ++j) {
+      const double v = (double)A2[ir + (int64_t)j * lda];
+      const double *rr = sR + (j - c0) * rw;
+#pragma unroll
+      for (int q = 0; q < LMAX; ++q)
+        if (q < l) {
+          up[q] = fma(v, rr[q], up[q]);
+          uq[q] = fma(v, rr[l + q], uq[q]);
+        }
+    }
   }
+  // fixed-order sum of the slices, then every wavefront takes the total
+  for (int ww = 0; ww < CHG_NW; ++ww) {
+    __syncthreads();
+    if (w == ww) {
+#pragma unroll
+      for (int q = 0; q < LMAX; ++q)
+        if (q < l) {
+          const double a0 = (ww == 0) ? 0.0 : su[q * 64 + lane];
+          const double b0 = (ww == 0) ? 0.0 : su[(LMAX + q) * 64 + lane];
+          su[q * 64 + lane] = a0 + up[q];
+          su[(LMAX + q) * 64 + lane] = b0 + uq[q];
+        }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < LMAX; ++q)
+    if (q < l) {
+      up[q] = su[q * 64 + lane];
+      uq[q] = su[(LMAX + q) * 64 + lane];
+    }
+  double xp[KMAX], xq[KMAX];
 #pragma unroll
   for (int c = 0; c < KMAX; ++c) {
     xp[c] = (c < k) ? (double)X1p[ir + (int64_t)c * m] : 0.0;
     xq[c] = (c < k) ? (double)X1q[ir + (int64_t)c * m] : 0.0;
   }
+  // phase 2: row differences d_ij for the wavefront's columns
   double acc = 0.0;
-  for (int j = 0; j < n2; ++j) {
-    const double *vp = Vp + (int64_t)j * l, *vq = Vq + (int64_t)j * l;
-    const double *zp = Zp + (int64_t)j * k, *zq = Zq + (int64_t)j * k;
-    double d = 0.0;
+  for (int c0 = 0; c0 < n2; c0 += crow) {
+    const int c1 = min(n2, c0 + crow), len = c1 - c0;
+    if (!(c0 == 0 && c1 == n2)) stage(c0, c1);  // one chunk: still staged
+    const int j0 = c0 + w * len / CHG_NW, j1 = c0 + (w + 1) * len / CHG_NW;
+    for (int j = j0; j < j1; ++j) {
+      const double *rr = sR + (j - c0) * rw;
+      double d = 0.0;
 #pragma unroll
-    for (int q = 0; q < LMAX; ++q)
-      if (q < l) d = fma(up[q], vp[q], fma(-uq[q], vq[q], d));
+      for (int q = 0; q < LMAX; ++q)
+        if (q < l) d = fma(up[q], rr[q], fma(-uq[q], rr[l + q], d));
 #pragma unroll
-    for (int c = 0; c < KMAX; ++c)
-      if (c < k) d = fma(xp[c], zp[c], fma(-xq[c], zq[c], d));
-    acc = fma(d, d, acc);
+      for (int c = 0; c < KMAX; ++c)
+        if (c < k) d = fma(xp[c], rr[2 * l + c], fma(-xq[c], rr[2 * l + k + c], d));
+      acc = fma(d, d, acc);
+    }
   }
   acc = wave_sum(act ? acc : 0.0);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (lane == 0) sacc[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int ww = 0; ww < CHG_NW; ++ww) t += sacc[ww];
+    part[blockIdx.x] = t;
+  }
 }
 
 // Copy an m x k matrix (ld m) into a caller buffer with leading dimension ld.
@@ -447,23 +730,68 @@ void launch_f1(hipStream_t s, int64_t m, int k, const T *A, int64_t lda, const T
   hipLaunchKernelGGL(k_f1<T>, dim3(nwg), dim3(256), 0, s, m, k, A, lda, W1, ldw, wc, X1, part);
 }
 
+// LDS plan of k_update: staged G elements (grows) and dynamic LDS bytes;
+// and the lanes per round of k_rowsolve_lds.
+template <typename T>
+UpdatePlan update_plan(int k, bool constw) {
+  UpdatePlan pl;
+  const size_t cap = 163840 - 1024;
+  const size_t fixed = (size_t)2 * k * k * sizeof(T);
+  size_t g = std::min<size_t>(8192, (cap - fixed) / sizeof(T));
+  g = std::max<size_t>(g, (size_t)k * 64);
+  g = g / k * k;
+  pl.grows = (int)g;
+  pl.shm = (g + 2 * (size_t)k * k) * sizeof(T);
+  const size_t per = (size_t)(k * (k + 1) / 2 + 2 * k) * sizeof(T);
+  pl.nl = 64;
+  while (pl.nl > 1 && per * pl.nl + (size_t)k * k * sizeof(T) > 65536) pl.nl >>= 1;
+  (void)constw;
+  return pl;
+}
+
 template <typename T, int KMAX>
 static void launch_update_k(hipStream_t s, const UpdateArgs<T> &a) {
   const unsigned grid = (unsigned)((a.m + 63) / 64);
+  const UpdatePlan pl = update_plan<T>(a.k, a.constw);
   if (a.constw) {
-    hipLaunchKernelGGL((k_update<T, KMAX, true>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.n2, a.A,
-                       a.lda, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Zt, a.Tt, a.St, a.part, 64, a.st,
-                       a.flags);
+    if (pl.shm > 65536)
+      (void)hipFuncSetAttribute((const void *)k_update<T, KMAX, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.shm);
+    hipLaunchKernelGGL((k_update<T, KMAX, true>), dim3(grid), dim3(64 * UPD_NW), pl.shm, s, a.m,
+                       a.k, a.n, a.A, a.lda, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Gt, a.Tt, a.St,
+                       a.part, a.Eb, pl.grows, a.st);
+    return;
+  }
+  if (pl.shm > 65536)
+    (void)hipFuncSetAttribute((const void *)k_update<T, KMAX, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.shm);
+  hipLaunchKernelGGL((k_update<T, KMAX, false>), dim3(grid), dim3(64 * UPD_NW), pl.shm, s, a.m,
+                     a.k, a.n, a.A, a.lda, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Gt, a.Tt, a.St,
+                     a.part, a.Eb, pl.grows, a.st);
+  if (sizeof(T) == 4 && a.k <= 24) {
+    if (a.k <= 8)
+      hipLaunchKernelGGL((k_rowsolve_reg<T, 8>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
+                         a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
+    else if (a.k <= 16)
+      hipLaunchKernelGGL((k_rowsolve_reg<T, 16>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
+                         a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
+    else
+      hipLaunchKernelGGL((k_rowsolve_reg<T, 24>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
+                         a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
   } else {
-    const size_t shm = (size_t)(a.k * (a.k + 1) / 2 + a.k) * a.nl * sizeof(T);
-    hipLaunchKernelGGL((k_update<T, KMAX, false>), dim3(grid), dim3(64), shm, s, a.m, a.k, a.n2,
-                       a.A, a.lda, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Zt, a.Tt, a.St, a.part, a.nl,
-                       a.st, a.flags);
+    const size_t shm = (size_t)a.k * a.k * sizeof(T) +
+                       (size_t)(a.k * (a.k + 1) / 2 + 2 * a.k) * pl.nl * sizeof(T);
+    hipLaunchKernelGGL((k_rowsolve_lds<T, KMAX>), dim3(grid), dim3(64), shm, s, a.m, a.k, a.A,
+                       a.lda, a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, pl.nl, a.st, a.flags);
   }
 }
 
 template <typename T>
 void launch_update(hipStream_t s, const UpdateArgs<T> &a) {
+  // refuse to launch with a missing operand (the kernels have no null checks)
+  if (!a.A || !a.X1o || !a.X1n || !a.Gt || !a.Tt || !a.St || !a.part || !a.st || !a.flags ||
+      (!a.constw && (!a.Eb || !a.W1)))
+    return;
   if (a.k <= 8) launch_update_k<T, 8>(s, a);
   else if (a.k <= 16) launch_update_k<T, 16>(s, a);
   else if (a.k <= 32) launch_update_k<T, 32>(s, a);
@@ -498,11 +826,11 @@ static void launch_change_k(hipStream_t s, int64_t m, int k, int n2, int l, cons
                             const SmallState *st) {
   const unsigned grid = (unsigned)((m + 63) / 64);
   if (l <= 8)
-    hipLaunchKernelGGL((k_change<T, KMAX, 8>), dim3(grid), dim3(64), 0, s, m, k, n2, l, A, lda,
-                       X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+    hipLaunchKernelGGL((k_change<T, KMAX, 8>), dim3(grid), dim3(64 * CHG_NW), 0, s, m, k, n2, l,
+                       A, lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
   else
-    hipLaunchKernelGGL((k_change<T, KMAX, WLRA_BMAX>), dim3(grid), dim3(64), 0, s, m, k, n2, l, A,
-                       lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+    hipLaunchKernelGGL((k_change<T, KMAX, WLRA_BMAX>), dim3(grid), dim3(64 * CHG_NW), 0, s, m, k,
+                       n2, l, A, lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
 }
 
 template <typename T>
@@ -533,6 +861,7 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
   template void launch_f1<T>(hipStream_t, int64_t, int, const T *, int64_t, const T *, int64_t,   \
                              double, const T *, double *, int);                                   \
   template void launch_update<T>(hipStream_t, const UpdateArgs<T> &);                             \
+  template UpdatePlan update_plan<T>(int, bool);                                                 \
   template void launch_x2<T>(hipStream_t, int64_t, int, int, int, const T *, int64_t, const T *,  \
                              const T *, const T *, T *, int64_t);                                 \
   template void launch_copy_out<T>(hipStream_t, int64_t, int64_t, const T *, T *, int64_t);     \

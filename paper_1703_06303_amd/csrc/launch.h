@@ -11,7 +11,7 @@
 template <typename T>
 struct UpdateArgs {
   int64_t m;
-  int k, n2;
+  int k, n;
   const T *A;
   int64_t lda;
   const T *W1;
@@ -20,9 +20,9 @@ struct UpdateArgs {
   bool constw;
   const T *X1o;
   T *X1n;
-  const T *Zt, *Tt, *St;
+  const T *Gt, *Tt, *St;   // Gt = [-S; Z] (n x k), Tt = T, St = S (row-major)
+  T *Eb;                   // m x k right-hand sides of the per-row solve
   double *part;
-  int nl;
   const SmallState *st;
   int *flags;
 };
@@ -42,6 +42,13 @@ void launch_f1(hipStream_t s, int64_t m, int k, const T *A, int64_t lda, const T
                double wc, const T *X1, double *part, int nwg);
 template <typename T>
 void launch_update(hipStream_t s, const UpdateArgs<T> &a);
+struct UpdatePlan {
+  int nl;      // Cholesky lanes per round
+  int grows;   // G elements staged per chunk
+  size_t shm;  // dynamic LDS bytes
+};
+template <typename T>
+UpdatePlan update_plan(int k, bool constw);
 template <typename T>
 void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
                const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2);
@@ -68,7 +75,8 @@ struct SmallArgs {
 
 template <typename T>
 struct SmallOut {
-  T *Zt, *Tt, *St, *Vr;  // row-pass operands (K^-1 folded in when W1 is constant)
+  T *Gt, *Tt, *St, *Vr;  // row-pass operands (K^-1 folded in when W1 is constant):
+                         // Gt = [-S; Z] is n x k row-major
   T *Zx;                 // plain Z = (I - V V^T) C^T for the dense X2 output
 };
 

@@ -18,7 +18,6 @@
 #define EIG_GUARD 3
 #define EIG_DEG 12
 #define EIG_MAXIT 60
-#define UPD_LDS_BUDGET 65536
 
 enum KernelKind {
   KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_XTX, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
@@ -117,7 +116,7 @@ struct Ptrs {
   double *part, *GA, *P, *G1, *R, *B, *C, *M;
   double *Y, *Wb, *F0, *F1, *F2, *theta, *scratch, *upd_part, *chg_part;
   double *Zd[2], *Vd[2];
-  void *Zt, *Tt, *St, *Vr, *Zx;
+  void *Gt, *Tt, *St, *Vr, *Zx, *Eb;
   SmallState *st;
   int *flags;
 };
@@ -180,7 +179,8 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.Zd[1], (size_t)(n2 * kk) * d},
       {(void **)&p.Vd[0], (size_t)(n2 * ll) * d},
       {(void **)&p.Vd[1], (size_t)(n2 * ll) * d},
-      {&p.Zt, (size_t)(n2 * kk) * z.elt},
+      {&p.Gt, (size_t)((n2 + kk) * kk) * z.elt},
+      {&p.Eb, (size_t)(m * kk) * z.elt},
       {&p.Tt, (size_t)(kk * kk) * z.elt},
       {&p.St, (size_t)(kk * kk) * z.elt},
       {&p.Vr, (size_t)(n2 * ll) * z.elt},
@@ -306,7 +306,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   sa.scratch = P.scratch; sa.st = P.st; sa.flags = P.flags; sa.wconst = constw ? wc : 0.0;
   sa.eig_maxit = EIG_MAXIT; sa.eig_deg = EIG_DEG;
   sa.upd_part = P.upd_part; sa.chg_part = P.chg_part; sa.nchg = z.nwg_upd;
-  SmallOut<T> so{static_cast<T *>(P.Zt), static_cast<T *>(P.Tt), static_cast<T *>(P.St),
+  SmallOut<T> so{static_cast<T *>(P.Gt), static_cast<T *>(P.Tt), static_cast<T *>(P.St),
                  static_cast<T *>(P.Vr), static_cast<T *>(P.Zx)};
 
   int cur = 0;
@@ -339,16 +339,11 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     // X1_{p+1} from X1_p (Algorithm 1 steps 7-9), then the sums for p+1.
     T *X1n = static_cast<T *>(P.X1[cur ^ 1]);
     UpdateArgs<T> ua{};
-    ua.m = m; ua.k = (int)k; ua.n2 = (int)n2; ua.A = A; ua.lda = pr->lda; ua.W1 = W1;
+    ua.m = m; ua.k = (int)k; ua.n = (int)pr->n; ua.A = A; ua.lda = pr->lda; ua.W1 = W1;
     ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1c; ua.X1n = X1n;
-    ua.Zt = so.Zt; ua.Tt = so.Tt; ua.St = so.St; ua.part = P.upd_part; ua.st = P.st;
+    ua.Gt = so.Gt; ua.Tt = so.Tt; ua.St = so.St; ua.part = P.upd_part; ua.st = P.st;
+    ua.Eb = static_cast<T *>(P.Eb);
     ua.flags = P.flags;
-    {
-      const size_t per = (size_t)(k * (k + 1) / 2 + k) * sizeof(T);
-      int nl = 64;
-      while (nl > 1 && per * nl > UPD_LDS_BUDGET) nl >>= 1;
-      ua.nl = nl;
-    }
     PROF(h, KK_UPDATE, launch_update<T>(s, ua));
     PROF(h, KK_XTA,
          (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p,
