@@ -19,6 +19,11 @@ Functions and the passage each follows:
   closed_form_column_weights  a derived special case of (5): W1(i, j) = w_j
   swlr                      Algorithm 1 (Section 3), with the X1 row update
                             below eq. (9) and the stopping rule of Section 4.1
+  round_bf16                BF16 rounding (IEEE binary32 truncated to 8 exponent
+                            and 7 fraction bits, round to nearest even)
+  swlr_mixed                the reduced-precision schedule: Algorithm 1 on
+                            [A1, bf16(A2)] to a looser threshold, then one
+                            sweep of Algorithm 1 on A itself
 
 Readings taken where the paper is loose (all listed in the design notes):
   * X_p = [X1_p, X1_p C_p + D_p] uses the C_p, D_p computed from X1_p; on
@@ -218,6 +223,47 @@ def swlr(A, W1, k, r, tol=1e-7, max_sweeps=200, X1_0=None, row_chunk=4096):
         X_prev = X
         X1 = X1_new
         p += 1
+
+
+def round_bf16(x):
+    """Nearest BF16 value of each float32 entry (ties to the even BF16
+    neighbour), returned as float64.  A BF16 number is the upper 16 bits of
+    an IEEE binary32 number: sign, 8 exponent bits, 7 fraction bits."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    keep = u >> 16
+    rest = u & 0xFFFF
+    up = (rest > 0x8000) | ((rest == 0x8000) & (keep & 1 == 1))
+    keep = keep + up.astype(np.uint64)
+    return (keep << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# Threshold of the reduced-precision phase (a reading of this project: the
+# paper has no mixed-precision schedule).
+MIXED_TOL = 1e-4
+
+
+def swlr_mixed(A, W1, k, r, tol=1e-7, max_sweeps=200, X1_0=None, mixed_tol=MIXED_TOL):
+    """Reduced-precision schedule, in float64 arithmetic.
+
+    Phase 1: Algorithm 1 on the perturbed matrix [A1, bf16(A2)] (A2 rounded
+    to BF16 from float32), stopping at max(tol, mixed_tol) (tol > 0) or
+    after max_sweeps - 1 X1 updates.  Phase 2: Algorithm 1 on A itself from
+    the X1 reached, for one more X1 update when max_sweeps allows it.  The
+    result is phase 2's X_p with sweeps = all X1 updates and the status of
+    phase 1."""
+    A = np.asarray(A, dtype=np.float64)
+    if k == 0:
+        return swlr(A, W1, k, r, tol=tol, max_sweeps=max_sweeps, X1_0=X1_0)
+    Ab = A.copy()
+    Ab[:, k:] = round_bf16(A[:, k:])
+    tol1 = max(tol, mixed_tol) if tol > 0 else tol
+    first = swlr(Ab, W1, k, r, tol=tol1, max_sweeps=max(max_sweeps - 1, 0), X1_0=X1_0)
+    extra = min(first.sweeps + 1, max_sweeps) - first.sweeps
+    second = swlr(A, W1, k, r, tol=0.0, max_sweeps=extra, X1_0=first.X1)
+    second.sweeps = first.sweeps + extra
+    second.status = first.status
+    second.F = first.F + second.F
+    return second
 
 
 def stationarity_residual(A, W1, k, X1, C, D):

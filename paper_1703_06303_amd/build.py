@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libwlra.so")
 SOURCES = ["wlra_api.hip", "k_stream.hip", "k_small.hip", "k_eig.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result"]
+         "-Wno-unused-result", "-Wno-unused-value"]
 
 
 def build(verbose=False):

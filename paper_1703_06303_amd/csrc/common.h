@@ -15,6 +15,22 @@
 #define DEV_EIG_MAXIT 8
 #define DEV_ROWSOLVE 16
 
+// BF16 storage of A2 in mixed precision: the bit pattern of the upper half of
+// an IEEE float.  Widening to float is exact; narrowing rounds to nearest
+// even (inputs are checked finite before it matters).
+struct bf16s {
+  uint16_t u;
+};
+
+__device__ __forceinline__ float to_f(float x) { return x; }
+__device__ __forceinline__ double to_f(double x) { return x; }
+__device__ __forceinline__ float to_f(bf16s x) { return __uint_as_float((uint32_t)x.u << 16); }
+__device__ __forceinline__ bf16s bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return bf16s{(uint16_t)(u >> 16)};
+}
+
 // Per-solve device state shared by the small-step kernels (all double).
 // Index p below is the sweep of Algorithm 1: X_p = [X1_p, X1_p C_p + D_p].
 struct SmallState {

@@ -4,21 +4,39 @@
 // dimension, so a wavefront whose 64 lanes take 64 consecutive rows reads
 // 64 consecutive elements of each column: every global load below is
 // coalesced.  Sums over rows accumulate in double in every precision.
+#include <type_traits>
+
 #include "common.h"
+
+// Element (i, j) of [A1 A2] as T.  A2 is either part of A (A + k lda, same
+// type) or a separate copy in BF16 (mixed precision).
+template <typename T, typename TA2>
+__device__ __forceinline__ T a_elem(const T *__restrict__ A, int64_t lda,
+                                    const TA2 *__restrict__ A2, int64_t lda2, int k, int64_t i,
+                                    int j) {
+  if constexpr (std::is_same<T, TA2>::value) {
+    return A[i + (int64_t)j * lda];
+  } else {
+    return j < k ? A[i + (int64_t)j * lda] : (T)to_f(A2[i + (int64_t)(j - k) * lda2]);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Input checks (problem (5) needs finite A and W1 > 0; Theorem 2 assumes
-// (W1)_ij > 0).  flags |= DEV_BAD_A / DEV_BAD_W.
+// (W1)_ij > 0).  flags |= DEV_BAD_A / DEV_BAD_W.  When A2b is given, the
+// same read also stages A2 in BF16 (m x (n - k), leading dimension m) for the
+// mixed-precision sweeps.
 template <typename T>
 __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, const T *__restrict__ A,
                                                   int64_t lda, int64_t k, const T *__restrict__ W1,
-                                                  int64_t ldw, int *flags) {
+                                                  int64_t ldw, int *flags, bf16s *__restrict__ A2b) {
   int bad_a = 0, bad_w = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
       const T v = A[i + j * lda];
       if (!isfinite(v)) bad_a = 1;
+      if (A2b != nullptr && j >= k) A2b[i + (j - k) * m] = bf16_rne((float)v);
       if (W1 != nullptr && j < k) {
         const T w = W1[i + j * ldw];
         if (!(w > T(0)) || !isfinite(w)) bad_w = 1;
@@ -89,8 +107,8 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
       const int rr = e & 31, cc = e >> 5;
       const int64_t row = rb + rr;
       const bool rin = row < r1;
-      px[u] = (rin && i0 + cc < k1) ? (double)X[row + (int64_t)(i0 + cc) * ldx] : 0.0;
-      py[u] = (rin && j0 + cc < k2) ? (double)Y[row + (int64_t)(j0 + cc) * ldy] : 0.0;
+      px[u] = (rin && i0 + cc < k1) ? (double)to_f(X[row + (int64_t)(i0 + cc) * ldx]) : 0.0;
+      py[u] = (rin && j0 + cc < k2) ? (double)to_f(Y[row + (int64_t)(j0 + cc) * ldy]) : 0.0;
     }
   };
   if (r0 < r1) fetch(r0);
@@ -185,9 +203,10 @@ __global__ __launch_bounds__(256) void k_f1(int64_t m, int k, const T *__restric
 // right-hand sides e for k_rowsolve.
 // Partials per workgroup: (||(A1 - X1') o W1||^2, ||X1' - X1||^2).
 #define UPD_NW 4
-template <typename T, int KMAX, bool CONSTW>
+template <typename T, int KMAX, bool CONSTW, typename TA2>
 __global__ __launch_bounds__(64 * UPD_NW) void k_update(
-    int64_t m, int k, int n, const T *__restrict__ A, int64_t lda, const T *__restrict__ W1,
+    int64_t m, int k, int n, const T *__restrict__ A, int64_t lda, const TA2 *__restrict__ A2,
+    int64_t lda2, const T *__restrict__ W1,
     int64_t ldw, T wc, const T *__restrict__ X1o, T *__restrict__ X1n, const T *__restrict__ Gt,
     const T *__restrict__ Tt, const T *__restrict__ St, double *__restrict__ part,
     T *__restrict__ Eb, int grows, const SmallState *__restrict__ st) {
@@ -240,7 +259,7 @@ __global__ __launch_bounds__(64 * UPD_NW) void k_update(
     for (; j + 8 <= j1; j += 8) {
       T v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = A[ir + (int64_t)(j + u) * lda];
+      for (int u = 0; u < 8; ++u) v[u] = a_elem<T, TA2>(A, lda, A2, lda2, k, ir, j + u);
       const T *g = sG + (j - c0) * k;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -250,7 +269,7 @@ __global__ __launch_bounds__(64 * UPD_NW) void k_update(
       }
     }
     for (; j < j1; ++j) {
-      const T v0 = A[ir + (int64_t)j * lda];
+      const T v0 = a_elem<T, TA2>(A, lda, A2, lda2, k, ir, j);
       const T *g = sG + (j - c0) * k;
 #pragma unroll
       for (int c = 0; c < KMAX; ++c)
@@ -561,9 +580,9 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
 // per workgroup.
 #define CHG_NW 4
 #define CHG_STAGE 12288  // doubles of [V_p V_q Z_p Z_q] rows staged per chunk
-template <typename T, int KMAX, int LMAX>
+template <typename T, int KMAX, int LMAX, typename TA2>
 __global__ __launch_bounds__(64 * CHG_NW) void k_change(
-    int64_t m, int k, int n2, int l, const T *__restrict__ A, int64_t lda,
+    int64_t m, int k, int n2, int l, const TA2 *__restrict__ A2, int64_t lda,
     const T *__restrict__ X1p, const T *__restrict__ X1q, const double *__restrict__ Zp,
     const double *__restrict__ Zq, const double *__restrict__ Vp, const double *__restrict__ Vq,
     double *__restrict__ part, const SmallState *__restrict__ st) {
@@ -576,7 +595,6 @@ __global__ __launch_bounds__(64 * CHG_NW) void k_change(
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const bool act = i < m;
   const int64_t ir = act ? i : (m - 1);
-  const T *A2 = A + (int64_t)k * lda;
   const int rw = 2 * l + 2 * k;                 // staged row: [vp | vq | zp | zq]
   const int crow = max(1, CHG_STAGE / max(rw, 1));
   auto stage = [&](int c0, int c1) {
@@ -604,7 +622,7 @@ __global__ __launch_bounds__(64 * CHG_NW) void k_change(
     for (; j + 8 <= j1; j += 8) {
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (double)A2[ir + (int64_t)(j + u) * lda];
+      for (int u = 0; u < 8; ++u) v[u] = (double)to_f(A2[ir + (int64_t)(j + u) * lda]);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const double *rr = sR + (j + u - c0) * rw;
@@ -617,7 +635,7 @@ __global__ __launch_bounds__(64 * CHG_NW) void k_change(
       }
     }
     for (; j < j1; ++j) {
-      const double v = (double)A2[ir + (int64_t)j * lda];
+      const double v = (double)to_f(A2[ir + (int64_t)j * lda]);
       const double *rr = sR + (j - c0) * rw;
 #pragma unroll
       for (int q = 0; q < LMAX; ++q)
@@ -699,9 +717,9 @@ __global__ __launch_bounds__(256) void k_copy_out(int64_t m, int64_t k, const T 
 
 template <typename T>
 void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t lda, int64_t k,
-                     const T *W1, int64_t ldw, int *flags) {
+                     const T *W1, int64_t ldw, int *flags, bf16s *A2b) {
   dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)std::min<int64_t>(n, 1024));
-  hipLaunchKernelGGL(k_validate<T>, grid, dim3(256), 0, s, m, n, A, lda, k, W1, ldw, flags);
+  hipLaunchKernelGGL(k_validate<T>, grid, dim3(256), 0, s, m, n, A, lda, k, W1, ldw, flags, A2b);
 }
 
 template <typename T>
@@ -749,25 +767,38 @@ UpdatePlan update_plan(int k, bool constw) {
   return pl;
 }
 
+template <typename T, int KMAX, bool CONSTW, typename TA2>
+static void launch_update_kernel(hipStream_t s, const UpdateArgs<T> &a, const TA2 *A2,
+                                 int64_t lda2, const UpdatePlan &pl) {
+  const unsigned grid = (unsigned)((a.m + 63) / 64);
+  if (pl.shm > 65536)
+    (void)hipFuncSetAttribute((const void *)k_update<T, KMAX, CONSTW, TA2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.shm);
+  hipLaunchKernelGGL((k_update<T, KMAX, CONSTW, TA2>), dim3(grid), dim3(64 * UPD_NW), pl.shm, s,
+                     a.m, a.k, a.n, a.A, a.lda, A2, lda2, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Gt,
+                     a.Tt, a.St, a.part, a.Eb, pl.grows, a.st);
+}
+
+template <typename T, int KMAX, bool CONSTW>
+static void launch_update_a2(hipStream_t s, const UpdateArgs<T> &a, const UpdatePlan &pl) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.A2b != nullptr) {
+      launch_update_kernel<T, KMAX, CONSTW, bf16s>(s, a, a.A2b, a.ldb, pl);
+      return;
+    }
+  }
+  launch_update_kernel<T, KMAX, CONSTW, T>(s, a, a.A + (int64_t)a.k * a.lda, a.lda, pl);
+}
+
 template <typename T, int KMAX>
 static void launch_update_k(hipStream_t s, const UpdateArgs<T> &a) {
   const unsigned grid = (unsigned)((a.m + 63) / 64);
   const UpdatePlan pl = update_plan<T>(a.k, a.constw);
   if (a.constw) {
-    if (pl.shm > 65536)
-      (void)hipFuncSetAttribute((const void *)k_update<T, KMAX, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.shm);
-    hipLaunchKernelGGL((k_update<T, KMAX, true>), dim3(grid), dim3(64 * UPD_NW), pl.shm, s, a.m,
-                       a.k, a.n, a.A, a.lda, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Gt, a.Tt, a.St,
-                       a.part, a.Eb, pl.grows, a.st);
+    launch_update_a2<T, KMAX, true>(s, a, pl);
     return;
   }
-  if (pl.shm > 65536)
-    (void)hipFuncSetAttribute((const void *)k_update<T, KMAX, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.shm);
-  hipLaunchKernelGGL((k_update<T, KMAX, false>), dim3(grid), dim3(64 * UPD_NW), pl.shm, s, a.m,
-                     a.k, a.n, a.A, a.lda, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Gt, a.Tt, a.St,
-                     a.part, a.Eb, pl.grows, a.st);
+  launch_update_a2<T, KMAX, false>(s, a, pl);
   if (sizeof(T) == 4 && a.k <= 24) {
     if (a.k <= 8)
       hipLaunchKernelGGL((k_rowsolve_reg<T, 8>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
@@ -819,28 +850,48 @@ void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64
   else launch_x2_k<T, 64>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2);
 }
 
-template <typename T, int KMAX>
-static void launch_change_k(hipStream_t s, int64_t m, int k, int n2, int l, const T *A,
-                            int64_t lda, const T *X1p, const T *X1q, const double *Zp,
+template <typename T, int KMAX, typename TA2>
+static void launch_change_k(hipStream_t s, int64_t m, int k, int n2, int l, const TA2 *A2,
+                            int64_t lda2, const T *X1p, const T *X1q, const double *Zp,
                             const double *Zq, const double *Vp, const double *Vq, double *part,
                             const SmallState *st) {
   const unsigned grid = (unsigned)((m + 63) / 64);
   if (l <= 8)
-    hipLaunchKernelGGL((k_change<T, KMAX, 8>), dim3(grid), dim3(64 * CHG_NW), 0, s, m, k, n2, l,
-                       A, lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+    hipLaunchKernelGGL((k_change<T, KMAX, 8, TA2>), dim3(grid), dim3(64 * CHG_NW), 0, s, m, k, n2,
+                       l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
   else
-    hipLaunchKernelGGL((k_change<T, KMAX, WLRA_BMAX>), dim3(grid), dim3(64 * CHG_NW), 0, s, m, k,
-                       n2, l, A, lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+    hipLaunchKernelGGL((k_change<T, KMAX, WLRA_BMAX, TA2>), dim3(grid), dim3(64 * CHG_NW), 0, s, m,
+                       k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+}
+
+template <typename T, typename TA2>
+static void launch_change_t(hipStream_t s, int64_t m, int k, int n2, int l, const TA2 *A2,
+                            int64_t lda2, const T *X1p, const T *X1q, const double *Zp,
+                            const double *Zq, const double *Vp, const double *Vq, double *part,
+                            const SmallState *st) {
+  if (k <= 8)
+    launch_change_k<T, 8, TA2>(s, m, k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+  else if (k <= 16)
+    launch_change_k<T, 16, TA2>(s, m, k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+  else if (k <= 32)
+    launch_change_k<T, 32, TA2>(s, m, k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+  else
+    launch_change_k<T, 64, TA2>(s, m, k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
 }
 
 template <typename T>
 void launch_change(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-                   const T *X1p, const T *X1q, const double *Zp, const double *Zq,
-                   const double *Vp, const double *Vq, double *part, const SmallState *st) {
-  if (k <= 8) launch_change_k<T, 8>(s, m, k, n2, l, A, lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
-  else if (k <= 16) launch_change_k<T, 16>(s, m, k, n2, l, A, lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
-  else if (k <= 32) launch_change_k<T, 32>(s, m, k, n2, l, A, lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
-  else launch_change_k<T, 64>(s, m, k, n2, l, A, lda, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+                   const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q, const double *Zp,
+                   const double *Zq, const double *Vp, const double *Vq, double *part,
+                   const SmallState *st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (A2b != nullptr) {
+      launch_change_t<T, bf16s>(s, m, k, n2, l, A2b, ldb, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+      return;
+    }
+  }
+  launch_change_t<T, T>(s, m, k, n2, l, A + (int64_t)k * lda, lda, X1p, X1q, Zp, Zq, Vp, Vq, part,
+                        st);
 }
 
 template <typename T>
@@ -852,7 +903,7 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
 
 #define INST(T)                                                                                   \
   template void launch_validate<T>(hipStream_t, int64_t, int64_t, const T *, int64_t, int64_t,    \
-                                   const T *, int64_t, int *);                                    \
+                                   const T *, int64_t, int *, bf16s *);                           \
   template void launch_init_x1<T>(hipStream_t, int64_t, int64_t, int, uint64_t, const T *,        \
                                   int64_t, T *, int *);                                           \
   template void launch_tsgemm<T, T>(hipStream_t, int64_t, const T *, int64_t, int, const T *,     \
@@ -866,7 +917,15 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
                              const T *, const T *, T *, int64_t);                                 \
   template void launch_copy_out<T>(hipStream_t, int64_t, int64_t, const T *, T *, int64_t);     \
   template void launch_change<T>(hipStream_t, int64_t, int, int, int, const T *, int64_t,         \
-                                 const T *, const T *, const double *, const double *,            \
-                                 const double *, const double *, double *, const SmallState *);
+                                 const bf16s *, int64_t, const T *, const T *, const double *,    \
+                                 const double *, const double *, const double *, double *,        \
+                                 const SmallState *);
 INST(float)
 INST(double)
+// mixed precision: X1^T A2 and A2^T A2 with A2 in BF16
+template void launch_tsgemm<float, bf16s>(hipStream_t, int64_t, const float *, int64_t, int,
+                                          const bf16s *, int64_t, int, int, int, int64_t,
+                                          double *, double *, const int *);
+template void launch_tsgemm<bf16s, bf16s>(hipStream_t, int64_t, const bf16s *, int64_t, int,
+                                          const bf16s *, int64_t, int, int, int, int64_t,
+                                          double *, double *, const int *);

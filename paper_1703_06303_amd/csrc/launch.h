@@ -22,6 +22,8 @@ struct UpdateArgs {
   T *X1n;
   const T *Gt, *Tt, *St;   // Gt = [-S; Z] (n x k), Tt = T, St = S (row-major)
   T *Eb;                   // m x k right-hand sides of the per-row solve
+  const bf16s *A2b;        // mixed precision: A2 in BF16 (ld ldb); NULL: A2 = A + k lda
+  int64_t ldb;
   double *part;
   const SmallState *st;
   int *flags;
@@ -29,7 +31,7 @@ struct UpdateArgs {
 
 template <typename T>
 void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t lda, int64_t k,
-                     const T *W1, int64_t ldw, int *flags);
+                     const T *W1, int64_t ldw, int *flags, bf16s *A2b);
 template <typename T>
 void launch_init_x1(hipStream_t s, int64_t m, int64_t k, int mode, uint64_t seed, const T *src,
                     int64_t lds, T *X1, int *flags);
@@ -89,5 +91,6 @@ void launch_gastats(hipStream_t s, int n2, const double *GA, SmallState *st);
 void launch_decide(hipStream_t s, const SmallArgs &a);
 template <typename T>
 void launch_change(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-                   const T *X1p, const T *X1q, const double *Zp, const double *Zq,
-                   const double *Vp, const double *Vq, double *part, const SmallState *st);
+                   const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q, const double *Zp,
+                   const double *Zq, const double *Vp, const double *Vq, double *part,
+                   const SmallState *st);

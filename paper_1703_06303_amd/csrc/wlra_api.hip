@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/wlra.h"
@@ -18,6 +19,9 @@
 #define EIG_GUARD 3
 #define EIG_DEG 12
 #define EIG_MAXIT 60
+// Mixed precision: the BF16 sweeps stop at max(tol, MIXED_TOL) before the
+// exact refinement sweep.
+#define MIXED_TOL 1e-4
 
 enum KernelKind {
   KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_XTX, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
@@ -109,6 +113,7 @@ struct Sizes {
   int64_t rows_ga, rows_p;
   int nwg_upd, nwg_f1;
   size_t elt;
+  bool mixed;
 };
 
 struct Ptrs {
@@ -117,6 +122,7 @@ struct Ptrs {
   double *Y, *Wb, *F0, *F1, *F2, *theta, *scratch, *upd_part, *chg_part;
   double *Zd[2], *Vd[2];
   void *Gt, *Tt, *St, *Vr, *Zx, *Eb;
+  bf16s *Ab;  // mixed precision: BF16 copy of A2 (m x n2), else NULL
   SmallState *st;
   int *flags;
 };
@@ -130,8 +136,9 @@ int choose_splits(int64_t m, int tiles, int64_t *rows) {
   return std::max(1, s);
 }
 
-Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt) {
+Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mixed) {
   Sizes z;
+  z.mixed = mixed;
   z.m = m; z.n = n; z.k = k; z.r = r; z.n2 = n - k; z.l = r - k;
   z.b = z.l > 0 ? std::min<int64_t>(z.n2, z.l + EIG_GUARD) : 0;
   const int tga = (int)(((z.n2 + 31) / 32) * ((z.n2 + 31) / 32 + 1) / 2);
@@ -187,10 +194,11 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {&p.Zx, (size_t)(n2 * kk) * z.elt},
       {(void **)&p.st, sizeof(SmallState)},
       {(void **)&p.flags, 64},
+      {(void **)&p.Ab, z.mixed ? (size_t)(m * n2) * sizeof(bf16s) : 0},
   };
   for (auto &it : items) {
     const size_t off = L.add(it.bytes);
-    *it.dst = base ? (void *)(base + off) : nullptr;
+    *it.dst = (base && it.bytes) ? (void *)(base + off) : nullptr;
   }
   if (P) *P = p;
   return L;
@@ -242,7 +250,8 @@ int check_problem(const wlra_problem *p, int precision) {
 
 template <typename T>
 int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
-  const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T));
+  const bool mixed = (h->precision == WLRA_MIXED_BF16);
+  const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T), mixed);
   int rc = ensure_ws(h, make_layout(z, nullptr, nullptr).total);
   if (rc != WLRA_OK) return rc;
   Ptrs P;
@@ -259,15 +268,19 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   HIPCHK(hipMemsetAsync(P.flags, 0, 64, s));
   SmallState &sh = *h->st_host;
   memset(&sh, 0, sizeof(SmallState));
-  sh.tol = pr->tol;
-  sh.max_sweeps = (k > 0) ? pr->max_sweeps : 0;
+  // Mixed precision runs the sweeps on the BF16 copy of A2 with a looser
+  // threshold and one sweep fewer, then refines in exact arithmetic.
+  const int max_sweeps = (k > 0) ? pr->max_sweeps : 0;
+  sh.tol = (mixed && pr->tol > 0) ? std::max(pr->tol, MIXED_TOL) : pr->tol;
+  sh.max_sweeps = mixed ? std::max(max_sweeps - 1, 0) : max_sweeps;
   sh.eig_first = 1;
   const double eig_tol = pr->eig_tol > 0 ? pr->eig_tol
                          : (h->precision == WLRA_FP64 ? 64.0 * 2.220446049250313e-16 : 1e-10);
   sh.eig_floor = eig_tol;
   HIPCHK(hipMemcpyAsync(P.st, &sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
 
-  PROF(h, KK_VALIDATE, launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags));
+  PROF(h, KK_VALIDATE,
+       launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags, P.Ab));
   T *X1c = static_cast<T *>(P.X1[0]);
   if (k > 0) {
     const int mode = pr->init == WLRA_INIT_RANDOM ? 0 : 1;
@@ -275,17 +288,42 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : pr->lda;
     PROF(h, KK_INIT, launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags));
   }
-  // One-time Gram of the unweighted block: A2^T A2.
-  PROF(h, KK_GRAM,
-       (launch_tsgemm<T, T>(s, m, A2, pr->lda, (int)n2, A2, pr->lda, (int)n2, 1, z.splits_ga,
-                            z.rows_ga, P.part, P.GA, nullptr)));
+  // One-time Gram of the unweighted block: A2^T A2 (of the BF16 copy in
+  // mixed precision, so that M = G_A - B^T B stays consistent).
+  auto gram_A2 = [&](bool on_bf16) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (on_bf16) {
+        PROF(h, KK_GRAM,
+             (launch_tsgemm<bf16s, bf16s>(s, m, P.Ab, m, (int)n2, P.Ab, m, (int)n2, 1,
+                                          z.splits_ga, z.rows_ga, P.part, P.GA, nullptr)));
+        return;
+      }
+    }
+    PROF(h, KK_GRAM,
+         (launch_tsgemm<T, T>(s, m, A2, pr->lda, (int)n2, A2, pr->lda, (int)n2, 1, z.splits_ga,
+                              z.rows_ga, P.part, P.GA, nullptr)));
+  };
+  // X1^T A2 (k x n2) for the coefficients of the next small step.
+  auto gram_X1A2 = [&](const T *X1, bool on_bf16) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (on_bf16) {
+        PROF(h, KK_XTA,
+             (launch_tsgemm<float, bf16s>(s, m, X1, m, (int)k, P.Ab, m, (int)n2, 0, z.splits_p,
+                                          z.rows_p, P.part, P.P, nullptr)));
+        return;
+      }
+    }
+    PROF(h, KK_XTA,
+         (launch_tsgemm<T, T>(s, m, X1, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p, z.rows_p,
+                              P.part, P.P, nullptr)));
+  };
+  bool on_bf16 = mixed;  // A2 products on the BF16 copy (mixed phase)
+  gram_A2(on_bf16);
   // eig_floor is relative to ||A2^T A2||_F; k_gastats scales it.
   PROF(h, KK_GAST, launch_gastats(s, (int)n2, P.GA, P.st));
   int nparts = 0;
   if (k > 0) {
-    PROF(h, KK_XTA,
-         (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p,
-                              z.rows_p, P.part, P.P, nullptr)));
+    gram_X1A2(X1c, on_bf16);
     PROF(h, KK_XTX,
          (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_p, z.rows_p,
                               P.part, P.G1, nullptr)));
@@ -310,6 +348,8 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
                  static_cast<T *>(P.Vr), static_cast<T *>(P.Zx)};
 
   int cur = 0;
+  bool reeval = false;   // exact re-evaluation of X_p right after the mixed phase
+  int mixed_status = 0;
   for (int p = 0;; ++p) {
     // Small step for sweep p: R, B, C from the Grams of X1_p; the top r-k
     // eigenpairs of (P^perp A2)^T (P^perp A2); Z, T, S and F(X_p).
@@ -322,10 +362,10 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
       PROF(h, KK_EIG, launch_eig(s, sa));
     }
     PROF(h, KK_POST, launch_post<T>(s, sa, so));
-    if (p > 0)
+    if (p > 0 && !reeval)
       PROF(h, KK_CHANGE,
-           launch_change<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c,
-                            static_cast<const T *>(P.X1[cur ^ 1]), P.Zd[p & 1],
+           launch_change<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, on_bf16 ? P.Ab : nullptr,
+                            m, X1c, static_cast<const T *>(P.X1[cur ^ 1]), P.Zd[p & 1],
                             P.Zd[(p & 1) ^ 1], P.Vd[p & 1], P.Vd[(p & 1) ^ 1], P.chg_part, P.st));
     PROF(h, KK_DECIDE, launch_decide(s, sa));
     HIPCHK(hipMemcpyAsync(h->st_host, P.st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
@@ -335,6 +375,26 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
       pr->trace[p] = sh.F;
       pr->trace[pr->max_sweeps + 1 + p] = sh.err;
     }
+    reeval = false;
+    if (sh.done && on_bf16) {
+      // End of the mixed phase at X1_p: switch to A2 itself (exact G_A and
+      // X1_p^T A2), re-evaluate X_p without a change pass, then allow one
+      // more X1 update (the refinement sweep) within max_sweeps.
+      mixed_status = sh.status;
+      on_bf16 = false;
+      reeval = true;
+      sh.done = 0;
+      sh.have_prev = 0;
+      sh.tol = pr->tol;
+      sh.max_sweeps = std::min(p + 1, max_sweeps);
+      sh.eig_floor = eig_tol;
+      HIPCHK(hipMemcpyAsync(P.st, &sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
+      gram_A2(false);
+      PROF(h, KK_GAST, launch_gastats(s, (int)n2, P.GA, P.st));
+      if (k > 0) gram_X1A2(X1c, false);
+      --p;
+      continue;
+    }
     if (sh.done) break;
     // X1_{p+1} from X1_p (Algorithm 1 steps 7-9), then the sums for p+1.
     T *X1n = static_cast<T *>(P.X1[cur ^ 1]);
@@ -343,11 +403,11 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1c; ua.X1n = X1n;
     ua.Gt = so.Gt; ua.Tt = so.Tt; ua.St = so.St; ua.part = P.upd_part; ua.st = P.st;
     ua.Eb = static_cast<T *>(P.Eb);
+    ua.A2b = on_bf16 ? P.Ab : nullptr;
+    ua.ldb = m;
     ua.flags = P.flags;
     PROF(h, KK_UPDATE, launch_update<T>(s, ua));
-    PROF(h, KK_XTA,
-         (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p,
-                              z.rows_p, P.part, P.P, nullptr)));
+    gram_X1A2(X1n, on_bf16);
     PROF(h, KK_XTX,
          (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_p, z.rows_p,
                               P.part, P.G1, nullptr)));
@@ -371,7 +431,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   float ms = 0.f;
   hipEventElapsedTime(&ms, h->ev0, h->ev1);
   if (res) {
-    res->status = (k == 0) ? WLRA_OK : sh.status;
+    res->status = (k == 0) ? WLRA_OK : (mixed ? mixed_status : sh.status);
     res->sweeps = sh.sweep;
     res->objective = sh.F;
     res->abs_change = sh.err;
@@ -381,7 +441,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     res->eig_iters = sh.eig_iters;
     res->eig_matvecs = sh.eig_matvecs;
   }
-  return (k == 0) ? WLRA_OK : sh.status;
+  return (k == 0) ? WLRA_OK : (mixed ? mixed_status : sh.status);
 }
 
 }  // namespace
@@ -440,7 +500,8 @@ int wlra_create(wlra_handle *out, int device, void *hip_stream, int precision, u
 int wlra_reserve(wlra_handle h, int64_t m, int64_t n, int64_t k, int64_t r) {
   if (h == nullptr || m < 1 || n < 1 || k < 0 || r < k || r > std::min(m, n)) return WLRA_E_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
-  const Sizes z = make_sizes(m, n, k, r, h->precision == WLRA_FP64 ? 8 : 4);
+  const Sizes z = make_sizes(m, n, k, r, h->precision == WLRA_FP64 ? 8 : 4,
+                            h->precision == WLRA_MIXED_BF16);
   return ensure_ws(h, make_layout(z, nullptr, nullptr).total);
 }
 

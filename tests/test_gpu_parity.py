@@ -101,6 +101,8 @@ SHAPES = [
     (15, 5, 12, 0, 4, False),
     (10, 5, 8, 2, 7, False),
     (20, 30, 150, 60, 64, False),
+    (20, 30, 620, 50, 62, True),     # n2 = 570: eigen blocks outside LDS, chunked small steps
+    (24, 25, 700, 12, 20, False),    # n2 = 688
 ]
 
 

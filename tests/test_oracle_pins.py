@@ -245,3 +245,46 @@ def test_error_codes():
     with pytest.raises(O.OracleError) as e:
         O.swlr(A, W1, k, r, X1_0=X0d)
     assert e.value.code == O.E_RANK
+
+
+# -- reduced-precision schedule --------------------------------------------------
+
+def test_round_bf16_matches_library_and_ties():
+    """BF16 rounding equals torch's float32 -> bfloat16 conversion (round to
+    nearest even), including exact ties."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(50000) * 10.0 ** rng.uniform(-6, 6, 50000)).astype(np.float32)
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(O.round_bf16(x), ref)
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: the even neighbour is 1.
+    # 1 + 3 * 2^-8 is halfway between 1 + 2^-7 (odd) and 1 + 2^-6 (even).
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 1 + 2.0 ** -7],
+                    dtype=np.float32)
+    assert np.array_equal(O.round_bf16(ties), [1.0, 1 + 2.0 ** -6, -1.0, 1 + 2.0 ** -7])
+
+
+def test_mixed_schedule_special_cases():
+    """With one sweep allowed, phase 1 does no update and the schedule is one
+    plain sweep; on data whose A2 is already BF16-exact it is the plain
+    iteration split at the phase boundary."""
+    inst = video.small(m_hw=(8, 9), n=14, k=3, r=5, seed=8)
+    one = O.swlr_mixed(inst.A, inst.W1, inst.k, inst.r, tol=0.0, max_sweeps=1, X1_0=inst.X1_0)
+    ref = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=0.0, max_sweeps=1, X1_0=inst.X1_0)
+    assert one.sweeps == 1 and _relerr(one.X, ref.X) < 1e-13
+    A = np.round(inst.A * 16) / 16            # multiples of 1/16 below 8: BF16-exact
+    mix = O.swlr_mixed(A, inst.W1, inst.k, inst.r, tol=0.0, max_sweeps=4, X1_0=inst.X1_0)
+    ref = O.swlr(A, inst.W1, inst.k, inst.r, tol=0.0, max_sweeps=4, X1_0=inst.X1_0)
+    assert mix.sweeps == 4 and _relerr(mix.X, ref.X) < 1e-12
+
+
+def test_mixed_schedule_meets_objective():
+    """BF16 sweeps to 1e-4 and one exact sweep land within 1e-6 of the
+    converged objective (the accuracy the schedule is meant for)."""
+    inst = video.small(m_hw=(24, 32), n=60, k=8, r=11, rho=3, fg="blobs", seed=12,
+                       w1=("loguniform", 1.0, 4.0))
+    ref = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=1e-13, max_sweeps=500, X1_0=inst.X1_0)
+    mix = O.swlr_mixed(inst.A, inst.W1, inst.k, inst.r, tol=1e-7, max_sweeps=200,
+                       X1_0=inst.X1_0)
+    assert mix.status == O.OK
+    assert abs(mix.F[-1] - ref.F[-1]) / ref.F[-1] < 1e-6
