@@ -53,8 +53,15 @@ enum wlra_status {
 typedef enum {
   WLRA_FP64 = 0,
   WLRA_FP32 = 1,
-  WLRA_MIXED_BF16 = 2    /* A2 products in bf16 with fp32 accumulate, then one
-                            exact FP32 refinement sweep                       */
+  WLRA_MIXED_BF16 = 2    /* float storage; the validation pass stages A2 in
+                            BF16 (round to nearest even) and the sweeps run on
+                            [A1, bf16(A2)] (Grams of A2 summed in double, the
+                            row update in float) until the Section 4.1 rule
+                            holds at max(tol, 1e-5) or max_sweeps - 1 updates;
+                            then A2^T A2 and X1^T A2 are formed from A2 itself,
+                            X_p is re-evaluated and one exact sweep (the
+                            refinement) gives the returned X_{p+1}.  The
+                            status is that of the BF16 phase.               */
 } wlra_precision;
 
 /* Start X1_0 (Algorithm 1 leaves it open; Section 4.1 recommends a random
@@ -135,11 +142,23 @@ int wlra_reserve(wlra_handle h, int64_t m, int64_t n, int64_t k, int64_t r);
  * returned X_p.  Inputs are only read. */
 int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res);
 
-/* Solve `count` independent instances (uneven m, n, k, r allowed).  Returns
- * WLRA_E_ARG if any instance fails argument checks (nothing is run), else 0;
- * the status of each instance is in res[i].status. */
+/* Solve `count` independent instances of problem (5) (uneven m, n, k, r
+ * allowed; each one as wlra_solve would).  The instances run concurrently on
+ * the handle's batch lanes: each lane is an internal stream with its own
+ * workspace, driven by its own host thread, and takes the largest remaining
+ * instance (by m * n) whenever it is free.  The lanes start after the work
+ * already queued on the handle's stream, and that stream waits for all of
+ * them before later work.  Blocks until every result is on the host.
+ * Returns WLRA_E_ARG if any instance fails the argument checks (nothing is
+ * run), a negative status if the lanes cannot be set up, else 0; the status
+ * of each instance is in res[i].status (res[i].ms is its own time on its
+ * lane).  Instances must not share output buffers. */
 int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs,
                        wlra_result *res);
+
+/* Number of batch lanes used by wlra_solve_batched (1..16, default 4; 1 runs
+ * the instances one after another on the handle's stream). */
+int wlra_set_batch_lanes(wlra_handle h, int32_t lanes);
 
 int wlra_destroy(wlra_handle h);
 

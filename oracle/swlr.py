@@ -239,7 +239,7 @@ def round_bf16(x):
 
 # Threshold of the reduced-precision phase (a reading of this project: the
 # paper has no mixed-precision schedule).
-MIXED_TOL = 1e-4
+MIXED_TOL = 1e-5
 
 
 def swlr_mixed(A, W1, k, r, tol=1e-7, max_sweeps=200, X1_0=None, mixed_tol=MIXED_TOL):

@@ -7,7 +7,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -21,7 +23,9 @@
 #define EIG_MAXIT 60
 // Mixed precision: the BF16 sweeps stop at max(tol, MIXED_TOL) before the
 // exact refinement sweep.
-#define MIXED_TOL 1e-4
+#define MIXED_TOL 1e-5
+#define WLRA_BATCH_LANES_DEFAULT 4
+#define WLRA_BATCH_LANES_MAX 16
 
 enum KernelKind {
   KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_XTX, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
@@ -38,6 +42,11 @@ struct ProfEvent {
 
 struct wlra_ctx {
   int device = 0;
+  // batched solves: sub-handles, each on its own stream with its own
+  // workspace, driven by one host thread each (created on first use)
+  int batch_lanes = WLRA_BATCH_LANES_DEFAULT;
+  std::vector<wlra_ctx *> lanes;
+  bool owns_stream = false;
   hipStream_t stream = nullptr;
   int precision = 0;
   uint32_t flags = 0;
@@ -521,12 +530,111 @@ int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res) {
   return rc;
 }
 
+int wlra_set_batch_lanes(wlra_handle h, int32_t lanes) {
+  if (h == nullptr || lanes < 1 || lanes > WLRA_BATCH_LANES_MAX) return WLRA_E_ARG;
+  h->batch_lanes = lanes;
+  return WLRA_OK;
+}
+
+namespace {
+
+// Sub-handles for batched solves: one non-blocking stream (default priority)
+// and one workspace each.
+int ensure_lanes(wlra_ctx *h, int want) {
+  while ((int)h->lanes.size() < want) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return WLRA_E_HIP;
+    wlra_ctx *sub = nullptr;
+    const int rc = wlra_create(&sub, h->device, st, h->precision, h->flags);
+    if (rc != WLRA_OK) {
+      (void)hipStreamDestroy(st);
+      return rc;
+    }
+    sub->owns_stream = true;
+    h->lanes.push_back(sub);
+  }
+  return WLRA_OK;
+}
+
+size_t workspace_bytes(const wlra_problem &p, int precision) {
+  const Sizes z = make_sizes(p.m, p.n, p.k, p.r, precision == WLRA_FP64 ? 8 : 4,
+                             precision == WLRA_MIXED_BF16);
+  return make_layout(z, nullptr, nullptr).total;
+}
+
+}  // namespace
+
 int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs, wlra_result *res) {
   if (h == nullptr || count < 0 || (count > 0 && (probs == nullptr || res == nullptr)))
     return WLRA_E_ARG;
   for (int i = 0; i < count; ++i)
     if (check_problem(&probs[i], h->precision) == WLRA_E_ARG) return WLRA_E_ARG;
-  for (int i = 0; i < count; ++i) wlra_solve(h, &probs[i], &res[i]);
+  if (count == 0) return WLRA_OK;
+  if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+  const int nl = std::min<int>(count, h->batch_lanes);
+  if (nl <= 1) {
+    for (int i = 0; i < count; ++i) wlra_solve(h, &probs[i], &res[i]);
+    return WLRA_OK;
+  }
+  int rc = ensure_lanes(h, nl);
+  if (rc != WLRA_OK) return rc;
+  // Largest instances first (longest-processing-time order): the lanes take
+  // the next instance as they free up, so small clips fill in around big ones.
+  std::vector<int> order(count);
+  size_t ws_max = 0;
+  for (int i = 0; i < count; ++i) {
+    order[i] = i;
+    ws_max = std::max(ws_max, workspace_bytes(probs[i], h->precision));
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return probs[a].m * probs[a].n > probs[b].m * probs[b].n;
+  });
+  // Grow every lane's workspace once, before any lane starts (a free while
+  // other lanes run would synchronise the device).
+  for (int j = 0; j < nl; ++j) {
+    wlra_ctx *L = h->lanes[j];
+    if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+    rc = ensure_ws(L, ws_max);
+    if (rc != WLRA_OK) return rc;
+  }
+  // Order the lanes after the work already queued on the caller's stream.
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return WLRA_E_HIP;
+  if (hipEventRecord(ev, h->stream) != hipSuccess) return WLRA_E_HIP;
+  for (int j = 0; j < nl; ++j)
+    if (hipStreamWaitEvent(h->lanes[j]->stream, ev, 0) != hipSuccess) return WLRA_E_HIP;
+  std::atomic<int> next{0};
+  auto work = [&](int j) {
+    wlra_ctx *L = h->lanes[j];
+    for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) {
+      const int i = order[q];
+      wlra_solve(L, &probs[i], &res[i]);
+    }
+  };
+  std::vector<std::thread> th;
+  try {
+    for (int j = 1; j < nl; ++j) th.emplace_back(work, j);
+  } catch (...) {
+    // no more threads: the lanes already started share the remaining work
+  }
+  work(0);
+  for (auto &t : th) t.join();
+  // The caller's stream continues after every lane.
+  for (int j = 0; j < nl; ++j) {
+    wlra_ctx *L = h->lanes[j];
+    if (hipEventRecord(ev, L->stream) != hipSuccess ||
+        hipStreamWaitEvent(h->stream, ev, 0) != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      return WLRA_E_HIP;
+    }
+    for (int kk = 0; kk < KK_COUNT; ++kk) {
+      h->ms[kk] += L->ms[kk];
+      h->launches[kk] += L->launches[kk];
+      L->ms[kk] = 0.0;
+      L->launches[kk] = 0;
+    }
+  }
+  (void)hipEventDestroy(ev);
   return WLRA_OK;
 }
 
@@ -554,6 +662,8 @@ int wlra_profile(wlra_handle h, int32_t max, wlra_kstat *out, int32_t reset) {
 
 int wlra_destroy(wlra_handle h) {
   if (h == nullptr) return WLRA_OK;
+  for (wlra_ctx *L : h->lanes) wlra_destroy(L);
+  h->lanes.clear();
   for (auto &pe : h->pending) {
     h->pool.push_back(pe.e0);
     h->pool.push_back(pe.e1);
@@ -565,6 +675,7 @@ int wlra_destroy(wlra_handle h) {
   if (h->flags_host) hipHostFree(h->flags_host);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return WLRA_OK;
 }

@@ -54,8 +54,9 @@ class KStat(ctypes.Structure):
 
 FLAG_PROFILE = 1
 
-SYMBOLS = ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched", "wlra_destroy",
-           "wlra_profile", "wlra_validate", "wlra_strerror", "wlra_version")
+SYMBOLS = ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
+           "wlra_set_batch_lanes", "wlra_destroy", "wlra_profile", "wlra_validate",
+           "wlra_strerror", "wlra_version")
 
 _lib = None
 
@@ -74,6 +75,7 @@ def load(path: str = LIB_PATH):
     lib.wlra_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Result)]
     lib.wlra_solve_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
                                        ctypes.POINTER(Result)]
+    lib.wlra_set_batch_lanes.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.wlra_destroy.argtypes = [ctypes.c_void_p]
     lib.wlra_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(KStat),
                                  ctypes.c_int32]
@@ -82,7 +84,8 @@ def load(path: str = LIB_PATH):
     lib.wlra_strerror.restype = ctypes.c_char_p
     lib.wlra_version.argtypes = []
     for name in ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
-                 "wlra_destroy", "wlra_profile", "wlra_validate", "wlra_version"):
+                 "wlra_set_batch_lanes", "wlra_destroy", "wlra_profile", "wlra_validate",
+                 "wlra_version"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -204,6 +207,11 @@ class Solver:
             out["trace_F"] = list(tr[:max_sweeps + 1])
             out["trace_err"] = list(tr[max_sweeps + 1:])
         return X1, X2, out
+
+    def set_batch_lanes(self, lanes):
+        rc = self.lib.wlra_set_batch_lanes(self.h, int(lanes))
+        if rc != OK:
+            raise WlraError(rc)
 
     def solve_batched(self, problems):
         """Solve a list of Problem structs (already filled with pointers)."""

@@ -33,3 +33,27 @@ def gpu_solve(solver, inst, tol, max_sweeps, init="given", dense_w=None, want_x2
                                want_x2=want_x2, want_trace=want_trace, eig_tol=eig_tol,
                                raise_on_error=False)
     return host(X1), (host(X2) if X2 is not None else None), res
+
+
+def batch_problems(solver, insts, tol, max_sweeps, init="given", seeds=None):
+    """Device inputs and outputs plus filled Problem structs for a batch.
+    Returns (problems, keep) where keep holds every tensor the structs point
+    to, and keep["X1"], keep["X2"] the outputs per instance."""
+    import torch
+    from paper_1703_06303_amd.wlra import colmajor, make_problem
+    dt = solver.dtype
+    keep = {"A": [], "W1": [], "X0": [], "X1": [], "X2": []}
+    probs = []
+    for j, inst in enumerate(insts):
+        A = dev(inst.A, dt)
+        W1 = dev(inst.W1_dense(), dt) if (inst.W1 is not None and inst.k > 0) else None
+        X0 = dev(inst.X1_0, dt) if (init == "given" and inst.k > 0) else None
+        X1 = colmajor(torch.empty((inst.m, inst.k), dtype=dt, device="cuda"))
+        X2 = colmajor(torch.empty((inst.m, inst.n - inst.k), dtype=dt, device="cuda"))
+        for key, t in (("A", A), ("W1", W1), ("X0", X0), ("X1", X1), ("X2", X2)):
+            keep[key].append(t)
+        probs.append(make_problem(A, inst.k, inst.r, W1=W1, w1_const=inst.w1_const or 1.0,
+                                  tol=tol, max_sweeps=max_sweeps, init=init,
+                                  seed=(seeds[j] if seeds else 0), X1_init=X0, X1_out=X1,
+                                  X2_out=X2))
+    return probs, keep

@@ -279,7 +279,7 @@ def test_mixed_schedule_special_cases():
 
 
 def test_mixed_schedule_meets_objective():
-    """BF16 sweeps to 1e-4 and one exact sweep land within 1e-6 of the
+    """BF16 sweeps to 1e-5 and one exact sweep land within 1e-6 of the
     converged objective (the accuracy the schedule is meant for)."""
     inst = video.small(m_hw=(24, 32), n=60, k=8, r=11, rho=3, fg="blobs", seed=12,
                        w1=("loguniform", 1.0, 4.0))
