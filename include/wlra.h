@@ -70,7 +70,13 @@ typedef enum {
   WLRA_INIT_RANDOM = 0,  /* iid N(0,1) from Philox4x32-10 keyed by `seed`     */
   WLRA_INIT_GIVEN = 1,   /* X1_init (device, m x k, ld ldx0)                  */
   WLRA_INIT_A1 = 2,      /* X1_0 = A1                                         */
-  WLRA_INIT_LEARNED = 3  /* reserved for the learned warm start              */
+  WLRA_INIT_LEARNED = 3  /* learned warm start (not in the paper): a network
+                            maps a Gaussian sketch of A to an n x r basis Y,
+                            and X1_0 = L0 (L0^T L0)^-1 L0^T A1 with L0 = A Y
+                            (A1 projected on the predicted column space); if
+                            L0^T L0 is numerically singular the random start
+                            keyed by `seed` is used instead.  Needs `model`
+                            and r <= 32.                                      */
 } wlra_init;
 
 typedef struct {
@@ -96,6 +102,14 @@ typedef struct {
                               = F(X_p), trace[max_sweeps+1+p] = Error_p (p>=1)  */
   double eig_tol;          /* relative residual target of the H_{r-k} eigen
                               step; <= 0 selects the default for the precision  */
+  const float *model;      /* device, WLRA_INIT_LEARNED only: the network's
+                              wlra_mlp_param_count(n, r) parameters (below)     */
+  double *factors_out;     /* device, optional: the returned X_p's factors, in
+                              order R (k x k, upper, X1_p^T X1_p = R^T R),
+                              C (k x (n-k)), V (n-k x r-k, the top right
+                              singular vectors of P_perp A2) and their squared
+                              singular values (r-k), all column-major double:
+                              X2_p = X1_p C + (A2 - X1_p C) V V^T               */
 } wlra_problem;
 
 typedef struct {
@@ -172,6 +186,46 @@ int wlra_profile(wlra_handle h, int32_t max, wlra_kstat *out, int32_t reset);
 int wlra_validate(const wlra_problem *prob, int precision);
 
 const char *wlra_strerror(int status);
+
+/* ---- Learned warm start (a systems extension; the paper's start is random).
+ *
+ * Sketch: s = vec(Om^T A Ps) / ||Om^T A Ps||_F (512 floats, s[a + 16 b]) with
+ * Om (m x 16) and Ps (n x 32) iid N(0,1) from Philox4x32-10 under two fixed
+ * keys (0x5EEDA001, 0x5EEDA002), element (i, c) of Om being draw i + c m.
+ * Network: h1 = relu(W1 s + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3,
+ * 512 -> 256 -> 256 -> n r, Y = y as an n x r column-major basis.  Parameter
+ * vector (float, device): W1 (256 x 512 row-major), b1, W2 (256 x 256), b2,
+ * W3 (n r x 256), b3.
+ * Training target of a solved instance: T = [[I_k, C], [0, V^T]]^T (n x r),
+ * whose column space is the row space of the solution X_p (from
+ * factors_out).  Loss per sample, Q an orthonormal basis of T:
+ * ||Y - Q Q^T Y||_F^2 + ||Y^T Y - I||_F^2, averaged over the batch; Adam
+ * with beta1 0.9, beta2 0.999, eps 1e-8.  Batched arrays are row-major
+ * (sample-major); every pointer below is device memory unless noted. */
+
+/* Number of network parameters for (n, r), or -1 for bad sizes. */
+int64_t wlra_mlp_param_count(int64_t n, int64_t r);
+
+/* Fill `params` with a start: W_l = sqrt(2 / fan_in) N(0,1) draws keyed by
+ * seed + l (l = 1, 2, 3), biases 0. */
+int wlra_mlp_init(wlra_handle h, float *params, int64_t n, int64_t r, uint64_t seed);
+
+/* The 512-float sketch of A (m x n, column-major, the handle's storage type). */
+int wlra_sketch(wlra_handle h, int64_t m, int64_t n, const void *A, int64_t lda, float *out);
+
+/* Y (batch x n r) = network(X (batch x 512)). */
+int wlra_mlp_forward(wlra_handle h, const float *params, int64_t n, int64_t r, int32_t batch,
+                     const float *X, float *Y);
+
+/* One training step on a batch: loss and gradient for sketches X
+ * (batch x 512) and targets T (batch x n x r, each column-major), then an
+ * Adam update with step number `step` (1, 2, ...) of params, adam_m, adam_v
+ * (all of wlra_mlp_param_count floats).  step <= 0 computes the loss and
+ * gradient only.  *loss (host) gets the batch-mean loss; grad_out, when not
+ * NULL, the gradient.  Returns WLRA_E_RANK if a target basis is singular. */
+int wlra_mlp_train_step(wlra_handle h, float *params, float *adam_m, float *adam_v,
+                        int32_t step, int64_t n, int64_t r, int32_t batch, const float *X,
+                        const float *T, double lr, double *loss, float *grad_out);
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int wlra_version(void);

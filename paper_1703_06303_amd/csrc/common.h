@@ -14,6 +14,17 @@
 #define DEV_RANK 4
 #define DEV_EIG_MAXIT 8
 #define DEV_ROWSOLVE 16
+#define DEV_LEARN_FAIL 32
+
+// Learned warm start: sketch Om^T A Ps with Om m x 16 and Ps n x 32 (Philox
+// N(0,1) draws under fixed keys), network 512 -> 256 -> 256 -> n r.
+#define LEARN_SK_ROWS 16
+#define LEARN_SK_COLS 32
+#define LEARN_D_IN 512
+#define LEARN_HID 256
+#define LEARN_RMAX 32
+#define LEARN_SEED_OMEGA 0x5EEDA001ull
+#define LEARN_SEED_PSI 0x5EEDA002ull
 
 // BF16 storage of A2 in mixed precision: the bit pattern of the upper half of
 // an IEEE float.  Widening to float is exact; narrowing rounds to nearest

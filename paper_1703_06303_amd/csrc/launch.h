@@ -94,3 +94,24 @@ void launch_change(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, i
                    const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q, const double *Zp,
                    const double *Zq, const double *Vp, const double *Vq, double *part,
                    const SmallState *st);
+
+// Learned warm start (k_learn.hip).
+template <typename T>
+void launch_gauss_fill(hipStream_t s, int64_t count, uint64_t seed, double scale, T *out);
+void launch_fill_zero(hipStream_t s, int64_t count, float *out);
+template <typename T>
+void launch_sketch_finish(hipStream_t s, int n, const double *P1, const T *Ps, float *out);
+void launch_gemm(hipStream_t s, int mode, int M, int N, int K, const float *A, int lda,
+                 const float *B, int ldb, float *C, int ldc, const float *bias, int relu,
+                 const float *mask, int ldm);
+void launch_colsum(hipStream_t s, int M, int N, const float *A, float *out);
+void launch_subspace_loss(hipStream_t s, int n, int r, int batch, const float *y, const float *T,
+                          double lam, float *gy, double *loss_part, int *flags);
+void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, float *v, float lr,
+                 float b1, float b2, float eps, float bc1, float bc2);
+template <typename T, typename TS>
+void launch_tall_small(hipStream_t s, int64_t m, int kin, int c, const T *A, int64_t lda,
+                       const TS *S, int64_t rs, int64_t cs, T *out, int64_t ldo);
+template <typename T>
+void launch_decode_solve(hipStream_t s, int r, int k, const double *G, const double *H, T *Y,
+                         int *flags);

@@ -29,11 +29,12 @@
 
 enum KernelKind {
   KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_XTX, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
-  KK_POST, KK_CHANGE, KK_DECIDE, KK_UPDATE, KK_X2, KK_COPY, KK_COUNT
+  KK_POST, KK_CHANGE, KK_DECIDE, KK_UPDATE, KK_X2, KK_COPY, KK_LEARN, KK_COUNT
 };
 static const char *kKernelNames[KK_COUNT] = {
     "validate", "init_x1", "gram_A2", "gram_stats", "gram_X1A2", "gram_X1X1", "objective_f1",
-    "coef", "form_M", "eig", "post", "change", "decide", "update", "x2_out", "copy_out"};
+    "coef", "form_M", "eig", "post", "change", "decide", "update", "x2_out", "copy_out",
+    "learned_init"};
 
 struct ProfEvent {
   int kind;
@@ -52,6 +53,8 @@ struct wlra_ctx {
   uint32_t flags = 0;
   char *ws = nullptr;
   size_t ws_bytes = 0;
+  char *lws = nullptr;  // learned warm start: sketch and training buffers
+  size_t lws_bytes = 0;
   SmallState *st_host = nullptr;  // pinned
   int *flags_host = nullptr;      // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -123,6 +126,9 @@ struct Sizes {
   int nwg_upd, nwg_f1;
   size_t elt;
   bool mixed;
+  bool learned;
+  int splits_l1, splits_l2, splits_l3;  // Om^T A, L0^T L0, L0^T A1
+  int64_t rows_l1, rows_l2, rows_l3;
 };
 
 struct Ptrs {
@@ -132,6 +138,10 @@ struct Ptrs {
   double *Zd[2], *Vd[2];
   void *Gt, *Tt, *St, *Vr, *Zx, *Eb;
   bf16s *Ab;  // mixed precision: BF16 copy of A2 (m x n2), else NULL
+  // learned warm start (NULL unless the start is learned)
+  void *Om, *Ps, *L0, *Yc;
+  double *P1, *LG, *LH, *lpart;
+  float *sk, *lh1, *lh2, *yv;
   SmallState *st;
   int *flags;
 };
@@ -145,15 +155,20 @@ int choose_splits(int64_t m, int tiles, int64_t *rows) {
   return std::max(1, s);
 }
 
-Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mixed) {
+Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mixed,
+                 bool learned = false) {
   Sizes z;
   z.mixed = mixed;
+  z.learned = learned;
   z.m = m; z.n = n; z.k = k; z.r = r; z.n2 = n - k; z.l = r - k;
   z.b = z.l > 0 ? std::min<int64_t>(z.n2, z.l + EIG_GUARD) : 0;
   const int tga = (int)(((z.n2 + 31) / 32) * ((z.n2 + 31) / 32 + 1) / 2);
   z.splits_ga = choose_splits(m, std::max(1, tga), &z.rows_ga);
   const int tp = (int)(((std::max<int64_t>(k, 1) + 31) / 32) * ((z.n2 + 31) / 32));
   z.splits_p = choose_splits(m, std::max(1, tp), &z.rows_p);
+  z.splits_l1 = choose_splits(m, (int)((n + 31) / 32), &z.rows_l1);
+  z.splits_l2 = choose_splits(m, 1, &z.rows_l2);
+  z.splits_l3 = choose_splits(m, (int)((std::max<int64_t>(k, 1) + 31) / 32), &z.rows_l3);
   z.nwg_upd = (int)((m + 63) / 64);
   z.nwg_f1 = 256;
   z.elt = elt;
@@ -204,6 +219,22 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.st, sizeof(SmallState)},
       {(void **)&p.flags, 64},
       {(void **)&p.Ab, z.mixed ? (size_t)(m * n2) * sizeof(bf16s) : 0},
+      {&p.Om, z.learned ? (size_t)(m * LEARN_SK_ROWS) * z.elt : 0},
+      {&p.Ps, z.learned ? (size_t)(z.n * LEARN_SK_COLS) * z.elt : 0},
+      {&p.L0, z.learned ? (size_t)(m * z.r) * z.elt : 0},
+      {&p.Yc, z.learned ? (size_t)(z.r * kk) * z.elt : 0},
+      {(void **)&p.P1, z.learned ? (size_t)(LEARN_SK_ROWS * z.n) * d : 0},
+      {(void **)&p.LG, z.learned ? (size_t)(z.r * z.r) * d : 0},
+      {(void **)&p.LH, z.learned ? (size_t)(z.r * kk) * d : 0},
+      {(void **)&p.lpart,
+       z.learned ? std::max<size_t>((size_t)z.splits_l1 * LEARN_SK_ROWS * z.n,
+                                    std::max<size_t>((size_t)z.splits_l2 * z.r * z.r,
+                                                     (size_t)z.splits_l3 * z.r * kk)) * d
+                 : 0},
+      {(void **)&p.sk, z.learned ? (size_t)LEARN_D_IN * sizeof(float) : 0},
+      {(void **)&p.lh1, z.learned ? (size_t)LEARN_HID * sizeof(float) : 0},
+      {(void **)&p.lh2, z.learned ? (size_t)LEARN_HID * sizeof(float) : 0},
+      {(void **)&p.yv, z.learned ? (size_t)(z.n * z.r) * sizeof(float) : 0},
   };
   for (auto &it : items) {
     const size_t off = L.add(it.bytes);
@@ -246,7 +277,9 @@ int check_problem(const wlra_problem *p, int precision) {
   if (p->max_sweeps < 0) return WLRA_E_ARG;
   if (k > 0 && (p->X1_out == nullptr || p->ldx1 < m)) return WLRA_E_ARG;
   if (p->X2_out != nullptr && p->ldx2 < m) return WLRA_E_ARG;
-  if (p->init < WLRA_INIT_RANDOM || p->init > WLRA_INIT_A1) return WLRA_E_ARG;
+  if (p->init < WLRA_INIT_RANDOM || p->init > WLRA_INIT_LEARNED) return WLRA_E_ARG;
+  if (k > 0 && p->init == WLRA_INIT_LEARNED && (p->model == nullptr || r > LEARN_RMAX))
+    return WLRA_E_ARG;
   if (k > 0 && p->init == WLRA_INIT_GIVEN && (p->X1_init == nullptr || p->ldx0 < m)) return WLRA_E_ARG;
   if (!(p->tol == p->tol)) return WLRA_E_ARG;
   return WLRA_OK;
@@ -260,7 +293,8 @@ int check_problem(const wlra_problem *p, int precision) {
 template <typename T>
 int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   const bool mixed = (h->precision == WLRA_MIXED_BF16);
-  const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T), mixed);
+  const bool learned = (pr->k > 0 && pr->init == WLRA_INIT_LEARNED);
+  const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T), mixed, learned);
   int rc = ensure_ws(h, make_layout(z, nullptr, nullptr).total);
   if (rc != WLRA_OK) return rc;
   Ptrs P;
@@ -291,8 +325,43 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   PROF(h, KK_VALIDATE,
        launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags, P.Ab));
   T *X1c = static_cast<T *>(P.X1[0]);
-  if (k > 0) {
-    const int mode = pr->init == WLRA_INIT_RANDOM ? 0 : 1;
+  bool need_init = (k > 0);
+  if (learned) {
+    // X1_0 = L0 (L0^T L0)^-1 L0^T A1 with L0 = A Y, Y = network(sketch of A)
+    const int64_t n = pr->n, nr = n * z.r;
+    const float *W1m = pr->model, *b1 = W1m + LEARN_HID * LEARN_D_IN;
+    const float *W2m = b1 + LEARN_HID, *b2 = W2m + LEARN_HID * LEARN_HID;
+    const float *W3m = b2 + LEARN_HID, *b3 = W3m + nr * LEARN_HID;
+    T *Om = static_cast<T *>(P.Om), *Ps = static_cast<T *>(P.Ps);
+    T *L0 = static_cast<T *>(P.L0), *Yc = static_cast<T *>(P.Yc);
+    auto seq = [&]() {
+      launch_gauss_fill<T>(s, m * LEARN_SK_ROWS, LEARN_SEED_OMEGA, 1.0, Om);
+      launch_gauss_fill<T>(s, n * LEARN_SK_COLS, LEARN_SEED_PSI, 1.0, Ps);
+      launch_tsgemm<T, T>(s, m, Om, m, LEARN_SK_ROWS, A, pr->lda, (int)n, 0, z.splits_l1,
+                          z.rows_l1, P.lpart, P.P1, nullptr);
+      launch_sketch_finish<T>(s, (int)n, P.P1, Ps, P.sk);
+      launch_gemm(s, 0, 1, LEARN_HID, LEARN_D_IN, P.sk, LEARN_D_IN, W1m, LEARN_D_IN, P.lh1,
+                  LEARN_HID, b1, 1, nullptr, 0);
+      launch_gemm(s, 0, 1, LEARN_HID, LEARN_HID, P.lh1, LEARN_HID, W2m, LEARN_HID, P.lh2,
+                  LEARN_HID, b2, 1, nullptr, 0);
+      launch_gemm(s, 0, 1, (int)nr, LEARN_HID, P.lh2, LEARN_HID, W3m, LEARN_HID, P.yv, (int)nr,
+                  b3, 0, nullptr, 0);
+      launch_tall_small<T, float>(s, m, (int)n, (int)z.r, A, pr->lda, P.yv, 1, n, L0, m);
+      launch_tsgemm<T, T>(s, m, L0, m, (int)z.r, L0, m, (int)z.r, 0, z.splits_l2, z.rows_l2,
+                          P.lpart, P.LG, nullptr);
+      launch_tsgemm<T, T>(s, m, L0, m, (int)z.r, A, pr->lda, (int)k, 0, z.splits_l3, z.rows_l3,
+                          P.lpart, P.LH, nullptr);
+      launch_decode_solve<T>(s, (int)z.r, (int)k, P.LG, P.LH, Yc, P.flags);
+      launch_tall_small<T, T>(s, m, (int)z.r, (int)k, L0, m, Yc, k, 1, X1c, m);
+    };
+    PROF(h, KK_LEARN, seq());
+    HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // the plain random start is the fallback when the decode fails
+    need_init = (*h->flags_host & DEV_LEARN_FAIL) != 0;
+  }
+  if (need_init) {
+    const int mode = (pr->init == WLRA_INIT_RANDOM || pr->init == WLRA_INIT_LEARNED) ? 0 : 1;
     const T *src = pr->init == WLRA_INIT_GIVEN ? static_cast<const T *>(pr->X1_init) : A;
     const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : pr->lda;
     PROF(h, KK_INIT, launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags));
@@ -430,6 +499,21 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   if (dflags & DEV_RANK) return WLRA_E_RANK;
   if (k > 0)
     PROF(h, KK_COPY, launch_copy_out<T>(s, m, k, X1c, static_cast<T *>(pr->X1_out), pr->ldx1));
+  if (pr->factors_out != nullptr) {
+    // R (k x k), C (k x n2), V (n2 x l), theta (l): the returned X_p's factors
+    double *f = pr->factors_out;
+    const size_t d = sizeof(double);
+    if (k > 0) {
+      HIPCHK(hipMemcpyAsync(f, P.R, (size_t)(k * k) * d, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(f + k * k, P.C, (size_t)(k * n2) * d, hipMemcpyDeviceToDevice, s));
+    }
+    if (l > 0) {
+      HIPCHK(hipMemcpyAsync(f + k * k + k * n2, P.Y, (size_t)(n2 * l) * d,
+                            hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(f + k * k + k * n2 + n2 * l, P.theta, (size_t)l * d,
+                            hipMemcpyDeviceToDevice, s));
+    }
+  }
   if (pr->X2_out != nullptr)
     PROF(h, KK_X2,
          launch_x2<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c, so.Zx, so.Vr,
@@ -558,7 +642,8 @@ int ensure_lanes(wlra_ctx *h, int want) {
 
 size_t workspace_bytes(const wlra_problem &p, int precision) {
   const Sizes z = make_sizes(p.m, p.n, p.k, p.r, precision == WLRA_FP64 ? 8 : 4,
-                             precision == WLRA_MIXED_BF16);
+                             precision == WLRA_MIXED_BF16,
+                             p.k > 0 && p.init == WLRA_INIT_LEARNED);
   return make_layout(z, nullptr, nullptr).total;
 }
 
@@ -638,6 +723,192 @@ int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs, 
   return WLRA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Learned warm start: training and inference entry points.
+extern "C++" {
+namespace {
+
+int ensure_lws(wlra_ctx *h, size_t bytes) {
+  if (bytes <= h->lws_bytes) return WLRA_OK;
+  if (h->lws) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return WLRA_E_HIP;
+    (void)hipFree(h->lws);
+    h->lws = nullptr;
+    h->lws_bytes = 0;
+  }
+  const size_t want = bytes + bytes / 4;
+  if (hipMalloc(&h->lws, want) != hipSuccess) {
+    h->lws = nullptr;
+    return WLRA_E_NOMEM;
+  }
+  h->lws_bytes = want;
+  return WLRA_OK;
+}
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+template <typename P>
+void mlp_offsets(P *base, int64_t o, P **W1, P **b1, P **W2, P **b2, P **W3, P **b3) {
+  *W1 = base;
+  *b1 = *W1 + LEARN_HID * LEARN_D_IN;
+  *W2 = *b1 + LEARN_HID;
+  *b2 = *W2 + LEARN_HID * LEARN_HID;
+  *W3 = *b2 + LEARN_HID;
+  *b3 = *W3 + o * LEARN_HID;
+}
+
+template <typename T>
+int sketch_impl(wlra_ctx *h, int64_t m, int64_t n, const T *A, int64_t lda, float *out) {
+  int64_t rows = 0;
+  const int splits = choose_splits(m, (int)((n + 31) / 32), &rows);
+  const size_t b_om = al256((size_t)(m * LEARN_SK_ROWS) * sizeof(T));
+  const size_t b_ps = al256((size_t)(n * LEARN_SK_COLS) * sizeof(T));
+  const size_t b_p1 = al256((size_t)(LEARN_SK_ROWS * n) * sizeof(double));
+  const size_t b_pt = al256((size_t)splits * LEARN_SK_ROWS * n * sizeof(double));
+  int rc = ensure_lws(h, b_om + b_ps + b_p1 + b_pt);
+  if (rc != WLRA_OK) return rc;
+  T *Om = reinterpret_cast<T *>(h->lws);
+  T *Ps = reinterpret_cast<T *>(h->lws + b_om);
+  double *P1 = reinterpret_cast<double *>(h->lws + b_om + b_ps);
+  double *part = reinterpret_cast<double *>(h->lws + b_om + b_ps + b_p1);
+  hipStream_t s = h->stream;
+  launch_gauss_fill<T>(s, m * LEARN_SK_ROWS, LEARN_SEED_OMEGA, 1.0, Om);
+  launch_gauss_fill<T>(s, n * LEARN_SK_COLS, LEARN_SEED_PSI, 1.0, Ps);
+  launch_tsgemm<T, T>(s, m, Om, m, LEARN_SK_ROWS, A, lda, (int)n, 0, splits, rows, part, P1,
+                      nullptr);
+  launch_sketch_finish<T>(s, (int)n, P1, Ps, out);
+  return hipStreamSynchronize(s) == hipSuccess ? WLRA_OK : WLRA_E_HIP;
+}
+
+}  // namespace
+}  // extern "C++"
+
+int64_t wlra_mlp_param_count(int64_t n, int64_t r) {
+  if (n < 1 || r < 1 || r > n || r > LEARN_RMAX || n > WLRA_NMAX + WLRA_KMAX) return -1;
+  const int64_t o = n * r;
+  return (int64_t)LEARN_HID * LEARN_D_IN + LEARN_HID + (int64_t)LEARN_HID * LEARN_HID +
+         LEARN_HID + o * LEARN_HID + o;
+}
+
+int wlra_mlp_init(wlra_handle h, float *params, int64_t n, int64_t r, uint64_t seed) {
+  if (h == nullptr || params == nullptr || wlra_mlp_param_count(n, r) < 0) return WLRA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+  const int64_t o = n * r;
+  float *W1, *b1, *W2, *b2, *W3, *b3;
+  mlp_offsets<float>(params, o, &W1, &b1, &W2, &b2, &W3, &b3);
+  hipStream_t s = h->stream;
+  launch_gauss_fill<float>(s, (int64_t)LEARN_HID * LEARN_D_IN, seed + 1, sqrt(2.0 / LEARN_D_IN), W1);
+  launch_fill_zero(s, LEARN_HID, b1);
+  launch_gauss_fill<float>(s, (int64_t)LEARN_HID * LEARN_HID, seed + 2, sqrt(2.0 / LEARN_HID), W2);
+  launch_fill_zero(s, LEARN_HID, b2);
+  launch_gauss_fill<float>(s, o * LEARN_HID, seed + 3, sqrt(2.0 / LEARN_HID), W3);
+  launch_fill_zero(s, o, b3);
+  return hipStreamSynchronize(s) == hipSuccess ? WLRA_OK : WLRA_E_HIP;
+}
+
+int wlra_sketch(wlra_handle h, int64_t m, int64_t n, const void *A, int64_t lda, float *out) {
+  if (h == nullptr || A == nullptr || out == nullptr || m < 1 || n < 1 || lda < m)
+    return WLRA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+  if (h->precision == WLRA_FP64)
+    return sketch_impl<double>(h, m, n, static_cast<const double *>(A), lda, out);
+  return sketch_impl<float>(h, m, n, static_cast<const float *>(A), lda, out);
+}
+
+int wlra_mlp_forward(wlra_handle h, const float *params, int64_t n, int64_t r, int32_t batch,
+                     const float *X, float *Y) {
+  if (h == nullptr || params == nullptr || X == nullptr || Y == nullptr || batch < 1 ||
+      wlra_mlp_param_count(n, r) < 0)
+    return WLRA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+  const int64_t o = n * r;
+  const size_t bh = al256((size_t)batch * LEARN_HID * sizeof(float));
+  int rc = ensure_lws(h, 2 * bh);
+  if (rc != WLRA_OK) return rc;
+  float *h1 = reinterpret_cast<float *>(h->lws), *h2 = reinterpret_cast<float *>(h->lws + bh);
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+  mlp_offsets<const float>(params, o, &W1, &b1, &W2, &b2, &W3, &b3);
+  hipStream_t s = h->stream;
+  launch_gemm(s, 0, batch, LEARN_HID, LEARN_D_IN, X, LEARN_D_IN, W1, LEARN_D_IN, h1, LEARN_HID,
+              b1, 1, nullptr, 0);
+  launch_gemm(s, 0, batch, LEARN_HID, LEARN_HID, h1, LEARN_HID, W2, LEARN_HID, h2, LEARN_HID, b2,
+              1, nullptr, 0);
+  launch_gemm(s, 0, batch, (int)o, LEARN_HID, h2, LEARN_HID, W3, LEARN_HID, Y, (int)o, b3, 0,
+              nullptr, 0);
+  return hipStreamSynchronize(s) == hipSuccess ? WLRA_OK : WLRA_E_HIP;
+}
+
+int wlra_mlp_train_step(wlra_handle h, float *params, float *adam_m, float *adam_v,
+                        int32_t step, int64_t n, int64_t r, int32_t batch, const float *X,
+                        const float *T, double lr, double *loss, float *grad_out) {
+  const int64_t P = wlra_mlp_param_count(n, r);
+  if (h == nullptr || params == nullptr || X == nullptr || T == nullptr || batch < 1 ||
+      batch > 65535 || P < 0 || (step > 0 && (adam_m == nullptr || adam_v == nullptr)))
+    return WLRA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+  const int64_t o = n * r;
+  const int B = batch;
+  const size_t bh = al256((size_t)B * LEARN_HID * sizeof(float));
+  const size_t bo = al256((size_t)B * o * sizeof(float));
+  const size_t bp = al256((size_t)P * sizeof(float));
+  const size_t bl = al256((size_t)B * sizeof(double));
+  int rc = ensure_lws(h, 4 * bh + 2 * bo + bp + bl + 256);
+  if (rc != WLRA_OK) return rc;
+  char *w = h->lws;
+  float *h1 = reinterpret_cast<float *>(w), *h2 = reinterpret_cast<float *>(w + bh);
+  float *gh2 = reinterpret_cast<float *>(w + 2 * bh), *gh1 = reinterpret_cast<float *>(w + 3 * bh);
+  float *y = reinterpret_cast<float *>(w + 4 * bh);
+  float *gy = reinterpret_cast<float *>(w + 4 * bh + bo);
+  float *g = reinterpret_cast<float *>(w + 4 * bh + 2 * bo);
+  double *lp = reinterpret_cast<double *>(w + 4 * bh + 2 * bo + bp);
+  int *dflag = reinterpret_cast<int *>(w + 4 * bh + 2 * bo + bp + bl);
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+  mlp_offsets<const float>(params, o, &W1, &b1, &W2, &b2, &W3, &b3);
+  float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
+  mlp_offsets<float>(g, o, &gW1, &gb1, &gW2, &gb2, &gW3, &gb3);
+  hipStream_t s = h->stream;
+  HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int), s));
+  // forward
+  launch_gemm(s, 0, B, LEARN_HID, LEARN_D_IN, X, LEARN_D_IN, W1, LEARN_D_IN, h1, LEARN_HID, b1,
+              1, nullptr, 0);
+  launch_gemm(s, 0, B, LEARN_HID, LEARN_HID, h1, LEARN_HID, W2, LEARN_HID, h2, LEARN_HID, b2, 1,
+              nullptr, 0);
+  launch_gemm(s, 0, B, (int)o, LEARN_HID, h2, LEARN_HID, W3, LEARN_HID, y, (int)o, b3, 0,
+              nullptr, 0);
+  // loss and its gradient with respect to the output
+  launch_subspace_loss(s, (int)n, (int)r, B, y, T, 1.0, gy, lp, dflag);
+  // backward
+  launch_gemm(s, 2, (int)o, LEARN_HID, B, gy, (int)o, h2, LEARN_HID, gW3, LEARN_HID, nullptr, 0,
+              nullptr, 0);
+  launch_colsum(s, B, (int)o, gy, gb3);
+  launch_gemm(s, 1, B, LEARN_HID, (int)o, gy, (int)o, W3, LEARN_HID, gh2, LEARN_HID, nullptr, 0,
+              h2, LEARN_HID);
+  launch_gemm(s, 2, LEARN_HID, LEARN_HID, B, gh2, LEARN_HID, h1, LEARN_HID, gW2, LEARN_HID,
+              nullptr, 0, nullptr, 0);
+  launch_colsum(s, B, LEARN_HID, gh2, gb2);
+  launch_gemm(s, 1, B, LEARN_HID, LEARN_HID, gh2, LEARN_HID, W2, LEARN_HID, gh1, LEARN_HID,
+              nullptr, 0, h1, LEARN_HID);
+  launch_gemm(s, 2, LEARN_HID, LEARN_D_IN, B, gh1, LEARN_HID, X, LEARN_D_IN, gW1, LEARN_D_IN,
+              nullptr, 0, nullptr, 0);
+  launch_colsum(s, B, LEARN_HID, gh1, gb1);
+  if (grad_out != nullptr)
+    HIPCHK(hipMemcpyAsync(grad_out, g, (size_t)P * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (step > 0) {
+    const double b1c = 1.0 - pow(0.9, step), b2c = 1.0 - pow(0.999, step);
+    launch_adam(s, P, params, g, adam_m, adam_v, (float)lr, 0.9f, 0.999f, 1e-8f, (float)b1c,
+                (float)b2c);
+  }
+  std::vector<double> lh((size_t)B);
+  int fl = 0;
+  HIPCHK(hipMemcpyAsync(lh.data(), lp, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&fl, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double tot = 0.0;
+  for (double v : lh) tot += v;
+  if (loss) *loss = tot / B;
+  return (fl & DEV_LEARN_FAIL) ? WLRA_E_RANK : WLRA_OK;
+}
+
 int wlra_profile(wlra_handle h, int32_t max, wlra_kstat *out, int32_t reset) {
   if (h == nullptr || max < 0 || (max > 0 && out == nullptr)) return WLRA_E_ARG;
   if (!(h->flags & WLRA_FLAG_PROFILE)) return 0;
@@ -671,6 +942,7 @@ int wlra_destroy(wlra_handle h) {
   for (hipEvent_t e : h->pool)
     if (e) hipEventDestroy(e);
   if (h->ws) hipFree(h->ws);
+  if (h->lws) hipFree(h->lws);
   if (h->st_host) hipHostFree(h->st_host);
   if (h->flags_host) hipHostFree(h->flags_host);
   if (h->ev0) hipEventDestroy(h->ev0);

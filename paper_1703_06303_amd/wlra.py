@@ -18,7 +18,8 @@ E_ARG, E_WEIGHT, E_NONFINITE, E_RANK, E_NOMEM, E_HIP, E_NODEVICE = -1, -2, -3, -
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 INIT_RANDOM, INIT_GIVEN, INIT_A1, INIT_LEARNED = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16}
-INITS = {"random": INIT_RANDOM, "given": INIT_GIVEN, "a1": INIT_A1}
+INITS = {"random": INIT_RANDOM, "given": INIT_GIVEN, "a1": INIT_A1, "learned": INIT_LEARNED}
+SKETCH_DIM = 512
 
 
 class Problem(ctypes.Structure):
@@ -33,6 +34,8 @@ class Problem(ctypes.Structure):
         ("X2_out", ctypes.c_void_p), ("ldx2", ctypes.c_int64),
         ("trace", ctypes.POINTER(ctypes.c_double)),
         ("eig_tol", ctypes.c_double),
+        ("model", ctypes.c_void_p),
+        ("factors_out", ctypes.c_void_p),
     ]
 
 
@@ -56,7 +59,8 @@ FLAG_PROFILE = 1
 
 SYMBOLS = ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
            "wlra_set_batch_lanes", "wlra_destroy", "wlra_profile", "wlra_validate",
-           "wlra_strerror", "wlra_version")
+           "wlra_strerror", "wlra_version", "wlra_mlp_param_count", "wlra_mlp_init",
+           "wlra_sketch", "wlra_mlp_forward", "wlra_mlp_train_step")
 
 _lib = None
 
@@ -83,6 +87,16 @@ def load(path: str = LIB_PATH):
     lib.wlra_strerror.argtypes = [ctypes.c_int]
     lib.wlra_strerror.restype = ctypes.c_char_p
     lib.wlra_version.argtypes = []
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.wlra_mlp_param_count.argtypes = [i64, i64]
+    lib.wlra_mlp_param_count.restype = i64
+    lib.wlra_mlp_init.argtypes = [vp, vp, i64, i64, ctypes.c_uint64]
+    lib.wlra_sketch.argtypes = [vp, i64, i64, vp, i64, vp]
+    lib.wlra_mlp_forward.argtypes = [vp, vp, i64, i64, i32, vp, vp]
+    lib.wlra_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, i64, i64, i32, vp, vp,
+                                        ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+    for name in ("wlra_mlp_init", "wlra_sketch", "wlra_mlp_forward", "wlra_mlp_train_step"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
                  "wlra_set_batch_lanes", "wlra_destroy", "wlra_profile", "wlra_validate",
                  "wlra_version"):
@@ -110,8 +124,22 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def mlp_param_count(n, r):
+    """Number of parameters of the warm-start network for (n, r)."""
+    c = load().wlra_mlp_param_count(int(n), int(r))
+    if c < 0:
+        raise WlraError(E_ARG)
+    return int(c)
+
+
+def factors_size(n, k, r):
+    n2, l = n - k, r - k
+    return k * k + k * n2 + n2 * l + l
+
+
 def make_problem(A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init="random",
-                 seed=0, X1_init=None, X1_out=None, X2_out=None, trace=None, eig_tol=0.0):
+                 seed=0, X1_init=None, X1_out=None, X2_out=None, trace=None, eig_tol=0.0,
+                 model=None, factors_out=None):
     """Fill a Problem from tensors (column-major device tensors or None)."""
     m, n = A.shape
     p = Problem()
@@ -132,6 +160,8 @@ def make_problem(A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init=
     p.ldx2 = X2_out.stride(1) if (X2_out is not None and X2_out.shape[1] > 1) else m
     p.trace = trace if trace is not None else ctypes.POINTER(ctypes.c_double)()
     p.eig_tol = float(eig_tol)
+    p.model = _ptr(model)
+    p.factors_out = _ptr(factors_out)
     return p
 
 
@@ -185,18 +215,24 @@ class Solver:
             raise WlraError(rc)
 
     def solve(self, A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init="random",
-              seed=0, X1_init=None, want_x2=False, want_trace=False, eig_tol=0.0, raise_on_error=True):
+              seed=0, X1_init=None, want_x2=False, want_trace=False, eig_tol=0.0, raise_on_error=True,
+              model=None, want_factors=False):
         """Solve problem (5).  A, W1, X1_init: column-major device tensors of
-        the handle's dtype.  Returns (X1, X2 or None, result dict)."""
+        the handle's dtype; model: float32 device tensor of network parameters
+        (init="learned").  Returns (X1, X2 or None, result dict); with
+        want_factors the dict holds "factors" = (R, C, V, theta) as float64
+        device tensors."""
         import torch
         m, n = A.shape
+        fac = (torch.empty(factors_size(n, k, r), dtype=torch.float64, device=A.device)
+               if want_factors else None)
         X1 = colmajor(torch.empty((m, k), dtype=self.dtype, device=A.device))
         X2 = colmajor(torch.empty((m, n - k), dtype=self.dtype, device=A.device)) if want_x2 else None
         tr = (ctypes.c_double * (2 * (max_sweeps + 1)))() if want_trace else None
         p = make_problem(A, k, r, W1=W1, w1_const=w1_const, tol=tol, max_sweeps=max_sweeps,
                          init=init, seed=seed, X1_init=X1_init, X1_out=X1, X2_out=X2,
                          trace=ctypes.cast(tr, ctypes.POINTER(ctypes.c_double)) if tr is not None else None,
-                         eig_tol=eig_tol)
+                         eig_tol=eig_tol, model=model, factors_out=fac)
         res = Result()
         rc = self.lib.wlra_solve(self.h, ctypes.byref(p), ctypes.byref(res))
         if rc < 0 and raise_on_error:
@@ -206,7 +242,49 @@ class Solver:
         if tr is not None:
             out["trace_F"] = list(tr[:max_sweeps + 1])
             out["trace_err"] = list(tr[max_sweeps + 1:])
+        if fac is not None:
+            n2, l = n - k, r - k
+            o1, o2, o3 = k * k, k * k + k * n2, k * k + k * n2 + n2 * l
+            out["factors"] = (fac[:o1].view(k, k).t(), fac[o1:o2].view(n2, k).t(),
+                              fac[o2:o3].view(l, n2).t(), fac[o3:])
         return X1, X2, out
+
+    # -- learned warm start -------------------------------------------------
+    def _chk(self, rc):
+        if rc != OK:
+            raise WlraError(rc)
+
+    def mlp_init(self, params, n, r, seed):
+        self._chk(self.lib.wlra_mlp_init(self.h, _ptr(params), n, r, seed))
+
+    def sketch(self, A):
+        """512-float sketch of a column-major device matrix A."""
+        import torch
+        m, n = A.shape
+        out = torch.empty(SKETCH_DIM, dtype=torch.float32, device=A.device)
+        lda = A.stride(1) if n > 1 else m
+        self._chk(self.lib.wlra_sketch(self.h, m, n, _ptr(A), lda, _ptr(out)))
+        return out
+
+    def mlp_forward(self, params, n, r, X):
+        import torch
+        Y = torch.empty((X.shape[0], n * r), dtype=torch.float32, device=X.device)
+        self._chk(self.lib.wlra_mlp_forward(self.h, _ptr(params), n, r, X.shape[0],
+                                            _ptr(X.contiguous()), _ptr(Y)))
+        return Y
+
+    def mlp_train_step(self, params, adam_m, adam_v, step, n, r, X, T, lr, want_grad=False):
+        """One training step (step <= 0: loss and gradient only).  X: B x 512,
+        T: B x (n r) targets (each n x r column-major).  Returns (loss, grad)."""
+        import torch
+        loss = ctypes.c_double()
+        g = torch.empty_like(params) if want_grad else None
+        rc = self.lib.wlra_mlp_train_step(self.h, _ptr(params), _ptr(adam_m), _ptr(adam_v), step,
+                                          n, r, X.shape[0], _ptr(X.contiguous()),
+                                          _ptr(T.contiguous()), float(lr), ctypes.byref(loss),
+                                          _ptr(g))
+        self._chk(rc)
+        return loss.value, g
 
     def set_batch_lanes(self, lanes):
         rc = self.lib.wlra_set_batch_lanes(self.h, int(lanes))

@@ -18,7 +18,7 @@ def rel(X, Y):
 
 
 def gpu_solve(solver, inst, tol, max_sweeps, init="given", dense_w=None, want_x2=True,
-              want_trace=False, eig_tol=0.0, A=None):
+              want_trace=False, eig_tol=0.0, A=None, model=None, want_factors=False, seed=0):
     """Run one instance through the C ABI.  dense_w: pass W1 as a matrix
     (default: a matrix unless the instance has a constant weight)."""
     dt = solver.dtype
@@ -31,7 +31,8 @@ def gpu_solve(solver, inst, tol, max_sweeps, init="given", dense_w=None, want_x2
     X1, X2, res = solver.solve(Ad, inst.k, inst.r, W1=W1, w1_const=inst.w1_const or 1.0,
                                tol=tol, max_sweeps=max_sweeps, init=init, X1_init=X0,
                                want_x2=want_x2, want_trace=want_trace, eig_tol=eig_tol,
-                               raise_on_error=False)
+                               raise_on_error=False, model=model, want_factors=want_factors,
+                               seed=seed)
     return host(X1), (host(X2) if X2 is not None else None), res
 
 

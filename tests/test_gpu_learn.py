@@ -1,0 +1,132 @@
+"""The learned warm start on the GPU through the C ABI, against the FP64
+oracle of oracle/learn.py: sketch, network start, forward pass, loss and
+gradient, Adam step, decode of X1_0 inside a solve, the random-start
+fallback, and the solution factors the training targets are built from."""
+import numpy as np
+import pytest
+
+from gen import video
+from oracle import learn as L
+from oracle import swlr as O
+
+from .gpu_util import dev, gpu_solve, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def s64():
+    from paper_1703_06303_amd.wlra import Solver
+    return Solver("fp64")
+
+
+@pytest.fixture(scope="module")
+def s32():
+    from paper_1703_06303_amd.wlra import Solver
+    return Solver("fp32")
+
+
+def _inst(seed=3, m_hw=(20, 24), n=40, k=6, r=9, dtype=np.float64):
+    return video.make_instance(m_hw[0], m_hw[1], n, k, r, 2, fg="blobs",
+                               w1=("loguniform", 1.0, 3.0), seed=seed, dtype=dtype)
+
+
+def _params_gpu(n, r, seed):
+    import torch
+    from paper_1703_06303_amd.wlra import mlp_param_count
+    return torch.empty(mlp_param_count(n, r), dtype=torch.float32, device="cuda")
+
+
+def test_sketch_matches_oracle(s64, s32):
+    inst = _inst()
+    ref = L.sketch(inst.A)
+    got64 = host(s64.sketch(dev(inst.A, s64.dtype)))
+    got32 = host(s32.sketch(dev(inst.A, s32.dtype)))
+    assert np.abs(got64 - ref).max() <= 1e-6      # rounded to float on output
+    assert np.abs(got32 - ref).max() <= 1e-5
+
+
+def test_network_start_matches_oracle(s32):
+    n, r = 40, 9
+    p = _params_gpu(n, r, 0)
+    s32.mlp_init(p, n, r, 77)
+    ref = L.init_params(n, r, 77)
+    assert np.allclose(host(p), ref, rtol=1e-6, atol=1e-7)
+
+
+def test_forward_loss_gradient_and_adam_match_oracle(s32):
+    import torch
+    n, r, B = 40, 9, 6
+    rng = np.random.default_rng(1)
+    p64 = L.init_params(n, r, 5)
+    p64 = p64 + 0.01 * rng.standard_normal(p64.shape)   # non-zero biases too
+    p = torch.tensor(p64, dtype=torch.float32, device="cuda")
+    p64 = host(p)                                         # the float32 values both sides use
+    X = rng.standard_normal((B, L.D_IN))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    T = rng.standard_normal((B, n, r))
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    X = host(Xd)
+    Td = torch.tensor(np.stack([t.reshape(-1, order="F") for t in T]), dtype=torch.float32,
+                      device="cuda")
+    T = np.stack([t.reshape(n, r, order="F") for t in host(Td)])
+    y_ref, cache = L.forward(p64, X, n, r)
+    y = host(s32.mlp_forward(p, n, r, Xd))
+    assert rel(y, y_ref) <= 1e-5
+    loss_ref, gy = L.loss_and_grad_y(y_ref, T, n, r)
+    g_ref = L.backward(p64, cache, gy, n, r)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    loss, g = s32.mlp_train_step(p, m, v, 0, n, r, Xd, Td, 1e-3, want_grad=True)
+    assert loss == pytest.approx(loss_ref, rel=1e-5)
+    assert rel(host(g), g_ref) <= 1e-4
+    # one Adam step from zero moments
+    loss1, _ = s32.mlp_train_step(p, m, v, 1, n, r, Xd, Td, 1e-3)
+    p_ref, _, _ = L.adam_step(p64, host(g), np.zeros_like(p64), np.zeros_like(p64), 1, 1e-3)
+    assert np.allclose(host(p), p_ref, rtol=1e-5, atol=2e-6)
+
+
+def test_learned_start_decode_matches_oracle(s64):
+    """With max_sweeps = 0 the returned X1 is the start X1_0 itself."""
+    import torch
+    inst = _inst(seed=9)
+    n, r, k = inst.n, inst.r, inst.k
+    p = _params_gpu(n, r, 0)
+    s64.mlp_init(p, n, r, 31)
+    params = host(p)
+    y, _ = L.forward(params, L.sketch(inst.A)[None, :], n, r)
+    X1_ref = L.decode(inst.A, k, y[0].reshape(n, r, order="F"))
+    X1, _, res = gpu_solve(s64, inst, 0.0, 0, init="learned", want_x2=False, model=p)
+    print("learned start", res, flush=True)
+    assert rel(X1, X1_ref) <= 1e-4
+    # and the sweep from it is Algorithm 1 from that start
+    X1s, X2s, res = gpu_solve(s64, inst, 0.0, 3, init="learned", model=p)
+    ref = O.swlr(inst.A, inst.W1, k, r, tol=0.0, max_sweeps=3, X1_0=X1)
+    assert rel(np.hstack([X1s, X2s]), ref.X) <= 1e-9
+
+
+def test_learned_start_falls_back_to_random(s64):
+    """A network whose output is zero gives L0 = 0: the decode fails and the
+    random start keyed by the same seed is used."""
+    import torch
+    inst = _inst(seed=4)
+    p = torch.zeros(_params_gpu(inst.n, inst.r, 0).shape, dtype=torch.float32, device="cuda")
+    X1a, X2a, ra = gpu_solve(s64, inst, 0.0, 3, init="learned", model=p, seed=12)
+    X1b, X2b, rb = gpu_solve(s64, inst, 0.0, 3, init="random", seed=12)
+    assert np.array_equal(X1a, X1b) and np.array_equal(X2a, X2b)
+
+
+def test_factors_match_oracle(s64):
+    inst = _inst(seed=6)
+    k, r = inst.k, inst.r
+    ref = O.swlr(inst.A, inst.W1, k, r, tol=0.0, max_sweeps=4, X1_0=inst.X1_0)
+    _, _, res = gpu_solve(s64, inst, 0.0, 4, want_factors=True)
+    R, C, V, th = (host(t) for t in res["factors"])
+    assert rel(C, ref.C) <= 1e-10
+    assert np.allclose(np.triu(R), R) and rel(R.T @ R, ref.X1.T @ ref.X1) <= 1e-12
+    assert rel(V @ V.T, ref.V @ ref.V.T) <= 1e-9
+    assert np.allclose(th, ref.sigma[:r - k] ** 2, rtol=1e-10)
+    # the target basis spans the solution's rows
+    Q = L.orthonormal(L.target_basis(C, V, k, r))
+    X = ref.X
+    assert np.linalg.norm(X - (X @ Q) @ Q.T) <= 1e-9 * np.linalg.norm(X)
