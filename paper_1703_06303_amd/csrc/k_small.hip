@@ -5,7 +5,7 @@
 //            eigenpairs give D = H_{r-k}(P^perp A2) (steps 4 and 6)
 //   k_post   S = C C^T, T = (CV)(CV)^T, Z = (I - VV^T) C^T for the row pass
 //            (step 7) and the objective F(X_p)
-//   k_decide Error_p of Section 4.1 (from the exact row pass k_change) and
+//   k_decide Error_p of Section 4.1 (from the row pass k_change_q) and
 //            the stopping decision.
 // One workgroup each except k_formM.
 #include "common.h"
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
 //   Error_p = ||X_p - X_{p-1}||_F,  stop when Error_p < tol or
 //   Error_p / ||X_{p-1}||_F < tol, or when p = max_sweeps.
 // ||X1_p - X1_{p-1}||^2 comes from the row update (dx1), ||X2_p - X2_{p-1}||^2
-// from the row pass k_change (partials in chg_part).
+// from the row pass k_change_q (partials in chg_part).
 __global__ __launch_bounds__(256) void k_decide(SmallArgs a) {
   SmallState *st = a.st;
   if (st->done) return;

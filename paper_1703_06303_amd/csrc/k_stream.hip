@@ -570,125 +570,247 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
 }
 
 // ---------------------------------------------------------------------------
-// Error_p of Section 4.1, unweighted block: ||X2_p - X2_{p-1}||_F^2 summed
-// row by row in double, with x2_i = a2_i V V^T + x1_i Z^T for both sweeps.
-// Each row difference is formed directly, so no large Gram terms cancel and
-// changes far below sqrt(eps) ||X|| stay resolved.  Zp/Zq: n2 x k, Vp/Vq:
-// n2 x l, all row-major double.  A workgroup owns 64 rows; its CHG_NW
-// wavefronts first split the n2 columns to form u = a2 [V_p V_q] (summed
-// through LDS), then split them again for the row differences.  One partial
-// per workgroup.
-#define CHG_NW 4
-#define CHG_STAGE 12288  // doubles of [V_p V_q Z_p Z_q] rows staged per chunk
-template <typename T, int KMAX, int LMAX, typename TA2>
-__global__ __launch_bounds__(64 * CHG_NW) void k_change(
+// Error_p through a Gram of aligned differences.  Row i of X2_p - X2_{p-1} is
+//     d_i = a2_i (V_p V_p^T - V_q V_q^T) + x1p_i Z_p^T - x1q_i Z_q^T.
+// V_q is first rotated onto V_p: V_q' = V_q O with O the orthogonal polar
+// factor of V_q^T V_p (this leaves V_q V_q^T, hence X2_{p-1}, unchanged and
+// undoes sign flips, swaps and rotations of near-equal eigenvectors).  With
+// dV = V_q' - V_p and dZ = Z_q - Z_p,
+//     d_i = g_i H^T,  H = [V_p, dV, Z_p, dZ],
+//     g_i = [-a2_i dV, -a2_i V_q', x1p_i - x1q_i, -x1q_i],
+// and every product g_ia H_ja is of the size of d_i itself (one factor of
+// each pair is a difference), so ||d_i||^2 = g_i (H^T H) g_i^T loses only a
+// few ulps of ||d_i||^2 -- unlike a Gram of the undifferenced basis, whose
+// terms are ||x2_i||^2 in size.
+//
+// k_chgprep (one workgroup): O by Newton-Schulz iteration from V_q^T V_p,
+// made exactly orthogonal by two-pass Gram-Schmidt (a column that vanishes
+// is replaced by the unit vector farthest from the span of the others), and
+// H column-major into Hb (n2 x K, K = 2l + 2k).  Kg = H^T H (K x K) is then
+// formed by the tall-skinny product kernel.
+#define QR_T 512
+#define CHG_NW 4  // wavefronts per workgroup of the change row pass
+__global__ __launch_bounds__(QR_T) void k_chgprep(int n2, int k, int l,
+                                                  const double *__restrict__ Vp,
+                                                  const double *__restrict__ Vq,
+                                                  const double *__restrict__ Zp,
+                                                  const double *__restrict__ Zq,
+                                                  double *__restrict__ Hb, double *__restrict__ Kg,
+                                                  const SmallState *__restrict__ st) {
+  if (st->done || !st->have_prev) return;
+  __shared__ double X[WLRA_BMAX * WLRA_BMAX];
+  __shared__ double E[WLRA_BMAX * WLRA_BMAX];
+  __shared__ double red[QR_T / 64];
+  __shared__ double nrm[2];
+  const int K = 2 * l + 2 * k, t = threadIdx.x;
+  const int lane = t & 63;
+  const int B_ = WLRA_BMAX;
+  if (l > 0) {
+    // X = V_q^T V_p: a wavefront per entry, lanes over the rows
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    for (int e = wv; e < l * l; e += QR_T / 64) {
+      const int a = e % l, b = e / l;
+      double sacc = 0.0;
+      for (int i = lane; i < n2; i += 64)
+        sacc = fma(Vq[(int64_t)i * l + a], Vp[(int64_t)i * l + b], sacc);
+      sacc = wave_sum(sacc);
+      if (lane == 0) X[a + b * B_] = sacc;
+    }
+    __syncthreads();
+    // Newton-Schulz: X <- X (3 I - X^T X) / 2 until X^T X = I to rounding
+    for (int it = 0; it < 60; ++it) {
+      double dev = 0.0;
+      for (int e = t; e < l * l; e += QR_T) {
+        const int a = e % l, b = e / l;
+        double sacc = 0.0;
+        for (int q = 0; q < l; ++q) sacc = fma(X[q + a * B_], X[q + b * B_], sacc);
+        E[a + b * B_] = sacc;
+        const double d = sacc - (a == b ? 1.0 : 0.0);
+        dev = fma(d, d, dev);
+      }
+      dev = block_sum(dev, red);  // includes the barrier before E is read
+      if (!(dev > 1e-28)) break;
+      double xn[2];
+      int cnt = 0;
+      for (int e = t; e < l * l; e += QR_T) {
+        const int a = e % l, b = e / l;
+        double sacc = 0.0;
+        for (int q = 0; q < l; ++q) sacc = fma(X[a + q * B_], (q == b ? 3.0 : 0.0) - E[q + b * B_], sacc);
+        xn[cnt++] = 0.5 * sacc;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int e = t; e < l * l; e += QR_T) X[(e % l) + (e / l) * B_] = xn[cnt++];
+      __syncthreads();
+    }
+    // two-pass Gram-Schmidt on the columns of X (wavefront 0)
+    if (t < 64) {
+      for (int c = 0; c < l; ++c) {
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int q = 0; q < c; ++q) {
+            double dq = (lane < l) ? X[lane + q * B_] * X[lane + c * B_] : 0.0;
+            dq = wave_sum(dq);
+            if (lane < l) X[lane + c * B_] -= dq * X[lane + q * B_];
+            wave_sync();
+          }
+        }
+        double nn = (lane < l) ? X[lane + c * B_] * X[lane + c * B_] : 0.0;
+        nn = wave_sum(nn);
+        if (!(nn > 1e-20)) {
+          // replace by the unit vector with the largest residual
+          int best = 0;
+          double bres = -1.0;
+          for (int u = 0; u < l; ++u) {
+            double res = 1.0;
+            for (int q = 0; q < c; ++q) res -= X[u + q * B_] * X[u + q * B_];
+            if (res > bres) {
+              bres = res;
+              best = u;
+            }
+          }
+          if (lane < l) X[lane + c * B_] = (lane == best) ? 1.0 : 0.0;
+          wave_sync();
+          for (int pass = 0; pass < 2; ++pass)
+            for (int q = 0; q < c; ++q) {
+              double dq = (lane < l) ? X[lane + q * B_] * X[lane + c * B_] : 0.0;
+              dq = wave_sum(dq);
+              if (lane < l) X[lane + c * B_] -= dq * X[lane + q * B_];
+              wave_sync();
+            }
+          nn = (lane < l) ? X[lane + c * B_] * X[lane + c * B_] : 0.0;
+          nn = wave_sum(nn);
+        }
+        const double inv = 1.0 / sqrt(nn);
+        if (lane < l) X[lane + c * B_] *= inv;
+        wave_sync();
+      }
+    }
+    __syncthreads();
+  }
+  // H = [V_p, V_q O - V_p, Z_p, Z_q - Z_p], column-major n2 x K
+  for (int64_t e = t; e < (int64_t)n2 * K; e += QR_T) {
+    const int i = (int)(e % n2), c = (int)(e / n2);
+    double v;
+    if (c < l) {
+      v = Vp[(int64_t)i * l + c];
+    } else if (c < 2 * l) {
+      const int b = c - l;
+      double sacc = 0.0;
+      for (int a = 0; a < l; ++a) sacc = fma(Vq[(int64_t)i * l + a], X[a + b * B_], sacc);
+      v = sacc - Vp[(int64_t)i * l + b];
+    } else if (c < 2 * l + k) {
+      v = Zp[(int64_t)i * k + (c - 2 * l)];
+    } else {
+      const int b = c - 2 * l - k;
+      v = Zq[(int64_t)i * k + b] - Zp[(int64_t)i * k + b];
+    }
+    Hb[e] = v;
+  }
+  (void)nrm;
+  (void)Kg;
+}
+
+// Row pass: u_p = a2 V_p and u_d = a2 dV (wavefronts split the n2 columns,
+// rows of [V_p dV] staged through LDS from H, fixed-order sum); then g per
+// lane in LDS and g Kg g^T with the rows of Kg split between the wavefronts
+// (Kg read with uniform loads).  One partial per workgroup.
+template <typename T, int LMAX, typename TA2>
+__global__ __launch_bounds__(64 * CHG_NW) void k_change_q(
     int64_t m, int k, int n2, int l, const TA2 *__restrict__ A2, int64_t lda,
-    const T *__restrict__ X1p, const T *__restrict__ X1q, const double *__restrict__ Zp,
-    const double *__restrict__ Zq, const double *__restrict__ Vp, const double *__restrict__ Vq,
-    double *__restrict__ part, const SmallState *__restrict__ st) {
+    const T *__restrict__ X1p, const T *__restrict__ X1q, const double *__restrict__ Hb,
+    const double *__restrict__ Kg, int stage_rows, double *__restrict__ part,
+    const SmallState *__restrict__ st) {
   if (st->done) return;
-  __shared__ double sR[CHG_STAGE];
-  __shared__ double su[2 * LMAX * 64];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *sR = reinterpret_cast<double *>(smem_raw);   // staged [V_p dV] rows, later g
+  double *su = sR + (size_t)max(stage_rows * 2 * l, (2 * l + 2 * k) * 64);
   __shared__ double sacc[CHG_NW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const bool act = i < m;
   const int64_t ir = act ? i : (m - 1);
-  const int rw = 2 * l + 2 * k;                 // staged row: [vp | vq | zp | zq]
-  const int crow = max(1, CHG_STAGE / max(rw, 1));
-  auto stage = [&](int c0, int c1) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < (c1 - c0) * rw; e += 64 * CHG_NW) {
-      const int r = e / rw, q = e - r * rw, j = c0 + r;
-      double v;
-      if (q < l) v = Vp[(int64_t)j * l + q];
-      else if (q < 2 * l) v = Vq[(int64_t)j * l + (q - l)];
-      else if (q < 2 * l + k) v = Zp[(int64_t)j * k + (q - 2 * l)];
-      else v = Zq[(int64_t)j * k + (q - 2 * l - k)];
-      sR[e] = v;
-    }
-    __syncthreads();
-  };
-  // phase 1: u = a2 [V_p V_q], slices of the columns per wavefront
-  double up[LMAX], uq[LMAX];
+  const int rw = 2 * l, K = 2 * l + 2 * k;
+  double up[LMAX], ud[LMAX];
 #pragma unroll
-  for (int q = 0; q < LMAX; ++q) up[q] = uq[q] = 0.0;
-  for (int c0 = 0; c0 < n2; c0 += crow) {
-    const int c1 = min(n2, c0 + crow), len = c1 - c0;
-    stage(c0, c1);
-    const int j0 = c0 + w * len / CHG_NW, j1 = c0 + (w + 1) * len / CHG_NW;
-    int j = j0;
-    for (; j + 8 <= j1; j += 8) {
-      double v[8];
+  for (int q = 0; q < LMAX; ++q) up[q] = ud[q] = 0.0;
+  if (l > 0) {
+    for (int c0 = 0; c0 < n2; c0 += stage_rows) {
+      const int c1 = min(n2, c0 + stage_rows), len = c1 - c0;
+      __syncthreads();
+      for (int e = threadIdx.x; e < len * rw; e += 64 * CHG_NW) {
+        const int r = e / rw, q = e - r * rw, j = c0 + r;
+        sR[e] = Hb[j + (int64_t)q * n2];  // columns 0..2l-1 of H: [V_p dV]
+      }
+      __syncthreads();
+      const int j0 = c0 + w * len / CHG_NW, j1 = c0 + (w + 1) * len / CHG_NW;
+      int j = j0;
+      for (; j + 8 <= j1; j += 8) {
+        double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (double)to_f(A2[ir + (int64_t)(j + u) * lda]);
+        for (int u = 0; u < 8; ++u) v[u] = (double)to_f(A2[ir + (int64_t)(j + u) * lda]);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double *rr = sR + (j + u - c0) * rw;
+        for (int u = 0; u < 8; ++u) {
+          const double *rr = sR + (j + u - c0) * rw;
+#pragma unroll
+          for (int q = 0; q < LMAX; ++q)
+            if (q < l) {
+              up[q] = fma(v[u], rr[q], up[q]);
+              ud[q] = fma(v[u], rr[l + q], ud[q]);
+            }
+        }
+      }
+      for (; j < j1; ++j) {
+        const double v = (double)to_f(A2[ir + (int64_t)j * lda]);
+        const double *rr = sR + (j - c0) * rw;
 #pragma unroll
         for (int q = 0; q < LMAX; ++q)
           if (q < l) {
-            up[q] = fma(v[u], rr[q], up[q]);
-            uq[q] = fma(v[u], rr[l + q], uq[q]);
+            up[q] = fma(v, rr[q], up[q]);
+            ud[q] = fma(v, rr[l + q], ud[q]);
           }
       }
     }
-    for (; j < j1; ++j) {
-      const double v = (double)to_f(A2[ir + (int64_t)j * lda]);
-      const double *rr = sR + (j - c0) * rw;
+    // fixed-order sum of the wavefront slices
+    for (int ww = 0; ww < CHG_NW; ++ww) {
+      __syncthreads();
+      if (w == ww) {
 #pragma unroll
-      for (int q = 0; q < LMAX; ++q)
-        if (q < l) {
-          up[q] = fma(v, rr[q], up[q]);
-          uq[q] = fma(v, rr[l + q], uq[q]);
-        }
-    }
-  }
-  // fixed-order sum of the slices, then every wavefront takes the total
-  for (int ww = 0; ww < CHG_NW; ++ww) {
-    __syncthreads();
-    if (w == ww) {
-#pragma unroll
-      for (int q = 0; q < LMAX; ++q)
-        if (q < l) {
-          const double a0 = (ww == 0) ? 0.0 : su[q * 64 + lane];
-          const double b0 = (ww == 0) ? 0.0 : su[(LMAX + q) * 64 + lane];
-          su[q * 64 + lane] = a0 + up[q];
-          su[(LMAX + q) * 64 + lane] = b0 + uq[q];
-        }
+        for (int q = 0; q < LMAX; ++q)
+          if (q < l) {
+            const double a0 = (ww == 0) ? 0.0 : su[q * 64 + lane];
+            const double b0 = (ww == 0) ? 0.0 : su[(LMAX + q) * 64 + lane];
+            su[q * 64 + lane] = a0 + up[q];
+            su[(LMAX + q) * 64 + lane] = b0 + ud[q];
+          }
+      }
     }
   }
   __syncthreads();
+  // g = [-u_d, -(u_p + u_d), x1p - x1q, -x1q] per lane, column-major over lanes
+  if (w == 0) {
 #pragma unroll
-  for (int q = 0; q < LMAX; ++q)
-    if (q < l) {
-      up[q] = su[q * 64 + lane];
-      uq[q] = su[(LMAX + q) * 64 + lane];
-    }
-  double xp[KMAX], xq[KMAX];
-#pragma unroll
-  for (int c = 0; c < KMAX; ++c) {
-    xp[c] = (c < k) ? (double)X1p[ir + (int64_t)c * m] : 0.0;
-    xq[c] = (c < k) ? (double)X1q[ir + (int64_t)c * m] : 0.0;
+    for (int q = 0; q < LMAX; ++q)
+      if (q < l) {
+        const double pu = su[q * 64 + lane], du = su[(LMAX + q) * 64 + lane];
+        sR[q * 64 + lane] = -du;
+        sR[(l + q) * 64 + lane] = -(pu + du);
+      }
   }
-  // phase 2: row differences d_ij for the wavefront's columns
+  for (int c = w; c < k; c += CHG_NW) {
+    const double xp = (double)X1p[ir + (int64_t)c * m], xq = (double)X1q[ir + (int64_t)c * m];
+    sR[(2 * l + c) * 64 + lane] = xp - xq;
+    sR[(2 * l + k + c) * 64 + lane] = -xq;
+  }
+  __syncthreads();
+  // g Kg g^T = sum_a g_a (Kg_aa g_a + 2 sum_{b > a} Kg_ab g_b)
   double acc = 0.0;
-  for (int c0 = 0; c0 < n2; c0 += crow) {
-    const int c1 = min(n2, c0 + crow), len = c1 - c0;
-    if (!(c0 == 0 && c1 == n2)) stage(c0, c1);  // one chunk: still staged
-    const int j0 = c0 + w * len / CHG_NW, j1 = c0 + (w + 1) * len / CHG_NW;
-    for (int j = j0; j < j1; ++j) {
-      const double *rr = sR + (j - c0) * rw;
-      double d = 0.0;
-#pragma unroll
-      for (int q = 0; q < LMAX; ++q)
-        if (q < l) d = fma(up[q], rr[q], fma(-uq[q], rr[l + q], d));
-#pragma unroll
-      for (int c = 0; c < KMAX; ++c)
-        if (c < k) d = fma(xp[c], rr[2 * l + c], fma(-xq[c], rr[2 * l + k + c], d));
-      acc = fma(d, d, acc);
-    }
+  for (int a = w; a < K; a += CHG_NW) {
+    const double *ka = Kg + (int64_t)a * K;
+    const double ga = sR[a * 64 + lane];
+    double h = 0.0;
+    for (int b = a + 1; b < K; ++b) h = fma(ka[b], sR[b * 64 + lane], h);
+    acc = fma(ga, fma(ka[a], ga, 2.0 * h), acc);
   }
   acc = wave_sum(act ? acc : 0.0);
   if (lane == 0) sacc[w] = acc;
@@ -696,7 +818,7 @@ __global__ __launch_bounds__(64 * CHG_NW) void k_change(
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int ww = 0; ww < CHG_NW; ++ww) t += sacc[ww];
-    part[blockIdx.x] = t;
+    part[blockIdx.x] = fmax(t, 0.0);
   }
 }
 
@@ -850,48 +972,52 @@ void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64
   else launch_x2_k<T, 64>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2);
 }
 
-template <typename T, int KMAX, typename TA2>
-static void launch_change_k(hipStream_t s, int64_t m, int k, int n2, int l, const TA2 *A2,
-                            int64_t lda2, const T *X1p, const T *X1q, const double *Zp,
-                            const double *Zq, const double *Vp, const double *Vq, double *part,
-                            const SmallState *st) {
-  const unsigned grid = (unsigned)((m + 63) / 64);
-  if (l <= 8)
-    hipLaunchKernelGGL((k_change<T, KMAX, 8, TA2>), dim3(grid), dim3(64 * CHG_NW), 0, s, m, k, n2,
-                       l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
-  else
-    hipLaunchKernelGGL((k_change<T, KMAX, WLRA_BMAX, TA2>), dim3(grid), dim3(64 * CHG_NW), 0, s, m,
-                       k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+void launch_chgprep(hipStream_t s, int n2, int k, int l, const double *Vp, const double *Vq,
+                    const double *Zp, const double *Zq, double *Hb, double *Kg, int splits,
+                    int64_t rows_per_split, double *part, const SmallState *st) {
+  hipLaunchKernelGGL(k_chgprep, dim3(1), dim3(QR_T), 0, s, n2, k, l, Vp, Vq, Zp, Zq, Hb, Kg, st);
+  const int K = 2 * l + 2 * k;
+  // Kg = H^T H; skipped with the rest of the step once the solve is done
+  launch_tsgemm<double, double>(s, n2, Hb, n2, K, Hb, n2, K, 1, splits, rows_per_split, part, Kg,
+                                &st->done);
 }
 
-template <typename T, typename TA2>
-static void launch_change_t(hipStream_t s, int64_t m, int k, int n2, int l, const TA2 *A2,
-                            int64_t lda2, const T *X1p, const T *X1q, const double *Zp,
-                            const double *Zq, const double *Vp, const double *Vq, double *part,
-                            const SmallState *st) {
-  if (k <= 8)
-    launch_change_k<T, 8, TA2>(s, m, k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
-  else if (k <= 16)
-    launch_change_k<T, 16, TA2>(s, m, k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
-  else if (k <= 32)
-    launch_change_k<T, 32, TA2>(s, m, k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
-  else
-    launch_change_k<T, 64, TA2>(s, m, k, n2, l, A2, lda2, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+template <typename T, int LMAX, typename TA2>
+static void launch_change_qr_k(hipStream_t s, int64_t m, int k, int n2, int l, const TA2 *A2,
+                               int64_t lda2, const T *X1p, const T *X1q, const double *Hb,
+                               const double *Kg, double *part, const SmallState *st) {
+  const unsigned grid = (unsigned)((m + 63) / 64);
+  const int K = 2 * l + 2 * k;
+  int rows = n2;
+  if (l > 0) rows = std::min(n2, std::max(1, 8192 / (2 * l)));
+  const size_t stage = (size_t)std::max(rows * 2 * l, K * 64);
+  const size_t shm = (stage + (size_t)2 * LMAX * 64) * sizeof(double);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void *)k_change_q<T, LMAX, TA2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_change_q<T, LMAX, TA2>), dim3(grid), dim3(64 * CHG_NW), shm, s, m, k,
+                     n2, l, A2, lda2, X1p, X1q, Hb, Kg, rows, part, st);
 }
 
 template <typename T>
-void launch_change(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-                   const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q, const double *Zp,
-                   const double *Zq, const double *Vp, const double *Vq, double *part,
-                   const SmallState *st) {
+void launch_change_qr(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
+                      const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q,
+                      const double *Hb, const double *Kg, double *part, const SmallState *st) {
   if constexpr (std::is_same<T, float>::value) {
     if (A2b != nullptr) {
-      launch_change_t<T, bf16s>(s, m, k, n2, l, A2b, ldb, X1p, X1q, Zp, Zq, Vp, Vq, part, st);
+      if (l <= 8)
+        launch_change_qr_k<T, 8, bf16s>(s, m, k, n2, l, A2b, ldb, X1p, X1q, Hb, Kg, part, st);
+      else
+        launch_change_qr_k<T, WLRA_BMAX, bf16s>(s, m, k, n2, l, A2b, ldb, X1p, X1q, Hb, Kg, part,
+                                                st);
       return;
     }
   }
-  launch_change_t<T, T>(s, m, k, n2, l, A + (int64_t)k * lda, lda, X1p, X1q, Zp, Zq, Vp, Vq, part,
-                        st);
+  const T *A2 = A + (int64_t)k * lda;
+  if (l <= 8)
+    launch_change_qr_k<T, 8, T>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
+  else
+    launch_change_qr_k<T, WLRA_BMAX, T>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
 }
 
 template <typename T>
@@ -916,10 +1042,9 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
   template void launch_x2<T>(hipStream_t, int64_t, int, int, int, const T *, int64_t, const T *,  \
                              const T *, const T *, T *, int64_t);                                 \
   template void launch_copy_out<T>(hipStream_t, int64_t, int64_t, const T *, T *, int64_t);     \
-  template void launch_change<T>(hipStream_t, int64_t, int, int, int, const T *, int64_t,         \
-                                 const bf16s *, int64_t, const T *, const T *, const double *,    \
-                                 const double *, const double *, const double *, double *,        \
-                                 const SmallState *);
+  template void launch_change_qr<T>(hipStream_t, int64_t, int, int, int, const T *, int64_t,      \
+                                    const bf16s *, int64_t, const T *, const T *, const double *, \
+                                    const double *, double *, const SmallState *);
 INST(float)
 INST(double)
 // mixed precision: X1^T A2 and A2^T A2 with A2 in BF16

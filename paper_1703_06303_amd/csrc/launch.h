@@ -89,12 +89,6 @@ template <typename T>
 void launch_post(hipStream_t s, const SmallArgs &a, const SmallOut<T> &o);
 void launch_gastats(hipStream_t s, int n2, const double *GA, SmallState *st);
 void launch_decide(hipStream_t s, const SmallArgs &a);
-template <typename T>
-void launch_change(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-                   const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q, const double *Zp,
-                   const double *Zq, const double *Vp, const double *Vq, double *part,
-                   const SmallState *st);
-
 // Learned warm start (k_learn.hip).
 template <typename T>
 void launch_gauss_fill(hipStream_t s, int64_t count, uint64_t seed, double scale, T *out);
@@ -115,3 +109,12 @@ void launch_tall_small(hipStream_t s, int64_t m, int kin, int c, const T *A, int
 template <typename T>
 void launch_decode_solve(hipStream_t s, int r, int k, const double *G, const double *H, T *Y,
                          int *flags);
+
+// Error_p through a Gram of aligned factor differences (k_stream.hip).
+void launch_chgprep(hipStream_t s, int n2, int k, int l, const double *Vp, const double *Vq,
+                    const double *Zp, const double *Zq, double *Hb, double *Kg, int splits,
+                    int64_t rows_per_split, double *part, const SmallState *st);
+template <typename T>
+void launch_change_qr(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
+                      const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q,
+                      const double *Hb, const double *Kg, double *part, const SmallState *st);

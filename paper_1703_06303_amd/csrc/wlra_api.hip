@@ -29,12 +29,12 @@
 
 enum KernelKind {
   KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_XTX, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
-  KK_POST, KK_CHANGE, KK_DECIDE, KK_UPDATE, KK_X2, KK_COPY, KK_LEARN, KK_COUNT
+  KK_POST, KK_CHANGE, KK_DECIDE, KK_UPDATE, KK_X2, KK_COPY, KK_LEARN, KK_CHGQR, KK_COUNT
 };
 static const char *kKernelNames[KK_COUNT] = {
     "validate", "init_x1", "gram_A2", "gram_stats", "gram_X1A2", "gram_X1X1", "objective_f1",
     "coef", "form_M", "eig", "post", "change", "decide", "update", "x2_out", "copy_out",
-    "learned_init"};
+    "learned_init", "change_qr"};
 
 struct ProfEvent {
   int kind;
@@ -129,6 +129,8 @@ struct Sizes {
   bool learned;
   int splits_l1, splits_l2, splits_l3;  // Om^T A, L0^T L0, L0^T A1
   int64_t rows_l1, rows_l2, rows_l3;
+  int splits_kg;  // H^T H of the change pass (n2 rows)
+  int64_t rows_kg;
 };
 
 struct Ptrs {
@@ -138,6 +140,7 @@ struct Ptrs {
   double *Zd[2], *Vd[2];
   void *Gt, *Tt, *St, *Vr, *Zx, *Eb;
   bf16s *Ab;  // mixed precision: BF16 copy of A2 (m x n2), else NULL
+  double *Hb, *Rh;  // change pass: aligned basis [V_p dV Z_p dZ] and its Gram
   // learned warm start (NULL unless the start is learned)
   void *Om, *Ps, *L0, *Yc;
   double *P1, *LG, *LH, *lpart;
@@ -169,6 +172,11 @@ Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mi
   z.splits_l1 = choose_splits(m, (int)((n + 31) / 32), &z.rows_l1);
   z.splits_l2 = choose_splits(m, 1, &z.rows_l2);
   z.splits_l3 = choose_splits(m, (int)((std::max<int64_t>(k, 1) + 31) / 32), &z.rows_l3);
+  {
+    const int K = (int)(2 * z.l + 2 * k), tk = (K + 31) / 32;
+    z.splits_kg = choose_splits(std::max<int64_t>(z.n2, 1), std::max(1, tk * (tk + 1) / 2),
+                                &z.rows_kg);
+  }
   z.nwg_upd = (int)((m + 63) / 64);
   z.nwg_f1 = 256;
   z.elt = elt;
@@ -182,8 +190,11 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
   const size_t d = sizeof(double);
   const int64_t m = z.m, k = z.k, n2 = z.n2, l = z.l;
   const int64_t kk = std::max<int64_t>(k, 1), ll = std::max<int64_t>(l, 1);
-  const size_t part = std::max<size_t>((size_t)z.splits_ga * n2 * n2,
-                                       (size_t)z.splits_p * std::max<int64_t>(kk * n2, kk * kk));
+  const int64_t Kc = 2 * l + 2 * k;
+  const size_t part = std::max<size_t>(
+      std::max<size_t>((size_t)z.splits_ga * n2 * n2,
+                       (size_t)z.splits_p * std::max<int64_t>(kk * n2, kk * kk)),
+      (size_t)z.splits_kg * Kc * Kc);
   struct Item { void **dst; size_t bytes; };
   Ptrs p{};
   Item items[] = {
@@ -219,6 +230,8 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.st, sizeof(SmallState)},
       {(void **)&p.flags, 64},
       {(void **)&p.Ab, z.mixed ? (size_t)(m * n2) * sizeof(bf16s) : 0},
+      {(void **)&p.Hb, (size_t)(n2 * (2 * l + 2 * k)) * d},
+      {(void **)&p.Rh, (size_t)((2 * l + 2 * k) * (2 * l + 2 * k)) * d},
       {&p.Om, z.learned ? (size_t)(m * LEARN_SK_ROWS) * z.elt : 0},
       {&p.Ps, z.learned ? (size_t)(z.n * LEARN_SK_COLS) * z.elt : 0},
       {&p.L0, z.learned ? (size_t)(m * z.r) * z.elt : 0},
@@ -440,11 +453,17 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
       PROF(h, KK_EIG, launch_eig(s, sa));
     }
     PROF(h, KK_POST, launch_post<T>(s, sa, so));
-    if (p > 0 && !reeval)
+    if (p > 0 && !reeval) {
+      PROF(h, KK_CHGQR,
+           launch_chgprep(s, (int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1],
+                          P.Zd[p & 1], P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, z.splits_kg, z.rows_kg,
+                          P.part, P.st));
       PROF(h, KK_CHANGE,
-           launch_change<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, on_bf16 ? P.Ab : nullptr,
-                            m, X1c, static_cast<const T *>(P.X1[cur ^ 1]), P.Zd[p & 1],
-                            P.Zd[(p & 1) ^ 1], P.Vd[p & 1], P.Vd[(p & 1) ^ 1], P.chg_part, P.st));
+           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda,
+                               on_bf16 ? P.Ab : nullptr, m, X1c,
+                               static_cast<const T *>(P.X1[cur ^ 1]), P.Hb, P.Rh, P.chg_part,
+                               P.st));
+    }
     PROF(h, KK_DECIDE, launch_decide(s, sa));
     HIPCHK(hipMemcpyAsync(h->st_host, P.st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
