@@ -41,6 +41,7 @@ struct EigLDS {
   double rc[32], rs[32];
   int rp[32], rq[32];
   int ints[4];
+  double rmax;  // largest residual of the wanted vectors still unlocked
 };
 
 // Block handle: an offset into the LDS pool (RES) or a global pointer.
@@ -106,16 +107,25 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
       const bool rowok = r < n2;
       eig_d4 acc = {0.0, 0.0, 0.0, 0.0};
       int k = 0;
-      for (; k + 16 <= n2; k += 16) {
-        double a[4], bb[4];
+      // the next 16 x 16 slab of M is loaded while the current one multiplies
+      double a[4], an[4];
+      const int kmain = n2 & ~15;
+      if (kmain > 0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int kk = k + 4 * u + lk;
-          a[u] = rowok ? cx.M[r + (int64_t)kk * n2] : 0.0;
-          bb[u] = colok ? s.pool[xoff + kk + li * n2] : 0.0;
-        }
+        for (int u = 0; u < 4; ++u) a[u] = rowok ? cx.M[r + (int64_t)(4 * u + lk) * n2] : 0.0;
+      }
+      for (; k + 16 <= n2; k += 16) {
+        const bool more = k + 16 < kmain;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          an[u] = (rowok && more) ? cx.M[r + (int64_t)(k + 16 + 4 * u + lk) * n2] : 0.0;
+        double bb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bb[u] = colok ? s.pool[xoff + k + 4 * u + lk + li * n2] : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = an[u];
       }
       for (; k < n2; k += 4) {
         const int kk = k + lk;
@@ -303,6 +313,16 @@ __device__ __forceinline__ void blk_jacobi(EigLDS &s, int nb) {
   if (t < 64) {
     double *H = s.H, *S = s.S;
     for (int e = t; e < B_ * B_; e += 64) S[e] = ((e % B_) == (e / B_)) ? 1.0 : 0.0;
+    // H = Y^T (M Y) is symmetric only to rounding: average the two triangles
+    // so that the rotations can drive the off-diagonal mass to zero
+    for (int e = t; e < nb * nb; e += 64) {
+      const int a = e % nb, c = e / nb;
+      if (a < c) {
+        const double v = 0.5 * (H[a + c * B_] + H[c + a * B_]);
+        H[a + c * B_] = v;
+        H[c + a * B_] = v;
+      }
+    }
     const int nbp = nb + (nb & 1);
     const int half = nbp / 2;
     wave_sync();
@@ -423,18 +443,26 @@ __device__ __forceinline__ void blk_orth(EigLDS &s, const EigCtx &cx, Blk<RES> X
       }
       __syncthreads();
     }
-    // normalise columns
-    blk_gram<RES>(s, cx, X, nb, X, nb, s.H, true);
-    for (int c = t; c < nb; c += ET) s.res[c] = s.H[c + c * B_];
-    __syncthreads();
-    for (int e = t; e < n2 * nb; e += ET) {
-      const double d = s.res[e / n2];
-      X.at(s, e) *= (d > 0 ? 1.0 / sqrt(d) : 0.0);
+    // Gram, scaled to unit diagonal (D^-1/2 G D^-1/2 = R'^T R'), so that
+    // X R^-1 = X D^-1/2 R'^-1: the normalisation costs no pass over X
+    blk_gram<RES>(s, cx, X, nb, X, nb, s.H);
+    for (int c = t; c < nb; c += ET) {
+      const double d = s.H[c + c * B_];
+      s.res[c] = d > 0 ? 1.0 / sqrt(d) : 1.0;  // a zero column is left to the shift
     }
     __syncthreads();
-    blk_gram<RES>(s, cx, X, nb, X, nb, s.H);
+    for (int e = t; e < nb * nb; e += ET) {
+      const int a2 = e % nb, c = e / nb;
+      s.H[a2 + c * B_] *= s.res[a2] * s.res[c];
+    }
+    __syncthreads();
     if (blk_chol(s, s.H, nb, 0.0)) {
       blk_gram<RES>(s, cx, X, nb, X, nb, s.H);
+      for (int e = t; e < nb * nb; e += ET) {
+        const int a2 = e % nb, c = e / nb;
+        s.H[a2 + c * B_] *= s.res[a2] * s.res[c];
+      }
+      __syncthreads();
       double fro = 0.0;
       for (int e = 0; e < nb * nb; ++e) fro += s.H[(e % nb) + (e / nb) * B_] * s.H[(e % nb) + (e / nb) * B_];
       const double sh = 11.0 * ((double)n2 * nb + (double)nb * (nb + 1)) * 2.220446049250313e-16 * sqrt(fro);
@@ -444,6 +472,13 @@ __device__ __forceinline__ void blk_orth(EigLDS &s, const EigCtx &cx, Blk<RES> X
         return;
       }
     }
+    // R = R' D^1/2 (column c of R' times d_c^1/2), so that X R^-1 is the
+    // orthonormal factor of X itself
+    for (int e = t; e < nb * nb; e += ET) {
+      const int a2 = e % nb, c = e / nb;
+      if (a2 <= c) s.H[a2 + c * B_] /= s.res[c];
+    }
+    __syncthreads();
     blk_trsm<RES>(s, n2, X, nb, s.H);
   }
 }
@@ -457,12 +492,48 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
   const double maxamp = 1e6;
   Blk<RES> W = F0;
   if (st->eig_first) {
-    for (int e = t; e < n2 * b; e += ET) Y.at(s, e) = hash_unit((uint32_t)(e % n2), (uint32_t)(e / n2));
+    // Start from the columns of M with the largest diagonal entries (the
+    // frames whose residual energy is largest, on which the leading
+    // eigenvectors concentrate), plus a small deterministic perturbation
+    // that keeps the block of full rank.
+    if (t < 64) {
+      for (int q = 0; q < b; ++q) {
+        double best = -1.0;
+        int bi = 0;
+        for (int i = t; i < n2; i += 64) {
+          bool used = false;
+          for (int u = 0; u < q; ++u) used = used || (s.rp[u] == i);
+          const double v = used ? -1.0 : cx.M[i + (int64_t)i * n2];
+          if (v > best) {
+            best = v;
+            bi = i;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (t == 0) s.rp[q] = bi;
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < n2 * b; e += ET) {
+      const int i = e % n2, q = e / n2, j = s.rp[q];
+      const double mjj = cx.M[j + (int64_t)j * n2];
+      Y.at(s, e) = cx.M[i + (int64_t)j * n2] +
+                   1e-6 * fabs(mjj) * hash_unit((uint32_t)i, (uint32_t)q) + 1e-300;
+    }
   } else if (RES) {
     for (int e = t; e < n2 * b; e += ET) Y.at(s, e) = a.Y[e];
   }
   __syncthreads();
-  blk_orth<RES>(s, cx, Y, b, Y, 0, a.flags);
+  // a warm start is the previous sweep's Ritz block, orthonormal already
+  if (st->eig_first) blk_orth<RES>(s, cx, Y, b, Y, 0, a.flags);
   blk_op<RES>(s, cx, Y, b, W, Y, s.th, 0);
   blk_gram<RES>(s, cx, Y, b, W, b, s.H);
   blk_jacobi(s, b);
@@ -477,6 +548,9 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
       int lk = locked;
       while (lk < l && s.res[lk - locked] <= floor_) ++lk;
       s.ints[2] = lk;
+      double rm = 0.0;
+      for (int q = lk; q < l; ++q) rm = fmax(rm, s.res[q - locked]);
+      s.rmax = rm;
     }
     __syncthreads();
     locked = s.ints[2];
@@ -495,6 +569,17 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
     if (x > 1.0) {
       const int dmax = max(2, (int)(log(2.0 * maxamp) / acosh(x)));
       d = min(d, dmax);
+    }
+    // no higher than the residual reduction still needed asks for: the
+    // l-th Ritz vector's error shrinks by about T_d((th_l - e0) / h)
+    {
+      const double rmax = s.rmax;
+      const double xl = (s.th[l - 1] - e0) / h;
+      if (xl > 1.0 && rmax > 0.0) {
+        const double need = 4.0 * rmax / floor_;
+        const int dn = (need > 1.0) ? (int)ceil(acosh(need) / acosh(xl)) : 2;
+        d = min(d, max(2, dn));
+      }
     }
     const double sigma = h / (top - e0), tau = 2.0 / sigma;
     double s1 = sigma;

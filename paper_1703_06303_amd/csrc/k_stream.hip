@@ -140,22 +140,39 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
   if (i + 1 < k1 && j + 1 < k2) out[i + 1 + (int64_t)(j + 1) * k1] = a11;
 }
 
-// Sum of the split partials in a fixed order (deterministic).  For `sym`
-// the lower tiles are mirrored from the upper ones.
+// Sum of the split partials in a fixed order (deterministic).  A workgroup
+// takes 32 consecutive outputs; its RP_G thread groups each sum every RP_G-th
+// split (loads coalesced over the 32 outputs, several in flight per thread),
+// then the group sums are added in order.  For `sym` the lower tiles are
+// mirrored from the upper ones.
+#define RP_G 8
 __global__ __launch_bounds__(256) void k_reduce_parts(int k1, int k2, int splits, int sym,
                                                       const double *__restrict__ part,
                                                       double *__restrict__ out,
                                                       const int *skip) {
   if (skip != nullptr && *skip) return;
+  __shared__ double sp[RP_G][32];
   const int64_t total = (int64_t)k1 * k2;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(e % k1), j = (int)(e / k1);
-    int64_t src = e;
-    if (sym && (i >> 5) > (j >> 5)) src = j + (int64_t)i * k1;
+  const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
+  for (int64_t e0 = (int64_t)blockIdx.x * 32; e0 < total; e0 += (int64_t)gridDim.x * 32) {
+    const int64_t e = e0 + o;
     double acc = 0.0;
-    for (int s = 0; s < splits; ++s) acc += part[(int64_t)s * total + src];
-    out[e] = acc;
+    if (e < total) {
+      const int i = (int)(e % k1), j = (int)(e / k1);
+      int64_t src = e;
+      if (sym && (i >> 5) > (j >> 5)) src = j + (int64_t)i * k1;
+#pragma unroll 4
+      for (int sp_ = g; sp_ < splits; sp_ += RP_G) acc += part[(int64_t)sp_ * total + src];
+    }
+    sp[g][o] = acc;
+    __syncthreads();
+    if (g == 0 && e < total) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < RP_G; ++q) t += sp[q][o];
+      out[e] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -195,16 +212,19 @@ __global__ __launch_bounds__(256) void k_f1(int64_t m, int k, const T *__restric
 // When W1 is one constant w, K = w^2 I + S is shared: the small step
 // pre-multiplies Z, T and S by K^-1 and no per-row solve is needed.
 //
-// Work split: a workgroup owns 64 rows (one per lane); its UPD_NW wavefronts
+// Work split: a workgroup owns 64 rows (one per lane); its upd_nw wavefronts
 // each take a contiguous slice of the n columns of A = [A1 A2] against
 // G = [-S; Z] (n x k, row-major, input index first) and wavefront 0 adds
 // x1 T; the slices are summed in a fixed order through LDS.  With a constant
 // weight wavefront 0 writes X1' = A1 + e directly; otherwise it stores the
 // right-hand sides e for k_rowsolve.
 // Partials per workgroup: (||(A1 - X1') o W1||^2, ||X1' - X1||^2).
-#define UPD_NW 4
+// wavefronts per workgroup: 8 while the k accumulators fit the register
+// budget of 512 threads, 4 for k > 32
+template <int KMAX>
+constexpr int upd_nw() { return KMAX <= 32 ? 8 : 4; }
 template <typename T, int KMAX, bool CONSTW, typename TA2>
-__global__ __launch_bounds__(64 * UPD_NW) void k_update(
+__global__ __launch_bounds__(64 * upd_nw<KMAX>()) void k_update(
     int64_t m, int k, int n, const T *__restrict__ A, int64_t lda, const TA2 *__restrict__ A2,
     int64_t lda2, const T *__restrict__ W1,
     int64_t ldw, T wc, const T *__restrict__ X1o, T *__restrict__ X1n, const T *__restrict__ Gt,
@@ -224,7 +244,7 @@ __global__ __launch_bounds__(64 * UPD_NW) void k_update(
   const bool act = i < m;
   const int64_t ir = act ? i : (m - 1);
 
-  for (int e = threadIdx.x; e < k * k; e += 64 * UPD_NW) {
+  for (int e = threadIdx.x; e < k * k; e += 64 * upd_nw<KMAX>()) {
     sT[e] = Tt[e];
     sS[e] = St[e];
   }
@@ -250,11 +270,11 @@ __global__ __launch_bounds__(64 * UPD_NW) void k_update(
   for (int c0 = 0; c0 < n; c0 += rows_per) {
     const int c1 = min(n, c0 + rows_per);
     __syncthreads();
-    for (int e2 = threadIdx.x; e2 < (c1 - c0) * k; e2 += 64 * UPD_NW)
+    for (int e2 = threadIdx.x; e2 < (c1 - c0) * k; e2 += 64 * upd_nw<KMAX>())
       sG[e2] = Gt[(int64_t)c0 * k + e2];
     __syncthreads();
     const int len = c1 - c0;
-    const int j0 = c0 + w * len / UPD_NW, j1 = c0 + (w + 1) * len / UPD_NW;
+    const int j0 = c0 + w * len / upd_nw<KMAX>(), j1 = c0 + (w + 1) * len / upd_nw<KMAX>();
     int j = j0;
     for (; j + 8 <= j1; j += 8) {
       T v[8];
@@ -277,7 +297,7 @@ __global__ __launch_bounds__(64 * UPD_NW) void k_update(
     }
   }
   // fixed-order sum of the wavefront slices into wavefront 0
-  for (int q = 1; q < UPD_NW; ++q) {
+  for (int q = 1; q < upd_nw<KMAX>(); ++q) {
     __syncthreads();
     if (w == q) {
 #pragma unroll
@@ -589,7 +609,7 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
 // H column-major into Hb (n2 x K, K = 2l + 2k).  Kg = H^T H (K x K) is then
 // formed by the tall-skinny product kernel.
 #define QR_T 512
-#define CHG_NW 4  // wavefronts per workgroup of the change row pass
+#define CHG_NW 8  // wavefronts per workgroup of the change row pass
 __global__ __launch_bounds__(QR_T) void k_chgprep(int n2, int k, int l,
                                                   const double *__restrict__ Vp,
                                                   const double *__restrict__ Vq,
@@ -860,7 +880,7 @@ void launch_tsgemm(hipStream_t s, int64_t m, const TX *X, int64_t ldx, int k1, c
   hipLaunchKernelGGL((k_tsgemm<TX, TY>), dim3(ti, tj, splits), dim3(256), 0, s, m, X, ldx, k1, Y,
                      ldy, k2, sym, rows_per_split, part, skip);
   const int64_t total = (int64_t)k1 * k2;
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1024));
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 31) / 32, 4096));
   hipLaunchKernelGGL(k_reduce_parts, dim3(g), dim3(256), 0, s, k1, k2, splits, sym, part, out, skip);
 }
 
@@ -896,7 +916,7 @@ static void launch_update_kernel(hipStream_t s, const UpdateArgs<T> &a, const TA
   if (pl.shm > 65536)
     (void)hipFuncSetAttribute((const void *)k_update<T, KMAX, CONSTW, TA2>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.shm);
-  hipLaunchKernelGGL((k_update<T, KMAX, CONSTW, TA2>), dim3(grid), dim3(64 * UPD_NW), pl.shm, s,
+  hipLaunchKernelGGL((k_update<T, KMAX, CONSTW, TA2>), dim3(grid), dim3(64 * upd_nw<KMAX>()), pl.shm, s,
                      a.m, a.k, a.n, a.A, a.lda, A2, lda2, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Gt,
                      a.Tt, a.St, a.part, a.Eb, pl.grows, a.st);
 }
