@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwlra.so")
-SOURCES = ["wlra_api.hip", "k_stream.hip", "k_small.hip", "k_eig.hip", "k_learn.hip"]
+SOURCES = ["wlra_api.hip", "k_stream.hip", "k_small.hip", "k_eig.hip", "k_eigmw.hip",
+           "k_learn.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-pthread",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-value"]

@@ -25,6 +25,7 @@
 // pointer, fixed at compile time, so LDS blocks compile to ds_* accesses.
 #include "common.h"
 #include "launch.h"
+#include "eig_small.h"
 
 #define ET 512
 #define B_ WLRA_BMAX
@@ -226,37 +227,8 @@ __device__ __forceinline__ void blk_resid(EigLDS &s, int n2, Blk<RES> W, Blk<RES
 // Upper Cholesky in place of G (nb x nb, ld B_) by wavefront 0, with an
 // optional diagonal shift.  Returns nonzero on a non-positive pivot.
 __device__ __forceinline__ int blk_chol(EigLDS &s, double *G, int nb, double shift) {
-  const int t = threadIdx.x;
-  if (t < 64) {
-    if (t == 0) s.ints[0] = 0;
-    if (shift != 0.0)
-      for (int a = t; a < nb; a += 64) G[a + a * B_] += shift;
-    wave_sync();
-    for (int j = 0; j < nb; ++j) {
-      if (t == 0) {
-        double p = G[j + j * B_];
-        if (!(p > 0.0)) {
-          s.ints[0] = 1;
-          p = 1.0;
-        }
-        G[j + j * B_] = sqrt(p);
-      }
-      wave_sync();
-      const double rjj = G[j + j * B_];
-      for (int c = j + 1 + t; c < nb; c += 64) G[j + c * B_] /= rjj;
-      wave_sync();
-      const int rem = nb - j - 1;
-      for (int e = t; e < rem * rem; e += 64) {
-        const int aa = j + 1 + e % rem, cc = j + 1 + e / rem;
-        if (aa <= cc) G[aa + cc * B_] -= G[j + aa * B_] * G[j + cc * B_];
-      }
-      wave_sync();
-    }
-  }
-  __syncthreads();
-  return s.ints[0];
+  return small_chol_wave(G, nb, shift, s.ints);
 }
-
 
 // X (n2 x nb) <- X S (S nb x nb in LDS, ld B_).  Rows are copied to LDS
 // scratch in chunks, then each thread forms one output entry.
@@ -306,121 +278,10 @@ __device__ __forceinline__ void blk_trsm(EigLDS &s, int n2, Blk<RES> X, int nb, 
 }
 
 // Symmetric eigendecomposition of H (nb x nb) by parallel cyclic Jacobi on
-// wavefront 0 (round-robin pairing, nb/2 disjoint rotations per round).
-// On return th[0..nb) is descending and S holds the eigenvectors.
+// wavefront 0.  On return th[0..nb) is descending and S holds the
+// eigenvectors.
 __device__ __forceinline__ void blk_jacobi(EigLDS &s, int nb) {
-  const int t = threadIdx.x;
-  if (t < 64) {
-    double *H = s.H, *S = s.S;
-    for (int e = t; e < B_ * B_; e += 64) S[e] = ((e % B_) == (e / B_)) ? 1.0 : 0.0;
-    // H = Y^T (M Y) is symmetric only to rounding: average the two triangles
-    // so that the rotations can drive the off-diagonal mass to zero
-    for (int e = t; e < nb * nb; e += 64) {
-      const int a = e % nb, c = e / nb;
-      if (a < c) {
-        const double v = 0.5 * (H[a + c * B_] + H[c + a * B_]);
-        H[a + c * B_] = v;
-        H[c + a * B_] = v;
-      }
-    }
-    const int nbp = nb + (nb & 1);
-    const int half = nbp / 2;
-    wave_sync();
-    for (int sweep = 0; sweep < 40; ++sweep) {
-      double off = 0.0, tot = 0.0;
-      for (int e = t; e < nb * nb; e += 64) {
-        const int a = e % nb, c = e / nb;
-        const double v = H[a + c * B_];
-        tot += v * v;
-        if (a != c) off += v * v;
-      }
-      off = wave_sum(off);
-      tot = wave_sum(tot);
-      // converged once the off-diagonal mass is at the rounding level of H
-      if (!(off > 1e-28 * tot)) break;
-      for (int round = 0; round < nbp - 1; ++round) {
-        if (t < half) {
-          const int x0 = t, x1 = nbp - 1 - t;
-          int p = (x0 == 0) ? 0 : 1 + (x0 - 1 + round) % (nbp - 1);
-          int q = (x1 == 0) ? 0 : 1 + (x1 - 1 + round) % (nbp - 1);
-          if (p > q) {
-            const int tmp = p;
-            p = q;
-            q = tmp;
-          }
-          double c = 1.0, sn = 0.0;
-          if (q < nb) {
-            const double apq = H[p + q * B_];
-            if (fabs(apq) > 1e-300) {
-              const double tau = (H[q + q * B_] - H[p + p * B_]) / (2.0 * apq);
-              const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-              c = 1.0 / sqrt(1.0 + tt * tt);
-              sn = tt * c;
-            }
-          } else {
-            q = p;  // dummy partner: identity
-          }
-          s.rp[t] = p;
-          s.rq[t] = q;
-          s.rc[t] = c;
-          s.rs[t] = sn;
-        }
-        wave_sync();
-        // rows p, q
-        for (int e = t; e < half * nb; e += 64) {
-          const int pr = e % half, x = e / half;
-          const int p = s.rp[pr], q = s.rq[pr];
-          if (p == q) continue;
-          const double c = s.rc[pr], sn = s.rs[pr];
-          const double hp = H[p + x * B_], hq = H[q + x * B_];
-          H[p + x * B_] = c * hp - sn * hq;
-          H[q + x * B_] = sn * hp + c * hq;
-        }
-        wave_sync();
-        // columns p, q of H and of S
-        for (int e = t; e < half * nb; e += 64) {
-          const int pr = e % half, x = e / half;
-          const int p = s.rp[pr], q = s.rq[pr];
-          if (p == q) continue;
-          const double c = s.rc[pr], sn = s.rs[pr];
-          const double hp = H[x + p * B_], hq = H[x + q * B_];
-          H[x + p * B_] = c * hp - sn * hq;
-          H[x + q * B_] = sn * hp + c * hq;
-          const double vp = S[x + p * B_], vq = S[x + q * B_];
-          S[x + p * B_] = c * vp - sn * vq;
-          S[x + q * B_] = sn * vp + c * vq;
-        }
-        wave_sync();
-      }
-    }
-    // eigenvalues, sorted descending (selection sort with column swaps)
-    for (int a = t; a < nb; a += 64) s.th[a] = H[a + a * B_];
-    wave_sync();
-    for (int a = 0; a < nb; ++a) {
-      if (t == 0) {
-        int best = a;
-        for (int c = a + 1; c < nb; ++c)
-          if (s.th[c] > s.th[best]) best = c;
-        s.ints[1] = best;
-      }
-      wave_sync();
-      const int best = s.ints[1];
-      if (best != a) {
-        for (int x = t; x < nb; x += 64) {
-          const double v = S[x + a * B_];
-          S[x + a * B_] = S[x + best * B_];
-          S[x + best * B_] = v;
-        }
-        if (t == 0) {
-          const double v = s.th[a];
-          s.th[a] = s.th[best];
-          s.th[best] = v;
-        }
-      }
-      wave_sync();
-    }
-  }
-  __syncthreads();
+  small_jacobi_wave(s.H, s.S, s.th, s.rc, s.rs, s.rp, s.rq, s.ints, nb);
 }
 
 // Orthonormalise the nb columns of X against the `locked` columns of L and
@@ -655,5 +516,8 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
 }
 
 void launch_eig(hipStream_t s, const SmallArgs &a) {
+  // larger n2: the multi-workgroup kernel; the one-workgroup kernel serves
+  // small n2 and any case the cooperative launch is refused
+  if (eig_mw_groups(a.n2) > 0 && launch_eig_mw(s, a) == hipSuccess) return;
   hipLaunchKernelGGL(k_eig, dim3(1), dim3(ET), 0, s, a);
 }

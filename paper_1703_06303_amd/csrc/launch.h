@@ -73,6 +73,7 @@ struct SmallArgs {
   int *flags;
   double wconst;           // > 0: constant W1
   int eig_maxit, eig_deg;
+  double *epart;           // partial Grams of the multi-workgroup eigen kernel
 };
 
 template <typename T>
@@ -85,6 +86,11 @@ struct SmallOut {
 void launch_coef(hipStream_t s, const SmallArgs &a);
 void launch_formM(hipStream_t s, const SmallArgs &a);
 void launch_eig(hipStream_t s, const SmallArgs &a);
+// Multi-workgroup eigen kernel (k_eigmw.hip) for n2 >= EIG_MW_MIN: 16 rows of
+// M per workgroup; partial Grams need 2 x workgroups x WLRA_BMAX^2 doubles.
+#define EIG_MW_MIN 256
+int eig_mw_groups(int n2);
+hipError_t launch_eig_mw(hipStream_t s, const SmallArgs &a);
 template <typename T>
 void launch_post(hipStream_t s, const SmallArgs &a, const SmallOut<T> &o);
 void launch_gastats(hipStream_t s, int n2, const double *GA, SmallState *st);

@@ -141,6 +141,7 @@ struct Ptrs {
   void *Gt, *Tt, *St, *Vr, *Zx, *Eb;
   bf16s *Ab;  // mixed precision: BF16 copy of A2 (m x n2), else NULL
   double *Hb, *Rh;  // change pass: aligned basis [V_p dV Z_p dZ] and its Gram
+  double *epart;    // multi-workgroup eigen kernel: partial Grams
   // learned warm start (NULL unless the start is learned)
   void *Om, *Ps, *L0, *Yc;
   double *P1, *LG, *LH, *lpart;
@@ -232,6 +233,10 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.Ab, z.mixed ? (size_t)(m * n2) * sizeof(bf16s) : 0},
       {(void **)&p.Hb, (size_t)(n2 * (2 * l + 2 * k)) * d},
       {(void **)&p.Rh, (size_t)((2 * l + 2 * k) * (2 * l + 2 * k)) * d},
+      {(void **)&p.epart,
+       (l > 0 && eig_mw_groups((int)n2) > 0)
+           ? (size_t)2 * eig_mw_groups((int)n2) * WLRA_BMAX * WLRA_BMAX * d
+           : 0},
       {&p.Om, z.learned ? (size_t)(m * LEARN_SK_ROWS) * z.elt : 0},
       {&p.Ps, z.learned ? (size_t)(z.n * LEARN_SK_COLS) * z.elt : 0},
       {&p.L0, z.learned ? (size_t)(m * z.r) * z.elt : 0},
@@ -434,6 +439,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   sa.Y = P.Y; sa.Wb = P.Wb; sa.F0 = P.F0; sa.F1 = P.F1; sa.F2 = P.F2; sa.theta = P.theta;
   sa.scratch = P.scratch; sa.st = P.st; sa.flags = P.flags; sa.wconst = constw ? wc : 0.0;
   sa.eig_maxit = EIG_MAXIT; sa.eig_deg = EIG_DEG;
+  sa.epart = P.epart;
   sa.upd_part = P.upd_part; sa.chg_part = P.chg_part; sa.nchg = z.nwg_upd;
   SmallOut<T> so{static_cast<T *>(P.Gt), static_cast<T *>(P.Tt), static_cast<T *>(P.St),
                  static_cast<T *>(P.Vr), static_cast<T *>(P.Zx)};
