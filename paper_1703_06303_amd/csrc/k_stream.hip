@@ -79,9 +79,15 @@ __global__ __launch_bounds__(256) void k_init_x1(int64_t m, int64_t k, int mode,
 
 // ---------------------------------------------------------------------------
 // Tall-skinny transposed product:  part[s] = X[rows of split s]^T Y[rows of s]
-// (k1 x k2, double).  32 x 32 output tile per workgroup, 2 x 2 per thread;
-// row chunks of 32 are staged through LDS as double.  `sym` computes only the
-// tiles on or above the diagonal (X == Y).
+// (k1 x k2, double), on the FP64 matrix cores.  A workgroup owns a 32 x 32
+// output tile; its four wavefronts own 16 x 16 quadrants and multiply with
+// v_mfma_f64_16x16x4f64 (products of the float or BF16 inputs are exact in
+// double, sums in double).  Row chunks of 32 are staged through LDS as double
+// (column-major, padded), the next chunk being loaded into registers while
+// the current one multiplies.  `sym` computes only the tiles on or above the
+// diagonal (X == Y).  Fragment layouts (lane l): A[l % 16][l / 16],
+// B[l / 16][l % 16], accumulator v holds D[l / 16 + 4 v][l % 16].
+typedef double ts_d4 __attribute__((ext_vector_type(4)));
 template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict__ X, int64_t ldx,
                                                 int k1, const TY *__restrict__ Y, int64_t ldy,
@@ -90,15 +96,14 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
   if (skip != nullptr && *skip) return;
   const int ti = blockIdx.x, tj = blockIdx.y, s = blockIdx.z;
   if (sym && ti > tj) return;
-  __shared__ double sX[32][33];
+  __shared__ double sX[32][33];  // [column of X][row in chunk]
   __shared__ double sY[32][33];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int qi = w & 1, qj = w >> 1;
   const int i0 = ti * 32, j0 = tj * 32;
   const int64_t r0 = (int64_t)s * rows_per_split;
   const int64_t r1 = min(m, r0 + rows_per_split);
-  double a00 = 0, a01 = 0, a10 = 0, a11 = 0;
-  // each thread moves 4 + 4 elements per 32-row chunk; the next chunk is
-  // loaded into registers while the current one is multiplied
   double px[4], py[4];
   auto fetch = [&](int64_t rb) {
 #pragma unroll
@@ -111,6 +116,7 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
       py[u] = (rin && j0 + cc < k2) ? (double)to_f(Y[row + (int64_t)(j0 + cc) * ldy]) : 0.0;
     }
   };
+  ts_d4 acc = {0.0, 0.0, 0.0, 0.0};
   if (r0 < r1) fetch(r0);
   for (int64_t rb = r0; rb < r1; rb += 32) {
 #pragma unroll
@@ -121,23 +127,21 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
     }
     __syncthreads();
     if (rb + 32 < r1) fetch(rb + 32);
-#pragma unroll 8
-    for (int rr = 0; rr < 32; ++rr) {
-      const double x0 = sX[2 * tx][rr], x1 = sX[2 * tx + 1][rr];
-      const double y0 = sY[2 * ty][rr], y1 = sY[2 * ty + 1][rr];
-      a00 = fma(x0, y0, a00);
-      a01 = fma(x0, y1, a01);
-      a10 = fma(x1, y0, a10);
-      a11 = fma(x1, y1, a11);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int kk = 4 * u + lk;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[16 * qi + li][kk], sY[16 * qj + li][kk], acc,
+                                                 0, 0, 0);
     }
     __syncthreads();
   }
   double *out = part + (int64_t)s * k1 * k2;
-  const int i = i0 + 2 * tx, j = j0 + 2 * ty;
-  if (i < k1 && j < k2) out[i + (int64_t)j * k1] = a00;
-  if (i < k1 && j + 1 < k2) out[i + (int64_t)(j + 1) * k1] = a01;
-  if (i + 1 < k1 && j < k2) out[i + 1 + (int64_t)j * k1] = a10;
-  if (i + 1 < k1 && j + 1 < k2) out[i + 1 + (int64_t)(j + 1) * k1] = a11;
+  const int j = j0 + 16 * qj + li;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + 16 * qi + lk + 4 * v;
+    if (i < k1 && j < k2) out[i + (int64_t)j * k1] = acc[v];
+  }
 }
 
 // Sum of the split partials in a fixed order (deterministic).  A workgroup
