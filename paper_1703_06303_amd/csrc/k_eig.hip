@@ -8,8 +8,9 @@
 // the active vectors with a degree-d Chebyshev polynomial that damps [0, c]
 // (c = smallest Ritz value of the block; M is positive semidefinite), using
 // the three-term recurrence scaled so that values stay O(1).  Converged
-// leading Ritz vectors are locked and deflated (M - L Theta L^T) so the filter
-// cannot re-amplify them, and the degree is capped so the top active
+// leading Ritz vectors are locked and deflated (M <- M - L Theta L^T, in
+// place, once per locking event) so the filter cannot re-amplify them, and
+// the degree is capped so the top active
 // component grows at most ~1e6 times the others (the block is then safe for
 // Cholesky QR).  Each round ends with CholeskyQR2 (shifted on failure) and a
 // Rayleigh-Ritz step solved by parallel cyclic Jacobi.  A Ritz pair is
@@ -70,27 +71,39 @@ struct EigCtx {
   int n2, S, sl, row;    // slices of the matvec, this thread's slice and row
   int l0, l1;            // column range of M owned by this thread
   const double *M;
+  double *Mw;            // the same matrix, written by the deflation
 };
 
 template <bool RES>
 __device__ __forceinline__ void blk_gram(EigLDS &s, const EigCtx &cx, Blk<RES> X, int p, Blk<RES> Y,
                                          int q, double *G, bool diag = false);
 
-// Out[:, 0:nc] = M X[:, 0:nc] - L diag(thL) (L^T X), blocks n2 x * (ld n2).
+// Out[:, 0:nc] = M X[:, 0:nc], blocks n2 x * (ld n2), M as deflated so far.
 // On the FP64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16 x 4 slab
-// of M by a 4 x 16 slab of X.  Each wavefront owns whole 16-row tiles of the
-// output and runs over all of the inner index, so no cross-lane reduction is
-// needed.  Fragment layouts (lane l): A[l % 16][l / 16], B[l / 16][l % 16],
+// of M by a 4 x 16 slab of X.  The product is bound by the latency of the
+// reads of M from L2, so the work is cut for loads in flight: the waves form
+// two groups that each take half of the inner index; a wave owns every
+// fourth 16-row tile of the output and, per tile, issues all of its reads of
+// M (up to OP_KH per lane) before its first multiply.  The second group
+// writes its partial tiles to the output and the first group's, parked in
+// LDS, are added after a barrier (a fixed order).  Fragment layouts (lane l): A[l % 16][l / 16], B[l / 16][l % 16],
 // accumulator v holds D[l / 16 + 4 v][l % 16].
 typedef double eig_d4 __attribute__((ext_vector_type(4)));
+#define OP_KH 32   // k-steps of 4 per register batch of M
+#define OP_TPW 4   // row tiles per wave per pass (4 waves per group: 16 tiles)
 template <bool RES>
 __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, int nc,
-                                       Blk<RES> Out, Blk<RES> Lb, const double *thL, int locked) {
+                                       Blk<RES> Out) {
   const int t = threadIdx.x, n2 = cx.n2;
-  const int lane = t & 63, wv = t >> 6;
+  const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int li = lane & 15, lk = lane >> 4;
+  const int grp = wv >> 2, wq = wv & 3;
   const int cwmax = RES ? 16 : min(16, 8192 / n2);
   const int rtiles = (n2 + 15) / 16;
+  const int kq = (n2 + 3) / 4;
+  const int kh = (kq + 1) / 2;
+  const int ks0 = grp * kh, ks1 = min(kq, ks0 + kh);
+  double *part = s.pool + PART_OFF;  // 16 partial tiles of 16 x 16
   for (int c0 = 0; c0 < nc; c0 += cwmax) {
     const int cw = min(cwmax, nc - c0);
     int xoff;  // X columns c0.. as an LDS offset (column-major, ld n2)
@@ -103,60 +116,71 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
       xoff = STAGE_OFF;
     }
     const bool colok = li < cw;
-    for (int rt = wv; rt < rtiles; rt += ET / 64) {
-      const int r = rt * 16 + li;
-      const bool rowok = r < n2;
-      eig_d4 acc = {0.0, 0.0, 0.0, 0.0};
-      int k = 0;
-      // the next 16 x 16 slab of M is loaded while the current one multiplies
-      double a[4], an[4];
-      const int kmain = n2 & ~15;
-      if (kmain > 0) {
+    for (int rp0 = 0; rp0 < rtiles; rp0 += 4 * OP_TPW) {
+#pragma unroll 1
+      for (int j = 0; j < OP_TPW; ++j) {
+        const int rt = rp0 + wq + 4 * j;
+        if (rt >= rtiles) break;
+        const int r = rt * 16 + li;
+        const double *mrow = cx.M + min(r, n2 - 1);
+        eig_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int kb = ks0; kb < ks1; kb += OP_KH) {
+          const int nk = min(OP_KH, ks1 - kb);
+          double a[OP_KH];
+          // reads and multiplies in groups of 8 k-steps (the branch on the
+          // group is uniform): a group's LDS reads of X are all issued before
+          // its first multiply
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = rowok ? cx.M[r + (int64_t)(4 * u + lk) * n2] : 0.0;
-      }
-      for (; k + 16 <= n2; k += 16) {
-        const bool more = k + 16 < kmain;
+          for (int u0 = 0; u0 < OP_KH; u0 += 8) {
+            if (u0 < nk) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          an[u] = (rowok && more) ? cx.M[r + (int64_t)(k + 16 + 4 * u + lk) * n2] : 0.0;
-        double bb[4];
+              for (int u = u0; u < u0 + 8; ++u) {
+                // clamped, always in bounds and never masked (a masked read
+                // would be waited for at once): a row past n2 only feeds an
+                // output row that is not stored, and a k past n2 meets a
+                // zero of X
+                const int kk = 4 * (kb + u) + lk;
+                a[u] = mrow[(int64_t)min(kk, n2 - 1) * n2];
+              }
+            }
+          }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) bb[u] = colok ? s.pool[xoff + k + 4 * u + lk + li * n2] : 0.0;
+          for (int u0 = 0; u0 < OP_KH; u0 += 8) {
+            if (u0 < nk) {
+              double bb[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc, 0, 0, 0);
+              for (int u = 0; u < 8; ++u) {
+                const int kk = 4 * (kb + u0 + u) + lk;
+                const double v = s.pool[xoff + min(kk, n2 - 1) + (colok ? li : 0) * n2];
+                bb[u] = (colok && kk < n2 && u0 + u < nk) ? v : 0.0;
+              }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = an[u];
-      }
-      for (; k < n2; k += 4) {
-        const int kk = k + lk;
-        const bool kok = kk < n2;
-        const double a = (rowok && kok) ? cx.M[r + (int64_t)kk * n2] : 0.0;
-        const double bb = (colok && kok) ? s.pool[xoff + kk + li * n2] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
-      }
-      if (colok) {
+              for (int u = 0; u < 8; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u0 + u], bb[u], acc, 0, 0, 0);
+            }
+          }
+        }
+        // the first group parks its partial tile; the second writes its own
+        // to the output, which the partial is added to after the barrier
+        if (grp == 0) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = rt * 16 + lk + 4 * v;
-          if (row < n2) Out.at(s, row + (c0 + li) * n2) = acc[v];
+          for (int v = 0; v < 4; ++v) part[(rt - rp0) * 256 + (lk + 4 * v) * 16 + li] = acc[v];
+        } else if (colok) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rt * 16 + lk + 4 * v;
+            if (row < n2) Out.at(s, row + (c0 + li) * n2) = acc[v];
+          }
         }
       }
+      __syncthreads();
+      const int pr0 = rp0 * 16, prn = min(n2, (rp0 + 4 * OP_TPW) * 16) - pr0;
+      for (int e = t; e < prn * cw; e += ET) {
+        const int i = e % prn, c = e / prn;
+        Out.at(s, pr0 + i + (c0 + c) * n2) += part[(i >> 4) * 256 + (i & 15) * 16 + c];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  if (locked > 0) {
-    // Out -= L (diag(thL) L^T X)
-    blk_gram<RES>(s, cx, Lb, locked, X, nc, s.G);
-    for (int e = t; e < locked * nc; e += ET) s.G[(e % locked) + (e / locked) * B_] *= thL[e % locked];
-    __syncthreads();
-    for (int e = t; e < n2 * nc; e += ET) {
-      const int i = e % n2, c = e / n2;
-      double v = Out.at(s, e);
-      for (int a = 0; a < locked; ++a) v -= Lb.at(s, i + a * n2) * s.G[a + c * B_];
-      Out.at(s, e) = v;
-    }
-    __syncthreads();
   }
 }
 
@@ -277,6 +301,36 @@ __device__ __forceinline__ void blk_trsm(EigLDS &s, int n2, Blk<RES> X, int nb, 
   blk_rot<RES>(s, n2, X, nb, Ri);
 }
 
+// Hotelling deflation of newly locked Ritz pairs, once per locking event:
+// M <- M - sum_{a in [q0, q1)} th_a y_a y_a^T, in place in global memory (M
+// is formed afresh for every eigen step and read by nothing else).  The
+// filter steps then multiply by the deflated matrix directly.  Reads go in
+// batches of 8 per thread, clamped to stay in bounds, so that they are in
+// flight together.
+template <bool RES>
+__device__ __forceinline__ void blk_deflate(EigLDS &s, const EigCtx &cx, Blk<RES> Y, int q0, int q1) {
+  const int t = threadIdx.x, n2 = cx.n2, nn = n2 * n2;
+  double *M = cx.Mw;
+  for (int e0 = t; e0 < nn; e0 += 8 * ET) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = M[min(e0 + u * ET, nn - 1)];
+    for (int a = q0; a < q1; ++a) {
+      const double th = s.th[a];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(e0 + u * ET, nn - 1);
+        const int i = e % n2, j = e / n2;
+        v[u] -= th * Y.at(s, i + a * n2) * Y.at(s, j + a * n2);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + u * ET < nn) M[e0 + u * ET] = v[u];
+  }
+  __syncthreads();
+}
+
 // Symmetric eigendecomposition of H (nb x nb) by parallel cyclic Jacobi on
 // wavefront 0.  On return th[0..nb) is descending and S holds the
 // eigenvectors.
@@ -344,6 +398,7 @@ __device__ __forceinline__ void blk_orth(EigLDS &s, const EigCtx &cx, Blk<RES> X
   }
 }
 
+
 template <bool RES>
 __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const EigCtx &cx,
                                          Blk<RES> Y, Blk<RES> F0, Blk<RES> F1, Blk<RES> F2) {
@@ -395,12 +450,11 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
   __syncthreads();
   // a warm start is the previous sweep's Ritz block, orthonormal already
   if (st->eig_first) blk_orth<RES>(s, cx, Y, b, Y, 0, a.flags);
-  blk_op<RES>(s, cx, Y, b, W, Y, s.th, 0);
+  blk_op<RES>(s, cx, Y, b, W);
   blk_gram<RES>(s, cx, Y, b, W, b, s.H);
   blk_jacobi(s, b);
   blk_rot<RES>(s, n2, Y, b, s.S);
   blk_rot<RES>(s, n2, W, b, s.S);
-
   int locked = 0, it = 0, nmv = b;
   while (true) {
     // residuals ||W_q - th_q Y_q|| for q in [locked, l); lock the converged prefix
@@ -414,8 +468,13 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
       s.rmax = rm;
     }
     __syncthreads();
-    locked = s.ints[2];
-    if (locked >= l || it >= a.eig_maxit) break;
+    const int newl = s.ints[2];
+    if (newl >= l || it >= a.eig_maxit) {
+      locked = newl;
+      break;
+    }
+    if (newl > locked) blk_deflate<RES>(s, cx, Y, locked, newl);
+    locked = newl;
 
     const int act = b - locked;
     const Blk<RES> Ya = Y.plus(locked * n2);
@@ -447,13 +506,13 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
     Blk<RES> P0 = F0, P1 = F1, P2 = F2;
     for (int e = t; e < n2 * act; e += ET) P0.at(s, e) = Ya.at(s, e);
     __syncthreads();
-    blk_op<RES>(s, cx, P0, act, P1, Y, s.th, locked);
+    blk_op<RES>(s, cx, P0, act, P1);
     for (int e = t; e < n2 * act; e += ET) P1.at(s, e) = (P1.at(s, e) - e0 * P0.at(s, e)) * (s1 / h);
     __syncthreads();
     nmv += act * (d + 1);
     for (int j = 2; j <= d; ++j) {
       const double s2 = 1.0 / (tau - s1);
-      blk_op<RES>(s, cx, P1, act, P2, Y, s.th, locked);
+      blk_op<RES>(s, cx, P1, act, P2);
       for (int e = t; e < n2 * act; e += ET)
         P2.at(s, e) = 2.0 * (s2 / h) * (P2.at(s, e) - e0 * P1.at(s, e)) - (s1 * s2) * P0.at(s, e);
       __syncthreads();
@@ -468,7 +527,7 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
     blk_orth<RES>(s, cx, Ya, act, Y, locked, a.flags);
     // W (active columns) in F0: free once the filter is done
     const Blk<RES> Wa = W.plus(locked * n2);
-    blk_op<RES>(s, cx, Ya, act, Wa, Y, s.th, 0);
+    blk_op<RES>(s, cx, Ya, act, Wa);
     blk_gram<RES>(s, cx, Ya, act, Wa, act, s.H);
     // keep the locked Ritz values while Jacobi overwrites th[0..act)
     for (int q = t; q < locked; q += ET) s.res[q] = s.th[q];
@@ -501,6 +560,7 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
   EigCtx cx;
   cx.n2 = n2;
   cx.M = a.M;
+  cx.Mw = a.M;
   cx.S = max(1, min(8, ET / n2));
   cx.sl = t / n2;
   cx.row = (t < cx.S * n2) ? t % n2 : -1;

@@ -6,9 +6,12 @@
 //
 //  * workgroup g owns rows [16 g, 16 g + 16) of M (cached in its LDS when they
 //    fit) and of every n2 x b block, which live in global memory;
-//  * a block product Out = M X stages X in LDS and multiplies on the FP64
-//    matrix cores, the four wavefronts splitting the inner index (their
-//    partial 16 x 16 tiles are added in a fixed order);
+//  * a block product Out = M X reads X straight from L2 into registers (all
+//    of a wavefront's share at once) and multiplies on the FP64 matrix
+//    cores, the four wavefronts splitting the inner index (their partial
+//    16 x 16 tiles are added in a fixed order);
+//  * locked Ritz pairs are deflated once per locking event, each workgroup
+//    updating its own rows of M (M <- M - L Theta L^T);
 //  * a Gram X^T Y is formed from per-workgroup partial sums written to one of
 //    two alternating global buffers and, after a grid barrier, added in
 //    workgroup order by every workgroup;
@@ -30,7 +33,7 @@ namespace cg = cooperative_groups;
 #define MW_R 16       // rows per workgroup
 #define MW_B WLRA_BMAX
 #define MW_PART (MW_B * MW_B)
-#define MW_DYN 15360  // doubles of dynamic LDS (rows of M and staged X)
+#define MW_DYN 15360  // doubles of dynamic LDS (this workgroup's rows of M)
 
 typedef double mw_d4 __attribute__((ext_vector_type(4)));
 
@@ -48,12 +51,12 @@ struct MwShared {
 };
 
 struct Mw {
-  int n2, G, g, r0, r1, cw;
-  const double *M;
+  int n2, G, g, r0, r1;
+  double *M;     // global M (this workgroup's rows are deflated in place
+                 // when they are not cached)
   double *part;  // 2 x G x MW_PART doubles
   int pb;
   double *Ml;    // 16 x n2 rows of M (ld 16) in LDS, or nullptr
-  double *Xs;    // n2 x cw staged block columns (ld n2) in LDS
 };
 
 __device__ __forceinline__ void mw_sync() { cg::this_grid().sync(); }
@@ -64,9 +67,15 @@ __device__ void mw_gram(Mw &c, const double *X, int p, const double *Y, int q, d
   double *mine = c.part + ((size_t)c.pb * c.G + c.g) * MW_PART;
   for (int e = t; e < p * q; e += MW_T) {
     const int u = e % p, v = e / p;
+    const double *xu = X + (size_t)u * n2, *yv = Y + (size_t)v * n2;
     double acc = 0.0;
-    for (int i = c.r0; i < c.r1; ++i)
-      acc = fma(X[i + (size_t)u * n2], Y[i + (size_t)v * n2], acc);
+    // all 2 x 16 reads issued together (clamped; rows past r1 weigh 0)
+#pragma unroll
+    for (int ii = 0; ii < MW_R; ++ii) {
+      const int i = min(c.r0 + ii, n2 - 1);
+      const double w = (c.r0 + ii < c.r1) ? 1.0 : 0.0;
+      acc = fma(xu[i] * w, yv[i], acc);
+    }
     mine[u + v * MW_B] = acc;
   }
   mw_sync();
@@ -88,9 +97,13 @@ __device__ void mw_resid(Mw &c, MwShared &s, const double *W, const double *Y, i
   double *mine = c.part + ((size_t)c.pb * c.G + c.g) * MW_PART;
   for (int q = t; q < nq; q += MW_T) {
     const double th = s.th[q0 + q];
+    const double *wq = W + (size_t)(q0 + q) * n2, *yq = Y + (size_t)(q0 + q) * n2;
     double acc = 0.0;
-    for (int i = c.r0; i < c.r1; ++i) {
-      const double r = W[i + (size_t)(q0 + q) * n2] - th * Y[i + (size_t)(q0 + q) * n2];
+#pragma unroll
+    for (int ii = 0; ii < MW_R; ++ii) {
+      const int i = min(c.r0 + ii, n2 - 1);
+      const double w = (c.r0 + ii < c.r1) ? 1.0 : 0.0;
+      const double r = (wq[i] - th * yq[i]) * w;
       acc = fma(r, r, acc);
     }
     mine[q] = acc;
@@ -106,74 +119,103 @@ __device__ void mw_resid(Mw &c, MwShared &s, const double *W, const double *Y, i
   __syncthreads();
 }
 
-// Out[:, 0:nc] = M X - L diag(thL) (L^T X) on this workgroup's rows.  The
-// caller has written this workgroup's rows of X; the grid barrier at the start
-// completes X.  L^T X is summed from per-workgroup partials written before
-// that barrier (this workgroup's rows of L and X are final by then).
-__device__ void mw_op(Mw &c, MwShared &s, const double *X, int nc, double *Out, const double *L,
-                      const double *thL, int locked) {
+// Out[:, 0:nc] = M X on this workgroup's rows (M as deflated so far).  The
+// caller has written this workgroup's rows of X; the grid barrier at the
+// start completes X.  Each wavefront takes a quarter of the inner index and
+// loads its whole share of X (up to MW_KB k-steps of 4 per lane) into
+// registers before the first multiply; reads are clamped to stay in bounds
+// and masked by multiplying with zero, so none of them is waited for alone.
+#define MW_KB 40
+__device__ void mw_op(Mw &c, MwShared &s, const double *X, int nc, double *Out) {
   const int t = threadIdx.x, n2 = c.n2;
   const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  if (locked > 0) {
-    double *mine = c.part + ((size_t)c.pb * c.G + c.g) * MW_PART;
-    for (int e = t; e < locked * nc; e += MW_T) {
-      const int a = e % locked, q = e / locked;
-      double acc = 0.0;
-      for (int i = c.r0; i < c.r1; ++i)
-        acc = fma(L[i + (size_t)a * n2], X[i + (size_t)q * n2], acc);
-      mine[a + q * MW_B] = acc;
-    }
-  }
   mw_sync();
-  if (locked > 0) {  // diag(thL) L^T X, summed in workgroup order
-    const double *all = c.part + (size_t)c.pb * c.G * MW_PART;
-    for (int e = t; e < locked * nc; e += MW_T) {
-      const int a = e % locked, q = e / locked;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int w = 0; w < c.G; ++w) acc += all[(size_t)w * MW_PART + a + q * MW_B];
-      s.G[a + q * MW_B] = acc * thL[a];
-    }
-    c.pb ^= 1;
-  }
-  __syncthreads();
-  const int kc = ((n2 + 15) / 16) * 4;  // inner range per wavefront (multiple of 4)
-  const int k0 = wv * kc, k1 = min(n2, k0 + kc);
-  const int r = c.r0 + li;
-  const bool rowok = r < c.r1;
-  for (int c0 = 0; c0 < nc; c0 += c.cw) {
-    const int cwn = min(c.cw, nc - c0);
-    __syncthreads();
-    for (int e = t; e < n2 * cwn; e += MW_T) c.Xs[e] = X[(size_t)c0 * n2 + e];
-    __syncthreads();
-    const bool colok = li < cwn;
-    // two independent accumulation chains over alternate k slabs
-    mw_d4 acc = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int k = k0; k < k1; k += 8) {
-      const int kk0 = k + lk, kk1 = k + 4 + lk;
-      const bool ok0 = kk0 < k1, ok1 = kk1 < k1;
-      double a0 = 0.0, a1 = 0.0;
-      if (rowok && ok0) a0 = c.Ml ? c.Ml[kk0 * MW_R + li] : c.M[r + (size_t)kk0 * n2];
-      if (rowok && ok1) a1 = c.Ml ? c.Ml[kk1 * MW_R + li] : c.M[r + (size_t)kk1 * n2];
-      const double b0 = (colok && ok0) ? c.Xs[kk0 + li * n2] : 0.0;
-      const double b1 = (colok && ok1) ? c.Xs[kk1 + li * n2] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
-    }
+  const int kq = (n2 + 3) / 4;
+  const int kw = (kq + 3) / 4;
+  const int ks0 = wv * kw, ks1 = min(kq, ks0 + kw);
+  const int rcl = min(c.r0 + li, n2 - 1);
+  for (int c0 = 0; c0 < nc; c0 += 16) {
+    const int cwn = min(16, nc - c0);
+    const double *xc = X + (size_t)(c0 + min(li, cwn - 1)) * n2;
+    const double cm = (li < cwn) ? 1.0 : 0.0;
+    mw_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = ks0; kb < ks1; kb += MW_KB) {
+      const int nk = min(MW_KB, ks1 - kb);
+      double bb[MW_KB];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] += acc1[v];
+      for (int u0 = 0; u0 < MW_KB; u0 += 8) {
+        if (u0 < nk) {
+#pragma unroll
+          for (int u = u0; u < u0 + 8; ++u) bb[u] = xc[min(4 * (kb + u) + lk, n2 - 1)];
+        }
+      }
+#pragma unroll
+      for (int u0 = 0; u0 < MW_KB; u0 += 8) {
+        if (u0 < nk) {
+          double av[8], bv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int kk = 4 * (kb + u0 + u) + lk;
+            const int kc = min(kk, n2 - 1);
+            av[u] = c.Ml ? c.Ml[kc * MW_R + li] : c.M[rcl + (size_t)kc * n2];
+            bv[u] = bb[u0 + u] * ((u0 + u < nk && kk < n2) ? cm : 0.0);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+      }
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) s.tile[wv][(lk + 4 * v) * 16 + li] = acc[v];
     __syncthreads();
     for (int e = t; e < MW_R * cwn; e += MW_T) {
       const int rr = e % MW_R, cc = e / MW_R;
       const int row = c.r0 + rr;
-      if (row < c.r1) {
-        double v = ((s.tile[0][rr * 16 + cc] + s.tile[1][rr * 16 + cc]) + s.tile[2][rr * 16 + cc]) +
-                   s.tile[3][rr * 16 + cc];
-        for (int a = 0; a < locked; ++a) v -= L[row + (size_t)a * n2] * s.G[a + (c0 + cc) * MW_B];
-        Out[row + (size_t)(c0 + cc) * n2] = v;
+      if (row < c.r1)
+        Out[row + (size_t)(c0 + cc) * n2] =
+            ((s.tile[0][rr * 16 + cc] + s.tile[1][rr * 16 + cc]) + s.tile[2][rr * 16 + cc]) +
+            s.tile[3][rr * 16 + cc];
+    }
+    __syncthreads();
+  }
+}
+
+// Deflation of newly locked Ritz pairs [q0, q1) on this workgroup's rows of
+// M: M[i, j] -= sum_a th_a Y[i, a] Y[j, a].  Y is complete (a grid barrier
+// separates its last write from the locking decision).
+__device__ __noinline__ void mw_deflate(Mw &c, MwShared &s, const double *Y, int q0, int q1) {
+  const int t = threadIdx.x, n2 = c.n2, tot = MW_R * n2;
+  for (int e0 = t; e0 < tot; e0 += 8 * MW_T) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + u * MW_T, tot - 1);
+      const int li = e % MW_R, j = e / MW_R;
+      v[u] = c.Ml ? c.Ml[e] : c.M[min(c.r0 + li, n2 - 1) + (size_t)j * n2];
+    }
+    for (int a = q0; a < q1; ++a) {
+      const double th = s.th[a];
+      const double *ya = Y + (size_t)a * n2;
+      double yi[8], yj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(e0 + u * MW_T, tot - 1);
+        yi[u] = ya[min(c.r0 + e % MW_R, n2 - 1)];
+        yj[u] = ya[e / MW_R];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] -= th * yi[u] * yj[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * MW_T;
+      if (e < tot) {
+        const int li = e % MW_R, j = e / MW_R;
+        if (c.Ml)
+          c.Ml[e] = v[u];
+        else if (c.r0 + li < c.r1)
+          c.M[c.r0 + li + (size_t)j * n2] = v[u];
       }
     }
   }
@@ -242,7 +284,14 @@ __device__ int mw_orth(Mw &c, MwShared &s, double *X, int nb, const double *L, i
       for (int e = t; e < nr * nb; e += MW_T) {
         const int i = c.r0 + e % nr, q = e / nr;
         double v = X[i + (size_t)q * n2];
-        for (int a = 0; a < locked; ++a) v -= L[i + (size_t)a * n2] * s.G[a + q * MW_B];
+        for (int a0 = 0; a0 < locked; a0 += 8) {
+          double lv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) lv[u] = L[i + (size_t)min(a0 + u, locked - 1) * n2];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (a0 + u < locked) v -= lv[u] * s.G[a0 + u + q * MW_B];
+        }
         X[i + (size_t)q * n2] = v;
       }
       __syncthreads();
@@ -291,10 +340,8 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
   c.M = a.M;
   c.part = a.epart;
   c.pb = 0;
-  const bool cacheM = MW_R * n2 + 4 * n2 <= MW_DYN;
+  const bool cacheM = MW_R * n2 <= MW_DYN;
   c.Ml = cacheM ? dyn : nullptr;
-  c.Xs = cacheM ? dyn + MW_R * n2 : dyn;
-  c.cw = min(16, (MW_DYN - (cacheM ? MW_R * n2 : 0)) / n2);
   if (cacheM)
     for (int e = t; e < MW_R * n2; e += MW_T) {
       const int li = e % MW_R, kk = e / MW_R, r = c.r0 + li;
@@ -346,7 +393,7 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
       return;
     }
   }
-  mw_op(c, s, Y, b, W, Y, s.th, 0);
+  mw_op(c, s, Y, b, W);
   mw_gram(c, Y, b, W, b, s.H);
   small_jacobi_wave(s.H, s.S, s.th, s.rc, s.rs, s.rp, s.rq, s.ints, b);
   mw_rot(c, s, Y, b, s.S);
@@ -364,8 +411,13 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
       s.rmax = rm;
     }
     __syncthreads();
-    locked = s.ints[2];
-    if (locked >= l || it >= a.eig_maxit) break;
+    const int newl = s.ints[2];
+    if (newl >= l || it >= a.eig_maxit) {
+      locked = newl;
+      break;
+    }
+    if (newl > locked) mw_deflate(c, s, Y, locked, newl);
+    locked = newl;
 
     const int act = b - locked;
     double *Ya = Y + (size_t)locked * n2;
@@ -392,7 +444,7 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
       const int i = c.r0 + e % nr, q = e / nr;
       P0[i + (size_t)q * n2] = Ya[i + (size_t)q * n2];
     }
-    mw_op(c, s, P0, act, P1, Y, s.th, locked);
+    mw_op(c, s, P0, act, P1);
     for (int e = t; e < nr * act; e += MW_T) {
       const size_t o = c.r0 + e % nr + (size_t)(e / nr) * n2;
       P1[o] = (P1[o] - e0 * P0[o]) * (s1 / h);
@@ -400,7 +452,7 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
     nmv += act * (d + 1);
     for (int j = 2; j <= d; ++j) {
       const double s2 = 1.0 / (tau - s1);
-      mw_op(c, s, P1, act, P2, Y, s.th, locked);
+      mw_op(c, s, P1, act, P2);
       for (int e = t; e < nr * act; e += MW_T) {
         const size_t o = c.r0 + e % nr + (size_t)(e / nr) * n2;
         P2[o] = 2.0 * (s2 / h) * (P2[o] - e0 * P1[o]) - (s1 * s2) * P0[o];
@@ -421,7 +473,7 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
       break;
     }
     double *Wa = W + (size_t)locked * n2;
-    mw_op(c, s, Ya, act, Wa, Y, s.th, 0);
+    mw_op(c, s, Ya, act, Wa);
     mw_gram(c, Ya, act, Wa, act, s.H);
     for (int q = t; q < locked; q += MW_T) s.keep[q] = s.th[q];
     __syncthreads();
