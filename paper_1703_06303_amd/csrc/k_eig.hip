@@ -24,6 +24,8 @@
 // filter), else in global memory with LDS staging.  Blocks are addressed
 // through a handle that is either an offset into the LDS pool or a global
 // pointer, fixed at compile time, so LDS blocks compile to ds_* accesses.
+#include <cstdlib>
+
 #include "common.h"
 #include "launch.h"
 #include "eig_small.h"
@@ -72,6 +74,7 @@ struct EigCtx {
   int l0, l1;            // column range of M owned by this thread
   const double *M;
   double *Mw;            // the same matrix, written by the deflation
+  int xs;                // LDS offset of the padded copy of a 16-column block (blocks in LDS)
 };
 
 template <bool RES>
@@ -80,13 +83,19 @@ __device__ __forceinline__ void blk_gram(EigLDS &s, const EigCtx &cx, Blk<RES> X
 
 // Out[:, 0:nc] = M X[:, 0:nc], blocks n2 x * (ld n2), M as deflated so far.
 // On the FP64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16 x 4 slab
-// of M by a 4 x 16 slab of X.  The product is bound by the latency of the
-// reads of M from L2, so the work is cut for loads in flight: the waves form
-// two groups that each take half of the inner index; a wave owns every
-// fourth 16-row tile of the output and, per tile, issues all of its reads of
-// M (up to OP_KH per lane) before its first multiply.  The second group
-// writes its partial tiles to the output and the first group's, parked in
-// LDS, are added after a barrier (a fixed order).  Fragment layouts (lane l): A[l % 16][l / 16], B[l / 16][l % 16],
+// of M by a 4 x 16 slab of X.  The waves form two groups that each take half
+// of the inner index; a wave owns every fourth 16-row tile of the output and,
+// per tile, issues all of its reads of M (16 bytes per lane per two k-steps,
+// from the fragment-major storage) before its first multiply.  The second
+// group writes its partial tiles to the output and the first group's, parked
+// in LDS, are added after a barrier (a fixed order).
+//
+// The columns are first copied to an LDS buffer zero-padded to whole groups
+// of 8 k-steps, with an odd leading dimension (the 16 columns a
+// quarter-wavefront reads fall in distinct banks), so that the loop needs no
+// clamps or masks and its LDS reads take immediate offsets.  When the
+// buffer holds fewer than 16 columns, lanes past them read a zero column.
+// Fragment layouts (lane l): A[l % 16][l / 16], B[l / 16][l % 16],
 // accumulator v holds D[l / 16 + 4 v][l % 16].
 typedef double eig_d4 __attribute__((ext_vector_type(4)));
 #define OP_KH 32   // k-steps of 4 per register batch of M
@@ -98,49 +107,48 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
   const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const int grp = wv >> 2, wq = wv & 3;
-  const int cwmax = RES ? 16 : min(16, 8192 / n2);
   const int rtiles = (n2 + 15) / 16;
   const int kq = (n2 + 3) / 4;
-  const int kh = (kq + 1) / 2;
-  const int ks0 = grp * kh, ks1 = min(kq, ks0 + kh);
+  const int kq2 = (int)mf_kq2(n2);  // pairs of k-steps, padded to groups of 8 steps
+  const int kq8 = 2 * kq2;
+  const int xld = (4 * kq8) | 1;
+  // staged columns per pass; with fewer than 16 the next column is zero
+  const int fbase = RES ? cx.xs : STAGE_OFF;
+  const int cwf = RES ? 16 : min(16, 8192 / xld - 1);
+  const int ncopy = min(16, cwf + 1);
+  // group 0 takes k-steps [0, kh), group 1 [kh, kq8): whole groups of 8
+  const int kh = ((kq + 1) / 2 + 7) & ~7;
+  const int ks0 = grp * kh, ks1 = min(kq8, ks0 + kh);
   double *part = s.pool + PART_OFF;  // 16 partial tiles of 16 x 16
-  for (int c0 = 0; c0 < nc; c0 += cwmax) {
-    const int cw = min(cwmax, nc - c0);
-    int xoff;  // X columns c0.. as an LDS offset (column-major, ld n2)
-    if (RES) {
-      xoff = reinterpret_cast<const Blk<true> &>(X).off + c0 * n2;
-    } else {
-      const Blk<RES> Xs = X.plus(c0 * n2);
-      for (int e = t; e < n2 * cw; e += ET) s.pool[STAGE_OFF + e] = Xs.at(s, e);
-      __syncthreads();
-      xoff = STAGE_OFF;
+  for (int c0 = 0; c0 < nc; c0 += cwf) {
+    const int cw = min(cwf, nc - c0);
+    const Blk<RES> Xc = X.plus(c0 * n2);
+    for (int e = t; e < ncopy * xld; e += ET) {
+      const int i = e % xld, c = e / xld;
+      s.pool[fbase + e] = (i < n2 && c < cw) ? Xc.at(s, i + c * n2) : 0.0;
     }
+    __syncthreads();
     const bool colok = li < cw;
+    const double *xcol = s.pool + fbase + 4 * ks0 + lk + min(li, cwf) * xld;
     for (int rp0 = 0; rp0 < rtiles; rp0 += 4 * OP_TPW) {
 #pragma unroll 1
       for (int j = 0; j < OP_TPW; ++j) {
         const int rt = rp0 + wq + 4 * j;
         if (rt >= rtiles) break;
-        const int r = rt * 16 + li;
-        const double *mrow = cx.M + min(r, n2 - 1);
         eig_d4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int kb = ks0; kb < ks1; kb += OP_KH) {
-          const int nk = min(OP_KH, ks1 - kb);
+        const double2 *mt =
+            reinterpret_cast<const double2 *>(cx.M) + ((int64_t)rt * kq2 + ks0 / 2) * 64 + lane;
+        for (int kb = 0; kb < ks1 - ks0; kb += OP_KH) {
+          const int nk = min(OP_KH, ks1 - ks0 - kb);  // a multiple of 8
           double a[OP_KH];
-          // reads and multiplies in groups of 8 k-steps (the branch on the
-          // group is uniform): a group's LDS reads of X are all issued before
-          // its first multiply
 #pragma unroll
           for (int u0 = 0; u0 < OP_KH; u0 += 8) {
             if (u0 < nk) {
 #pragma unroll
-              for (int u = u0; u < u0 + 8; ++u) {
-                // clamped, always in bounds and never masked (a masked read
-                // would be waited for at once): a row past n2 only feeds an
-                // output row that is not stored, and a k past n2 meets a
-                // zero of X
-                const int kk = 4 * (kb + u) + lk;
-                a[u] = mrow[(int64_t)min(kk, n2 - 1) * n2];
+              for (int u = u0; u < u0 + 8; u += 2) {
+                const double2 v = mt[(int64_t)((kb + u) >> 1) * 64];
+                a[u] = v.x;
+                a[u + 1] = v.y;
               }
             }
           }
@@ -149,11 +157,7 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
             if (u0 < nk) {
               double bb[8];
 #pragma unroll
-              for (int u = 0; u < 8; ++u) {
-                const int kk = 4 * (kb + u0 + u) + lk;
-                const double v = s.pool[xoff + min(kk, n2 - 1) + (colok ? li : 0) * n2];
-                bb[u] = (colok && kk < n2 && u0 + u < nk) ? v : 0.0;
-              }
+              for (int u = 0; u < 8; ++u) bb[u] = xcol[4 * (kb + u0 + u)];
 #pragma unroll
               for (int u = 0; u < 8; ++u)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u0 + u], bb[u], acc, 0, 0, 0);
@@ -303,26 +307,29 @@ __device__ __forceinline__ void blk_trsm(EigLDS &s, int n2, Blk<RES> X, int nb, 
 
 // Hotelling deflation of newly locked Ritz pairs, once per locking event:
 // M <- M - sum_{a in [q0, q1)} th_a y_a y_a^T, in place in global memory (M
-// is formed afresh for every eigen step and read by nothing else).  The
+// is formed afresh for every eigen step and read by nothing else), walking
+// the fragment-major storage in order.  The
 // filter steps then multiply by the deflated matrix directly.  Reads go in
 // batches of 8 per thread, clamped to stay in bounds, so that they are in
 // flight together.
 template <bool RES>
 __device__ __forceinline__ void blk_deflate(EigLDS &s, const EigCtx &cx, Blk<RES> Y, int q0, int q1) {
-  const int t = threadIdx.x, n2 = cx.n2, nn = n2 * n2;
+  const int t = threadIdx.x, n2 = cx.n2;
+  const int64_t nn = mf_size(n2);
   double *M = cx.Mw;
-  for (int e0 = t; e0 < nn; e0 += 8 * ET) {
+  for (int64_t e0 = t; e0 < nn; e0 += 8 * ET) {
     double v[8];
+    int ii[8], jj[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = M[min(e0 + u * ET, nn - 1)];
+    for (int u = 0; u < 8; ++u) {
+      v[u] = M[min(e0 + u * ET, nn - 1)];
+      mf_rc(n2, min(e0 + u * ET, nn - 1), ii[u], jj[u]);
+    }
     for (int a = q0; a < q1; ++a) {
       const double th = s.th[a];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = min(e0 + u * ET, nn - 1);
-        const int i = e % n2, j = e / n2;
-        v[u] -= th * Y.at(s, i + a * n2) * Y.at(s, j + a * n2);
-      }
+      for (int u = 0; u < 8; ++u)
+        if (ii[u] < n2 && jj[u] < n2) v[u] -= th * Y.at(s, ii[u] + a * n2) * Y.at(s, jj[u] + a * n2);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
@@ -419,7 +426,7 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
         for (int i = t; i < n2; i += 64) {
           bool used = false;
           for (int u = 0; u < q; ++u) used = used || (s.rp[u] == i);
-          const double v = used ? -1.0 : cx.M[i + (int64_t)i * n2];
+          const double v = used ? -1.0 : cx.M[mf_idx(n2, i, i)];
           if (v > best) {
             best = v;
             bi = i;
@@ -440,8 +447,8 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
     __syncthreads();
     for (int e = t; e < n2 * b; e += ET) {
       const int i = e % n2, q = e / n2, j = s.rp[q];
-      const double mjj = cx.M[j + (int64_t)j * n2];
-      Y.at(s, e) = cx.M[i + (int64_t)j * n2] +
+      const double mjj = cx.M[mf_idx(n2, j, j)];
+      Y.at(s, e) = cx.M[mf_idx(n2, i, j)] +
                    1e-6 * fabs(mjj) * hash_unit((uint32_t)i, (uint32_t)q) + 1e-300;
     }
   } else if (RES) {
@@ -566,7 +573,11 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
   cx.row = (t < cx.S * n2) ? t % n2 : -1;
   cx.l0 = cx.sl * n2 / cx.S;
   cx.l1 = (cx.sl + 1) * n2 / cx.S;
-  if (4 * n2 * b <= PART_OFF) {
+  // the blocks live in LDS when they fit with room after them for the padded
+  // copy of a 16-column block (the product's B operand)
+  const int xld = (8 * (int)mf_kq2(n2)) | 1;
+  cx.xs = 4 * n2 * b;
+  if (4 * n2 * b + 16 * xld <= PART_OFF) {
     eig_body<true>(s, a, cx, Blk<true>{0}, Blk<true>{n2 * b}, Blk<true>{2 * n2 * b},
                    Blk<true>{3 * n2 * b});
   } else {
@@ -578,6 +589,8 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
 void launch_eig(hipStream_t s, const SmallArgs &a) {
   // larger n2: the multi-workgroup kernel; the one-workgroup kernel serves
   // small n2 and any case the cooperative launch is refused
-  if (eig_mw_groups(a.n2) > 0 && launch_eig_mw(s, a) == hipSuccess) return;
+  // (WLRA_EIG_ONE_WG set in the environment forces the one-workgroup kernel)
+  if (eig_mw_groups(a.n2) > 0 && getenv("WLRA_EIG_ONE_WG") == nullptr && launch_eig_mw(s, a) == hipSuccess)
+    return;
   hipLaunchKernelGGL(k_eig, dim3(1), dim3(ET), 0, s, a);
 }

@@ -158,7 +158,7 @@ __device__ void mw_op(Mw &c, MwShared &s, const double *X, int nc, double *Out) 
           for (int u = 0; u < 8; ++u) {
             const int kk = 4 * (kb + u0 + u) + lk;
             const int kc = min(kk, n2 - 1);
-            av[u] = c.Ml ? c.Ml[kc * MW_R + li] : c.M[rcl + (size_t)kc * n2];
+            av[u] = c.Ml ? c.Ml[kc * MW_R + li] : c.M[mf_idx(n2, rcl, kc)];
             bv[u] = bb[u0 + u] * ((u0 + u < nk && kk < n2) ? cm : 0.0);
           }
 #pragma unroll
@@ -192,7 +192,7 @@ __device__ __noinline__ void mw_deflate(Mw &c, MwShared &s, const double *Y, int
     for (int u = 0; u < 8; ++u) {
       const int e = min(e0 + u * MW_T, tot - 1);
       const int li = e % MW_R, j = e / MW_R;
-      v[u] = c.Ml ? c.Ml[e] : c.M[min(c.r0 + li, n2 - 1) + (size_t)j * n2];
+      v[u] = c.Ml ? c.Ml[e] : c.M[mf_idx(n2, min(c.r0 + li, n2 - 1), j)];
     }
     for (int a = q0; a < q1; ++a) {
       const double th = s.th[a];
@@ -215,7 +215,7 @@ __device__ __noinline__ void mw_deflate(Mw &c, MwShared &s, const double *Y, int
         if (c.Ml)
           c.Ml[e] = v[u];
         else if (c.r0 + li < c.r1)
-          c.M[c.r0 + li + (size_t)j * n2] = v[u];
+          c.M[mf_idx(n2, c.r0 + li, j)] = v[u];
       }
     }
   }
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
   if (cacheM)
     for (int e = t; e < MW_R * n2; e += MW_T) {
       const int li = e % MW_R, kk = e / MW_R, r = c.r0 + li;
-      c.Ml[e] = (r < c.r1) ? a.M[r + (size_t)kk * n2] : 0.0;
+      c.Ml[e] = (r < c.r1) ? a.M[mf_idx(n2, r, kk)] : 0.0;
     }
   const double floor_ = st->eig_floor;
   const double maxamp = 1e6;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
         for (int i = t; i < n2; i += 64) {
           bool used = false;
           for (int u = 0; u < q; ++u) used = used || (s.rp[u] == i);
-          const double v = used ? -1.0 : a.M[i + (size_t)i * n2];
+          const double v = used ? -1.0 : a.M[mf_idx(n2, i, i)];
           if (v > best) {
             best = v;
             bi = i;
@@ -383,8 +383,8 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
     __syncthreads();
     for (int e = t; e < nr * b; e += MW_T) {
       const int i = c.r0 + e % nr, q = e / nr, j = s.rp[q];
-      const double mjj = a.M[j + (size_t)j * n2];
-      Y[i + (size_t)q * n2] = a.M[i + (size_t)j * n2] +
+      const double mjj = a.M[mf_idx(n2, j, j)];
+      Y[i + (size_t)q * n2] = a.M[mf_idx(n2, i, j)] +
                               1e-6 * fabs(mjj) * hash_unit((uint32_t)i, (uint32_t)q) + 1e-300;
     }
     __syncthreads();

@@ -139,18 +139,24 @@ __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
 }
 
 // -----------------------------------------------------------------------------
+// M in the fragment-major layout of the eigen step (padding entries zero).
 __global__ __launch_bounds__(256) void k_formM(int n2, int k, const double *__restrict__ GA,
                                                const double *__restrict__ B,
                                                double *__restrict__ M, const SmallState *st) {
   if (st->done) return;
-  const int64_t total = (int64_t)n2 * n2;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % n2), j = (int)(e / n2);
-    const double *bi = B + (int64_t)i * k, *bj = B + (int64_t)j * k;
-    double s = 0.0;
-    for (int c = 0; c < k; ++c) s = fma(bi[c], bj[c], s);
-    M[e] = GA[e] - s;
+  const int64_t total = mf_size(n2);
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    int i, j;
+    mf_rc(n2, f, i, j);
+    double v = 0.0;
+    if (i < n2 && j < n2) {
+      const double *bi = B + (int64_t)i * k, *bj = B + (int64_t)j * k;
+      double s = 0.0;
+      for (int c = 0; c < k; ++c) s = fma(bi[c], bj[c], s);
+      v = GA[i + (int64_t)j * n2] - s;
+    }
+    M[f] = v;
   }
 }
 
@@ -392,7 +398,7 @@ void launch_coef(hipStream_t s, const SmallArgs &a) {
 }
 
 void launch_formM(hipStream_t s, const SmallArgs &a) {
-  const int64_t total = (int64_t)a.n2 * a.n2;
+  const int64_t total = mf_size(a.n2);
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1024));
   hipLaunchKernelGGL(k_formM, dim3(g), dim3(256), 0, s, a.n2, a.k, a.GA, a.B, a.M, a.st);
 }

@@ -58,6 +58,28 @@ template <typename T>
 void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, int64_t ld);
 
 // Small-step kernels (k_small.hip, k_eig.hip).
+// The eigen step's matrix M (n2 x n2, symmetric, double) is stored
+// fragment-major for v_mfma_f64_16x16x4f64: 16-row tiles, then pairs of
+// 4-column k-steps, then the 64 lanes of a wavefront, then the pair, so that
+// the A operand of two consecutive k-steps is one contiguous 16-byte read per
+// lane (lane = 16 * (column % 4) + row % 16).  The k-steps are padded to a
+// multiple of 8; entries past n2 are zero.
+__host__ __device__ inline int64_t mf_kq2(int n2) { return (((n2 + 3) / 4 + 7) & ~7) / 2; }
+__host__ __device__ inline int64_t mf_size(int n2) {
+  return (int64_t)((n2 + 15) / 16) * mf_kq2(n2) * 128;
+}
+__host__ __device__ inline int64_t mf_idx(int n2, int i, int j) {
+  const int q = j >> 2;
+  return ((((int64_t)(i >> 4) * mf_kq2(n2) + (q >> 1)) * 64 + (j & 3) * 16 + (i & 15)) << 1) + (q & 1);
+}
+// (row, column) of fragment-major offset f
+__host__ __device__ inline void mf_rc(int n2, int64_t f, int &i, int &j) {
+  const int h = (int)(f & 1), lane = (int)((f >> 1) & 63);
+  const int64_t T = f >> 7, kq2 = mf_kq2(n2);
+  i = (int)(T / kq2) * 16 + (lane & 15);
+  j = 4 * (2 * (int)(T % kq2) + h) + (lane >> 4);
+}
+
 struct SmallArgs {
   int k, n2, l, b;
   int nparts;              // workgroups of the last row pass (f1, dx1 pairs)

@@ -208,7 +208,7 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.R, (size_t)(kk * kk) * d},
       {(void **)&p.B, (size_t)(kk * n2) * d},
       {(void **)&p.C, (size_t)(kk * n2) * d},
-      {(void **)&p.M, (size_t)(n2 * n2) * d},
+      {(void **)&p.M, (size_t)mf_size((int)n2) * d},
       {(void **)&p.Y, (size_t)(n2 * WLRA_BMAX) * d},
       {(void **)&p.Wb, (size_t)(n2 * WLRA_BMAX) * d},
       {(void **)&p.F0, (size_t)(n2 * WLRA_BMAX) * d},

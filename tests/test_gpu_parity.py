@@ -103,6 +103,7 @@ SHAPES = [
     (20, 30, 150, 60, 64, False),
     (20, 30, 620, 50, 62, True),     # n2 = 570: eigen blocks outside LDS, chunked small steps
     (24, 25, 700, 12, 20, False),    # n2 = 688
+    (16, 16, 250, 20, 33, False),    # n2 = 230, block of 16: one-workgroup eigen step, blocks in global memory
 ]
 
 
@@ -119,6 +120,23 @@ def test_ragged_shapes_fp64(s64, h, w, n, k, r, const):
         X = np.hstack([X1, X2]) if k > 0 else X2
         assert rel(X, ref.X) <= 1e-10
         assert abs(res["objective"] - ref.F[-1]) <= 1e-11 * ref.F[-1]
+
+
+@pytest.mark.parametrize("h,w,n,k,r,const", [(20, 30, 620, 50, 62, True), (16, 16, 300, 20, 40, False)])
+def test_one_workgroup_eigen_step_for_large_n2(s64, monkeypatch, h, w, n, k, r, const):
+    """The one-workgroup eigen kernel also serves n2 >= 256 when the
+    cooperative launch is refused; WLRA_EIG_ONE_WG forces that path (with a
+    staged block narrower than 16 columns at n2 = 570)."""
+    monkeypatch.setenv("WLRA_EIG_ONE_WG", "1")
+    wspec = ("const", 7.5) if const else ("loguniform", 0.0, 2.5)
+    inst = video.make_instance(h, w, n, k, r, 2, fg="bernoulli", fg_p=0.1, fg_lo=0.5, fg_hi=1.0,
+                               noise=0.05, w1=wspec, seed=2000 + h * w + n + k)
+    ref = _oracle(inst, 0.0, 3)
+    X1, X2, res = gpu_solve(s64, inst, 0.0, 3)
+    print("one-workgroup eigen step", (h * w, n, k, r), res, flush=True)
+    assert res["rc"] in (0, 1)
+    assert rel(np.hstack([X1, X2]), ref.X) <= 1e-10
+    assert abs(res["objective"] - ref.F[-1]) <= 1e-11 * ref.F[-1]
 
 
 def test_fp32_ragged(s32):
