@@ -43,30 +43,38 @@ __device__ __forceinline__ int small_chol_wave(double *G, int nb, double shift, 
 
 // Symmetric eigendecomposition of H (nb x nb) by parallel cyclic Jacobi on
 // wavefront 0 (round-robin pairing, nb/2 disjoint rotations per round).
-// On return th[0..nb) is descending and S holds the eigenvectors.
-__device__ __forceinline__ void small_jacobi_wave(double *H, double *S, double *th, double *rc,
-                                                  double *rs, int *rp, int *rq, int *ints, int nb) {
+// A round applies all of its rotations from both sides in one pass,
+// H' = J^T H J and S' = S J, reading H, S and writing H2, S2 (the buffers
+// then swap): index x of pair (p, q) maps to al[x] * row x + be[x] * row
+// pt[x].  On return th[0..nb) is descending (ties by index) and S holds the
+// eigenvectors; H2 and S2 are scratch (WLRA_BMAX^2 doubles each), rk holds
+// nb ints of scratch.
+__device__ __forceinline__ void small_jacobi_wave(double *H, double *S, double *H2, double *S2,
+                                                  double *th, double *al, double *be, int *pt,
+                                                  int *rk, int nb) {
   const int t = threadIdx.x;
+  constexpr int L = WLRA_BMAX;
   if (t < 64) {
-    for (int e = t; e < WLRA_BMAX * WLRA_BMAX; e += 64) S[e] = ((e % WLRA_BMAX) == (e / WLRA_BMAX)) ? 1.0 : 0.0;
+    for (int e = t; e < L * L; e += 64) S[e] = ((e % L) == (e / L)) ? 1.0 : 0.0;
     // H = Y^T (M Y) is symmetric only to rounding: average the two triangles
     // so that the rotations can drive the off-diagonal mass to zero
     for (int e = t; e < nb * nb; e += 64) {
       const int a = e % nb, c = e / nb;
       if (a < c) {
-        const double v = 0.5 * (H[a + c * WLRA_BMAX] + H[c + a * WLRA_BMAX]);
-        H[a + c * WLRA_BMAX] = v;
-        H[c + a * WLRA_BMAX] = v;
+        const double v = 0.5 * (H[a + c * L] + H[c + a * L]);
+        H[a + c * L] = v;
+        H[c + a * L] = v;
       }
     }
     const int nbp = nb + (nb & 1);
     const int half = nbp / 2;
+    double *Hc = H, *Hn = H2, *Sc = S, *Sn = S2;
     wave_sync();
     for (int sweep = 0; sweep < 40; ++sweep) {
       double off = 0.0, tot = 0.0;
       for (int e = t; e < nb * nb; e += 64) {
         const int a = e % nb, c = e / nb;
-        const double v = H[a + c * WLRA_BMAX];
+        const double v = Hc[a + c * L];
         tot += v * v;
         if (a != c) off += v * v;
       }
@@ -84,78 +92,71 @@ __device__ __forceinline__ void small_jacobi_wave(double *H, double *S, double *
             p = q;
             q = tmp;
           }
-          double c = 1.0, sn = 0.0;
           if (q < nb) {
-            const double apq = H[p + q * WLRA_BMAX];
+            double c = 1.0, sn = 0.0;
+            const double apq = Hc[p + q * L];
             if (fabs(apq) > 1e-300) {
-              const double tau = (H[q + q * WLRA_BMAX] - H[p + p * WLRA_BMAX]) / (2.0 * apq);
+              const double tau = (Hc[q + q * L] - Hc[p + p * L]) / (2.0 * apq);
               const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
               c = 1.0 / sqrt(1.0 + tt * tt);
               sn = tt * c;
             }
-          } else {
-            q = p;  // dummy partner: identity
+            al[p] = c;
+            be[p] = -sn;
+            pt[p] = q;
+            al[q] = c;
+            be[q] = sn;
+            pt[q] = p;
+          } else {  // paired with the dummy index: identity
+            al[p] = 1.0;
+            be[p] = 0.0;
+            pt[p] = p;
           }
-          rp[t] = p;
-          rq[t] = q;
-          rc[t] = c;
-          rs[t] = sn;
         }
         wave_sync();
-        // rows p, q
-        for (int e = t; e < half * nb; e += 64) {
-          const int pr = e % half, x = e / half;
-          const int p = rp[pr], q = rq[pr];
-          if (p == q) continue;
-          const double c = rc[pr], sn = rs[pr];
-          const double hp = H[p + x * WLRA_BMAX], hq = H[q + x * WLRA_BMAX];
-          H[p + x * WLRA_BMAX] = c * hp - sn * hq;
-          H[q + x * WLRA_BMAX] = sn * hp + c * hq;
+        // upper triangle of J^T H J, mirrored (the result stays symmetric)
+        for (int e = t; e < nb * nb; e += 64) {
+          const int x = e % nb, y = e / nb;
+          if (x > y) continue;
+          const int px = pt[x], py = pt[y];
+          const double ax = al[x], bx = be[x], ay = al[y], by = be[y];
+          const double v = (ax * ay * Hc[x + y * L] + ax * by * Hc[x + py * L]) +
+                           (bx * ay * Hc[px + y * L] + bx * by * Hc[px + py * L]);
+          Hn[x + y * L] = v;
+          Hn[y + x * L] = v;
+        }
+        for (int e = t; e < nb * nb; e += 64) {
+          const int x = e % nb, y = e / nb;
+          Sn[x + y * L] = al[y] * Sc[x + y * L] + be[y] * Sc[x + pt[y] * L];
         }
         wave_sync();
-        // columns p, q of H and of S
-        for (int e = t; e < half * nb; e += 64) {
-          const int pr = e % half, x = e / half;
-          const int p = rp[pr], q = rq[pr];
-          if (p == q) continue;
-          const double c = rc[pr], sn = rs[pr];
-          const double hp = H[x + p * WLRA_BMAX], hq = H[x + q * WLRA_BMAX];
-          H[x + p * WLRA_BMAX] = c * hp - sn * hq;
-          H[x + q * WLRA_BMAX] = sn * hp + c * hq;
-          const double vp = S[x + p * WLRA_BMAX], vq = S[x + q * WLRA_BMAX];
-          S[x + p * WLRA_BMAX] = c * vp - sn * vq;
-          S[x + q * WLRA_BMAX] = sn * vp + c * vq;
-        }
-        wave_sync();
+        double *tp = Hc;
+        Hc = Hn;
+        Hn = tp;
+        tp = Sc;
+        Sc = Sn;
+        Sn = tp;
       }
     }
-    // eigenvalues, sorted descending (selection sort with column swaps)
-    for (int a = t; a < nb; a += 64) th[a] = H[a + a * WLRA_BMAX];
+    // eigenvalues descending (ties by index): rank of each, then the
+    // eigenvector columns move to their ranks, into S
+    for (int a = t; a < nb; a += 64) al[a] = Hc[a + a * L];
     wave_sync();
-    for (int a = 0; a < nb; ++a) {
-      if (t == 0) {
-        int best = a;
-        for (int c = a + 1; c < nb; ++c)
-          if (th[c] > th[best]) best = c;
-        ints[1] = best;
-      }
-      wave_sync();
-      const int best = ints[1];
-      if (best != a) {
-        for (int x = t; x < nb; x += 64) {
-          const double v = S[x + a * WLRA_BMAX];
-          S[x + a * WLRA_BMAX] = S[x + best * WLRA_BMAX];
-          S[x + best * WLRA_BMAX] = v;
-        }
-        if (t == 0) {
-          const double v = th[a];
-          th[a] = th[best];
-          th[best] = v;
-        }
-      }
-      wave_sync();
+    for (int a = t; a < nb; a += 64) {
+      int r = 0;
+      for (int c = 0; c < nb; ++c) r += (al[c] > al[a]) || (al[c] == al[a] && c < a);
+      rk[a] = r;
+      th[r] = al[a];
     }
+    wave_sync();
+    double *dst = (Sc == S) ? S2 : S;
+    for (int e = t; e < nb * nb; e += 64) {
+      const int x = e % nb, a = e / nb;
+      dst[x + rk[a] * L] = Sc[x + a * L];
+    }
+    wave_sync();
+    if (dst != S)
+      for (int e = t; e < nb * nb; e += 64) S[(e % nb) + (e / nb) * L] = dst[(e % nb) + (e / nb) * L];
   }
   __syncthreads();
 }
-

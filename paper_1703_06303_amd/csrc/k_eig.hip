@@ -189,20 +189,44 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
 }
 
 // G (p x q, ld B_) = X^T Y over n2 rows.  Global blocks are staged through
-// LDS first when they fit.  Each wavefront takes whole (a, c) pairs, lanes
-// stride over the rows and a fixed xor tree sums them (deterministic).
-// `diag` computes only a == c (p == q).
+// LDS first when they fit.  On the FP64 matrix cores: the output is cut into
+// 16 x 16 tiles (at most 4) and the inner index into chunks, one (tile,
+// chunk) per wavefront; the partial tiles are added in chunk order
+// (deterministic).  Column indices are clamped into the blocks (a clamped
+// column only feeds an output entry that is not stored) and the last k-step
+// is masked.  `diag` stores only a == c (p == q).
 __device__ __forceinline__ void gram_pairs(EigLDS &s, int n2, int xoff, int p, int yoff, int q,
                                            double *G, bool diag) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int pairs = diag ? p : p * q;
-  for (int pr = wv; pr < pairs; pr += ET / 64) {
-    const int a = diag ? pr : pr % p, c = diag ? pr : pr / p;
-    const int xa = xoff + a * n2, yc = yoff + c * n2;
-    double acc = 0.0;
-    for (int i = lane; i < n2; i += 64) acc = fma(s.pool[xa + i], s.pool[yc + i], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) G[a + c * B_] = acc;
+  const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int tp = (p + 15) / 16, tq = (q + 15) / 16, T = tp * tq;
+  const int K = (ET / 64) / T;
+  double *part = s.pool + PART_OFF;  // (ET / 64) partial tiles
+  if (wv < T * K) {
+    const int tile = wv % T, kc = wv / T;
+    const int ti = tile % tp, tj = tile / tp;
+    const int ks = (n2 + 3) / 4, per = (ks + K - 1) / K;
+    const int s0 = kc * per, s1 = min(ks, s0 + per);
+    const double *xa = s.pool + xoff + min(16 * ti + li, p - 1) * n2;
+    const double *yb = s.pool + yoff + min(16 * tj + li, q - 1) * n2;
+    eig_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int st = s0; st < s1; ++st) {
+      const int kk = 4 * st + lk;
+      const double av = xa[min(kk, n2 - 1)];
+      const double bv = (kk < n2) ? yb[kk] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[wv * 256 + (lk + 4 * v) * 16 + li] = acc[v];
+  }
+  __syncthreads();
+  for (int e = t; e < p * q; e += ET) {
+    const int a = e % p, c = e / p;
+    if (diag && a != c) continue;
+    const int tile = (a >> 4) + (c >> 4) * tp;
+    double sum = 0.0;
+    for (int kc = 0; kc < K; ++kc) sum += part[(tile + kc * T) * 256 + (a & 15) * 16 + (c & 15)];
+    G[a + c * B_] = sum;
   }
   __syncthreads();
 }
@@ -315,34 +339,41 @@ __device__ __forceinline__ void blk_trsm(EigLDS &s, int n2, Blk<RES> X, int nb, 
 template <bool RES>
 __device__ __forceinline__ void blk_deflate(EigLDS &s, const EigCtx &cx, Blk<RES> Y, int q0, int q1) {
   const int t = threadIdx.x, n2 = cx.n2;
-  const int64_t nn = mf_size(n2);
+  const int nn = (int)mf_size(n2), kq2 = (int)mf_kq2(n2);
+  // offset f = e0 + u * ET: its lane/pair bits are fixed by t, its 128-double
+  // block advances by 4 per u (no division in the loop)
+  const int h = t & 1, lane = (t >> 1) & 63;
+  const int ri = lane & 15, cj = 4 * h + (lane >> 4);
   double *M = cx.Mw;
-  for (int64_t e0 = t; e0 < nn; e0 += 8 * ET) {
-    double v[8];
-    int ii[8], jj[8];
+  for (int e0 = t; e0 < nn; e0 += 16 * ET) {
+    double v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      v[u] = M[min(e0 + u * ET, nn - 1)];
-      mf_rc(n2, min(e0 + u * ET, nn - 1), ii[u], jj[u]);
+    for (int u = 0; u < 16; ++u) v[u] = M[min(e0 + u * ET, nn - 1)];
+    const int T0 = e0 >> 7;
+    int rt = T0 / kq2, q2 = T0 - rt * kq2;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = rt * 16 + ri, j = 8 * q2 + cj;
+      if (e0 + u * ET < nn && i < n2 && j < n2)
+        for (int a = q0; a < q1; ++a) v[u] -= s.th[a] * Y.at(s, i + a * n2) * Y.at(s, j + a * n2);
+      q2 += 4;
+      if (q2 >= kq2) {
+        q2 -= kq2;
+        ++rt;
+      }
     }
-    for (int a = q0; a < q1; ++a) {
-      const double th = s.th[a];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (ii[u] < n2 && jj[u] < n2) v[u] -= th * Y.at(s, ii[u] + a * n2) * Y.at(s, jj[u] + a * n2);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 16; ++u)
       if (e0 + u * ET < nn) M[e0 + u * ET] = v[u];
   }
   __syncthreads();
 }
 
 // Symmetric eigendecomposition of H (nb x nb) by parallel cyclic Jacobi on
-// wavefront 0.  On return th[0..nb) is descending and S holds the
-// eigenvectors.
+// wavefront 0, with G and the partial-sum region of the pool as scratch.  On
+// return th[0..nb) is descending and S holds the eigenvectors.
 __device__ __forceinline__ void blk_jacobi(EigLDS &s, int nb) {
-  small_jacobi_wave(s.H, s.S, s.th, s.rc, s.rs, s.rp, s.rq, s.ints, nb);
+  small_jacobi_wave(s.H, s.S, s.G, s.pool + PART_OFF, s.th, s.rc, s.rs, s.rp, s.rq, nb);
 }
 
 // Orthonormalise the nb columns of X against the `locked` columns of L and

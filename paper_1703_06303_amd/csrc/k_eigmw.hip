@@ -388,19 +388,35 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
                               1e-6 * fabs(mjj) * hash_unit((uint32_t)i, (uint32_t)q) + 1e-300;
     }
     __syncthreads();
-    if (mw_orth(c, s, Y, b, Y, 0)) {
-      if (c.g == 0 && t == 0) atomicOr(a.flags, DEV_EIG_MAXIT);
-      return;
-    }
   }
-  mw_op(c, s, Y, b, W);
-  mw_gram(c, Y, b, W, b, s.H);
-  small_jacobi_wave(s.H, s.S, s.th, s.rc, s.rs, s.rp, s.rq, s.ints, b);
-  mw_rot(c, s, Y, b, s.S);
-  mw_rot(c, s, W, b, s.S);
-
-  int locked = 0, it = 0, nmv = b;
+  // each round: re-orthonormalisation (after a filter, or of a cold start),
+  // Rayleigh-Ritz on the active columns, residuals and locking, then the
+  // filter (a single copy of each step keeps the kernel's register use down)
+  int locked = 0, it = 0, nmv = 0;
+  bool orth = first;  // a cold start orthonormalises its columns first
   while (true) {
+    if (orth && mw_orth(c, s, Y + (size_t)locked * n2, b - locked, Y, locked)) {
+      if (c.g == 0 && t == 0) atomicOr(a.flags, DEV_EIG_MAXIT);
+      if (it == 0 && first) return;  // nothing valid to report
+      break;
+    }
+    const int act = b - locked;
+    double *Ya = Y + (size_t)locked * n2;
+    double *Wa = W + (size_t)locked * n2;
+    mw_op(c, s, Ya, act, Wa);
+    nmv += act;
+    mw_gram(c, Ya, act, Wa, act, s.H);
+    for (int q = t; q < locked; q += MW_T) s.keep[q] = s.th[q];
+    __syncthreads();
+    small_jacobi_wave(s.H, s.S, s.G, &s.tile[0][0], s.th, s.rc, s.rs, s.rp, s.rq, act);
+    mw_rot(c, s, Ya, act, s.S);
+    mw_rot(c, s, Wa, act, s.S);
+    if (t == 0) {
+      for (int q = act - 1; q >= 0; --q) s.th[locked + q] = s.th[q];
+      for (int q = 0; q < locked; ++q) s.th[q] = s.keep[q];
+    }
+    __syncthreads();
+
     mw_resid(c, s, W, Y, locked, l);
     if (t == 0) {
       int lk = locked;
@@ -419,8 +435,8 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
     if (newl > locked) mw_deflate(c, s, Y, locked, newl);
     locked = newl;
 
-    const int act = b - locked;
-    double *Ya = Y + (size_t)locked * n2;
+    const int actf = b - locked;
+    double *Yf = Y + (size_t)locked * n2;
     const double cc = s.th[b - 1];
     const double e0 = 0.5 * cc;
     double h = 0.5 * cc;
@@ -440,20 +456,20 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
     const double sigma = h / (top - e0), tau = 2.0 / sigma;
     double s1 = sigma;
     double *P0 = F0, *P1 = F1, *P2 = F2;
-    for (int e = t; e < nr * act; e += MW_T) {
+    for (int e = t; e < nr * actf; e += MW_T) {
       const int i = c.r0 + e % nr, q = e / nr;
-      P0[i + (size_t)q * n2] = Ya[i + (size_t)q * n2];
+      P0[i + (size_t)q * n2] = Yf[i + (size_t)q * n2];
     }
-    mw_op(c, s, P0, act, P1);
-    for (int e = t; e < nr * act; e += MW_T) {
+    mw_op(c, s, P0, actf, P1);
+    for (int e = t; e < nr * actf; e += MW_T) {
       const size_t o = c.r0 + e % nr + (size_t)(e / nr) * n2;
       P1[o] = (P1[o] - e0 * P0[o]) * (s1 / h);
     }
-    nmv += act * (d + 1);
+    nmv += actf * d;
     for (int j = 2; j <= d; ++j) {
       const double s2 = 1.0 / (tau - s1);
-      mw_op(c, s, P1, act, P2);
-      for (int e = t; e < nr * act; e += MW_T) {
+      mw_op(c, s, P1, actf, P2);
+      for (int e = t; e < nr * actf; e += MW_T) {
         const size_t o = c.r0 + e % nr + (size_t)(e / nr) * n2;
         P2[o] = 2.0 * (s2 / h) * (P2[o] - e0 * P1[o]) - (s1 * s2) * P0[o];
       }
@@ -463,28 +479,12 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
       P2 = tmp;
       s1 = s2;
     }
-    for (int e = t; e < nr * act; e += MW_T) {
+    for (int e = t; e < nr * actf; e += MW_T) {
       const size_t o = c.r0 + e % nr + (size_t)(e / nr) * n2;
-      Ya[o] = P1[o];
+      Yf[o] = P1[o];
     }
     __syncthreads();
-    if (mw_orth(c, s, Ya, act, Y, locked)) {
-      if (c.g == 0 && t == 0) atomicOr(a.flags, DEV_EIG_MAXIT);
-      break;
-    }
-    double *Wa = W + (size_t)locked * n2;
-    mw_op(c, s, Ya, act, Wa);
-    mw_gram(c, Ya, act, Wa, act, s.H);
-    for (int q = t; q < locked; q += MW_T) s.keep[q] = s.th[q];
-    __syncthreads();
-    small_jacobi_wave(s.H, s.S, s.th, s.rc, s.rs, s.rp, s.rq, s.ints, act);
-    mw_rot(c, s, Ya, act, s.S);
-    mw_rot(c, s, Wa, act, s.S);
-    if (t == 0) {
-      for (int q = act - 1; q >= 0; --q) s.th[locked + q] = s.th[q];
-      for (int q = 0; q < locked; ++q) s.th[q] = s.keep[q];
-    }
-    __syncthreads();
+    orth = true;
     ++it;
   }
   if (c.g == 0) {

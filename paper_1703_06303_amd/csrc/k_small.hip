@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_formM(int n2, int k, const double *__re
   for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
        f += (int64_t)gridDim.x * blockDim.x) {
     int i, j;
-    mf_rc(n2, f, i, j);
+    mf_rc(n2, (int)f, i, j);
     double v = 0.0;
     if (i < n2 && j < n2) {
       const double *bi = B + (int64_t)i * k, *bj = B + (int64_t)j * k;

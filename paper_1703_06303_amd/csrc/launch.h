@@ -72,12 +72,13 @@ __host__ __device__ inline int64_t mf_idx(int n2, int i, int j) {
   const int q = j >> 2;
   return ((((int64_t)(i >> 4) * mf_kq2(n2) + (q >> 1)) * 64 + (j & 3) * 16 + (i & 15)) << 1) + (q & 1);
 }
-// (row, column) of fragment-major offset f
-__host__ __device__ inline void mf_rc(int n2, int64_t f, int &i, int &j) {
-  const int h = (int)(f & 1), lane = (int)((f >> 1) & 63);
-  const int64_t T = f >> 7, kq2 = mf_kq2(n2);
-  i = (int)(T / kq2) * 16 + (lane & 15);
-  j = 4 * (2 * (int)(T % kq2) + h) + (lane >> 4);
+// (row, column) of fragment-major offset f (< 2^31 for n2 <= WLRA_NMAX)
+__host__ __device__ inline void mf_rc(int n2, int f, int &i, int &j) {
+  const int h = f & 1, lane = (f >> 1) & 63;
+  const int T = f >> 7, kq2 = (int)mf_kq2(n2);
+  const int rt = T / kq2;
+  i = rt * 16 + (lane & 15);
+  j = 4 * (2 * (T - rt * kq2) + h) + (lane >> 4);
 }
 
 struct SmallArgs {
