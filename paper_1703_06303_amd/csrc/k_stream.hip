@@ -216,106 +216,111 @@ __global__ __launch_bounds__(256) void k_f1(int64_t m, int k, const T *__restric
 // When W1 is one constant w, K = w^2 I + S is shared: the small step
 // pre-multiplies Z, T and S by K^-1 and no per-row solve is needed.
 //
-// Work split: a workgroup owns 64 rows (one per lane); its upd_nw wavefronts
-// each take a contiguous slice of the n columns of A = [A1 A2] against
-// G = [-S; Z] (n x k, row-major, input index first) and wavefront 0 adds
-// x1 T; the slices are summed in a fixed order through LDS.  With a constant
-// weight wavefront 0 writes X1' = A1 + e directly; otherwise it stores the
-// right-hand sides e for k_rowsolve.
+// Work split: a workgroup owns 64 rows; E (64 x k) = [A1 A2 X1] [-S; Z; T]
+// is a product with inner dimension n + k, run on the matrix cores
+// (v_mfma_f32_16x16x4f32 for float, v_mfma_f64_16x16x4f64 for double; BF16
+// entries of A2 are widened exactly): wavefront w owns rows 16w..16w+15 and
+// all 16-column tiles of E.  Rows of B = [-S; Z; T] (input index first) are
+// staged through LDS in chunks, zero past k; each wavefront reads its A
+// operand straight from global memory, UB k-steps of 4 at a time with all
+// reads in flight (clamped, so never masked), and sums in a fixed order.
+// E goes through LDS to wavefront 0, one row per lane, which finishes as
+// before: with a constant weight it writes X1' = A1 + e directly; otherwise
+// it stores the right-hand sides e for k_rowsolve.
 // Partials per workgroup: (||(A1 - X1') o W1||^2, ||X1' - X1||^2).
-// wavefronts per workgroup: 8 while the k accumulators fit the register
-// budget of 512 threads, 4 for k > 32
+// MFMA fragment layouts (lane l): A[l % 16][l / 16], B[l / 16][l % 16];
+// accumulator v holds D[4 (l / 16) + v][l % 16] (float) or
+// D[l / 16 + 4 v][l % 16] (double).
+#define UPD_T 256
+template <typename T>
+struct UpdMma;
+template <>
+struct UpdMma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+template <>
+struct UpdMma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
 template <int KMAX>
-constexpr int upd_nw() { return KMAX <= 32 ? 8 : 4; }
+constexpr int upd_kp() { return ((KMAX + 15) / 16) * 16; }
 template <typename T, int KMAX, bool CONSTW, typename TA2>
-__global__ __launch_bounds__(64 * upd_nw<KMAX>()) void k_update(
+__global__ __launch_bounds__(UPD_T) void k_update(
     int64_t m, int k, int n, const T *__restrict__ A, int64_t lda, const TA2 *__restrict__ A2,
     int64_t lda2, const T *__restrict__ W1,
     int64_t ldw, T wc, const T *__restrict__ X1o, T *__restrict__ X1n, const T *__restrict__ Gt,
     const T *__restrict__ Tt, const T *__restrict__ St, double *__restrict__ part,
     T *__restrict__ Eb, int grows, const SmallState *__restrict__ st) {
   if (st->done) return;
-  // LDS: [staged rows of G (grows elements) | reused as the k x 64 slice sum]
-  //      [T k x k] [S k x k]
+  constexpr int KP = upd_kp<KMAX>(), NT = KP / 16, UB = 32;
+  typedef typename UpdMma<T>::acc_t acc_t;
+  // LDS: [B chunk: grows x KP] [E: 64 x (KP + 1)]
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *sG = reinterpret_cast<T *>(smem_raw);
-  T *red = sG;
-  T *sT = sG + grows;
-  T *sS = sT + k * k;
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-  const bool act = i < m;
-  const int64_t ir = act ? i : (m - 1);
-
-  for (int e = threadIdx.x; e < k * k; e += 64 * upd_nw<KMAX>()) {
-    sT[e] = Tt[e];
-    sS[e] = St[e];
+  T *sB = reinterpret_cast<T *>(smem_raw);
+  T *sE = sB + (size_t)grows * KP;
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int ntot = n + k;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int64_t ra = min(r0 + 16 * w + li, m - 1);  // this lane's A-operand row (clamped)
+  acc_t acc[NT];
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct) acc[ct] = acc_t{0, 0, 0, 0};
+  for (int j0 = 0; j0 < ntot; j0 += grows) {
+    const int jl = min(grows, ntot - j0);
+    const int nsteps = (jl + 3) / 4;
+    __syncthreads();
+    for (int e = t; e < 4 * nsteps * KP; e += UPD_T) {
+      const int jr = e / KP, c = e - jr * KP, j = j0 + jr;
+      T v = T(0);
+      if (jr < jl && c < k) v = (j < n) ? Gt[(int64_t)j * k + c] : Tt[(j - n) * k + c];
+      sB[e] = v;
+    }
+    __syncthreads();
+    for (int s0 = 0; s0 < nsteps; s0 += UB) {
+      T av[UB];
+#pragma unroll
+      for (int u0 = 0; u0 < UB; u0 += 8) {
+        if (s0 + u0 < nsteps) {
+#pragma unroll
+          for (int u = u0; u < u0 + 8; ++u) {
+            // clamped column: past n + k the staged B rows are zero
+            const int jc = min(j0 + 4 * (s0 + u) + lk, ntot - 1);
+            av[u] = (jc < n) ? a_elem<T, TA2>(A, lda, A2, lda2, k, ra, jc) : X1o[ra + (int64_t)(jc - n) * m];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (s0 + u < nsteps) {
+          const T *brow = sB + (4 * (s0 + u) + lk) * KP + li;
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) acc[ct] = UpdMma<T>::mma(av[u], brow[16 * ct], acc[ct]);
+        }
+      }
+    }
   }
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      sE[(16 * w + UpdMma<T>::row(lk, v)) * (KP + 1) + 16 * ct + li] = acc[ct][v];
+  __syncthreads();
+  if (w > 0) return;
+  const int64_t i = r0 + lane;
+  const bool act = i < m;
   T e[KMAX];
 #pragma unroll
-  for (int c = 0; c < KMAX; ++c) e[c] = T(0);
-  __syncthreads();
-  if (w == 0) {
-    T xo[KMAX];
-#pragma unroll
-    for (int cp = 0; cp < KMAX; ++cp) xo[cp] = (cp < k) ? X1o[ir + (int64_t)cp * m] : T(0);
-#pragma unroll
-    for (int cp = 0; cp < KMAX; ++cp)
-      if (cp < k) {
-        const T *row = sT + cp * k;
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c)
-          if (c < k) e[c] = fma(xo[cp], row[c], e[c]);
-      }
-  }
-  // A = [A1 A2] times G = [-S; Z], rows of G staged through LDS in chunks.
-  const int rows_per = grows / k;
-  for (int c0 = 0; c0 < n; c0 += rows_per) {
-    const int c1 = min(n, c0 + rows_per);
-    __syncthreads();
-    for (int e2 = threadIdx.x; e2 < (c1 - c0) * k; e2 += 64 * upd_nw<KMAX>())
-      sG[e2] = Gt[(int64_t)c0 * k + e2];
-    __syncthreads();
-    const int len = c1 - c0;
-    const int j0 = c0 + w * len / upd_nw<KMAX>(), j1 = c0 + (w + 1) * len / upd_nw<KMAX>();
-    int j = j0;
-    for (; j + 8 <= j1; j += 8) {
-      T v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = a_elem<T, TA2>(A, lda, A2, lda2, k, ir, j + u);
-      const T *g = sG + (j - c0) * k;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c)
-          if (c < k) e[c] = fma(v[u], g[u * k + c], e[c]);
-      }
-    }
-    for (; j < j1; ++j) {
-      const T v0 = a_elem<T, TA2>(A, lda, A2, lda2, k, ir, j);
-      const T *g = sG + (j - c0) * k;
-#pragma unroll
-      for (int c = 0; c < KMAX; ++c)
-        if (c < k) e[c] = fma(v0, g[c], e[c]);
-    }
-  }
-  // fixed-order sum of the wavefront slices into wavefront 0
-  for (int q = 1; q < upd_nw<KMAX>(); ++q) {
-    __syncthreads();
-    if (w == q) {
-#pragma unroll
-      for (int c = 0; c < KMAX; ++c)
-        if (c < k) red[c * 64 + lane] = e[c];
-    }
-    __syncthreads();
-    if (w == 0) {
-#pragma unroll
-      for (int c = 0; c < KMAX; ++c)
-        if (c < k) e[c] += red[c * 64 + lane];
-    }
-  }
-  if (w > 0) return;
+  for (int c = 0; c < KMAX; ++c) e[c] = (c < k) ? sE[lane * (KP + 1) + c] : T(0);
 
   if (!CONSTW) {
     // right-hand sides for the per-row solve (k_rowsolve)
@@ -899,13 +904,10 @@ void launch_f1(hipStream_t s, int64_t m, int k, const T *A, int64_t lda, const T
 template <typename T>
 UpdatePlan update_plan(int k, bool constw) {
   UpdatePlan pl;
-  const size_t cap = 163840 - 1024;
-  const size_t fixed = (size_t)2 * k * k * sizeof(T);
-  size_t g = std::min<size_t>(8192, (cap - fixed) / sizeof(T));
-  g = std::max<size_t>(g, (size_t)k * 64);
-  g = g / k * k;
-  pl.grows = (int)g;
-  pl.shm = (g + 2 * (size_t)k * k) * sizeof(T);
+  // rows of B = [-S; Z; T] staged per chunk (a multiple of 4, 64 KiB of LDS)
+  const int kp = ((k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64) + 15) / 16 * 16;
+  pl.grows = (int)(65536 / ((size_t)kp * sizeof(T)));
+  pl.shm = ((size_t)pl.grows * kp + (size_t)64 * (kp + 1)) * sizeof(T);
   const size_t per = (size_t)(k * (k + 1) / 2 + 2 * k) * sizeof(T);
   pl.nl = 64;
   while (pl.nl > 1 && per * pl.nl + (size_t)k * k * sizeof(T) > 65536) pl.nl >>= 1;
@@ -920,7 +922,7 @@ static void launch_update_kernel(hipStream_t s, const UpdateArgs<T> &a, const TA
   if (pl.shm > 65536)
     (void)hipFuncSetAttribute((const void *)k_update<T, KMAX, CONSTW, TA2>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.shm);
-  hipLaunchKernelGGL((k_update<T, KMAX, CONSTW, TA2>), dim3(grid), dim3(64 * upd_nw<KMAX>()), pl.shm, s,
+  hipLaunchKernelGGL((k_update<T, KMAX, CONSTW, TA2>), dim3(grid), dim3(UPD_T), pl.shm, s,
                      a.m, a.k, a.n, a.A, a.lda, A2, lda2, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Gt,
                      a.Tt, a.St, a.part, a.Eb, pl.grows, a.st);
 }
