@@ -31,15 +31,16 @@ __global__ __launch_bounds__(256) void k_gastats(int n2, const double *__restric
 }
 
 // -----------------------------------------------------------------------------
-// Columns of P are staged through LDS (stride k+1) in chunks; one thread
-// solves one column in place: forward with R^T gives B, backward with R
-// gives C.
-#define COEF_STAGE 12288
+// Cholesky of G1 = X1^T X1 by wavefront 0 (rank check on the pivots); then
+// one thread per column of P: forward substitution with R^T gives that
+// column of B, backward substitution with R gives the column of C, the
+// column held in registers (k <= KMAX) and R read from LDS (every thread
+// reads the same entry at once).
+template <int KMAX>
 __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
   SmallState *st = a.st;
   if (st->done) return;
   __shared__ double sR[64 * 64];
-  __shared__ double sP[COEF_STAGE];
   __shared__ double red[4];
   __shared__ int fail;
   const int k = a.k, n2 = a.n2, t = threadIdx.x;
@@ -56,7 +57,10 @@ __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
     st->dx1 = dx;
     fail = 0;
   }
-  for (int e = t; e < k * k; e += 256) sR[(e % k) + (e / k) * 64] = a.G1[e];
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int r = e % 64, c = e / 64;
+    sR[e] = (r < k && c < k) ? a.G1[r + c * k] : 0.0;
+  }
   __syncthreads();
   double gmax = 0, tr = 0;
   for (int i = 0; i < k; ++i) {
@@ -66,26 +70,32 @@ __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
   // A pivot below k * eps * max diag(X1^T X1) means X1 is numerically
   // rank deficient (cond(X1) > 1 / sqrt(k eps)).
   const double thr = (double)k * 2.220446049250313e-16 * gmax;
-  for (int j = 0; j < k; ++j) {
-    if (t == 0) {
-      double p = sR[j + j * 64];
-      if (!(p > thr)) {
-        fail = 1;
-        p = gmax > 0 ? gmax : 1.0;
+  if (t < 64) {
+    for (int j = 0; j < k; ++j) {
+      if (t == 0) {
+        double p = sR[j + j * 64];
+        if (!(p > thr)) {
+          fail = 1;
+          p = gmax > 0 ? gmax : 1.0;
+        }
+        sR[j + j * 64] = sqrt(p);
       }
-      sR[j + j * 64] = sqrt(p);
+      wave_sync();
+      const double rjj = sR[j + j * 64];
+      for (int c = j + 1 + t; c < k; c += 64) sR[j + c * 64] /= rjj;
+      wave_sync();
+      const int rem = k - j - 1;
+      for (int e = t; e < rem * rem; e += 64) {
+        const int aa = j + 1 + e % rem, cc = j + 1 + e / rem;
+        if (aa <= cc) sR[aa + cc * 64] -= sR[j + aa * 64] * sR[j + cc * 64];
+      }
+      wave_sync();
     }
-    __syncthreads();
-    const double rjj = sR[j + j * 64];
-    for (int c = j + 1 + t; c < k; c += 256) sR[j + c * 64] /= rjj;
-    __syncthreads();
-    const int rem = k - j - 1;
-    for (int e = t; e < rem * rem; e += 256) {
-      const int aa = j + 1 + e % rem, cc = j + 1 + e / rem;
-      if (aa <= cc) sR[aa + cc * 64] -= sR[j + aa * 64] * sR[j + cc * 64];
-    }
-    __syncthreads();
+    // the strict lower triangle is never read below; keep it zero
+    for (int e = t; e < k * k; e += 64)
+      if ((e % k) > (e / k)) sR[(e % k) + (e / k) * 64] = 0.0;
   }
+  __syncthreads();
   if (fail) {
     if (t == 0) {
       atomicOr(a.flags, DEV_RANK);
@@ -97,39 +107,47 @@ __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
     const int r = e % k, c = e / k;
     a.R[e] = (r <= c) ? sR[r + c * 64] : 0.0;
   }
-  const int ld = k + 1;
-  const int cw = max(1, COEF_STAGE / max(ld, 1));
   double nb2 = 0.0;
-  for (int j0 = 0; j0 < n2; j0 += cw) {
-    const int nc = min(cw, n2 - j0);
-    for (int e = t; e < nc * k; e += 256) sP[(e % k) + (e / k) * ld] = a.P[(int64_t)j0 * k + e];
-    __syncthreads();
-    for (int jj = t; jj < nc; jj += 256) {  // B = R^-T P
-      double *x = sP + jj * ld;
-      for (int i = 0; i < k; ++i) {
+  for (int jj = t; jj < n2; jj += 256) {
+    const double *pc = a.P + (int64_t)jj * k;
+    double x[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) x[i] = (i < k) ? pc[i] : 0.0;
+    // B = R^-T P
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      if (i < k) {
         double s = x[i];
+#pragma unroll
         for (int q = 0; q < i; ++q) s -= sR[q + i * 64] * x[q];
         x[i] = s / sR[i + i * 64];
       }
+      // keep the reads of R inside their row (unrolled, the compiler would
+      // otherwise hoist all of R into registers)
+      asm volatile("" ::: "memory");
     }
-    __syncthreads();
-    for (int e = t; e < nc * k; e += 256) {
-      const double v = sP[(e % k) + (e / k) * ld];
-      a.B[(int64_t)j0 * k + e] = v;
-      nb2 += v * v;
-    }
-    __syncthreads();
-    for (int jj = t; jj < nc; jj += 256) {  // C = R^-1 B
-      double *x = sP + jj * ld;
-      for (int i = k - 1; i >= 0; --i) {
+    double *bc = a.B + (int64_t)jj * k;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+      if (i < k) {
+        bc[i] = x[i];
+        nb2 += x[i] * x[i];
+      }
+    // C = R^-1 B (entries past k are zero on both sides)
+#pragma unroll
+    for (int i = KMAX - 1; i >= 0; --i) {
+      if (i < k) {
         double s = x[i];
-        for (int q = i + 1; q < k; ++q) s -= sR[i + q * 64] * x[q];
+#pragma unroll
+        for (int q = i + 1; q < KMAX; ++q) s -= sR[i + q * 64] * x[q];
         x[i] = s / sR[i + i * 64];
       }
+      asm volatile("" ::: "memory");
     }
-    __syncthreads();
-    for (int e = t; e < nc * k; e += 256) a.C[(int64_t)j0 * k + e] = sP[(e % k) + (e / k) * ld];
-    __syncthreads();
+    double *cc = a.C + (int64_t)jj * k;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+      if (i < k) cc[i] = x[i];
   }
   nb2 = block_sum(nb2, red);
   if (t == 0) {
@@ -394,7 +412,10 @@ void launch_gastats(hipStream_t s, int n2, const double *GA, SmallState *st) {
 }
 
 void launch_coef(hipStream_t s, const SmallArgs &a) {
-  hipLaunchKernelGGL(k_coef, dim3(1), dim3(256), 0, s, a);
+  if (a.k <= 8) hipLaunchKernelGGL(k_coef<8>, dim3(1), dim3(256), 0, s, a);
+  else if (a.k <= 16) hipLaunchKernelGGL(k_coef<16>, dim3(1), dim3(256), 0, s, a);
+  else if (a.k <= 32) hipLaunchKernelGGL(k_coef<32>, dim3(1), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_coef<64>, dim3(1), dim3(256), 0, s, a);
 }
 
 void launch_formM(hipStream_t s, const SmallArgs &a) {
