@@ -131,6 +131,8 @@ struct Sizes {
   int64_t rows_l1, rows_l2, rows_l3;
   int splits_kg;  // H^T H of the change pass (n2 rows)
   int64_t rows_kg;
+  int splits_g1;  // X1^T X1
+  int64_t rows_g1;
 };
 
 struct Ptrs {
@@ -150,8 +152,10 @@ struct Ptrs {
   int *flags;
 };
 
+// Row splits of a tall-skinny product: about 2048 workgroups in all (eight
+// per CU, so that each walks few row chunks), at least 256 rows each.
 int choose_splits(int64_t m, int tiles, int64_t *rows) {
-  int s = (int)std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, (m + 255) / 256));
+  int s = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles, (m + 255) / 256));
   int64_t r = (m + s - 1) / s;
   r = (r + 31) / 32 * 32;
   s = (int)((m + r - 1) / r);
@@ -170,6 +174,10 @@ Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mi
   z.splits_ga = choose_splits(m, std::max(1, tga), &z.rows_ga);
   const int tp = (int)(((std::max<int64_t>(k, 1) + 31) / 32) * ((z.n2 + 31) / 32));
   z.splits_p = choose_splits(m, std::max(1, tp), &z.rows_p);
+  {
+    const int tk1 = (int)((std::max<int64_t>(k, 1) + 31) / 32);
+    z.splits_g1 = choose_splits(m, tk1 * tk1, &z.rows_g1);
+  }
   z.splits_l1 = choose_splits(m, (int)((n + 31) / 32), &z.rows_l1);
   z.splits_l2 = choose_splits(m, 1, &z.rows_l2);
   z.splits_l3 = choose_splits(m, (int)((std::max<int64_t>(k, 1) + 31) / 32), &z.rows_l3);
@@ -195,7 +203,7 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
   const size_t part = std::max<size_t>(
       std::max<size_t>((size_t)z.splits_ga * n2 * n2,
                        (size_t)z.splits_p * std::max<int64_t>(kk * n2, kk * kk)),
-      (size_t)z.splits_kg * Kc * Kc);
+      std::max<size_t>((size_t)z.splits_kg * Kc * Kc, (size_t)z.splits_g1 * kk * kk));
   struct Item { void **dst; size_t bytes; };
   Ptrs p{};
   Item items[] = {
@@ -421,7 +429,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   if (k > 0) {
     gram_X1A2(X1c, on_bf16);
     PROF(h, KK_XTX,
-         (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_p, z.rows_p,
+         (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_g1, z.rows_g1,
                               P.part, P.G1, nullptr)));
     PROF(h, KK_F1, launch_f1<T>(s, m, (int)k, A, pr->lda, W1, pr->ldw, wc, X1c, P.upd_part,
                                 z.nwg_f1));
@@ -512,7 +520,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     PROF(h, KK_UPDATE, launch_update<T>(s, ua));
     gram_X1A2(X1n, on_bf16);
     PROF(h, KK_XTX,
-         (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_p, z.rows_p,
+         (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_g1, z.rows_g1,
                               P.part, P.G1, nullptr)));
     nparts = z.nwg_upd;
     cur ^= 1;
