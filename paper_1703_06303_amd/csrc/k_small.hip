@@ -182,7 +182,8 @@ __global__ __launch_bounds__(256) void k_formM(int n2, int k, const double *__re
 // k_post (1024 threads).  The two long sums over n2 (CV = C V and S = C C^T)
 // stage column chunks of C and row chunks of V through LDS, each thread
 // owning fixed output entries; everything else is elementwise with short
-// inner products.  Small matrices are column-major in the global scratch.
+// inner products.  Small matrices are column-major in the global scratch
+// (CV, S, T, K^-1); the n2-row outputs are left to k_postz.
 
 // In-place Cholesky (upper, K = R^T R) of a k x k matrix in LDS (ld 64).
 __device__ int small_chol64(double *K, int k, int *fail) {
@@ -227,8 +228,7 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
   double *CV = ws;                       // k x l
   double *S = CV + 64 * 32;              // k x k
   double *Tm = S + 64 * 64;              // k x k
-  double *Zk = Tm + 64 * 64;             // n2 x k row-major, K^-1 folded in
-  double *Zd = a.Zcur;                   // n2 x k row-major, plain Z
+  double *Ki = Tm + 64 * 64;             // K^-1, k x k (constant weight)
 
   // ---- CV = C V and S = C C^T ----------------------------------------------
   const int ncv = k * l, nss = k * k, nout = ncv + nss;
@@ -275,19 +275,6 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
     for (int q = 0; q < l; ++q) s_ = fma(CV[c + q * k], CV[d + q * k], s_);
     Tm[e] = s_;
   }
-  for (int e = t; e < n2 * k; e += 1024) {
-    const int j = e / k, c = e - j * k;
-    double s_ = a.C[(int64_t)j * k + c];
-    for (int q = 0; q < l; ++q) s_ -= V[j + (int64_t)q * n2] * CV[c + q * k];
-    Zd[e] = s_;
-    o.Zx[e] = (T)s_;
-  }
-  for (int e = t; e < n2 * l; e += 1024) {
-    const int j = e / l, q = e - j * l;
-    const double v = V[j + (int64_t)q * n2];
-    a.Vcur[e] = v;
-    o.Vr[e] = (T)v;
-  }
   __syncthreads();
   const bool constw = a.wconst > 0;
   if (constw) {
@@ -316,23 +303,27 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
       sK[r + c * 64] = v;
     }
     __syncthreads();
-    // S K^-1, T K^-1 (col-major k x k) and Z K^-1 (row-major n2 x k)
+    // S K^-1, T K^-1 (col-major k x k), each factor staged in LDS (sC is
+    // free now; k*k <= 4096); Z K^-1 is formed by k_postz
+    for (int e = t; e < k * k; e += 1024) {
+      sC[e] = S[e];
+      Ki[e] = sK[(e % k) + (e / k) * 64];
+    }
+    __syncthreads();
     for (int e = t; e < k * k; e += 1024) {
       const int r = e % k, c = e / k;
-      double vs = 0.0, vt = 0.0;
-      for (int q = 0; q < k; ++q) {
-        vs = fma(S[r + q * k], sK[q + c * 64], vs);
-        vt = fma(Tm[r + q * k], sK[q + c * 64], vt);
-      }
+      double vs = 0.0;
+      for (int q = 0; q < k; ++q) vs = fma(sC[r + q * k], sK[q + c * 64], vs);
       sKi[r + c * 64] = vs;      // S K^-1
-      sV[r + c * 64] = vt;       // T K^-1 (sV is free now; k*k <= 4096)
     }
-    for (int e = t; e < n2 * k; e += 1024) {
-      const int j = e / k, c = e - j * k;
-      const double *zr = Zd + (int64_t)j * k;
-      double v = 0.0;
-      for (int q = 0; q < k; ++q) v = fma(zr[q], sK[q + c * 64], v);
-      Zk[e] = v;
+    __syncthreads();
+    for (int e = t; e < k * k; e += 1024) sC[e] = Tm[e];
+    __syncthreads();
+    for (int e = t; e < k * k; e += 1024) {
+      const int r = e % k, c = e / k;
+      double vt = 0.0;
+      for (int q = 0; q < k; ++q) vt = fma(sC[r + q * k], sK[q + c * 64], vt);
+      sV[r + c * 64] = vt;       // T K^-1 (sV is free now)
     }
     __syncthreads();
     for (int e = t; e < k * k; e += 1024) {
@@ -340,9 +331,6 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
       S[e] = sKi[r + c * 64];
       Tm[e] = sV[r + c * 64];
     }
-    __syncthreads();
-  } else {
-    for (int e = t; e < n2 * k; e += 1024) Zk[e] = Zd[e];
     __syncthreads();
   }
   // typed copies for the row pass (row-major, input index first)
@@ -352,7 +340,6 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
     o.Tt[r * k + c] = (T)Tm[e];
     o.Gt[r * k + c] = (T)(-S[e]);
   }
-  for (int e = t; e < n2 * k; e += 1024) o.Gt[(int64_t)k * k + e] = (T)Zk[e];
   if (t == 0) {
     // F(X_p) = ||(A1 - X1) o W1||^2 + ||P^perp A2||^2 - sum of the top r-k
     // eigenvalues of M, with ||P^perp A2||^2 = ||A2||^2 - ||B||^2.
@@ -365,6 +352,57 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
       st->gap = __builtin_inf();
     else
       st->gap = sqrt(fmax(a.theta[l - 1], 0.0)) - sqrt(fmax(a.theta[l], 0.0));
+  }
+}
+
+// The n2-row part of the small step, one workgroup per PZ_R rows j: the
+// row-major copy of V, Z = (I - V V^T) C^T = C^T - V (CV)^T (kept in double
+// for the change pass, typed for the X2 output), and the rows of the row-pass
+// panel: Z K^-1 with a constant weight (K^-1 from k_post), else Z.  CV and
+// K^-1 are staged in LDS; every product has k or l terms.
+#define PZ_R 16
+template <typename T>
+__global__ __launch_bounds__(256) void k_postz(SmallArgs a, SmallOut<T> o) {
+  SmallState *st = a.st;
+  if (st->done) return;
+  __shared__ double sCV[64 * 32];
+  __shared__ double sKi[64 * 64];
+  __shared__ double sVr[PZ_R * 32];
+  __shared__ double sZ[PZ_R * 65];
+  const int k = a.k, n2 = a.n2, l = a.l, t = threadIdx.x;
+  const int j0 = blockIdx.x * PZ_R, nr = min(PZ_R, n2 - j0);
+  const double *CV = a.scratch;
+  const double *Ki = a.scratch + 64 * 32 + 2 * 64 * 64;
+  const bool constw = a.wconst > 0;
+  for (int e = t; e < k * l; e += 256) sCV[e] = CV[e];
+  if (constw)
+    for (int e = t; e < k * k; e += 256) sKi[e] = Ki[e];
+  const double *V = a.Y;  // first l columns, ld n2
+  for (int e = t; e < nr * l; e += 256) {
+    const int r = e % nr, q = e / nr, j = j0 + r;
+    const double v = V[j + (int64_t)q * n2];
+    sVr[r * 32 + q] = v;
+    a.Vcur[(int64_t)j * l + q] = v;
+    o.Vr[(int64_t)j * l + q] = (T)v;
+  }
+  __syncthreads();
+  for (int e = t; e < nr * k; e += 256) {
+    const int r = e / k, c = e - r * k, j = j0 + r;
+    double s_ = a.C[(int64_t)j * k + c];
+    for (int q = 0; q < l; ++q) s_ -= sVr[r * 32 + q] * sCV[c + q * k];
+    sZ[r * 65 + c] = s_;
+    a.Zcur[(int64_t)j * k + c] = s_;
+    o.Zx[(int64_t)j * k + c] = (T)s_;
+  }
+  __syncthreads();
+  for (int e = t; e < nr * k; e += 256) {
+    const int r = e / k, c = e - r * k, j = j0 + r;
+    double v = sZ[r * 65 + c];
+    if (constw) {
+      v = 0.0;
+      for (int q = 0; q < k; ++q) v = fma(sZ[r * 65 + q], sKi[q + c * k], v);
+    }
+    o.Gt[(int64_t)k * k + (int64_t)j * k + c] = (T)v;
   }
 }
 
@@ -431,6 +469,8 @@ void launch_decide(hipStream_t s, const SmallArgs &a) {
 template <typename T>
 void launch_post(hipStream_t s, const SmallArgs &a, const SmallOut<T> &o) {
   hipLaunchKernelGGL(k_post<T>, dim3(1), dim3(1024), 0, s, a, o);
+  if (a.n2 > 0)
+    hipLaunchKernelGGL(k_postz<T>, dim3((a.n2 + PZ_R - 1) / PZ_R), dim3(256), 0, s, a, o);
 }
 template void launch_post<float>(hipStream_t, const SmallArgs &, const SmallOut<float> &);
 template void launch_post<double>(hipStream_t, const SmallArgs &, const SmallOut<double> &);

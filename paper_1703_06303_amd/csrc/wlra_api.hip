@@ -223,7 +223,7 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.F1, (size_t)(n2 * WLRA_BMAX) * d},
       {(void **)&p.F2, (size_t)(n2 * WLRA_BMAX) * d},
       {(void **)&p.theta, (size_t)WLRA_BMAX * d},
-      {(void **)&p.scratch, (size_t)(2048 + 2 * 4096 + 64 * n2) * d},
+      {(void **)&p.scratch, (size_t)(2048 + 3 * 4096) * d},
       {(void **)&p.upd_part, (size_t)2 * std::max(z.nwg_upd, z.nwg_f1) * d},
       {(void **)&p.chg_part, (size_t)z.nwg_upd * d},
       {(void **)&p.Zd[0], (size_t)(n2 * kk) * d},
