@@ -12,15 +12,22 @@
 #include "launch.h"
 
 // -----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gastats(int n2, const double *__restrict__ GA,
-                                                 SmallState *st) {
-  __shared__ double red[4];
+// Trace and Frobenius norm of G_A = A2^T A2 (one workgroup; 8 reads in
+// flight per thread, the trace from the diagonal alone).
+__global__ __launch_bounds__(1024) void k_gastats(int n2, const double *__restrict__ GA,
+                                                  SmallState *st) {
+  __shared__ double red[16];
+  const int64_t nn = (int64_t)n2 * n2;
   double tr = 0, f = 0;
-  for (int e = threadIdx.x; e < n2 * n2; e += 256) {
-    const double v = GA[e];
-    f += v * v;
-    if (e % n2 == e / n2) tr += v;
+  for (int64_t e0 = threadIdx.x; e0 < nn; e0 += 8 * 1024) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = GA[min(e0 + u * 1024, nn - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + u * 1024 < nn) f += v[u] * v[u];
   }
+  for (int i = threadIdx.x; i < n2; i += 1024) tr += GA[i + (int64_t)i * n2];
   tr = block_sum(tr, red);
   f = block_sum(f, red);
   if (threadIdx.x == 0) {
@@ -446,7 +453,7 @@ __global__ __launch_bounds__(256) void k_decide(SmallArgs a) {
 
 // -----------------------------------------------------------------------------
 void launch_gastats(hipStream_t s, int n2, const double *GA, SmallState *st) {
-  hipLaunchKernelGGL(k_gastats, dim3(1), dim3(256), 0, s, n2, GA, st);
+  hipLaunchKernelGGL(k_gastats, dim3(1), dim3(1024), 0, s, n2, GA, st);
 }
 
 void launch_coef(hipStream_t s, const SmallArgs &a) {
