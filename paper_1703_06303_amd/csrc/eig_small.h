@@ -41,6 +41,81 @@ __device__ __forceinline__ int small_chol_wave(double *G, int nb, double shift, 
 }
 
 
+// The same Jacobi for nb <= 8 with H and S in registers: lane x + nb y of
+// wavefront 0 holds H[x][y] and S[x][y]; a round's rotation parameters and
+// its J^T H J, S J updates use cross-lane reads (ds_bpermute) only, and each
+// lane below the diagonal takes its entry from the mirrored lane so that H
+// stays exactly symmetric.  Same pairing, rotation formulas, stopping test
+// and output (th descending, ties by index; S's columns) as below.
+__device__ __forceinline__ void small_jacobi_reg(double *H, double *S, double *th, int *rk,
+                                                 int nb) {
+  const int t = threadIdx.x;
+  constexpr int L = WLRA_BMAX;
+  if (t < 64) {
+    const int nn = nb * nb;
+    const bool in = t < nn;
+    const int x = in ? t % nb : 0, y = in ? t / nb : 0;
+    double h = in ? ((x == y) ? H[x + y * L] : 0.5 * (H[x + y * L] + H[y + x * L])) : 0.0;
+    double sv = (in && x == y) ? 1.0 : 0.0;
+    const int nbp = nb + (nb & 1), per = nbp - 1;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      const double v2 = h * h;
+      const double off = wave_sum((in && x != y) ? v2 : 0.0);
+      const double tot = wave_sum(v2);
+      if (!(off > 1e-28 * tot)) break;
+      for (int round = 0; round < per; ++round) {
+        // partner of an index in this round's circle arrangement (nb is the
+        // dummy of an odd nb)
+        auto partner = [&](int i) {
+          const int pos = (i == 0) ? 0 : 1 + ((i - 1 - round) % per + per) % per;
+          const int pp = nbp - 1 - pos;
+          return (pp == 0) ? 0 : 1 + (pp - 1 + round) % per;
+        };
+        const int px = partner(x), py = partner(y);
+        const bool paired = px < nb && px != x;
+        const int p = paired ? min(x, px) : x, q = paired ? max(x, px) : x;
+        const double hpp = __shfl(h, p + p * nb, 64), hqq = __shfl(h, q + q * nb, 64);
+        const double hpq = __shfl(h, p + q * nb, 64);
+        double c = 1.0, sn = 0.0;
+        if (paired && fabs(hpq) > 1e-300) {
+          const double tau = (hqq - hpp) / (2.0 * hpq);
+          const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          sn = tt * c;
+        }
+        const double ax = paired ? c : 1.0, bx = paired ? ((x == p) ? -sn : sn) : 0.0;
+        // lane y holds index y as its x (y < nb), so its coefficients are y's
+        const double ay = __shfl(ax, y, 64), by = __shfl(bx, y, 64);
+        const int pxe = paired ? px : x, pye = (py < nb && py != y) ? py : y;
+        const double h_xpy = __shfl(h, x + pye * nb, 64), h_pxy = __shfl(h, pxe + y * nb, 64);
+        const double h_pxpy = __shfl(h, pxe + pye * nb, 64);
+        const double s_xpy = __shfl(sv, x + pye * nb, 64);
+        const double hn = (ax * ay * h + ax * by * h_xpy) + (bx * ay * h_pxy + bx * by * h_pxpy);
+        const double hm = __shfl(hn, y + x * nb, 64);  // the upper entry, for x > y
+        const double sn2 = ay * sv + by * s_xpy;
+        if (in) {
+          h = (x <= y) ? hn : hm;
+          sv = sn2;
+        }
+      }
+    }
+    // eigenvalues descending (ties by index): the diagonal goes through H
+    // (no longer needed), ranks per index, S's columns to their ranks
+    if (in && x == y) H[x + x * L] = h;
+    wave_sync();
+    if (t < nb) {
+      int r = 0;
+      for (int c = 0; c < nb; ++c)
+        r += (H[c + c * L] > H[t + t * L]) || (H[c + c * L] == H[t + t * L] && c < t);
+      rk[t] = r;
+      th[r] = H[t + t * L];
+    }
+    wave_sync();
+    if (in) S[x + rk[y] * L] = sv;
+  }
+  __syncthreads();
+}
+
 // Symmetric eigendecomposition of H (nb x nb) by parallel cyclic Jacobi on
 // wavefront 0 (round-robin pairing, nb/2 disjoint rotations per round).
 // A round applies all of its rotations from both sides in one pass,
@@ -52,6 +127,10 @@ __device__ __forceinline__ int small_chol_wave(double *G, int nb, double shift, 
 __device__ __forceinline__ void small_jacobi_wave(double *H, double *S, double *H2, double *S2,
                                                   double *th, double *al, double *be, int *pt,
                                                   int *rk, int nb) {
+  if (nb <= 8) {
+    small_jacobi_reg(H, S, th, rk, nb);
+    return;
+  }
   const int t = threadIdx.x;
   constexpr int L = WLRA_BMAX;
   if (t < 64) {
