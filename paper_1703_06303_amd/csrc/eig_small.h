@@ -8,7 +8,9 @@
 
 // Upper Cholesky in place of G (nb x nb, ld WLRA_BMAX) by wavefront 0, with an
 // optional diagonal shift.  Returns nonzero on a non-positive pivot.
+__device__ __forceinline__ int small_chol_reg(double *G, int nb, double shift, int *ints);
 __device__ __forceinline__ int small_chol_wave(double *G, int nb, double shift, int *ints) {
+  if (nb <= 8) return small_chol_reg(G, nb, shift, ints);
   const int t = threadIdx.x;
   if (t < 64) {
     if (t == 0) ints[0] = 0;
@@ -40,6 +42,37 @@ __device__ __forceinline__ int small_chol_wave(double *G, int nb, double shift, 
   return ints[0];
 }
 
+
+// The same Cholesky for nb <= 8 with G in registers: lane x + nb y of
+// wavefront 0 holds G[x][y]; a step reads the pivot and row j across lanes.
+// Writes the same entries as the LDS version (the upper triangle) and the
+// same failure flag.
+__device__ __forceinline__ int small_chol_reg(double *G, int nb, double shift, int *ints) {
+  const int t = threadIdx.x;
+  constexpr int L = WLRA_BMAX;
+  if (t < 64) {
+    const bool in = t < nb * nb;
+    const int x = in ? t % nb : 0, y = in ? t / nb : 0;
+    double g = in ? G[x + y * L] : 0.0;
+    if (in && x == y) g += shift;
+    int bad = 0;
+    for (int j = 0; j < nb; ++j) {
+      double p = __shfl(g, j + j * nb, 64);
+      if (!(p > 0.0)) {
+        bad = 1;
+        p = 1.0;
+      }
+      const double rjj = sqrt(p);
+      if (in && x == j) g = (y == j) ? rjj : ((y > j) ? g / rjj : g);
+      const double rx = __shfl(g, j + x * nb, 64), ry = __shfl(g, j + y * nb, 64);
+      if (in && x > j && x <= y) g -= rx * ry;
+    }
+    if (in && x <= y) G[x + y * L] = g;
+    if (t == 0) ints[0] = bad;
+  }
+  __syncthreads();
+  return ints[0];
+}
 
 // The same Jacobi for nb <= 8 with H and S in registers: lane x + nb y of
 // wavefront 0 holds H[x][y] and S[x][y]; a round's rotation parameters and
