@@ -44,11 +44,12 @@ FP32_PEAK_TFLOPS = 157.3
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by
 # the same counters read for a plain copy of known size (reads x2.0, writes
-# x1.0).  An entry holds only while the kernel's source file is byte-identical
-# to the one measured (SHA-256 below); otherwise traffic is reported as null.
+# x1.0).  An entry holds only while the kernel's source files are
+# byte-identical to the ones measured (SHA-256 of their concatenation, in the
+# order listed); otherwise traffic is reported as null.
 TRAFFIC = {
-    ("eig", "config2", "mixed"): (681946, "k_eig.hip",
-                                  "bd4953e2e6d9367c469245ff9200bf3777afbb7cbe879cdd5aa811b6c7129c0c"),
+    ("eig", "config2", "mixed"): (685649, ("k_eig.hip", "eig_small.h", "launch.h", "common.h"),
+                                  "26d60fdb74b80985226deb28e81025cbeabf47349bb2313b49ebf18d4b021059"),
 }
 
 
@@ -57,14 +58,15 @@ def measured_traffic(kernel, workload_name, precision):
     ent = TRAFFIC.get((kernel, workload_name, precision))
     if ent is None:
         return None
-    nbytes, src, sha = ent
-    path = os.path.join(ROOT, "paper_1703_06303_amd", "csrc", src)
+    nbytes, srcs, sha = ent
+    h = hashlib.sha256()
     try:
-        with open(path, "rb") as f:
-            cur = hashlib.sha256(f.read()).hexdigest()
+        for src in srcs:
+            with open(os.path.join(ROOT, "paper_1703_06303_amd", "csrc", src), "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
-    return nbytes if cur == sha else None
+    return nbytes if h.hexdigest() == sha else None
 
 
 def workload(name):
