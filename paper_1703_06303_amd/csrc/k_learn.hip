@@ -36,18 +36,32 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_sketch_finish(int n, const double *__restrict__ P1,
                                                        const T *__restrict__ Ps,
                                                        float *__restrict__ out) {
+  // chunks of the n columns of P1 (16 x n) and rows of Psi (n x 32) in LDS
+  constexpr int CH = 256;
+  __shared__ double sP[LEARN_SK_ROWS * CH];
+  __shared__ double sQ[CH * LEARN_SK_COLS];
   __shared__ double red[4];
-  double v[2];
-  double ss = 0.0;
+  double v[2] = {0.0, 0.0};
+  for (int j0 = 0; j0 < n; j0 += CH) {
+    const int nj = min(CH, n - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < LEARN_SK_ROWS * nj; e += 256) sP[e] = P1[(int64_t)j0 * LEARN_SK_ROWS + e];
+    for (int e = threadIdx.x; e < nj * LEARN_SK_COLS; e += 256) {
+      const int jj = e % nj, b = e / nj;
+      sQ[jj * LEARN_SK_COLS + b] = (double)Ps[j0 + jj + (int64_t)b * n];
+    }
+    __syncthreads();
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int o = threadIdx.x + 256 * u;  // 0..511
-    const int a = o % LEARN_SK_ROWS, b = o / LEARN_SK_ROWS;
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc = fma(P1[a + (int64_t)j * LEARN_SK_ROWS], (double)Ps[j + (int64_t)b * n], acc);
-    v[u] = acc;
-    ss += acc * acc;
+    for (int u = 0; u < 2; ++u) {
+      const int o = threadIdx.x + 256 * u;  // 0..511
+      const int a = o % LEARN_SK_ROWS, b = o / LEARN_SK_ROWS;
+      double acc = v[u];
+      for (int jj = 0; jj < nj; ++jj)
+        acc = fma(sP[a + jj * LEARN_SK_ROWS], sQ[jj * LEARN_SK_COLS + b], acc);
+      v[u] = acc;
+    }
   }
+  double ss = v[0] * v[0] + v[1] * v[1];
   ss = block_sum(ss, red);
   const double inv = ss > 0 ? 1.0 / sqrt(ss) : 0.0;
 #pragma unroll
@@ -277,7 +291,20 @@ __global__ __launch_bounds__(64) void k_tall_small(int64_t m, int kin, int c,
       sS[e] = (T)S[(int64_t)(j0 + jj) * rs + (int64_t)q * cs];
     }
     __syncthreads();
-    for (int jj = 0; jj < nr; ++jj) {
+    int jj = 0;
+    for (; jj + 8 <= nr; jj += 8) {  // 8 reads of A in flight
+      T a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = A[ir + (int64_t)(j0 + jj + u) * lda];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const T *srow = sS + (jj + u) * c;
+#pragma unroll
+        for (int q = 0; q < CMAX; ++q)
+          if (q < c) acc[q] = fma(a[u], srow[q], acc[q]);
+      }
+    }
+    for (; jj < nr; ++jj) {
       const T a = A[ir + (int64_t)(j0 + jj) * lda];
       const T *srow = sS + jj * c;
 #pragma unroll
@@ -293,54 +320,84 @@ __global__ __launch_bounds__(64) void k_tall_small(int64_t m, int kin, int c,
 }
 
 // Y = G^-1 H (G r x r SPD, H r x k, both column-major double) by Cholesky in
-// LDS; Y stored typed, row-major r x k (element (q, c) at Y[q k + c]).  A
-// non-positive pivot or a non-finite entry sets DEV_LEARN_FAIL.
+// LDS (lower, right-looking, by wavefront 0); then one thread per column of
+// H solves L L^T y = h with the column in registers.  Y is stored typed,
+// row-major r x k (element (q, c) at Y[q k + c]).  A pivot below 1e-13 of
+// the largest diagonal entry or a non-finite entry sets DEV_LEARN_FAIL.
 template <typename T>
 __global__ __launch_bounds__(256) void k_decode_solve(int r, int k, const double *__restrict__ Gg,
                                                       const double *__restrict__ H,
                                                       T *__restrict__ Y, int *flags) {
-  __shared__ double G[LEARN_RMAX * LEARN_RMAX];
+  constexpr int L = LEARN_RMAX;
+  __shared__ double G[L * L];
   __shared__ int bad;
   const int t = threadIdx.x;
   if (t == 0) bad = 0;
-  for (int e = t; e < r * r; e += 256) G[(e % r) + (e / r) * LEARN_RMAX] = Gg[e];
+  for (int e = t; e < L * L; e += 256) {
+    const int a = e % L, b = e / L;
+    G[e] = (a < r && b < r) ? Gg[a + b * r] : 0.0;
+  }
   __syncthreads();
-  if (t == 0) {
-    double dmax = 0.0;
-    for (int j = 0; j < r; ++j) dmax = fmax(dmax, G[j + j * LEARN_RMAX]);
+  double dmax = 0.0;
+  for (int j = 0; j < r; ++j) dmax = fmax(dmax, G[j + j * L]);
+  if (t < 64) {
     for (int j = 0; j < r; ++j) {
-      double d = G[j + j * LEARN_RMAX];
-      for (int q = 0; q < j; ++q) d -= G[j + q * LEARN_RMAX] * G[j + q * LEARN_RMAX];
-      if (!(d > 1e-13 * dmax)) {
-        bad = 1;
-        d = 1.0;
+      if (t == 0) {
+        double d = G[j + j * L];
+        if (!(d > 1e-13 * dmax)) {
+          bad = 1;
+          d = 1.0;
+        }
+        G[j + j * L] = sqrt(d);
       }
-      const double ljj = sqrt(d);
-      G[j + j * LEARN_RMAX] = ljj;
-      for (int i = j + 1; i < r; ++i) {
-        double s = G[i + j * LEARN_RMAX];
-        for (int q = 0; q < j; ++q) s -= G[i + q * LEARN_RMAX] * G[j + q * LEARN_RMAX];
-        G[i + j * LEARN_RMAX] = s / ljj;
+      wave_sync();
+      const double ljj = G[j + j * L];
+      for (int i = j + 1 + t; i < r; i += 64) G[i + j * L] /= ljj;
+      wave_sync();
+      const int rem = r - j - 1;
+      for (int e = t; e < rem * rem; e += 64) {
+        const int i = j + 1 + e % rem, q = j + 1 + e / rem;
+        if (q <= i) G[i + q * L] -= G[i + j * L] * G[q + j * L];
       }
+      wave_sync();
     }
+    // the strict upper triangle is never read below; keep it zero
+    for (int e = t; e < r * r; e += 64)
+      if ((e % r) < (e / r)) G[(e % r) + (e / r) * L] = 0.0;
   }
   __syncthreads();
   for (int c = t; c < k; c += 256) {
-    double x[LEARN_RMAX];
-    for (int i = 0; i < r; ++i) {
-      double s = H[i + (int64_t)c * r];
-      for (int q = 0; q < i; ++q) s -= G[i + q * LEARN_RMAX] * x[q];
-      x[i] = s / G[i + i * LEARN_RMAX];
+    double x[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) x[i] = (i < r) ? H[i + (int64_t)c * r] : 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      if (i < r) {
+        double s = x[i];
+#pragma unroll
+        for (int q = 0; q < i; ++q) s -= G[i + q * L] * x[q];
+        x[i] = s / G[i + i * L];
+      }
+      asm volatile("" ::: "memory");  // keep each row's reads of L in place
     }
-    for (int i = r - 1; i >= 0; --i) {
-      double s = x[i];
-      for (int q = i + 1; q < r; ++q) s -= G[q + i * LEARN_RMAX] * x[q];
-      x[i] = s / G[i + i * LEARN_RMAX];
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+      if (i < r) {
+        double s = x[i];
+#pragma unroll
+        for (int q = i + 1; q < L; ++q) s -= G[q + i * L] * x[q];
+        x[i] = s / G[i + i * L];
+      }
+      asm volatile("" ::: "memory");
     }
-    for (int i = 0; i < r; ++i) {
-      if (!isfinite(x[i])) bad = 1;
-      Y[(int64_t)i * k + c] = (T)x[i];
-    }
+    int nb = 0;
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+      if (i < r) {
+        nb |= !isfinite(x[i]);
+        Y[(int64_t)i * k + c] = (T)x[i];
+      }
+    if (nb) bad = 1;
   }
   __syncthreads();
   if (t == 0 && bad) atomicOr(flags, DEV_LEARN_FAIL);
