@@ -424,9 +424,36 @@ void launch_sketch_finish(hipStream_t s, int n, const double *P1, const T *Ps, f
   hipLaunchKernelGGL(k_sketch_finish<T>, dim3(1), dim3(256), 0, s, n, P1, Ps, out);
 }
 
+// One row (inference): y (1 x N) = x B^T (+ bias) (relu), B N x K row-major;
+// a wavefront per output, lanes over K, a fixed xor-tree sum.
+__global__ __launch_bounds__(256) void k_gemv0(int N, int K, const float *__restrict__ x,
+                                               const float *__restrict__ B, int ldb,
+                                               float *__restrict__ y, const float *__restrict__ bias,
+                                               int relu) {
+  const int lane = threadIdx.x & 63;
+  const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= N) return;
+  const float *row = B + (int64_t)n * ldb;
+  float acc = 0.f;
+  for (int k = lane; k < K; k += 64) acc = fmaf(x[k], row[k], acc);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    float v = acc;
+    if (bias) v += bias[n];
+    if (relu) v = fmaxf(v, 0.f);
+    y[n] = v;
+  }
+}
+
 void launch_gemm(hipStream_t s, int mode, int M, int N, int K, const float *A, int lda,
                  const float *B, int ldb, float *C, int ldc, const float *bias, int relu,
                  const float *mask, int ldm) {
+  if (mode == 0 && M == 1 && mask == nullptr) {
+    hipLaunchKernelGGL(k_gemv0, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, N, K, A, B, ldb, C,
+                       bias, relu);
+    return;
+  }
   dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT));
   if (mode == 0)
     hipLaunchKernelGGL(k_gemm<0>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias,
