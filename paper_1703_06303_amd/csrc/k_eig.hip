@@ -81,25 +81,24 @@ template <bool RES>
 __device__ __forceinline__ void blk_gram(EigLDS &s, const EigCtx &cx, Blk<RES> X, int p, Blk<RES> Y,
                                          int q, double *G, bool diag = false);
 
-// Out[:, 0:nc] = M X[:, 0:nc], blocks n2 x * (ld n2), M as deflated so far.
-// On the FP64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16 x 4 slab
-// of M by a 4 x 16 slab of X.  The waves form two groups that each take half
-// of the inner index; a wave owns every fourth 16-row tile of the output and,
-// per tile, issues all of its reads of M (16 bytes per lane per two k-steps,
-// from the fragment-major storage) before its first multiply.  The second
-// group writes its partial tiles to the output and the first group's, parked
-// in LDS, are added after a barrier (a fixed order).
+// Out[:, 0:nc] = M X[:, 0:nc], blocks n2 x * (ld n2), M as deflated so far,
+// in passes of 8 columns.  On the FP64 matrix cores with
+// v_mfma_f64_4x4x4_4b_f64 (a 16 x 4 slab of M times a 4 x 4 slab of X per
+// instruction, so the few columns of the eigen block are not padded to 16).
+// The waves form two groups that each take half of the inner index; a wave
+// owns every fourth 16-row tile of the output and, per tile, issues all of
+// its reads of M (16 bytes per lane per two k-steps, from the fragment-major
+// storage) before its first multiply.  The second group writes its partial
+// tiles to the output and the first group's, parked in LDS, are added after
+// a barrier (a fixed order).
 //
 // The columns are first copied to an LDS buffer zero-padded to whole groups
-// of 8 k-steps, with an odd leading dimension (the 16 columns a
-// quarter-wavefront reads fall in distinct banks), so that the loop needs no
+// of 8 k-steps, with an odd leading dimension, so that the loop needs no
 // clamps or masks and its LDS reads take immediate offsets.  When the
-// buffer holds fewer than 16 columns, lanes past them read a zero column.
-// Fragment layouts (lane l): A[l % 16][l / 16], B[l / 16][l % 16],
-// accumulator v holds D[l / 16 + 4 v][l % 16].
+// buffer holds fewer than 8 columns, lanes past them read a zero column.
 typedef double eig_d4 __attribute__((ext_vector_type(4)));
 #define OP_KH 32   // k-steps of 4 per register batch of M
-#define OP_TPW 4   // row tiles per wave per pass (4 waves per group: 16 tiles)
+#define OP_TPW 4   // row tiles per wave per round (4 waves per group: 16 tiles)
 template <bool RES>
 __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, int nc,
                                        Blk<RES> Out) {
@@ -112,10 +111,10 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
   const int kq2 = (int)mf_kq2(n2);  // pairs of k-steps, padded to groups of 8 steps
   const int kq8 = 2 * kq2;
   const int xld = (4 * kq8) | 1;
-  // staged columns per pass; with fewer than 16 the next column is zero
+  // staged columns per pass (8); with fewer, the next column is zero
   const int fbase = RES ? cx.xs : STAGE_OFF;
-  const int cwf = RES ? 16 : min(16, 8192 / xld - 1);
-  const int ncopy = min(16, cwf + 1);
+  const int cwf = RES ? 8 : min(8, 8192 / xld - 1);
+  const int ncopy = min(8, cwf + 1);
   // group 0 takes k-steps [0, kh), group 1 [kh, kq8): whole groups of 8
   const int kh = ((kq + 1) / 2 + 7) & ~7;
   const int ks0 = grp * kh, ks1 = min(kq8, ks0 + kh);
@@ -128,18 +127,23 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
       s.pool[fbase + e] = (i < n2 && c < cw) ? Xc.at(s, i + c * n2) : 0.0;
     }
     __syncthreads();
-    const bool colok = li < cw;
-    const double *xcol = s.pool + fbase + 4 * ks0 + lk + min(li, cwf) * xld;
     for (int rp0 = 0; rp0 < rtiles; rp0 += 4 * OP_TPW) {
 #pragma unroll 1
       for (int j = 0; j < OP_TPW; ++j) {
         const int rt = rp0 + wq + 4 * j;
         if (rt >= rtiles) break;
-        eig_d4 acc = {0.0, 0.0, 0.0, 0.0};
         const double2 *mt =
             reinterpret_cast<const double2 *>(cx.M) + ((int64_t)rt * kq2 + ks0 / 2) * 64 + lane;
+        // v_mfma_f64_4x4x4_4b_f64: four 4 x 4 blocks (rows 4b..4b+3) per
+        // instruction, one instruction per 4 columns.  Its A operand is the
+        // same fragment as the 16 x 16 x 4 one (lane l: row l % 16, k l / 16);
+        // B[k][j] sits at lane 16k + 4b + j and D[i][j] at lane 16i + 4b + j.
+        // Even and odd k-steps go to separate accumulators (four chains).
+        const double *xq0 = s.pool + fbase + 4 * ks0 + lk + min(li & 3, cwf) * xld;
+        const double *xq1 = s.pool + fbase + 4 * ks0 + lk + min(4 + (li & 3), cwf) * xld;
+        double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
         for (int kb = 0; kb < ks1 - ks0; kb += OP_KH) {
-          const int nk = min(OP_KH, ks1 - ks0 - kb);  // a multiple of 8
+          const int nk = min(OP_KH, ks1 - ks0 - kb);
           double a[OP_KH];
 #pragma unroll
           for (int u0 = 0; u0 < OP_KH; u0 += 8) {
@@ -155,25 +159,32 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
 #pragma unroll
           for (int u0 = 0; u0 < OP_KH; u0 += 8) {
             if (u0 < nk) {
-              double bb[8];
+              double b0[8], b1[8];
 #pragma unroll
-              for (int u = 0; u < 8; ++u) bb[u] = xcol[4 * (kb + u0 + u)];
+              for (int u = 0; u < 8; ++u) {
+                b0[u] = xq0[4 * (kb + u0 + u)];
+                b1[u] = xq1[4 * (kb + u0 + u)];
+              }
 #pragma unroll
-              for (int u = 0; u < 8; ++u)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u0 + u], bb[u], acc, 0, 0, 0);
+              for (int u = 0; u < 8; u += 2) {
+                c00 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u], b0[u], c00, 0, 0, 0);
+                c10 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u], b1[u], c10, 0, 0, 0);
+                c01 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u + 1], b0[u + 1], c01, 0, 0, 0);
+                c11 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u + 1], b1[u + 1], c11, 0, 0, 0);
+              }
             }
           }
         }
-        // the first group parks its partial tile; the second writes its own
-        // to the output, which the partial is added to after the barrier
+        const int row_t = 4 * ((lane >> 2) & 3) + (lane >> 4), col = lane & 3;
+        const double d0 = c00 + c01, d1 = c10 + c11;
         if (grp == 0) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) part[(rt - rp0) * 256 + (lk + 4 * v) * 16 + li] = acc[v];
-        } else if (colok) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = rt * 16 + lk + 4 * v;
-            if (row < n2) Out.at(s, row + (c0 + li) * n2) = acc[v];
+          part[(rt - rp0) * 256 + row_t * 16 + col] = d0;
+          part[(rt - rp0) * 256 + row_t * 16 + 4 + col] = d1;
+        } else {
+          const int row = rt * 16 + row_t;
+          if (row < n2) {
+            if (col < cw) Out.at(s, row + (c0 + col) * n2) = d0;
+            if (4 + col < cw) Out.at(s, row + (c0 + 4 + col) * n2) = d1;
           }
         }
       }
