@@ -104,16 +104,18 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
   const int i0 = ti * 32, j0 = tj * 32;
   const int64_t r0 = (int64_t)s * rows_per_split;
   const int64_t r1 = min(m, r0 + rows_per_split);
-  double px[4], py[4];
+  TX px[4];  // raw reads of the next chunk, converted when stored
+  TY py[4];
+  // reads clamped into the operands (never skipped: a skipped read would be
+  // waited for on its own) and masked by multiplying with zero (finite)
   auto fetch = [&](int64_t rb) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = threadIdx.x + 256 * u;
       const int rr = e & 31, cc = e >> 5;
-      const int64_t row = rb + rr;
-      const bool rin = row < r1;
-      px[u] = (rin && i0 + cc < k1) ? (double)to_f(X[row + (int64_t)(i0 + cc) * ldx]) : 0.0;
-      py[u] = (rin && j0 + cc < k2) ? (double)to_f(Y[row + (int64_t)(j0 + cc) * ldy]) : 0.0;
+      const int64_t rowc = min(rb + rr, r1 - 1);
+      px[u] = X[rowc + (int64_t)min(i0 + cc, k1 - 1) * ldx];
+      py[u] = Y[rowc + (int64_t)min(j0 + cc, k2 - 1) * ldy];
     }
   };
   ts_d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -122,8 +124,10 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = threadIdx.x + 256 * u;
-      sX[e >> 5][e & 31] = px[u];
-      sY[e >> 5][e & 31] = py[u];
+      const int rr = e & 31, cc = e >> 5;
+      const bool rin = rb + rr < r1;
+      sX[cc][rr] = (double)to_f(px[u]) * ((rin && i0 + cc < k1) ? 1.0 : 0.0);
+      sY[cc][rr] = (double)to_f(py[u]) * ((rin && j0 + cc < k2) ? 1.0 : 0.0);
     }
     __syncthreads();
     if (rb + 32 < r1) fetch(rb + 32);
@@ -275,40 +279,48 @@ __global__ __launch_bounds__(UPD_T) void k_update(
   acc_t acc[NT];
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct) acc[ct] = acc_t{0, 0, 0, 0};
-  for (int j0 = 0; j0 < ntot; j0 += grows) {
-    const int jl = min(grows, ntot - j0);
-    const int nsteps = (jl + 3) / 4;
-    __syncthreads();
-    for (int e = t; e < 4 * nsteps * KP; e += UPD_T) {
-      const int jr = e / KP, c = e - jr * KP, j = j0 + jr;
-      T v = T(0);
-      if (jr < jl && c < k) v = (j < n) ? Gt[(int64_t)j * k + c] : Tt[(j - n) * k + c];
-      sB[e] = v;
-    }
-    __syncthreads();
-    for (int s0 = 0; s0 < nsteps; s0 += UB) {
-      T av[UB];
+  // the inner index in three segments of one source each (A1, A2, X1), so
+  // that every read is a plain load (a choice between sources per element
+  // would make the compiler wait for each read on its own); a segment's last
+  // k-step is padded with zero rows of B and clamped reads
+  auto segment = [&](const auto *src, int64_t ld, int ja, int jb) {
+    for (int j0 = ja; j0 < jb; j0 += grows) {
+      const int jl = min(grows, jb - j0);
+      const int nsteps = (jl + 3) / 4;
+      __syncthreads();
+      for (int e = t; e < 4 * nsteps * KP; e += UPD_T) {
+        const int jr = e / KP, c = e - jr * KP, j = j0 + jr;
+        T v = T(0);
+        if (jr < jl && c < k) v = (j < n) ? Gt[(int64_t)j * k + c] : Tt[(j - n) * k + c];
+        sB[e] = v;
+      }
+      __syncthreads();
+      for (int s0 = 0; s0 < nsteps; s0 += UB) {
+        T av[UB];
 #pragma unroll
-      for (int u0 = 0; u0 < UB; u0 += 8) {
-        if (s0 + u0 < nsteps) {
+        for (int u0 = 0; u0 < UB; u0 += 8) {
+          if (s0 + u0 < nsteps) {
 #pragma unroll
-          for (int u = u0; u < u0 + 8; ++u) {
-            // clamped column: past n + k the staged B rows are zero
-            const int jc = min(j0 + 4 * (s0 + u) + lk, ntot - 1);
-            av[u] = (jc < n) ? a_elem<T, TA2>(A, lda, A2, lda2, k, ra, jc) : X1o[ra + (int64_t)(jc - n) * m];
+            for (int u = u0; u < u0 + 8; ++u) {
+              const int jc = min(j0 + 4 * (s0 + u) + lk, jb - 1);
+              av[u] = (T)to_f(src[ra + (int64_t)(jc - ja) * ld]);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          if (s0 + u < nsteps) {
+            const T *brow = sB + (4 * (s0 + u) + lk) * KP + li;
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) acc[ct] = UpdMma<T>::mma(av[u], brow[16 * ct], acc[ct]);
           }
         }
       }
-#pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        if (s0 + u < nsteps) {
-          const T *brow = sB + (4 * (s0 + u) + lk) * KP + li;
-#pragma unroll
-          for (int ct = 0; ct < NT; ++ct) acc[ct] = UpdMma<T>::mma(av[u], brow[16 * ct], acc[ct]);
-        }
-      }
     }
-  }
+  };
+  segment(A, lda, 0, k);
+  segment(A2, lda2, k, n);
+  segment(X1o, m, n, ntot);
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
