@@ -283,16 +283,16 @@ __global__ __launch_bounds__(UPD_T) void k_update(
   // that every read is a plain load (a choice between sources per element
   // would make the compiler wait for each read on its own); a segment's last
   // k-step is padded with zero rows of B and clamped reads
-  auto segment = [&](const auto *src, int64_t ld, int ja, int jb) {
+  // (brow: row ja of B = [-S; Z; T], k entries per row)
+  auto segment = [&](const auto *src, int64_t ld, int ja, int jb, const T *brow0) {
     for (int j0 = ja; j0 < jb; j0 += grows) {
       const int jl = min(grows, jb - j0);
       const int nsteps = (jl + 3) / 4;
       __syncthreads();
       for (int e = t; e < 4 * nsteps * KP; e += UPD_T) {
-        const int jr = e / KP, c = e - jr * KP, j = j0 + jr;
-        T v = T(0);
-        if (jr < jl && c < k) v = (j < n) ? Gt[(int64_t)j * k + c] : Tt[(j - n) * k + c];
-        sB[e] = v;
+        const int jr = e / KP, c = e - jr * KP;
+        const T v = brow0[(int64_t)(j0 - ja + min(jr, jl - 1)) * k + min(c, k - 1)];
+        sB[e] = v * ((jr < jl && c < k) ? T(1) : T(0));
       }
       __syncthreads();
       for (int s0 = 0; s0 < nsteps; s0 += UB) {
@@ -318,9 +318,9 @@ __global__ __launch_bounds__(UPD_T) void k_update(
       }
     }
   };
-  segment(A, lda, 0, k);
-  segment(A2, lda2, k, n);
-  segment(X1o, m, n, ntot);
+  segment(A, lda, 0, k, Gt);
+  segment(A2, lda2, k, n, Gt + (int64_t)k * k);
+  segment(X1o, m, n, ntot, Tt);
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
@@ -344,16 +344,24 @@ __global__ __launch_bounds__(UPD_T) void k_update(
     return;
   }
   double f1 = 0.0, dx = 0.0;
+  // reads first, all in flight (row and column clamped), then the sums
+  const int64_t ic = act ? i : (m - 1);
+  T av[KMAX], xo[KMAX];
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) {
+    const int cc = min(c, k - 1);
+    av[c] = A[ic + (int64_t)cc * lda];
+    xo[c] = X1o[ic + (int64_t)cc * m];
+  }
   if (act) {
 #pragma unroll
     for (int c = 0; c < KMAX; ++c)
       if (c < k) {
-        const T x = A[i + (int64_t)c * lda] + e[c];
+        const T x = av[c] + e[c];
         X1n[i + (int64_t)c * m] = x;
-        const double wd = CONSTW ? (double)wc : (double)W1[i + (int64_t)c * ldw];
-        const double d = (double)A[i + (int64_t)c * lda] - (double)x;
-        f1 += d * d * wd * wd;
-        const double dd = (double)x - (double)X1o[i + (int64_t)c * m];
+        const double d = (double)av[c] - (double)x;
+        f1 += d * d * (double)wc * (double)wc;
+        const double dd = (double)x - (double)xo[c];
         dx += dd * dd;
       }
   }
@@ -382,11 +390,14 @@ __global__ __launch_bounds__(64) void k_rowsolve_reg(
   const bool act = i < m;
   const int64_t ir = act ? i : (m - 1);
   T e[KMAX], q[KMAX], L[KMAX * (KMAX + 1) / 2];
+  // clamped reads, all in flight; past k: e = 0 and q = 1 by arithmetic
 #pragma unroll
   for (int c = 0; c < KMAX; ++c) {
-    e[c] = (c < k) ? Eb[ir + (int64_t)c * m] : T(0);
-    const T wv = (c < k) ? W1[ir + (int64_t)c * ldw] : T(1);
-    q[c] = wv * wv;
+    const int cc = min(c, k - 1);
+    const T mf = (c < k) ? T(1) : T(0);
+    e[c] = Eb[ir + (int64_t)cc * m] * mf;
+    const T wv = W1[ir + (int64_t)cc * ldw];
+    q[c] = wv * wv * mf + (T(1) - mf);
   }
   int bad = 0;
 #pragma unroll
@@ -471,9 +482,15 @@ __global__ __launch_bounds__(64) void k_rowsolve_lds(
   const bool act = i < m;
   const int64_t ir = act ? i : (m - 1);
   for (int e2 = lane; e2 < k * k; e2 += 64) sS[e2] = St[e2];
-  T e[KMAX];
+  // all reads in flight first (clamped columns; entries past k are never used)
+  T e[KMAX], wq[KMAX];
 #pragma unroll
-  for (int c = 0; c < KMAX; ++c) e[c] = (c < k) ? Eb[ir + (int64_t)c * m] : T(0);
+  for (int c = 0; c < KMAX; ++c) {
+    const int cc = min(c, k - 1);
+    e[c] = Eb[ir + (int64_t)cc * m];
+    const T wv = W1[ir + (int64_t)cc * ldw];
+    wq[c] = wv * wv;
+  }
   __syncthreads();
   int bad = 0;
   {
@@ -488,8 +505,7 @@ __global__ __launch_bounds__(64) void k_rowsolve_lds(
         for (int c = 0; c < KMAX; ++c)
           if (c < k) {
             E[c * nl] = e[c];
-            const T wv = W1[ir + (int64_t)c * ldw];
-            Q[c * nl] = wv * wv;
+            Q[c * nl] = wq[c];
           }
         for (int jj = 0; jj < k; ++jj) {
           const int bj = jj * (jj + 1) / 2;
@@ -950,6 +966,19 @@ static void launch_update_a2(hipStream_t s, const UpdateArgs<T> &a, const Update
   launch_update_kernel<T, KMAX, CONSTW, T>(s, a, a.A + (int64_t)a.k * a.lda, a.lda, pl);
 }
 
+template <typename T>
+static void launch_rowsolve_reg(hipStream_t s, const UpdateArgs<T> &a, unsigned grid) {
+  if (a.k <= 8)
+    hipLaunchKernelGGL((k_rowsolve_reg<T, 8>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
+                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
+  else if (a.k <= 16)
+    hipLaunchKernelGGL((k_rowsolve_reg<T, 16>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
+                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
+  else
+    hipLaunchKernelGGL((k_rowsolve_reg<T, 24>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
+                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
+}
+
 template <typename T, int KMAX>
 static void launch_update_k(hipStream_t s, const UpdateArgs<T> &a) {
   const unsigned grid = (unsigned)((a.m + 63) / 64);
@@ -959,17 +988,14 @@ static void launch_update_k(hipStream_t s, const UpdateArgs<T> &a) {
     return;
   }
   launch_update_a2<T, KMAX, false>(s, a, pl);
-  if (sizeof(T) == 4 && a.k <= 24) {
-    if (a.k <= 8)
-      hipLaunchKernelGGL((k_rowsolve_reg<T, 8>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
-                         a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
-    else if (a.k <= 16)
-      hipLaunchKernelGGL((k_rowsolve_reg<T, 16>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
-                         a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
-    else
-      hipLaunchKernelGGL((k_rowsolve_reg<T, 24>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
-                         a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
-  } else {
+  // register-resident per-row solves for fp32 up to k = 24 (the fp64 factor would not fit)
+  if constexpr (sizeof(T) == 4) {
+    if (a.k <= 24) {
+      launch_rowsolve_reg<T>(s, a, grid);
+      return;
+    }
+  }
+  {
     const size_t shm = (size_t)a.k * a.k * sizeof(T) +
                        (size_t)(a.k * (a.k + 1) / 2 + 2 * a.k) * pl.nl * sizeof(T);
     hipLaunchKernelGGL((k_rowsolve_lds<T, KMAX>), dim3(grid), dim3(64), shm, s, a.m, a.k, a.A,
