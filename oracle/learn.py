@@ -28,8 +28,14 @@ averaged over the batch; lam = 1.
 
 Adam (Kingma and Ba, 2015) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
 
-Decode.  L0 = A Y (m x r) and X1_0 = L0 (L0^T L0)^-1 L0^T A1: the start is
-A1 projected on the column space the network predicts.
+Decode.  The network predicts a basis Y of the row space of X*.  The start
+is the best matrix with that row space under the objective of problem (5):
+row i of X_0 is z_i Y^T with
+    z_i = argmin_z  sum_{c<k} W1[i,c]^2 (A[i,c] - (Y z)_c)^2
+                  + sum_{c>=k} (A[i,c] - (Y z)_c)^2,
+a weighted least-squares problem per row (the objective separates over rows
+once the row space is fixed), and X1_0 = its first k columns.  With the exact
+row space of a fixed point of Algorithm 1 this returns that fixed point's X1.
 """
 import numpy as np
 
@@ -154,10 +160,26 @@ def adam_step(p, g, m, v, t, lr):
     return p - lr * mh / (np.sqrt(vh) + ADAM_EPS), m, v
 
 
-def decode(A, k, Y):
-    """X1_0 = L0 (L0^T L0)^-1 L0^T A1 with L0 = A Y."""
+def decode(A, W1, k, Y, row_chunk=512):
+    """X1_0 from the row-space basis Y (n x r): per row, the weighted least
+    squares fit z_i (QR of the stacked system [w_i * Y1; Y2] z = [w_i * a1_i;
+    a2_i], Y1 = Y[:k], Y2 = Y[k:]) and X1_0[i] = Y1 z_i.  W1: m x k or a
+    scalar."""
     A = np.asarray(A, dtype=np.float64)
-    L0 = A @ Y
-    G = L0.T @ L0
-    H = L0.T @ A[:, :k]
-    return L0 @ np.linalg.solve(G, H)
+    Y = np.asarray(Y, dtype=np.float64)
+    m, n = A.shape
+    if np.isscalar(W1):
+        W1 = np.full((m, k), float(W1))
+    W1 = np.asarray(W1, dtype=np.float64)
+    Y1, Y2 = Y[:k], Y[k:]
+    X1 = np.empty((m, k))
+    for i0 in range(0, m, row_chunk):
+        i1 = min(m, i0 + row_chunk)
+        w = W1[i0:i1]                                   # rows x k
+        M = np.concatenate([w[:, :, None] * Y1[None], np.broadcast_to(Y2, (i1 - i0,) + Y2.shape)],
+                           axis=1)                      # rows x n x r
+        b = np.concatenate([w * A[i0:i1, :k], A[i0:i1, k:]], axis=1)
+        Q, R = np.linalg.qr(M)
+        z = np.linalg.solve(R, np.einsum('inr,in->ir', Q, b)[:, :, None])[:, :, 0]
+        X1[i0:i1] = z @ Y1.T
+    return X1

@@ -95,7 +95,8 @@ def test_learned_start_decode_matches_oracle(s64):
     s64.mlp_init(p, n, r, 31)
     params = host(p)
     y, _ = L.forward(params, L.sketch(inst.A)[None, :], n, r)
-    X1_ref = L.decode(inst.A, k, y[0].reshape(n, r, order="F"))
+    W1 = inst.W1 if inst.W1 is not None else inst.w1_const
+    X1_ref = L.decode(inst.A, W1, k, y[0].reshape(n, r, order="F"))
     X1, _, res = gpu_solve(s64, inst, 0.0, 0, init="learned", want_x2=False, model=p)
     print("learned start", res, flush=True)
     assert rel(X1, X1_ref) <= 1e-4
@@ -106,8 +107,8 @@ def test_learned_start_decode_matches_oracle(s64):
 
 
 def test_learned_start_falls_back_to_random(s64):
-    """A network whose output is zero gives L0 = 0: the decode fails and the
-    random start keyed by the same seed is used."""
+    """A network whose output is zero predicts no row space: the decode
+    fails and the random start keyed by the same seed is used."""
     import torch
     inst = _inst(seed=4)
     p = torch.zeros(_params_gpu(inst.n, inst.r, 0).shape, dtype=torch.float32, device="cuda")

@@ -100,16 +100,51 @@ def test_target_basis_contains_the_solution_rows():
     assert np.allclose(Q.T @ Q, np.eye(inst.r), atol=1e-12)
 
 
-def test_decode_exact_and_invariant():
+def test_decode_returns_the_fixed_point_for_its_row_space():
+    """Once the row space is fixed, problem (5) separates over rows, and a
+    fixed point of Algorithm 1 is optimal among matrices with its own row
+    space (both stationarity conditions of the per-row problem are the X1
+    update and D = (P_perp A2) V V^T).  The decode of that row space must
+    therefore give the fixed point's X1 back, with log-uniform weights."""
+    inst = video.small(m_hw=(8, 10), n=14, k=4, r=6, rho=2, seed=17)
+    res = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=1e-14, max_sweeps=2000, X1_0=inst.X1_0)
+    assert res.status == O.OK
+    T = L.target_basis(res.C, res.V, inst.k, inst.r)
+    X1 = L.decode(inst.A, inst.W1, inst.k, T)
+    assert np.linalg.norm(X1 - res.X1) <= 1e-8 * np.linalg.norm(res.X1)
+    # a start off the fixed point is not returned unchanged
+    T2 = T + 0.1 * np.random.default_rng(3).standard_normal(T.shape)
+    assert np.linalg.norm(L.decode(inst.A, inst.W1, inst.k, T2) - res.X1) > 1e-4 * np.linalg.norm(res.X1)
+
+
+def test_decode_special_cases():
     rng = np.random.default_rng(9)
     m, n, k, r = 40, 12, 3, 5
-    A = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))   # rank r exactly
-    _, _, Vt = np.linalg.svd(A)
-    Y = Vt[:r].T
-    assert np.allclose(L.decode(A, k, Y), A[:, :k], atol=1e-10)
-    Y2 = rng.standard_normal((n, r))
+    A = rng.standard_normal((m, n))
+    W1 = 10.0 ** rng.uniform(0, 3, size=(m, k))
+    # the whole of R^n as row space: the start is A1 itself, for any weights
+    Yf = rng.standard_normal((n, n))
+    assert np.allclose(L.decode(A, W1, k, Yf), A[:, :k], atol=1e-9)
+    # unit weights: orthogonal projection of the rows of A on span(Y)
+    Y = rng.standard_normal((n, r))
+    Pr = Y @ np.linalg.solve(Y.T @ Y, Y.T)
+    assert np.allclose(L.decode(A, 1.0, k, Y), (A @ Pr)[:, :k], atol=1e-10)
+    # only the row space matters
     M = rng.standard_normal((r, r)) + 3 * np.eye(r)
-    assert np.allclose(L.decode(A, k, Y2), L.decode(A, k, Y2 @ M), atol=1e-9)
+    assert np.allclose(L.decode(A, W1, k, Y), L.decode(A, W1, k, Y @ M), atol=1e-9)
+    # optimality in the row space: perturbing a row's coefficients raises
+    # that row's weighted residual, and the decode's x1 is the optimum's
+    X1 = L.decode(A, W1, k, Y)
+    def row_cost(i, z):
+        x = Y @ z
+        return np.sum((W1[i] * (A[i, :k] - x[:k])) ** 2) + np.sum((A[i, k:] - x[k:]) ** 2)
+    for i in (0, 7, 31):
+        z = np.linalg.lstsq(np.vstack([W1[i][:, None] * Y[:k], Y[k:]]),
+                            np.concatenate([W1[i] * A[i, :k], A[i, k:]]), rcond=None)[0]
+        c0 = row_cost(i, z)
+        for _ in range(5):
+            assert row_cost(i, z + 1e-3 * rng.standard_normal(r)) > c0
+        assert np.allclose(Y[:k] @ z, X1[i], atol=1e-9)
 
 
 def test_sketch_of_a_single_entry_is_an_outer_product():
