@@ -1,7 +1,8 @@
 // Learned warm start: Gaussian sketch of A, the MLP 512 -> 256 -> 256 -> n r
-// (forward, backward, Adam) and the decode X1_0 = L0 (L0^T L0)^-1 L0^T A1 with
-// L0 = A Y.  Not part of the paper (which starts Algorithm 1 from a random
-// X1_0); the sweep that follows is unchanged.
+// (forward, backward, Adam) and the decode of the predicted row basis Y into
+// X1_0 (k_ldecode, then the row-update kernels).  Not part of the paper
+// (which starts Algorithm 1 from a random X1_0); the sweep that follows is
+// unchanged.
 //
 // Network matrices are row-major float: activations B x features, weights
 // out x in.  Sums over the m rows of A use the tall-skinny product kernel
@@ -265,142 +266,179 @@ __global__ __launch_bounds__(256) void k_adam(int64_t P, float *__restrict__ p,
 }
 
 // ---------------------------------------------------------------------------
-// Decode.  out (m x c, column-major, ld ldo) = A (m x kin, ld lda) times a
-// small kin x c matrix S with element (j, q) at S[j rs + q cs]; one row per
-// lane, rows of S staged through LDS.
-#define TS_STAGE_BYTES 32768
-template <typename T, typename TS, int CMAX>
-__global__ __launch_bounds__(64) void k_tall_small(int64_t m, int kin, int c,
-                                                   const T *__restrict__ A, int64_t lda,
-                                                   const TS *__restrict__ S, int64_t rs,
-                                                   int64_t cs, T *__restrict__ out, int64_t ldo) {
-  constexpr int TS_STAGE = TS_STAGE_BYTES / sizeof(T);
-  __shared__ T sS[TS_STAGE];
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const bool act = i < m;
-  const int64_t ir = act ? i : (m - 1);
-  T acc[CMAX];
-#pragma unroll
-  for (int q = 0; q < CMAX; ++q) acc[q] = T(0);
-  const int rows = max(1, TS_STAGE / max(c, 1));
-  for (int j0 = 0; j0 < kin; j0 += rows) {
-    const int nr = min(rows, kin - j0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nr * c; e += 64) {
-      const int jj = e / c, q = e - jj * c;
-      sS[e] = (T)S[(int64_t)(j0 + jj) * rs + (int64_t)q * cs];
-    }
-    __syncthreads();
-    int jj = 0;
-    for (; jj + 8 <= nr; jj += 8) {  // 8 reads of A in flight
-      T a[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = A[ir + (int64_t)(j0 + jj + u) * lda];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const T *srow = sS + (jj + u) * c;
-#pragma unroll
-        for (int q = 0; q < CMAX; ++q)
-          if (q < c) acc[q] = fma(a[u], srow[q], acc[q]);
-      }
-    }
-    for (; jj < nr; ++jj) {
-      const T a = A[ir + (int64_t)(j0 + jj) * lda];
-      const T *srow = sS + jj * c;
-#pragma unroll
-      for (int q = 0; q < CMAX; ++q)
-        if (q < c) acc[q] = fma(a, srow[q], acc[q]);
-    }
-  }
-  if (act) {
-#pragma unroll
-    for (int q = 0; q < CMAX; ++q)
-      if (q < c) out[i + (int64_t)q * ldo] = acc[q];
-  }
-}
-
-// Y = G^-1 H (G r x r SPD, H r x k, both column-major double) by Cholesky in
-// LDS (lower, right-looking, by wavefront 0); then one thread per column of
-// H solves L L^T y = h with the column in registers.  Y is stored typed,
-// row-major r x k (element (q, c) at Y[q k + c]).  A pivot below 1e-13 of
-// the largest diagonal entry or a non-finite entry sets DEV_LEARN_FAIL.
+// Decode of the predicted row basis Y (n x r, Y[j + n q], r <= LEARN_RMAX).
+// With the row space fixed, problem (5) separates over rows; row i of the
+// start is the weighted least-squares fit z_i Y^T.  Writing the rows of
+// span(Y^T) as [x1, x1 C + u W^T] (C = (Y1^+)^T Y2^T, k x n2, from the k x r
+// block Y1 = Y[:k]; W = Y2 P_b, P_b the projector on null(Y1)), the fit of
+// u is a plain projection and what is left for x1 is the k x k problem
+//     x1 (diag(w_i^2) + S) = a1 diag(w_i^2) + a2 Z,
+// Z = (I - P_W) C^T, S = C Z, which is the row update of Algorithm 1
+// (steps 7-9) with these S and Z and no X1 term.  This kernel forms them in
+// double on one workgroup:
+//   G = Y1 Y1^T (Cholesky), F = G^-1 Y1, P_b = I - Y1^T F,
+//   C^T = Y2 F^T, W = Y2 P_b, N = W^T W + (I - P_b)  (SPD when W has rank
+//   r - k; N^-1 on range(W^T) is the pseudo-inverse of W^T W),
+//   Z = C^T - W N^-1 W^T C^T, S = C Z (symmetrised),
+// and writes them as the row update's operands: Gt = [-S; Z] ((k + n2) x k
+// row-major), St = S, Tt = 0.  ws holds C^T, W and Z (double, n2 x (2k + r),
+// column-major).  Y is first scaled to ||Y||_F^2 = r (the row space does not
+// change).  A zero Y, a pivot of G or N below 1e-13 of its largest diagonal
+// entry, or a non-finite result sets DEV_LEARN_FAIL.
 template <typename T>
-__global__ __launch_bounds__(256) void k_decode_solve(int r, int k, const double *__restrict__ Gg,
-                                                      const double *__restrict__ H,
-                                                      T *__restrict__ Y, int *flags) {
+__global__ __launch_bounds__(256) void k_ldecode(int n, int k, int r, const float *__restrict__ yv,
+                                                 double *__restrict__ ws, T *__restrict__ Gt,
+                                                 T *__restrict__ Tt, T *__restrict__ St,
+                                                 int *flags) {
   constexpr int L = LEARN_RMAX;
-  __shared__ double G[L * L];
+  __shared__ double sY1[L * L], sG[L * L], sF[L * L], sP[L * L], sN[L * L], sU[L * L];
+  __shared__ double red[8];
   __shared__ int bad;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, n2 = n - k;
+  double *Ct = ws, *Wm = ws + (int64_t)n2 * k, *Zt = Wm + (int64_t)n2 * r;
   if (t == 0) bad = 0;
+  // scale so that ||Y||_F^2 = r
+  double ss = 0.0;
+  for (int64_t e = t; e < (int64_t)n * r; e += 256) ss += (double)yv[e] * (double)yv[e];
+  ss = block_sum(ss, red);
+  if (!(ss > 0.0) || !isfinite(ss)) {
+    if (t == 0) atomicOr(flags, DEV_LEARN_FAIL);
+    return;
+  }
+  const double sc = sqrt((double)r / ss);
   for (int e = t; e < L * L; e += 256) {
-    const int a = e % L, b = e / L;
-    G[e] = (a < r && b < r) ? Gg[a + b * r] : 0.0;
+    const int a = e % L, q = e / L;
+    sY1[e] = (a < k && q < r) ? sc * (double)yv[a + (int64_t)n * q] : 0.0;
   }
   __syncthreads();
-  double dmax = 0.0;
-  for (int j = 0; j < r; ++j) dmax = fmax(dmax, G[j + j * L]);
-  if (t < 64) {
-    for (int j = 0; j < r; ++j) {
-      if (t == 0) {
-        double d = G[j + j * L];
-        if (!(d > 1e-13 * dmax)) {
-          bad = 1;
-          d = 1.0;
+  // G = Y1 Y1^T (k x k, column-major in sG)
+  for (int e = t; e < k * k; e += 256) {
+    const int a = e % k, b = e / k;
+    double v = 0.0;
+    for (int q = 0; q < r; ++q) v = fma(sY1[a + q * L], sY1[b + q * L], v);
+    sG[a + b * L] = v;
+  }
+  __syncthreads();
+  // in-place lower Cholesky of an SPD matrix in LDS (ld L) by wavefront 0
+  auto chol = [&](double *Mx, int nn) {
+    if (t < 64) {
+      double dmax = 0.0;
+      for (int j = 0; j < nn; ++j) dmax = fmax(dmax, Mx[j + j * L]);
+      for (int j = 0; j < nn; ++j) {
+        if (t == 0) {
+          double d = Mx[j + j * L];
+          if (!(d > 1e-13 * dmax)) {
+            bad = 1;
+            d = 1.0;
+          }
+          Mx[j + j * L] = sqrt(d);
         }
-        G[j + j * L] = sqrt(d);
+        wave_sync();
+        const double ljj = Mx[j + j * L];
+        for (int i = j + 1 + t; i < nn; i += 64) Mx[i + j * L] /= ljj;
+        wave_sync();
+        const int rem = nn - j - 1;
+        for (int e = t; e < rem * rem; e += 64) {
+          const int i = j + 1 + e % rem, q = j + 1 + e / rem;
+          if (q <= i) Mx[i + q * L] -= Mx[i + j * L] * Mx[q + j * L];
+        }
+        wave_sync();
       }
-      wave_sync();
-      const double ljj = G[j + j * L];
-      for (int i = j + 1 + t; i < r; i += 64) G[i + j * L] /= ljj;
-      wave_sync();
-      const int rem = r - j - 1;
-      for (int e = t; e < rem * rem; e += 64) {
-        const int i = j + 1 + e % rem, q = j + 1 + e / rem;
-        if (q <= i) G[i + q * L] -= G[i + j * L] * G[q + j * L];
-      }
-      wave_sync();
     }
-    // the strict upper triangle is never read below; keep it zero
-    for (int e = t; e < r * r; e += 64)
-      if ((e % r) < (e / r)) G[(e % r) + (e / r) * L] = 0.0;
+    __syncthreads();
+  };
+  // X (nn x cols, ld L) <- (L L^T)^-1 X, one thread per column
+  auto chol_solve = [&](const double *Lx, int nn, double *X, int cols) {
+    for (int c = t; c < cols; c += 256) {
+      double *x = X + c * L;
+      for (int i = 0; i < nn; ++i) {
+        double v = x[i];
+        for (int q = 0; q < i; ++q) v -= Lx[i + q * L] * x[q];
+        x[i] = v / Lx[i + i * L];
+      }
+      for (int i = nn - 1; i >= 0; --i) {
+        double v = x[i];
+        for (int q = i + 1; q < nn; ++q) v -= Lx[q + i * L] * x[q];
+        x[i] = v / Lx[i + i * L];
+      }
+    }
+    __syncthreads();
+  };
+  chol(sG, k);
+  // F = G^-1 Y1 (k x r)
+  for (int e = t; e < L * L; e += 256) sF[e] = sY1[e];
+  __syncthreads();
+  chol_solve(sG, k, sF, r);
+  // P_b = I - Y1^T F (r x r)
+  for (int e = t; e < r * r; e += 256) {
+    const int q = e % r, q2 = e / r;
+    double v = (q == q2) ? 1.0 : 0.0;
+    for (int a = 0; a < k; ++a) v -= sY1[a + q * L] * sF[a + q2 * L];
+    sP[q + q2 * L] = v;
   }
   __syncthreads();
-  for (int c = t; c < k; c += 256) {
-    double x[L];
-#pragma unroll
-    for (int i = 0; i < L; ++i) x[i] = (i < r) ? H[i + (int64_t)c * r] : 0.0;
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-      if (i < r) {
-        double s = x[i];
-#pragma unroll
-        for (int q = 0; q < i; ++q) s -= G[i + q * L] * x[q];
-        x[i] = s / G[i + i * L];
-      }
-      asm volatile("" ::: "memory");  // keep each row's reads of L in place
+  // C^T = Y2 F^T (n2 x k) and W = Y2 P_b (n2 x r)
+  for (int64_t e = t; e < (int64_t)n2 * (k + r); e += 256) {
+    const int j = (int)(e % n2), c = (int)(e / n2);
+    double v = 0.0;
+    if (c < k) {
+      for (int q = 0; q < r; ++q) v = fma((double)yv[k + j + (int64_t)n * q], sF[c + q * L], v);
+      Ct[j + (int64_t)c * n2] = sc * v;
+    } else {
+      const int q2 = c - k;
+      for (int q = 0; q < r; ++q) v = fma((double)yv[k + j + (int64_t)n * q], sP[q + q2 * L], v);
+      Wm[j + (int64_t)q2 * n2] = sc * v;
     }
-#pragma unroll
-    for (int i = L - 1; i >= 0; --i) {
-      if (i < r) {
-        double s = x[i];
-#pragma unroll
-        for (int q = i + 1; q < L; ++q) s -= G[q + i * L] * x[q];
-        x[i] = s / G[i + i * L];
-      }
-      asm volatile("" ::: "memory");
+  }
+  __syncthreads();
+  // N = W^T W + (I - P_b) (r x r) and U = W^T C^T (r x k, in sU)
+  for (int e = t; e < r * (r + k); e += 256) {
+    const int q = e % r, c = e / r;
+    const double *wq = Wm + (int64_t)q * n2;
+    const double *v2 = (c < r) ? Wm + (int64_t)c * n2 : Ct + (int64_t)(c - r) * n2;
+    double v = 0.0;
+    for (int j = 0; j < n2; ++j) v = fma(wq[j], v2[j], v);
+    if (c < r)
+      sN[q + c * L] = v + ((q == c) ? 1.0 : 0.0) - sP[q + c * L];
+    else
+      sU[q + (c - r) * L] = v;
+  }
+  __syncthreads();
+  chol(sN, r);
+  chol_solve(sN, r, sU, k);
+  // Z = C^T - W (N^-1 U) (n2 x k)
+  for (int64_t e = t; e < (int64_t)n2 * k; e += 256) {
+    const int j = (int)(e % n2), c = (int)(e / n2);
+    double v = Ct[j + (int64_t)c * n2];
+    for (int q = 0; q < r; ++q) v -= Wm[j + (int64_t)q * n2] * sU[q + c * L];
+    Zt[j + (int64_t)c * n2] = v;
+    Gt[(int64_t)(k + j) * k + c] = (T)v;
+    if (!isfinite(v)) bad = 1;
+  }
+  __syncthreads();
+  // S = C Z, symmetrised; Gt's first k rows are -S; T = 0
+  for (int e = t; e < k * k; e += 256) {
+    const int a = e % k, c = e / k;
+    double v1 = 0.0, v2 = 0.0;
+    for (int j = 0; j < n2; ++j) {
+      v1 = fma(Ct[j + (int64_t)a * n2], Zt[j + (int64_t)c * n2], v1);
+      v2 = fma(Ct[j + (int64_t)c * n2], Zt[j + (int64_t)a * n2], v2);
     }
-    int nb = 0;
-#pragma unroll
-    for (int i = 0; i < L; ++i)
-      if (i < r) {
-        nb |= !isfinite(x[i]);
-        Y[(int64_t)i * k + c] = (T)x[i];
-      }
-    if (nb) bad = 1;
+    const double sv = 0.5 * (v1 + v2);
+    if (!isfinite(sv)) bad = 1;
+    St[a * k + c] = (T)sv;
+    Gt[a * k + c] = (T)(-sv);
+    Tt[a * k + c] = T(0);
   }
   __syncthreads();
   if (t == 0 && bad) atomicOr(flags, DEV_LEARN_FAIL);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(int64_t count, T *__restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -482,34 +520,23 @@ void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, f
                      eps, bc1, bc2);
 }
 
-template <typename T, typename TS>
-void launch_tall_small(hipStream_t s, int64_t m, int kin, int c, const T *A, int64_t lda,
-                       const TS *S, int64_t rs, int64_t cs, T *out, int64_t ldo) {
-  if (c < 1 || c > 64) return;  // the kernel holds at most 64 accumulators
-  const unsigned grid = (unsigned)((m + 63) / 64);
-  if (c <= 32)
-    hipLaunchKernelGGL((k_tall_small<T, TS, 32>), dim3(grid), dim3(64), 0, s, m, kin, c, A, lda, S,
-                       rs, cs, out, ldo);
-  else
-    hipLaunchKernelGGL((k_tall_small<T, TS, 64>), dim3(grid), dim3(64), 0, s, m, kin, c, A, lda, S,
-                       rs, cs, out, ldo);
+template <typename T>
+void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, double *ws, T *Gt, T *Tt,
+                    T *St, int *flags) {
+  hipLaunchKernelGGL(k_ldecode<T>, dim3(1), dim3(256), 0, s, n, k, r, yv, ws, Gt, Tt, St, flags);
 }
 
 template <typename T>
-void launch_decode_solve(hipStream_t s, int r, int k, const double *G, const double *H, T *Y,
-                         int *flags) {
-  hipLaunchKernelGGL(k_decode_solve<T>, dim3(1), dim3(256), 0, s, r, k, G, H, Y, flags);
+void launch_zero(hipStream_t s, int64_t count, T *out) {
+  hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(count, 4096)), dim3(256), 0, s, count, out);
 }
 
 #define INST_L(T)                                                                               \
   template void launch_gauss_fill<T>(hipStream_t, int64_t, uint64_t, double, T *);            \
   template void launch_sketch_finish<T>(hipStream_t, int, const double *, const T *, float *); \
-  template void launch_tall_small<T, T>(hipStream_t, int64_t, int, int, const T *, int64_t,    \
-                                        const T *, int64_t, int64_t, T *, int64_t);            \
-  template void launch_decode_solve<T>(hipStream_t, int, int, const double *, const double *,   \
-                                       T *, int *);
+  template void launch_ldecode<T>(hipStream_t, int, int, int, const float *, double *, T *, T *, \
+                                  T *, int *);                                                 \
+  template void launch_zero<T>(hipStream_t, int64_t, T *);
 INST_L(float)
 INST_L(double)
-template void launch_tall_small<double, float>(hipStream_t, int64_t, int, int, const double *,
-                                               int64_t, const float *, int64_t, int64_t, double *,
-                                               int64_t);
+

@@ -132,12 +132,11 @@ void launch_subspace_loss(hipStream_t s, int n, int r, int batch, const float *y
                           double lam, float *gy, double *loss_part, int *flags);
 void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, float *v, float lr,
                  float b1, float b2, float eps, float bc1, float bc2);
-template <typename T, typename TS>
-void launch_tall_small(hipStream_t s, int64_t m, int kin, int c, const T *A, int64_t lda,
-                       const TS *S, int64_t rs, int64_t cs, T *out, int64_t ldo);
 template <typename T>
-void launch_decode_solve(hipStream_t s, int r, int k, const double *G, const double *H, T *Y,
-                         int *flags);
+void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, double *ws, T *Gt, T *Tt,
+                    T *St, int *flags);
+template <typename T>
+void launch_zero(hipStream_t s, int64_t count, T *out);
 
 // Error_p through a Gram of aligned factor differences (k_stream.hip).
 void launch_chgprep(hipStream_t s, int n2, int k, int l, const double *Vp, const double *Vq,

@@ -127,8 +127,8 @@ struct Sizes {
   size_t elt;
   bool mixed;
   bool learned;
-  int splits_l1, splits_l2, splits_l3;  // Om^T A, L0^T L0, L0^T A1
-  int64_t rows_l1, rows_l2, rows_l3;
+  int splits_l1;  // Om^T A of the learned start's sketch
+  int64_t rows_l1;
   int splits_kg;  // H^T H of the change pass (n2 rows)
   int64_t rows_kg;
   int splits_g1;  // X1^T X1
@@ -145,8 +145,8 @@ struct Ptrs {
   double *Hb, *Rh;  // change pass: aligned basis [V_p dV Z_p dZ] and its Gram
   double *epart;    // multi-workgroup eigen kernel: partial Grams
   // learned warm start (NULL unless the start is learned)
-  void *Om, *Ps, *L0, *Yc;
-  double *P1, *LG, *LH, *lpart;
+  void *Om, *Ps;
+  double *P1, *Ld, *lpart;  // Ld: the decode's C^T, W and Z (n2 x (2k + r))
   float *sk, *lh1, *lh2, *yv;
   SmallState *st;
   int *flags;
@@ -179,8 +179,6 @@ Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mi
     z.splits_g1 = choose_splits(m, tk1 * tk1, &z.rows_g1);
   }
   z.splits_l1 = choose_splits(m, (int)((n + 31) / 32), &z.rows_l1);
-  z.splits_l2 = choose_splits(m, 1, &z.rows_l2);
-  z.splits_l3 = choose_splits(m, (int)((std::max<int64_t>(k, 1) + 31) / 32), &z.rows_l3);
   {
     const int K = (int)(2 * z.l + 2 * k), tk = (K + 31) / 32;
     z.splits_kg = choose_splits(std::max<int64_t>(z.n2, 1), std::max(1, tk * (tk + 1) / 2),
@@ -247,16 +245,10 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
            : 0},
       {&p.Om, z.learned ? (size_t)(m * LEARN_SK_ROWS) * z.elt : 0},
       {&p.Ps, z.learned ? (size_t)(z.n * LEARN_SK_COLS) * z.elt : 0},
-      {&p.L0, z.learned ? (size_t)(m * z.r) * z.elt : 0},
-      {&p.Yc, z.learned ? (size_t)(z.r * kk) * z.elt : 0},
       {(void **)&p.P1, z.learned ? (size_t)(LEARN_SK_ROWS * z.n) * d : 0},
-      {(void **)&p.LG, z.learned ? (size_t)(z.r * z.r) * d : 0},
-      {(void **)&p.LH, z.learned ? (size_t)(z.r * kk) * d : 0},
+      {(void **)&p.Ld, z.learned ? (size_t)(z.n2 * (2 * kk + z.r)) * d : 0},
       {(void **)&p.lpart,
-       z.learned ? std::max<size_t>((size_t)z.splits_l1 * LEARN_SK_ROWS * z.n,
-                                    std::max<size_t>((size_t)z.splits_l2 * z.r * z.r,
-                                                     (size_t)z.splits_l3 * z.r * kk)) * d
-                 : 0},
+       z.learned ? (size_t)z.splits_l1 * LEARN_SK_ROWS * z.n * d : 0},
       {(void **)&p.sk, z.learned ? (size_t)LEARN_D_IN * sizeof(float) : 0},
       {(void **)&p.lh1, z.learned ? (size_t)LEARN_HID * sizeof(float) : 0},
       {(void **)&p.lh2, z.learned ? (size_t)LEARN_HID * sizeof(float) : 0},
@@ -353,13 +345,16 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   T *X1c = static_cast<T *>(P.X1[0]);
   bool need_init = (k > 0);
   if (learned) {
-    // X1_0 = L0 (L0^T L0)^-1 L0^T A1 with L0 = A Y, Y = network(sketch of A)
-    const int64_t n = pr->n, nr = n * z.r;
+    // Y = network(sketch of A), the predicted row basis; X1_0 is the
+    // per-row weighted least-squares fit in span(Y^T): k_ldecode forms the
+    // row update's operands, the row-update kernels solve the k x k systems.
+    const int64_t n = pr->n;
     const float *W1m = pr->model, *b1 = W1m + LEARN_HID * LEARN_D_IN;
     const float *W2m = b1 + LEARN_HID, *b2 = W2m + LEARN_HID * LEARN_HID;
-    const float *W3m = b2 + LEARN_HID, *b3 = W3m + nr * LEARN_HID;
+    const float *W3m = b2 + LEARN_HID, *b3 = W3m + n * z.r * LEARN_HID;
     T *Om = static_cast<T *>(P.Om), *Ps = static_cast<T *>(P.Ps);
-    T *L0 = static_cast<T *>(P.L0), *Yc = static_cast<T *>(P.Yc);
+    T *Gt = static_cast<T *>(P.Gt), *Tt = static_cast<T *>(P.Tt), *St = static_cast<T *>(P.St);
+    T *X1z = static_cast<T *>(P.X1[1]);
     auto seq = [&]() {
       launch_gauss_fill<T>(s, m * LEARN_SK_ROWS, LEARN_SEED_OMEGA, 1.0, Om);
       launch_gauss_fill<T>(s, n * LEARN_SK_COLS, LEARN_SEED_PSI, 1.0, Ps);
@@ -370,21 +365,32 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
                   LEARN_HID, b1, 1, nullptr, 0);
       launch_gemm(s, 0, 1, LEARN_HID, LEARN_HID, P.lh1, LEARN_HID, W2m, LEARN_HID, P.lh2,
                   LEARN_HID, b2, 1, nullptr, 0);
-      launch_gemm(s, 0, 1, (int)nr, LEARN_HID, P.lh2, LEARN_HID, W3m, LEARN_HID, P.yv, (int)nr,
-                  b3, 0, nullptr, 0);
-      launch_tall_small<T, float>(s, m, (int)n, (int)z.r, A, pr->lda, P.yv, 1, n, L0, m);
-      launch_tsgemm<T, T>(s, m, L0, m, (int)z.r, L0, m, (int)z.r, 0, z.splits_l2, z.rows_l2,
-                          P.lpart, P.LG, nullptr);
-      launch_tsgemm<T, T>(s, m, L0, m, (int)z.r, A, pr->lda, (int)k, 0, z.splits_l3, z.rows_l3,
-                          P.lpart, P.LH, nullptr);
-      launch_decode_solve<T>(s, (int)z.r, (int)k, P.LG, P.LH, Yc, P.flags);
-      launch_tall_small<T, T>(s, m, (int)z.r, (int)k, L0, m, Yc, k, 1, X1c, m);
+      launch_gemm(s, 0, 1, (int)(n * z.r), LEARN_HID, P.lh2, LEARN_HID, W3m, LEARN_HID, P.yv,
+                  (int)(n * z.r), b3, 0, nullptr, 0);
+      launch_ldecode<T>(s, (int)n, (int)k, (int)z.r, P.yv, P.Ld, Gt, Tt, St, P.flags);
+      launch_zero<T>(s, m * k, X1z);
+      UpdateArgs<T> ua{};
+      ua.m = m; ua.k = (int)k; ua.n = (int)n; ua.A = A; ua.lda = pr->lda; ua.W1 = W1;
+      ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1z; ua.X1n = X1c;
+      ua.Gt = Gt; ua.Tt = Tt; ua.St = St; ua.part = P.upd_part; ua.st = P.st;
+      ua.Eb = static_cast<T *>(P.Eb);
+      ua.A2b = nullptr;
+      ua.ldb = m;
+      ua.flags = P.flags;
+      launch_update<T>(s, ua);
     };
     PROF(h, KK_LEARN, seq());
     HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    // the plain random start is the fallback when the decode fails
-    need_init = (*h->flags_host & DEV_LEARN_FAIL) != 0;
+    // the plain random start is the fallback when the decode fails (its
+    // flags are then cleared: they describe the discarded start only)
+    const int lf = DEV_LEARN_FAIL | DEV_ROWSOLVE;
+    need_init = (*h->flags_host & lf) != 0;
+    if (need_init) {
+      *h->flags_host &= ~lf;
+      HIPCHK(hipMemcpyAsync(P.flags, h->flags_host, sizeof(int), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
   }
   if (need_init) {
     const int mode = (pr->init == WLRA_INIT_RANDOM || pr->init == WLRA_INIT_LEARNED) ? 0 : 1;
