@@ -269,166 +269,292 @@ __global__ __launch_bounds__(256) void k_adam(int64_t P, float *__restrict__ p,
 // Decode of the predicted row basis Y (n x r, Y[j + n q], r <= LEARN_RMAX).
 // With the row space fixed, problem (5) separates over rows; row i of the
 // start is the weighted least-squares fit z_i Y^T.  Writing the rows of
-// span(Y^T) as [x1, x1 C + u W^T] (C = (Y1^+)^T Y2^T, k x n2, from the k x r
-// block Y1 = Y[:k]; W = Y2 P_b, P_b the projector on null(Y1)), the fit of
-// u is a plain projection and what is left for x1 is the k x k problem
+// span(Y^T) as [x1, x1 C + u W^T] (C^T = Y2 F^T with F = (Y1 Y1^T)^-1 Y1,
+// Y1 = Y[:k], Y2 = Y[k:]; W = Y2 P_b, P_b = I - Y1^T F the projector on
+// null(Y1)), the fit of u is a plain projection and what is left for x1 is
+// the k x k problem
 //     x1 (diag(w_i^2) + S) = a1 diag(w_i^2) + a2 Z,
-// Z = (I - P_W) C^T, S = C Z, which is the row update of Algorithm 1
-// (steps 7-9) with these S and Z and no X1 term.  This kernel forms them in
-// double on one workgroup:
-//   G = Y1 Y1^T (Cholesky), F = G^-1 Y1, P_b = I - Y1^T F,
-//   C^T = Y2 F^T, W = Y2 P_b, N = W^T W + (I - P_b)  (SPD when W has rank
-//   r - k; N^-1 on range(W^T) is the pseudo-inverse of W^T W),
-//   Z = C^T - W N^-1 W^T C^T, S = C Z (symmetrised),
-// and writes them as the row update's operands: Gt = [-S; Z] ((k + n2) x k
-// row-major), St = S, Tt = 0.  ws holds C^T, W and Z (double, n2 x (2k + r),
-// column-major).  Y is first scaled to ||Y||_F^2 = r (the row space does not
-// change).  A zero Y, a pivot of G or N below 1e-13 of its largest diagonal
-// entry, or a non-finite result sets DEV_LEARN_FAIL.
+// Z = (I - P_W) C^T, S = C Z: the row update of Algorithm 1 (steps 7-9)
+// with these S and Z and no X1 term.  Y2 enters only through its r x r Gram
+// Gy = Y2^T Y2 and the final product Z = Y2 Q:
+//   N = P_b Gy P_b + (I - P_b)   (SPD when W has rank r - k; N^-1 on
+//                                  range(W^T) is the pseudo-inverse of W^T W)
+//   Q = F^T - P_b N^-1 P_b Gy F^T,   Z = Y2 Q,   S = F Gy Q (symmetrised).
+// Output as the row update's operands: Gt = [-S; Z] ((k + n2) x k,
+// row-major), St = S, Tt = 0.  One workgroup, all in double; Y is first
+// scaled to ||Y||_F^2 = r (the row space does not change).  A zero Y, a
+// pivot of Y1 Y1^T or N below 1e-13 of its largest diagonal entry, or a
+// non-finite result sets DEV_LEARN_FAIL.
+// Lower Cholesky in place of the SPD nn x nn matrix M (LDS, ld L, nn <= L
+// <= 64) by wavefront 0: one row per lane in registers, column j handed to
+// every lane through colbuf.  A pivot below 1e-13 of the largest diagonal
+// entry sets *bad (and is replaced by 1).  The strict upper triangle is
+// left as it was.
+template <int L>
+__device__ __forceinline__ void ld_chol_wave(double *M, int nn, double *colbuf, int *bad) {
+  const int i = threadIdx.x;
+  double dmax = 0.0;
+  for (int j = 0; j < nn; ++j) dmax = fmax(dmax, M[j + j * L]);
+  double a[L];
+#pragma unroll
+  for (int q = 0; q < L; ++q) a[q] = M[min(i, L - 1) + q * L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    if (j < nn) {
+      double d = __shfl(a[j], j, 64);
+      if (!(d > 1e-13 * dmax)) {
+        if (i == 0) *bad = 1;
+        d = 1.0;
+      }
+      const double ljj = sqrt(d), inv = 1.0 / ljj;
+      a[j] = (i == j) ? ljj : a[j] * inv;
+      colbuf[i] = a[j];
+      wave_sync();
+#pragma unroll
+      for (int q = j + 1; q < L; ++q)
+        if (q < nn) a[q] = fma(-a[j], colbuf[q], a[q]);
+      wave_sync();
+    }
+  }
+  if (i < nn) {
+#pragma unroll
+    for (int q = 0; q < L; ++q)
+      if (q <= i && q < nn) M[i + q * L] = a[q];
+  }
+  wave_sync();
+}
+
+// X (nn x cols, ld L, cols <= 64) <- (Lm Lm^T)^-1 X with Lm from
+// ld_chol_wave, by wavefront 0: one column per lane in registers, Lm read
+// from LDS (the same element in every lane).
+template <int L>
+__device__ __forceinline__ void ld_solve_wave(const double *Lm, int nn, double *X, int cols) {
+  const int c = threadIdx.x;
+  if (c < cols) {
+    double x[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) x[i] = X[i + c * L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      if (i < nn) {
+        double v = x[i];
+#pragma unroll
+        for (int q = 0; q < i; ++q) v = fma(-Lm[i + q * L], x[q], v);
+        x[i] = v / Lm[i + i * L];
+      }
+      asm volatile("" ::: "memory");  // keep each row's reads of Lm in place
+    }
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+      if (i < nn) {
+        double v = x[i];
+#pragma unroll
+        for (int q = i + 1; q < L; ++q)
+          if (q < nn) v = fma(-Lm[q + i * L], x[q], v);
+        x[i] = v / Lm[i + i * L];
+      }
+      asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+      if (i < nn) X[i + c * L] = x[i];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_ldecode(int n, int k, int r, const float *__restrict__ yv,
-                                                 double *__restrict__ ws, T *__restrict__ Gt,
-                                                 T *__restrict__ Tt, T *__restrict__ St,
-                                                 int *flags) {
-  constexpr int L = LEARN_RMAX;
-  __shared__ double sY1[L * L], sG[L * L], sF[L * L], sP[L * L], sN[L * L], sU[L * L];
+                                                 T *__restrict__ Gt, T *__restrict__ Tt,
+                                                 T *__restrict__ St, int *flags) {
+  constexpr int L = LEARN_RMAX, NT = 256;
+  // sA: Y1, later Gy; sB: Y1 Y1^T, later products; sT: temporaries
+  __shared__ double sA[L * L], sB[L * L], sF[L * L], sP[L * L], sN[L * L], sU[L * L], sT[L * L];
   __shared__ double red[8];
   __shared__ int bad;
   const int t = threadIdx.x, n2 = n - k;
-  double *Ct = ws, *Wm = ws + (int64_t)n2 * k, *Zt = Wm + (int64_t)n2 * r;
   if (t == 0) bad = 0;
-  // scale so that ||Y||_F^2 = r
   double ss = 0.0;
-  for (int64_t e = t; e < (int64_t)n * r; e += 256) ss += (double)yv[e] * (double)yv[e];
+  const int64_t ny = (int64_t)n * r;
+  for (int64_t e0 = t; e0 < ny; e0 += 8 * NT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = yv[min(e0 + u * NT, ny - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + u * NT < ny) ss = fma((double)v[u], (double)v[u], ss);
+  }
   ss = block_sum(ss, red);
   if (!(ss > 0.0) || !isfinite(ss)) {
     if (t == 0) atomicOr(flags, DEV_LEARN_FAIL);
     return;
   }
   const double sc = sqrt((double)r / ss);
-  for (int e = t; e < L * L; e += 256) {
-    const int a = e % L, q = e / L;
-    sY1[e] = (a < k && q < r) ? sc * (double)yv[a + (int64_t)n * q] : 0.0;
+  {
+    constexpr int EPT = L * L / NT;
+    float v[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = t + u * NT, a = min(e % L, k - 1), q = min(e / L, r - 1);
+      v[u] = yv[a + (int64_t)n * q];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = t + u * NT;
+      sA[e] = ((e % L) < k && (e / L) < r) ? sc * (double)v[u] : 0.0;
+    }
   }
   __syncthreads();
-  // G = Y1 Y1^T (k x k, column-major in sG)
-  for (int e = t; e < k * k; e += 256) {
+  __shared__ double colbuf[64];
+  auto chol = [&](double *Mx, int nn) {
+    if (t < 64) ld_chol_wave<L>(Mx, nn, colbuf, &bad);
+    __syncthreads();
+  };
+  auto chol_solve = [&](const double *Lx, int nn, double *X, int cols) {
+    if (t < 64) ld_solve_wave<L>(Lx, nn, X, cols);
+    __syncthreads();
+  };
+  // Out (rows x cols) = X Y, inner dimension inner, all ld L
+  auto mm = [&](double *Out, const double *X, const double *Y, int rows, int cols, int inner) {
+    for (int e = t; e < rows * cols; e += NT) {
+      const int a = e % rows, c = e / rows;
+      double v = 0.0;
+      for (int b = 0; b < inner; ++b) v = fma(X[a + b * L], Y[b + c * L], v);
+      Out[a + c * L] = v;
+    }
+    __syncthreads();
+  };
+  // Y1 Y1^T: (a, b) = sum_q Y1[a, q] Y1[b, q]
+  for (int e = t; e < k * k; e += NT) {
     const int a = e % k, b = e / k;
     double v = 0.0;
-    for (int q = 0; q < r; ++q) v = fma(sY1[a + q * L], sY1[b + q * L], v);
-    sG[a + b * L] = v;
+    for (int q = 0; q < r; ++q) v = fma(sA[a + q * L], sA[b + q * L], v);
+    sB[a + b * L] = v;
   }
   __syncthreads();
-  // in-place lower Cholesky of an SPD matrix in LDS (ld L) by wavefront 0
-  auto chol = [&](double *Mx, int nn) {
-    if (t < 64) {
-      double dmax = 0.0;
-      for (int j = 0; j < nn; ++j) dmax = fmax(dmax, Mx[j + j * L]);
-      for (int j = 0; j < nn; ++j) {
-        if (t == 0) {
-          double d = Mx[j + j * L];
-          if (!(d > 1e-13 * dmax)) {
-            bad = 1;
-            d = 1.0;
-          }
-          Mx[j + j * L] = sqrt(d);
-        }
-        wave_sync();
-        const double ljj = Mx[j + j * L];
-        for (int i = j + 1 + t; i < nn; i += 64) Mx[i + j * L] /= ljj;
-        wave_sync();
-        const int rem = nn - j - 1;
-        for (int e = t; e < rem * rem; e += 64) {
-          const int i = j + 1 + e % rem, q = j + 1 + e / rem;
-          if (q <= i) Mx[i + q * L] -= Mx[i + j * L] * Mx[q + j * L];
-        }
-        wave_sync();
-      }
-    }
-    __syncthreads();
-  };
-  // X (nn x cols, ld L) <- (L L^T)^-1 X, one thread per column
-  auto chol_solve = [&](const double *Lx, int nn, double *X, int cols) {
-    for (int c = t; c < cols; c += 256) {
-      double *x = X + c * L;
-      for (int i = 0; i < nn; ++i) {
-        double v = x[i];
-        for (int q = 0; q < i; ++q) v -= Lx[i + q * L] * x[q];
-        x[i] = v / Lx[i + i * L];
-      }
-      for (int i = nn - 1; i >= 0; --i) {
-        double v = x[i];
-        for (int q = i + 1; q < nn; ++q) v -= Lx[q + i * L] * x[q];
-        x[i] = v / Lx[i + i * L];
-      }
-    }
-    __syncthreads();
-  };
-  chol(sG, k);
-  // F = G^-1 Y1 (k x r)
-  for (int e = t; e < L * L; e += 256) sF[e] = sY1[e];
+  chol(sB, k);
+  for (int e = t; e < L * L; e += NT) sF[e] = sA[e];
   __syncthreads();
-  chol_solve(sG, k, sF, r);
-  // P_b = I - Y1^T F (r x r)
-  for (int e = t; e < r * r; e += 256) {
+  chol_solve(sB, k, sF, r);  // F = (Y1 Y1^T)^-1 Y1 (k x r)
+  // P_b = I - Y1^T F (r x r, symmetric)
+  for (int e = t; e < r * r; e += NT) {
     const int q = e % r, q2 = e / r;
     double v = (q == q2) ? 1.0 : 0.0;
-    for (int a = 0; a < k; ++a) v -= sY1[a + q * L] * sF[a + q2 * L];
+    for (int a = 0; a < k; ++a) v -= sA[a + q * L] * sF[a + q2 * L];
     sP[q + q2 * L] = v;
   }
   __syncthreads();
-  // C^T = Y2 F^T (n2 x k) and W = Y2 P_b (n2 x r)
-  for (int64_t e = t; e < (int64_t)n2 * (k + r); e += 256) {
-    const int j = (int)(e % n2), c = (int)(e / n2);
-    double v = 0.0;
-    if (c < k) {
-      for (int q = 0; q < r; ++q) v = fma((double)yv[k + j + (int64_t)n * q], sF[c + q * L], v);
-      Ct[j + (int64_t)c * n2] = sc * v;
-    } else {
-      const int q2 = c - k;
-      for (int q = 0; q < r; ++q) v = fma((double)yv[k + j + (int64_t)n * q], sP[q + q2 * L], v);
-      Wm[j + (int64_t)q2 * n2] = sc * v;
+  // Gy = Y2^T Y2 (r x r) over the n2 rows, staged through sN in chunks of
+  // rows; each thread keeps its entries in registers
+  {
+    constexpr int EPT = (L * L + NT - 1) / NT;
+    double acc[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) acc[u] = 0.0;
+    const int crow = (L * L) / r;  // rows per chunk
+    for (int j0 = 0; j0 < n2; j0 += crow) {
+      const int jl = min(crow, n2 - j0);
+      {
+        constexpr int SPT = L * L / NT;  // jl * r <= L * L
+        float v[SPT];
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+          const int e = min(t + u * NT, jl * r - 1), jr = e % jl, q = e / jl;
+          v[u] = yv[k + j0 + jr + (int64_t)n * q];
+        }
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+          const int e = t + u * NT;
+          if (e < jl * r) sN[(e % jl) + (e / jl) * crow] = sc * (double)v[u];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int e = t + u * NT;
+        if (e < r * r) {
+          const int q = e % r, q2 = e / r;
+          double v = acc[u];
+          for (int jr = 0; jr < jl; ++jr) v = fma(sN[jr + q * crow], sN[jr + q2 * crow], v);
+          acc[u] = v;
+        }
+      }
+      __syncthreads();
     }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = t + u * NT;
+      if (e < r * r) sA[(e % r) + (e / r) * L] = acc[u];  // sA = Gy from here on
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // N = W^T W + (I - P_b) (r x r) and U = W^T C^T (r x k, in sU)
-  for (int e = t; e < r * (r + k); e += 256) {
+  mm(sT, sA, sP, r, r, r);  // Gy P_b
+  // N = P_b (Gy P_b) + I - P_b
+  for (int e = t; e < r * r; e += NT) {
+    const int q = e % r, q2 = e / r;
+    double v = ((q == q2) ? 1.0 : 0.0) - sP[q + q2 * L];
+    for (int b = 0; b < r; ++b) v = fma(sP[q + b * L], sT[b + q2 * L], v);
+    sN[q + q2 * L] = v;
+  }
+  // Gy F^T (r x k): (q, c) = sum_b Gy[q, b] F[c, b]
+  for (int e = t; e < r * k; e += NT) {
     const int q = e % r, c = e / r;
-    const double *wq = Wm + (int64_t)q * n2;
-    const double *v2 = (c < r) ? Wm + (int64_t)c * n2 : Ct + (int64_t)(c - r) * n2;
     double v = 0.0;
-    for (int j = 0; j < n2; ++j) v = fma(wq[j], v2[j], v);
-    if (c < r)
-      sN[q + c * L] = v + ((q == c) ? 1.0 : 0.0) - sP[q + c * L];
-    else
-      sU[q + (c - r) * L] = v;
+    for (int b = 0; b < r; ++b) v = fma(sA[q + b * L], sF[c + b * L], v);
+    sB[q + c * L] = v;
   }
   __syncthreads();
+  mm(sU, sP, sB, r, k, r);  // U = P_b Gy F^T
   chol(sN, r);
-  chol_solve(sN, r, sU, k);
-  // Z = C^T - W (N^-1 U) (n2 x k)
-  for (int64_t e = t; e < (int64_t)n2 * k; e += 256) {
-    const int j = (int)(e % n2), c = (int)(e / n2);
-    double v = Ct[j + (int64_t)c * n2];
-    for (int q = 0; q < r; ++q) v -= Wm[j + (int64_t)q * n2] * sU[q + c * L];
-    Zt[j + (int64_t)c * n2] = v;
-    Gt[(int64_t)(k + j) * k + c] = (T)v;
-    if (!isfinite(v)) bad = 1;
+  chol_solve(sN, r, sU, k);    // N^-1 U
+  // Q = F^T - P_b N^-1 U (r x k) in sT
+  for (int e = t; e < r * k; e += NT) {
+    const int q = e % r, c = e / r;
+    double v = sF[c + q * L];
+    for (int b = 0; b < r; ++b) v -= sP[q + b * L] * sU[b + c * L];
+    sT[q + c * L] = v;
   }
   __syncthreads();
-  // S = C Z, symmetrised; Gt's first k rows are -S; T = 0
-  for (int e = t; e < k * k; e += 256) {
+  mm(sB, sA, sT, r, k, r);  // Gy Q (r x k)
+  // S = F (Gy Q), symmetrised; Gt's first k rows are -S; T = 0
+  for (int e = t; e < k * k; e += NT) {
     const int a = e % k, c = e / k;
     double v1 = 0.0, v2 = 0.0;
-    for (int j = 0; j < n2; ++j) {
-      v1 = fma(Ct[j + (int64_t)a * n2], Zt[j + (int64_t)c * n2], v1);
-      v2 = fma(Ct[j + (int64_t)c * n2], Zt[j + (int64_t)a * n2], v2);
+    for (int b = 0; b < r; ++b) {
+      v1 = fma(sF[a + b * L], sB[b + c * L], v1);
+      v2 = fma(sF[c + b * L], sB[b + a * L], v2);
     }
     const double sv = 0.5 * (v1 + v2);
     if (!isfinite(sv)) bad = 1;
     St[a * k + c] = (T)sv;
     Gt[a * k + c] = (T)(-sv);
     Tt[a * k + c] = T(0);
+  }
+  // Z = Y2 Q: one row per thread, the k entries in registers
+  for (int j = t; j < n2; j += NT) {
+    double z[L];
+#pragma unroll
+    for (int c = 0; c < L; ++c) z[c] = 0.0;
+    for (int q0 = 0; q0 < r; q0 += 8) {
+      float yq[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) yq[u] = yv[k + j + (int64_t)n * min(q0 + u, r - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (q0 + u < r) {
+          const double y = sc * (double)yq[u];
+#pragma unroll
+          for (int c = 0; c < L; ++c) z[c] = fma(y, sT[q0 + u + c * L], z[c]);
+        }
+        asm volatile("" ::: "memory");  // one row of Q's reads at a time
+      }
+    }
+    int nb = 0;
+#pragma unroll
+    for (int c = 0; c < L; ++c)
+      if (c < k) {
+        nb |= !isfinite(z[c]);
+        Gt[(int64_t)(k + j) * k + c] = (T)z[c];
+      }
+    if (nb) bad = 1;
   }
   __syncthreads();
   if (t == 0 && bad) atomicOr(flags, DEV_LEARN_FAIL);
@@ -521,9 +647,9 @@ void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, f
 }
 
 template <typename T>
-void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, double *ws, T *Gt, T *Tt,
-                    T *St, int *flags) {
-  hipLaunchKernelGGL(k_ldecode<T>, dim3(1), dim3(256), 0, s, n, k, r, yv, ws, Gt, Tt, St, flags);
+void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, T *Gt, T *Tt, T *St,
+                    int *flags) {
+  hipLaunchKernelGGL(k_ldecode<T>, dim3(1), dim3(256), 0, s, n, k, r, yv, Gt, Tt, St, flags);
 }
 
 template <typename T>
@@ -534,8 +660,8 @@ void launch_zero(hipStream_t s, int64_t count, T *out) {
 #define INST_L(T)                                                                               \
   template void launch_gauss_fill<T>(hipStream_t, int64_t, uint64_t, double, T *);            \
   template void launch_sketch_finish<T>(hipStream_t, int, const double *, const T *, float *); \
-  template void launch_ldecode<T>(hipStream_t, int, int, int, const float *, double *, T *, T *, \
-                                  T *, int *);                                                 \
+  template void launch_ldecode<T>(hipStream_t, int, int, int, const float *, T *, T *, T *,     \
+                                  int *);                                                      \
   template void launch_zero<T>(hipStream_t, int64_t, T *);
 INST_L(float)
 INST_L(double)

@@ -53,11 +53,15 @@ __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, const T 
 
 // ---------------------------------------------------------------------------
 // X1_0: mode 0 = iid N(0,1) (Philox4x32-10 + Box-Muller), 1 = copy of a given
-// matrix, 2 = copy of A1.  Non-finite given entries set DEV_BAD_A.
+// matrix, 2 = copy of A1.  Non-finite given entries set DEV_BAD_A.  With a
+// gate, nothing is written unless *gate is nonzero.
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_x1(int64_t m, int64_t k, int mode, uint64_t seed,
                                                  const T *__restrict__ src, int64_t lds,
-                                                 T *__restrict__ X1, int *flags) {
+                                                 T *__restrict__ X1, int *flags,
+                                                 const int *__restrict__ gate) {
+  // a start that replaces a learned one is written only if that one failed
+  if (gate != nullptr && *gate == 0) return;
   const int64_t total = m * k;
   int bad = 0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -903,10 +907,11 @@ void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t ld
 
 template <typename T>
 void launch_init_x1(hipStream_t s, int64_t m, int64_t k, int mode, uint64_t seed, const T *src,
-                    int64_t lds, T *X1, int *flags) {
+                    int64_t lds, T *X1, int *flags, const int *gate) {
   const int64_t total = m * k;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 2048));
-  hipLaunchKernelGGL(k_init_x1<T>, dim3(g), dim3(256), 0, s, m, k, mode, seed, src, lds, X1, flags);
+  hipLaunchKernelGGL(k_init_x1<T>, dim3(g), dim3(256), 0, s, m, k, mode, seed, src, lds, X1, flags,
+                     gate);
 }
 
 template <typename TX, typename TY>
@@ -1095,7 +1100,7 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
   template void launch_validate<T>(hipStream_t, int64_t, int64_t, const T *, int64_t, int64_t,    \
                                    const T *, int64_t, int *, bf16s *);                           \
   template void launch_init_x1<T>(hipStream_t, int64_t, int64_t, int, uint64_t, const T *,        \
-                                  int64_t, T *, int *);                                           \
+                                  int64_t, T *, int *, const int *);                              \
   template void launch_tsgemm<T, T>(hipStream_t, int64_t, const T *, int64_t, int, const T *,     \
                                     int64_t, int, int, int, int64_t, double *, double *,          \
                                     const int *);                                                 \

@@ -34,7 +34,7 @@ void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t ld
                      const T *W1, int64_t ldw, int *flags, bf16s *A2b);
 template <typename T>
 void launch_init_x1(hipStream_t s, int64_t m, int64_t k, int mode, uint64_t seed, const T *src,
-                    int64_t lds, T *X1, int *flags);
+                    int64_t lds, T *X1, int *flags, const int *gate = nullptr);
 template <typename TX, typename TY>
 void launch_tsgemm(hipStream_t s, int64_t m, const TX *X, int64_t ldx, int k1, const TY *Y,
                    int64_t ldy, int k2, int sym, int splits, int64_t rows_per_split, double *part,
@@ -133,8 +133,8 @@ void launch_subspace_loss(hipStream_t s, int n, int r, int batch, const float *y
 void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, float *v, float lr,
                  float b1, float b2, float eps, float bc1, float bc2);
 template <typename T>
-void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, double *ws, T *Gt, T *Tt,
-                    T *St, int *flags);
+void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, T *Gt, T *Tt, T *St,
+                    int *flags);
 template <typename T>
 void launch_zero(hipStream_t s, int64_t count, T *out);
 

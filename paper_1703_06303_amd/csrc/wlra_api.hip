@@ -146,7 +146,7 @@ struct Ptrs {
   double *epart;    // multi-workgroup eigen kernel: partial Grams
   // learned warm start (NULL unless the start is learned)
   void *Om, *Ps;
-  double *P1, *Ld, *lpart;  // Ld: the decode's C^T, W and Z (n2 x (2k + r))
+  double *P1, *lpart;
   float *sk, *lh1, *lh2, *yv;
   SmallState *st;
   int *flags;
@@ -246,7 +246,6 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {&p.Om, z.learned ? (size_t)(m * LEARN_SK_ROWS) * z.elt : 0},
       {&p.Ps, z.learned ? (size_t)(z.n * LEARN_SK_COLS) * z.elt : 0},
       {(void **)&p.P1, z.learned ? (size_t)(LEARN_SK_ROWS * z.n) * d : 0},
-      {(void **)&p.Ld, z.learned ? (size_t)(z.n2 * (2 * kk + z.r)) * d : 0},
       {(void **)&p.lpart,
        z.learned ? (size_t)z.splits_l1 * LEARN_SK_ROWS * z.n * d : 0},
       {(void **)&p.sk, z.learned ? (size_t)LEARN_D_IN * sizeof(float) : 0},
@@ -343,7 +342,8 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   PROF(h, KK_VALIDATE,
        launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags, P.Ab));
   T *X1c = static_cast<T *>(P.X1[0]);
-  bool need_init = (k > 0);
+  const bool need_init = (k > 0);
+  int *lflag = nullptr;  // learned start: the random start is its fallback
   if (learned) {
     // Y = network(sketch of A), the predicted row basis; X1_0 is the
     // per-row weighted least-squares fit in span(Y^T): k_ldecode forms the
@@ -355,6 +355,9 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     T *Om = static_cast<T *>(P.Om), *Ps = static_cast<T *>(P.Ps);
     T *Gt = static_cast<T *>(P.Gt), *Tt = static_cast<T *>(P.Tt), *St = static_cast<T *>(P.St);
     T *X1z = static_cast<T *>(P.X1[1]);
+    // the decode's failures (k_ldecode, or a per-row solve) go to a flag
+    // word of their own, which gates the random start that replaces it
+    lflag = P.flags + 1;
     auto seq = [&]() {
       launch_gauss_fill<T>(s, m * LEARN_SK_ROWS, LEARN_SEED_OMEGA, 1.0, Om);
       launch_gauss_fill<T>(s, n * LEARN_SK_COLS, LEARN_SEED_PSI, 1.0, Ps);
@@ -367,7 +370,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
                   LEARN_HID, b2, 1, nullptr, 0);
       launch_gemm(s, 0, 1, (int)(n * z.r), LEARN_HID, P.lh2, LEARN_HID, W3m, LEARN_HID, P.yv,
                   (int)(n * z.r), b3, 0, nullptr, 0);
-      launch_ldecode<T>(s, (int)n, (int)k, (int)z.r, P.yv, P.Ld, Gt, Tt, St, P.flags);
+      launch_ldecode<T>(s, (int)n, (int)k, (int)z.r, P.yv, Gt, Tt, St, lflag);
       launch_zero<T>(s, m * k, X1z);
       UpdateArgs<T> ua{};
       ua.m = m; ua.k = (int)k; ua.n = (int)n; ua.A = A; ua.lda = pr->lda; ua.W1 = W1;
@@ -376,27 +379,16 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
       ua.Eb = static_cast<T *>(P.Eb);
       ua.A2b = nullptr;
       ua.ldb = m;
-      ua.flags = P.flags;
+      ua.flags = lflag;
       launch_update<T>(s, ua);
     };
     PROF(h, KK_LEARN, seq());
-    HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    // the plain random start is the fallback when the decode fails (its
-    // flags are then cleared: they describe the discarded start only)
-    const int lf = DEV_LEARN_FAIL | DEV_ROWSOLVE;
-    need_init = (*h->flags_host & lf) != 0;
-    if (need_init) {
-      *h->flags_host &= ~lf;
-      HIPCHK(hipMemcpyAsync(P.flags, h->flags_host, sizeof(int), hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
-    }
   }
   if (need_init) {
     const int mode = (pr->init == WLRA_INIT_RANDOM || pr->init == WLRA_INIT_LEARNED) ? 0 : 1;
     const T *src = pr->init == WLRA_INIT_GIVEN ? static_cast<const T *>(pr->X1_init) : A;
     const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : pr->lda;
-    PROF(h, KK_INIT, launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags));
+    PROF(h, KK_INIT, launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags, lflag));
   }
   // One-time Gram of the unweighted block: A2^T A2 (of the BF16 copy in
   // mixed precision, so that M = G_A - B^T B stays consistent).
