@@ -650,7 +650,8 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
 // H column-major into Hb (n2 x K, K = 2l + 2k).  Kg = H^T H (K x K) is then
 // formed by the tall-skinny product kernel.
 #define QR_T 512
-#define CHG_NW 8  // wavefronts per workgroup of the change row pass
+#define CHG_NW 8    // wavefronts per workgroup of the change row pass
+#define CHG_GLD 65  // leading dimension of g in LDS (padded against bank conflicts)
 __global__ __launch_bounds__(QR_T) void k_chgprep(int n2, int k, int l,
                                                   const double *__restrict__ Vp,
                                                   const double *__restrict__ Vq,
@@ -773,8 +774,11 @@ __global__ __launch_bounds__(QR_T) void k_chgprep(int n2, int k, int l,
 
 // Row pass: u_p = a2 V_p and u_d = a2 dV (wavefronts split the n2 columns,
 // rows of [V_p dV] staged through LDS from H, fixed-order sum); then g per
-// lane in LDS and g Kg g^T with the rows of Kg split between the wavefronts
-// (Kg read with uniform loads).  One partial per workgroup.
+// lane in LDS (K x 64, ld CHG_GLD, rows past m and entries past K zero) and
+// the workgroup's sum of g Kg g^T as <Kg, G^T G>: the Gram G^T G of its 64
+// rows in 16 x 16 tiles on v_mfma_f64_16x16x4f64 (tiles on or above the
+// diagonal, split between the wavefronts), each tile contracted with the
+// matching block of Kg.  One partial per workgroup.
 template <typename T, int LMAX, typename TA2>
 __global__ __launch_bounds__(64 * CHG_NW) void k_change_q(
     int64_t m, int k, int n2, int l, const TA2 *__restrict__ A2, int64_t lda,
@@ -784,7 +788,7 @@ __global__ __launch_bounds__(64 * CHG_NW) void k_change_q(
   if (st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *sR = reinterpret_cast<double *>(smem_raw);   // staged [V_p dV] rows, later g
-  double *su = sR + (size_t)max(stage_rows * 2 * l, (2 * l + 2 * k) * 64);
+  double *su = sR + (size_t)max(stage_rows * 2 * l, ((2 * l + 2 * k + 15) / 16) * 16 * CHG_GLD);
   __shared__ double sacc[CHG_NW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -799,37 +803,38 @@ __global__ __launch_bounds__(64 * CHG_NW) void k_change_q(
     for (int c0 = 0; c0 < n2; c0 += stage_rows) {
       const int c1 = min(n2, c0 + stage_rows), len = c1 - c0;
       __syncthreads();
-      for (int e = threadIdx.x; e < len * rw; e += 64 * CHG_NW) {
-        const int r = e / rw, q = e - r * rw, j = c0 + r;
-        sR[e] = Hb[j + (int64_t)q * n2];  // columns 0..2l-1 of H: [V_p dV]
+      // columns 0..2l-1 of H: [V_p dV]; eight clamped reads in flight
+      for (int e0 = threadIdx.x; e0 < len * rw; e0 += 8 * 64 * CHG_NW) {
+        double hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = min(e0 + u * 64 * CHG_NW, len * rw - 1), r = e / rw, q = e - r * rw;
+          hv[u] = Hb[c0 + r + (int64_t)q * n2];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (e0 + u * 64 * CHG_NW < len * rw) sR[e0 + u * 64 * CHG_NW] = hv[u];
       }
       __syncthreads();
       const int j0 = c0 + w * len / CHG_NW, j1 = c0 + (w + 1) * len / CHG_NW;
-      int j = j0;
-      for (; j + 8 <= j1; j += 8) {
-        double v[8];
+      // sixteen clamped column reads in flight, converted at the use
+      for (int j = j0; j < j1; j += 16) {
+        TA2 raw[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (double)to_f(A2[ir + (int64_t)(j + u) * lda]);
+        for (int u = 0; u < 16; ++u) raw[u] = A2[ir + (int64_t)min(j + u, j1 - 1) * lda];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double *rr = sR + (j + u - c0) * rw;
+        for (int u = 0; u < 16; ++u) {
+          if (j + u < j1) {
+            const double v = (double)to_f(raw[u]);
+            const double *rr = sR + (j + u - c0) * rw;
 #pragma unroll
-          for (int q = 0; q < LMAX; ++q)
-            if (q < l) {
-              up[q] = fma(v[u], rr[q], up[q]);
-              ud[q] = fma(v[u], rr[l + q], ud[q]);
-            }
-        }
-      }
-      for (; j < j1; ++j) {
-        const double v = (double)to_f(A2[ir + (int64_t)j * lda]);
-        const double *rr = sR + (j - c0) * rw;
-#pragma unroll
-        for (int q = 0; q < LMAX; ++q)
-          if (q < l) {
-            up[q] = fma(v, rr[q], up[q]);
-            ud[q] = fma(v, rr[l + q], ud[q]);
+            for (int q = 0; q < LMAX; ++q)
+              if (q < l) {
+                up[q] = fma(v, rr[q], up[q]);
+                ud[q] = fma(v, rr[l + q], ud[q]);
+              }
           }
+        }
       }
     }
     // fixed-order sum of the wavefront slices
@@ -848,32 +853,68 @@ __global__ __launch_bounds__(64 * CHG_NW) void k_change_q(
     }
   }
   __syncthreads();
-  // g = [-u_d, -(u_p + u_d), x1p - x1q, -x1q] per lane, column-major over lanes
+  // g = [-u_d, -(u_p + u_d), x1p - x1q, -x1q] per lane, zero past row m
+  const double am = act ? 1.0 : 0.0;
   if (w == 0) {
 #pragma unroll
     for (int q = 0; q < LMAX; ++q)
       if (q < l) {
         const double pu = su[q * 64 + lane], du = su[(LMAX + q) * 64 + lane];
-        sR[q * 64 + lane] = -du;
-        sR[(l + q) * 64 + lane] = -(pu + du);
+        sR[q * CHG_GLD + lane] = -du * am;
+        sR[(l + q) * CHG_GLD + lane] = -(pu + du) * am;
       }
   }
-  for (int c = w; c < k; c += CHG_NW) {
-    const double xp = (double)X1p[ir + (int64_t)c * m], xq = (double)X1q[ir + (int64_t)c * m];
-    sR[(2 * l + c) * 64 + lane] = xp - xq;
-    sR[(2 * l + k + c) * 64 + lane] = -xq;
+  for (int c0 = w; c0 < k; c0 += 4 * CHG_NW) {
+    T xp[4], xq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = min(c0 + u * CHG_NW, k - 1);
+      xp[u] = X1p[ir + (int64_t)c * m];
+      xq[u] = X1q[ir + (int64_t)c * m];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u * CHG_NW;
+      if (c < k) {
+        sR[(2 * l + c) * CHG_GLD + lane] = ((double)xp[u] - (double)xq[u]) * am;
+        sR[(2 * l + k + c) * CHG_GLD + lane] = -(double)xq[u] * am;
+      }
+    }
   }
+  const int nt = (K + 15) / 16;
+  for (int a = K + w; a < 16 * nt; a += CHG_NW) sR[a * CHG_GLD + lane] = 0.0;
   __syncthreads();
-  // g Kg g^T = sum_a g_a (Kg_aa g_a + 2 sum_{b > a} Kg_ab g_b)
+  // sum over the 64 rows of g Kg g^T = sum_{a,b} Kg_ab (G^T G)_ab
   double acc = 0.0;
-  for (int a = w; a < K; a += CHG_NW) {
-    const double *ka = Kg + (int64_t)a * K;
-    const double ga = sR[a * 64 + lane];
-    double h = 0.0;
-    for (int b = a + 1; b < K; ++b) h = fma(ka[b], sR[b * 64 + lane], h);
-    acc = fma(ga, fma(ka[a], ga, 2.0 * h), acc);
+  {
+    const int li = lane & 15, lk = lane >> 4;
+    int p = 0;
+    for (int ti = 0; ti < nt; ++ti)
+      for (int tj = ti; tj < nt; ++tj, ++p) {
+        if (p % CHG_NW != w) continue;
+        const double *ga = sR + (16 * ti + li) * CHG_GLD + lk;
+        const double *gb = sR + (16 * tj + li) * CHG_GLD + lk;
+        ts_d4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i0 = 0; i0 < 64; i0 += 4)
+          d = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[i0], gb[i0], d, 0, 0, 0);
+        // lane holds (G^T G)[16 ti + lk + 4 v][16 tj + li]
+        const int b = 16 * tj + li;
+        double kv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * ti + lk + 4 * v;
+          kv[v] = Kg[(int64_t)min(a, K - 1) * K + min(b, K - 1)];
+        }
+        const double wt = (ti == tj) ? 1.0 : 2.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * ti + lk + 4 * v;
+          acc = fma(wt * ((a < K && b < K) ? 1.0 : 0.0) * kv[v], d[v], acc);
+        }
+      }
   }
-  acc = wave_sum(act ? acc : 0.0);
+  acc = wave_sum(acc);
   if (lane == 0) sacc[w] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1059,7 +1100,7 @@ static void launch_change_qr_k(hipStream_t s, int64_t m, int k, int n2, int l, c
   const int K = 2 * l + 2 * k;
   int rows = n2;
   if (l > 0) rows = std::min(n2, std::max(1, 8192 / (2 * l)));
-  const size_t stage = (size_t)std::max(rows * 2 * l, K * 64);
+  const size_t stage = (size_t)std::max(rows * 2 * l, ((K + 15) / 16) * 16 * CHG_GLD);
   const size_t shm = (stage + (size_t)2 * LMAX * 64) * sizeof(double);
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void *)k_change_q<T, LMAX, TA2>,
