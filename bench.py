@@ -49,7 +49,7 @@ FP32_PEAK_TFLOPS = 157.3
 # order listed); otherwise traffic is reported as null.
 TRAFFIC = {
     ("eig", "config2", "mixed"): (689082, ("k_eig.hip", "eig_small.h", "launch.h", "common.h"),
-                                  "1d2fcb959cf5d5b79167fd24b01b82035d1f07e835b4b27abe9f315ee051422a"),
+                                  "0f5ed553bd32245c669c0148bae03fe2a22dc347e8294e90cf1fc0834c713e3d"),
 }
 
 

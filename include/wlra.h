@@ -71,12 +71,16 @@ typedef enum {
   WLRA_INIT_GIVEN = 1,   /* X1_init (device, m x k, ld ldx0)                  */
   WLRA_INIT_A1 = 2,      /* X1_0 = A1                                         */
   WLRA_INIT_LEARNED = 3  /* learned warm start (not in the paper): a network
-                            maps a Gaussian sketch of A to an n x r basis Y,
-                            and X1_0 = L0 (L0^T L0)^-1 L0^T A1 with L0 = A Y
-                            (A1 projected on the predicted column space); if
-                            L0^T L0 is numerically singular the random start
-                            keyed by `seed` is used instead.  Needs `model`
-                            and r <= 32.                                      */
+                            maps a Gaussian sketch of A to an n x r basis Y
+                            of the solution's row space, and row i of the
+                            start is the weighted least-squares fit of a_i
+                            in span(Y^T) (weights W1 on the first k entries,
+                            1 on the rest; problem (5) separates over rows
+                            once the row space is fixed); X1_0 is its first
+                            k columns.  If Y is zero or rank deficient, or a
+                            row's solve fails, the random start keyed by
+                            `seed` is used instead.  Needs `model` and
+                            r <= 32.                                          */
 } wlra_init;
 
 typedef struct {
