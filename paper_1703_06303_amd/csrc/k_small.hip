@@ -246,10 +246,28 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
   for (int j0 = 0; j0 < n2; j0 += cw) {
     const int nc = min(cw, n2 - j0);
     __syncthreads();
-    for (int e = t; e < nc * k; e += 1024) sC[e] = a.C[(int64_t)j0 * k + e];
-    for (int e = t; e < nc * l; e += 1024) {
-      const int jj = e / l, q = e - jj * l;
-      sV[e] = V[(j0 + jj) + (int64_t)q * n2];
+    // clamped reads, all in flight (nc k <= POST_CH, nc l <= 4096); no
+    // reads at all for k = 0 or l = 0
+    const int ncc = nc * k, nvv = nc * l;
+    if (ncc > 0) {
+      double cv[(POST_CH + 1023) / 1024];
+#pragma unroll
+      for (int u = 0; u < (POST_CH + 1023) / 1024; ++u)
+        cv[u] = a.C[(int64_t)j0 * k + min(t + 1024 * u, ncc - 1)];
+#pragma unroll
+      for (int u = 0; u < (POST_CH + 1023) / 1024; ++u)
+        if (t + 1024 * u < ncc) sC[t + 1024 * u] = cv[u];
+    }
+    if (nvv > 0) {
+      double vv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(t + 1024 * u, nvv - 1), jj = e / l, q = e - jj * l;
+        vv[u] = V[(j0 + jj) + (int64_t)q * n2];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (t + 1024 * u < nvv) sV[t + 1024 * u] = vv[u];
     }
     __syncthreads();
 #pragma unroll
@@ -271,15 +289,19 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
     const int o_ = t + 1024 * u;
-    if (o_ < ncv) CV[o_] = acc[u];
-    else if (o_ < nout) S[o_ - ncv] = acc[u];
+    if (o_ < ncv) {
+      CV[o_] = acc[u];
+      sK[o_] = acc[u];  // LDS copy of CV for T (k l <= 2048)
+    } else if (o_ < nout) {
+      S[o_ - ncv] = acc[u];
+    }
   }
   __syncthreads();
   // ---- T = (CV)(CV)^T, Z = C^T - V (CV)^T --------------------------------------
   for (int e = t; e < k * k; e += 1024) {
     const int c = e % k, d = e / k;
     double s_ = 0.0;
-    for (int q = 0; q < l; ++q) s_ = fma(CV[c + q * k], CV[d + q * k], s_);
+    for (int q = 0; q < l; ++q) s_ = fma(sK[c + q * k], sK[d + q * k], s_);
     Tm[e] = s_;
   }
   __syncthreads();
