@@ -147,6 +147,18 @@ def test_fp32_ragged(s32):
     assert rel(np.hstack([X1, X2]), ref.X) <= 1e-5
 
 
+@pytest.mark.parametrize("h,w,n,k,r", [(13, 11, 60, 33, 37), (9, 15, 90, 50, 55)])
+def test_fp32_large_k_row_solves(s32, h, w, n, k, r):
+    """FP32 with k > 24 and log-uniform W1 (the per-row factors live in
+    LDS); m is not a multiple of 64."""
+    inst = video.make_instance(h, w, n, k, r, 2, fg="blobs", noise=0.02,
+                               w1=("loguniform", 1.0, 4.0), seed=78 + k, dtype=np.float32)
+    ref = _oracle(inst, 0.0, 3)
+    X1, X2, res = gpu_solve(s32, inst, 0.0, 3)
+    print("fp32 large k", (h * w, n, k, r), res, flush=True)
+    assert rel(np.hstack([X1, X2]), ref.X) <= 1e-5
+
+
 def test_deterministic(s32, c2):
     a = gpu_solve(s32, c2, 0.0, 2)
     b = gpu_solve(s32, c2, 0.0, 2)
