@@ -22,8 +22,12 @@
 #define EIG_DEG 12
 #define EIG_MAXIT 60
 // Mixed precision: the BF16 sweeps stop at max(tol, MIXED_TOL) before the
-// exact refinement sweep.
+// exact refinement sweep.  Their eigen steps stop at a residual of
+// MIXED_EIG_TOL * ||A2^T A2||_F: M is formed from BF16 data there (relative
+// rounding 2^-9), and the phase only has to bring the iterate change below
+// MIXED_TOL; the exact phase returns to the full eigen tolerance.
 #define MIXED_TOL 1e-5
+#define MIXED_EIG_TOL 1e-7
 #define WLRA_BATCH_LANES_DEFAULT 4
 #define WLRA_BATCH_LANES_MAX 16
 
@@ -336,7 +340,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   sh.eig_first = 1;
   const double eig_tol = pr->eig_tol > 0 ? pr->eig_tol
                          : (h->precision == WLRA_FP64 ? 64.0 * 2.220446049250313e-16 : 1e-10);
-  sh.eig_floor = eig_tol;
+  sh.eig_floor = mixed ? std::max(eig_tol, MIXED_EIG_TOL) : eig_tol;
   HIPCHK(hipMemcpyAsync(P.st, &sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
 
   PROF(h, KK_VALIDATE,
