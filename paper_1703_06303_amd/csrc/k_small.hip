@@ -64,9 +64,21 @@ __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
     st->dx1 = dx;
     fail = 0;
   }
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int r = e % 64, c = e / 64;
-    sR[e] = (r < k && c < k) ? a.G1[r + c * k] : 0.0;
+  {
+    // clamped reads, all in flight; entries outside k x k are zero (and
+    // nothing is read for k = 0)
+    const int k1 = max(k, 1);
+    double gv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u, r = e % 64, c = e / 64;
+      gv[u] = (k > 0) ? a.G1[min(r, k1 - 1) + min(c, k1 - 1) * k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u, r = e % 64, c = e / 64;
+      sR[e] = (r < k && c < k) ? gv[u] : 0.0;
+    }
   }
   __syncthreads();
   double gmax = 0, tr = 0;
@@ -115,11 +127,11 @@ __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
     a.R[e] = (r <= c) ? sR[r + c * 64] : 0.0;
   }
   double nb2 = 0.0;
-  for (int jj = t; jj < n2; jj += 256) {
+  for (int jj = t; k > 0 && jj < n2; jj += 256) {
     const double *pc = a.P + (int64_t)jj * k;
     double x[KMAX];
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) x[i] = (i < k) ? pc[i] : 0.0;
+    for (int i = 0; i < KMAX; ++i) x[i] = pc[min(i, k - 1)];  // clamped; past k never used
     // B = R^-T P
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
