@@ -61,7 +61,10 @@ typedef enum {
                             then A2^T A2 and X1^T A2 are formed from A2 itself,
                             X_p is re-evaluated and one exact sweep (the
                             refinement) gives the returned X_{p+1}.  The
-                            status is that of the BF16 phase.               */
+                            BF16 phase's eigen steps stop at a residual of
+                            max(eig_tol, 1e-7) ||A2^T A2||_F, the exact ones
+                            at eig_tol.  The status is that of the BF16
+                            phase.                                          */
 } wlra_precision;
 
 /* Start X1_0 (Algorithm 1 leaves it open; Section 4.1 recommends a random
@@ -105,7 +108,8 @@ typedef struct {
   double *trace;           /* host, optional: 2*(max_sweeps+1) doubles; trace[p]
                               = F(X_p), trace[max_sweeps+1+p] = Error_p (p>=1)  */
   double eig_tol;          /* relative residual target of the H_{r-k} eigen
-                              step; <= 0 selects the default for the precision  */
+                              step (times ||A2^T A2||_F); <= 0 selects the
+                              default: 64 eps for FP64, 1e-10 otherwise       */
   const float *model;      /* device, WLRA_INIT_LEARNED only: the network's
                               wlra_mlp_param_count(n, r) parameters (below)     */
   double *factors_out;     /* device, optional: the returned X_p's factors, in
