@@ -160,7 +160,8 @@ def kernel_work(name, inst, res_list, elt, elt_a2, launches):
     if name == "gram_A2":
         return m * n2 * elt_a2, m * n2 * n2, "fp64"
     if name == "change":
-        return m * n2 * elt_a2 + 2 * m * k * elt, 2 * m * n2 * (2 * l + 2 * k), "hbm"
+        # a2 [V_p dV] per row, then the K x K form (K = 2l + 2k) per row
+        return m * n2 * elt_a2 + 2 * m * k * elt, m * (4 * l * n2 + (2 * l + 2 * k) ** 2), "hbm"
     if name == "eig":
         mv = sum(x["eig_matvecs"] for x in res_list)
         return 0, 2.0 * n2 * n2 * mv / max(launches, 1), "fp64"
