@@ -31,10 +31,18 @@
 extern "C" {
 #endif
 
-/* Status codes.  0 and 1 mean a valid result is in the outputs. */
+/* Status codes.  0, 1 and 2 mean a result is in the outputs; negative codes
+ * mean the outputs are not written (or, for WLRA_E_ROWSOLVE and WLRA_E_EIG,
+ * must not be used). */
 enum wlra_status {
   WLRA_OK = 0,            /* converged under the Section 4.1 rule             */
   WLRA_MAX_SWEEPS = 1,    /* max_sweeps X1 updates done; result is X_p        */
+  WLRA_INEXACT = 2,       /* a result X_p is returned, but the eigen step of
+                             its sweep stopped at its round limit (see
+                             WLRA_OPT_EIG_MAXIT) with a wanted Ritz pair still
+                             above its residual target: D_p is a rank-(r-k)
+                             matrix close to, but not within the stated
+                             accuracy of, H_{r-k}(P^perp A2)                 */
   WLRA_E_ARG = -1,        /* bad dimension, leading dimension or pointer      */
   WLRA_E_WEIGHT = -2,     /* a W1 entry is not > 0 or not finite (Theorem 2
                              assumes (W1)_ij > 0)                             */
@@ -43,7 +51,14 @@ enum wlra_status {
                              assumes rank(X1) = k (Section 3)                 */
   WLRA_E_NOMEM = -5,      /* workspace allocation failed                      */
   WLRA_E_HIP = -6,        /* a HIP runtime call failed                        */
-  WLRA_E_NODEVICE = -7    /* no usable gfx950 device                          */
+  WLRA_E_NODEVICE = -7,   /* no usable gfx950 device                          */
+  WLRA_E_ROWSOLVE = -8,   /* a per-row system diag(W1(i,:)^2) + C C^T of the
+                             X1 update (row formula below eq. (9)) had a
+                             pivot <= 0 in the storage precision (it is SPD in
+                             exact arithmetic; this happens when W1^2 is below
+                             the rounding of C C^T)                          */
+  WLRA_E_EIG = -9         /* the eigen step for H_{r-k} could not
+                             orthonormalise its block                        */
 };
 
 /* Arithmetic of a handle.  The storage type of A, W1, X1_init, X1_out and
@@ -177,6 +192,21 @@ int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res);
  * lane).  Instances must not share output buffers. */
 int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs,
                        wlra_result *res);
+
+/* Handle options (wlra_set_option).  They apply to later calls on the
+ * handle. */
+enum wlra_option {
+  WLRA_OPT_EIG_MAXIT = 1,   /* filter rounds per eigen step before it stops
+                               and reports WLRA_INEXACT (1..100000, default
+                               60)                                           */
+  WLRA_OPT_EIG_ONE_WG = 2   /* 1: the one-workgroup eigen kernel for every
+                               n - k (default 0: a cooperative multi-workgroup
+                               kernel for n - k >= 256)                      */
+};
+
+/* Set a handle option; WLRA_E_ARG for an unknown option or a value out of
+ * range. */
+int wlra_set_option(wlra_handle h, int32_t option, int64_t value);
 
 /* Number of batch lanes used by wlra_solve_batched (1..16, default 4; 1 runs
  * the instances one after another on the handle's stream). */

@@ -12,8 +12,8 @@
 #define DEV_BAD_A 1
 #define DEV_BAD_W 2
 #define DEV_RANK 4
-#define DEV_EIG_MAXIT 8
-#define DEV_ROWSOLVE 16
+#define DEV_EIG_ORTH 8     // the eigen step's block orthonormalisation failed
+#define DEV_ROWSOLVE 16    // a per-row system of the X1 update had a pivot <= 0
 #define DEV_LEARN_FAIL 32
 
 // Learned warm start: sketch Om^T A Ps with Om m x 16 and Ps n x 32 (Philox
@@ -69,6 +69,9 @@ struct SmallState {
   int32_t have_prev;  // 1 when the (p-1) quantities are valid
   int32_t eig_first;  // 1 until the eigen block holds a warm start
   int32_t eig_matvecs;  // products M y (single vectors), summed over sweeps
+  int32_t eig_fail;   // 1 when this sweep's eigen step stopped at its round
+                      // limit with a wanted Ritz pair above its residual target
+  int32_t pad_;
 };
 
 __device__ __forceinline__ void wave_sync() {

@@ -24,8 +24,6 @@
 // filter), else in global memory with LDS staging.  Blocks are addressed
 // through a handle that is either an offset into the LDS pool or a global
 // pointer, fixed at compile time, so LDS blocks compile to ds_* accesses.
-#include <cstdlib>
-
 #include "common.h"
 #include "launch.h"
 #include "eig_small.h"
@@ -432,7 +430,7 @@ __device__ __forceinline__ void blk_orth(EigLDS &s, const EigCtx &cx, Blk<RES> X
       const double sh = 11.0 * ((double)n2 * nb + (double)nb * (nb + 1)) * 2.220446049250313e-16 * sqrt(fro);
       shifted = 1;
       if (blk_chol(s, s.H, nb, sh)) {
-        if (t == 0) atomicOr(flags, DEV_EIG_MAXIT);
+        if (t == 0) atomicOr(flags, DEV_EIG_ORTH);
         return;
       }
     }
@@ -598,7 +596,7 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
     st->eig_iters += it;
     st->eig_matvecs += nmv;
     st->eig_first = 0;
-    if (it >= a.eig_maxit && locked < l) atomicOr(a.flags, DEV_EIG_MAXIT);
+    st->eig_fail = (it >= a.eig_maxit && locked < l) ? 1 : 0;
   }
 }
 
@@ -631,8 +629,8 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
 void launch_eig(hipStream_t s, const SmallArgs &a) {
   // larger n2: the multi-workgroup kernel; the one-workgroup kernel serves
   // small n2 and any case the cooperative launch is refused
-  // (WLRA_EIG_ONE_WG set in the environment forces the one-workgroup kernel)
-  if (eig_mw_groups(a.n2) > 0 && getenv("WLRA_EIG_ONE_WG") == nullptr && launch_eig_mw(s, a) == hipSuccess)
+  // (a.eig_one_wg, a handle option, forces the one-workgroup kernel)
+  if (eig_mw_groups(a.n2) > 0 && !a.eig_one_wg && launch_eig_mw(s, a) == hipSuccess)
     return;
   hipLaunchKernelGGL(k_eig, dim3(1), dim3(ET), 0, s, a);
 }

@@ -396,7 +396,7 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
   bool orth = first;  // a cold start orthonormalises its columns first
   while (true) {
     if (orth && mw_orth(c, s, Y + (size_t)locked * n2, b - locked, Y, locked)) {
-      if (c.g == 0 && t == 0) atomicOr(a.flags, DEV_EIG_MAXIT);
+      if (c.g == 0 && t == 0) atomicOr(a.flags, DEV_EIG_ORTH);
       if (it == 0 && first) return;  // nothing valid to report
       break;
     }
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
       st->eig_iters += it;
       st->eig_matvecs += nmv;
       st->eig_first = 0;
-      if (it >= a.eig_maxit && locked < l) atomicOr(a.flags, DEV_EIG_MAXIT);
+      st->eig_fail = (it >= a.eig_maxit && locked < l) ? 1 : 0;
     }
   }
 }

@@ -96,6 +96,7 @@ struct SmallArgs {
   int *flags;
   double wconst;           // > 0: constant W1
   int eig_maxit, eig_deg;
+  int eig_one_wg;          // 1: the one-workgroup eigen kernel for every n2
   double *epart;           // partial Grams of the multi-workgroup eigen kernel
 };
 

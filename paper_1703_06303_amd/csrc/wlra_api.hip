@@ -17,7 +17,7 @@
 #include "common.h"
 #include "launch.h"
 
-#define WLRA_VERSION 100
+#define WLRA_VERSION 200
 #define EIG_GUARD 3
 #define EIG_DEG 12
 #define EIG_MAXIT 60
@@ -55,6 +55,9 @@ struct wlra_ctx {
   hipStream_t stream = nullptr;
   int precision = 0;
   uint32_t flags = 0;
+  // options (wlra_set_option)
+  int eig_maxit = EIG_MAXIT;
+  int eig_one_wg = 0;
   char *ws = nullptr;
   size_t ws_bytes = 0;
   char *lws = nullptr;  // learned warm start: sketch and training buffers
@@ -448,7 +451,8 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   sa.R = P.R; sa.B = P.B; sa.C = P.C; sa.M = P.M;
   sa.Y = P.Y; sa.Wb = P.Wb; sa.F0 = P.F0; sa.F1 = P.F1; sa.F2 = P.F2; sa.theta = P.theta;
   sa.scratch = P.scratch; sa.st = P.st; sa.flags = P.flags; sa.wconst = constw ? wc : 0.0;
-  sa.eig_maxit = EIG_MAXIT; sa.eig_deg = EIG_DEG;
+  sa.eig_maxit = h->eig_maxit; sa.eig_deg = EIG_DEG;
+  sa.eig_one_wg = h->eig_one_wg;
   sa.epart = P.epart;
   sa.upd_part = P.upd_part; sa.chg_part = P.chg_part; sa.nchg = z.nwg_upd;
   SmallOut<T> so{static_cast<T *>(P.Gt), static_cast<T *>(P.Tt), static_cast<T *>(P.St),
@@ -531,7 +535,10 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const int dflags = *h->flags_host;
+  // a failed row solve first: a rank-deficient X1 can follow from it
+  if (dflags & DEV_ROWSOLVE) return WLRA_E_ROWSOLVE;
   if (dflags & DEV_RANK) return WLRA_E_RANK;
+  if (dflags & DEV_EIG_ORTH) return WLRA_E_EIG;
   if (k > 0)
     PROF(h, KK_COPY, launch_copy_out<T>(s, m, k, X1c, static_cast<T *>(pr->X1_out), pr->ldx1));
   if (pr->factors_out != nullptr) {
@@ -558,8 +565,11 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   prof_collect(h);
   float ms = 0.f;
   hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  int status = (k == 0) ? WLRA_OK : (mixed ? mixed_status : sh.status);
+  // the eigen step of the returned X_p's sweep (each step sets eig_fail)
+  if (sh.eig_fail) status = WLRA_INEXACT;
   if (res) {
-    res->status = (k == 0) ? WLRA_OK : (mixed ? mixed_status : sh.status);
+    res->status = status;
     res->sweeps = sh.sweep;
     res->objective = sh.F;
     res->abs_change = sh.err;
@@ -569,7 +579,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     res->eig_iters = sh.eig_iters;
     res->eig_matvecs = sh.eig_matvecs;
   }
-  return (k == 0) ? WLRA_OK : (mixed ? mixed_status : sh.status);
+  return status;
 }
 
 }  // namespace
@@ -589,6 +599,9 @@ const char *wlra_strerror(int status) {
     case WLRA_E_NOMEM: return "out of device memory";
     case WLRA_E_HIP: return "HIP runtime error";
     case WLRA_E_NODEVICE: return "no usable gfx950 device";
+    case WLRA_INEXACT: return "eigen step of the returned sweep stopped at its round limit";
+    case WLRA_E_ROWSOLVE: return "per-row system of the X1 update not positive definite in the storage precision";
+    case WLRA_E_EIG: return "eigen step could not orthonormalise its block";
     default: return "unknown status";
   }
 }
@@ -649,6 +662,24 @@ int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res) {
   return rc;
 }
 
+int wlra_set_option(wlra_handle h, int32_t option, int64_t value) {
+  if (h == nullptr) return WLRA_E_ARG;
+  switch (option) {
+    case WLRA_OPT_EIG_MAXIT:
+      if (value < 1 || value > 100000) return WLRA_E_ARG;
+      h->eig_maxit = (int)value;
+      break;
+    case WLRA_OPT_EIG_ONE_WG:
+      if (value != 0 && value != 1) return WLRA_E_ARG;
+      h->eig_one_wg = (int)value;
+      break;
+    default:
+      return WLRA_E_ARG;
+  }
+  for (wlra_ctx *L : h->lanes) wlra_set_option(L, option, value);
+  return WLRA_OK;
+}
+
 int wlra_set_batch_lanes(wlra_handle h, int32_t lanes) {
   if (h == nullptr || lanes < 1 || lanes > WLRA_BATCH_LANES_MAX) return WLRA_E_ARG;
   h->batch_lanes = lanes;
@@ -670,6 +701,8 @@ int ensure_lanes(wlra_ctx *h, int want) {
       return rc;
     }
     sub->owns_stream = true;
+    sub->eig_maxit = h->eig_maxit;
+    sub->eig_one_wg = h->eig_one_wg;
     h->lanes.push_back(sub);
   }
   return WLRA_OK;

@@ -13,8 +13,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwlra.so")
 
-OK, MAX_SWEEPS = 0, 1
+OK, MAX_SWEEPS, INEXACT = 0, 1, 2
 E_ARG, E_WEIGHT, E_NONFINITE, E_RANK, E_NOMEM, E_HIP, E_NODEVICE = -1, -2, -3, -4, -5, -6, -7
+E_ROWSOLVE, E_EIG = -8, -9
+OPT_EIG_MAXIT, OPT_EIG_ONE_WG = 1, 2
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 INIT_RANDOM, INIT_GIVEN, INIT_A1, INIT_LEARNED = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16}
@@ -58,7 +60,8 @@ class KStat(ctypes.Structure):
 FLAG_PROFILE = 1
 
 SYMBOLS = ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
-           "wlra_set_batch_lanes", "wlra_destroy", "wlra_profile", "wlra_validate",
+           "wlra_set_batch_lanes", "wlra_set_option", "wlra_destroy", "wlra_profile",
+           "wlra_validate",
            "wlra_strerror", "wlra_version", "wlra_mlp_param_count", "wlra_mlp_init",
            "wlra_sketch", "wlra_mlp_forward", "wlra_mlp_train_step")
 
@@ -80,6 +83,7 @@ def load(path: str = LIB_PATH):
     lib.wlra_solve_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
                                        ctypes.POINTER(Result)]
     lib.wlra_set_batch_lanes.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.wlra_set_option.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]
     lib.wlra_destroy.argtypes = [ctypes.c_void_p]
     lib.wlra_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(KStat),
                                  ctypes.c_int32]
@@ -98,7 +102,8 @@ def load(path: str = LIB_PATH):
     for name in ("wlra_mlp_init", "wlra_sketch", "wlra_mlp_forward", "wlra_mlp_train_step"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
-                 "wlra_set_batch_lanes", "wlra_destroy", "wlra_profile", "wlra_validate",
+                 "wlra_set_batch_lanes", "wlra_set_option", "wlra_destroy", "wlra_profile",
+                 "wlra_validate",
                  "wlra_version"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -285,6 +290,17 @@ class Solver:
                                           _ptr(g))
         self._chk(rc)
         return loss.value, g
+
+    def set_option(self, option, value):
+        rc = self.lib.wlra_set_option(self.h, int(option), int(value))
+        if rc != OK:
+            raise WlraError(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def set_batch_lanes(self, lanes):
         rc = self.lib.wlra_set_batch_lanes(self.h, int(lanes))

@@ -26,8 +26,8 @@ def test_exports_every_declared_symbol():
 
 def test_version_and_strerror():
     assert wlra.load().wlra_version() >= 100
-    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
-        assert wlra.strerror(code)
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8, -9):
+        assert wlra.strerror(code) != "unknown status"
 
 
 def _prob(**kw):
@@ -67,6 +67,11 @@ def test_bad_precision_and_null():
     assert wlra.validate(_prob(), 7) == wlra.E_ARG
     assert wlra.load().wlra_validate(None, 1) == wlra.E_ARG
     assert wlra.load().wlra_solve(None, None, None) == wlra.E_ARG
+
+
+def test_set_option_rejects_null_handle():
+    lib = wlra.load()
+    assert lib.wlra_set_option(None, wlra.OPT_EIG_MAXIT, 5) == wlra.E_ARG
 
 
 def test_create_without_device():

@@ -33,7 +33,9 @@ def _inst(i, h, w, n, k, r, const):
 @pytest.fixture(scope="module")
 def s64():
     from paper_1703_06303_amd.wlra import Solver
-    return Solver("fp64")
+    s = Solver("fp64")
+    yield s
+    s.close()
 
 
 @pytest.mark.parametrize("lanes", [1, 4, 7])
@@ -61,13 +63,13 @@ def test_batched_converged_mixed_precision():
     """A batch in mixed precision: every instance converges and meets its own
     oracle objective."""
     from paper_1703_06303_amd.wlra import Solver
-    smx = Solver("mixed")
     insts = [video.make_instance(h, w, n, k, r, 3, fg="blobs", w1=("loguniform", 1.0, 4.0),
                                  seed=7000 + i, dtype=np.float32)
              for i, (h, w, n, k, r) in enumerate([(24, 32, 60, 8, 11), (40, 48, 100, 12, 17),
                                                    (16, 20, 45, 5, 9), (30, 40, 80, 20, 23)])]
-    probs, keep = batch_problems(smx, insts, 1e-7, 200)
-    res = smx.solve_batched(probs)
+    with Solver("mixed") as smx:
+        probs, keep = batch_problems(smx, insts, 1e-7, 200)
+        res = smx.solve_batched(probs)
     for j, inst in enumerate(insts):
         ref = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=1e-13, max_sweeps=500, X1_0=inst.X1_0)
         print("mixed batch", j, res[j], "F*", ref.F[-1], flush=True)
@@ -92,3 +94,33 @@ def test_batched_statuses(s64):
         s64.solve_batched(bad)
     assert e.value.code == wlra.E_ARG
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_batched_largest_config4_clips_meet_fstar(precision):
+    """The six largest clips of the 64-clip batched workload (240 x 320
+    frames, m = 76800, k >= 33, n - k >= 256: the LDS per-row solves and the
+    cooperative eigen kernel) in one wlra_solve_batched call on four
+    concurrent lanes, from the library's random starts.  Each objective must
+    land within 1e-6 (relative) of the FP64 oracle's converged objective
+    stored in tests/golden/config4_fstar.json."""
+    import json
+    import os
+    from paper_1703_06303_amd.wlra import Solver
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config4_fstar.json")) as f:
+        fstar = {d["i"]: d["fstar"] for d in json.load(f)["instances"]}
+    shapes = video.config4_shapes()
+    big = [i for i, (h, w, n, k, r) in enumerate(shapes)
+           if h * w == 76800 and k >= 33 and n - k >= 256]
+    assert len(big) >= 4
+    insts = [video.config4_instance(i, shapes[i]) for i in big]
+    with Solver(precision) as s:
+        s.set_batch_lanes(4)
+        probs, keep = batch_problems(s, insts, 1e-7, 200, init="random",
+                                     seeds=[11 + i for i in big])
+        res = s.solve_batched(probs)
+    for j, i in enumerate(big):
+        e = abs(res[j]["objective"] - fstar[i]) / fstar[i]
+        print("config4 clip", i, shapes[i], precision, res[j], "relF", e, flush=True)
+        assert res[j]["status"] == 0
+        assert e <= 1e-6

@@ -17,13 +17,17 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def s64():
     from paper_1703_06303_amd.wlra import Solver
-    return Solver("fp64")
+    s = Solver("fp64")
+    yield s
+    s.close()
 
 
 @pytest.fixture(scope="module")
 def s32():
     from paper_1703_06303_amd.wlra import Solver
-    return Solver("fp32")
+    s = Solver("fp32")
+    yield s
+    s.close()
 
 
 def _inst(seed=3, m_hw=(20, 24), n=40, k=6, r=9, dtype=np.float64):
@@ -84,6 +88,34 @@ def test_forward_loss_gradient_and_adam_match_oracle(s32):
     loss1, _ = s32.mlp_train_step(p, m, v, 1, n, r, Xd, Td, 1e-3)
     p_ref, _, _ = L.adam_step(p64, host(g), np.zeros_like(p64), np.zeros_like(p64), 1, 1e-3)
     assert np.allclose(host(p), p_ref, rtol=1e-5, atol=2e-6)
+
+
+def test_adam_steps_match_oracle(s32):
+    """Four training steps in a row: each Adam update of the parameters and
+    of both moment vectors matches the oracle's update applied to the GPU's
+    state before the step and the gradient the GPU computed in that step (the
+    moments carry over from step to step, so t >= 2 checks the recurrences)."""
+    import torch
+    n, r, B = 30, 6, 5
+    rng = np.random.default_rng(3)
+    p = torch.tensor(L.init_params(n, r, 8), dtype=torch.float32, device="cuda")
+    X = rng.standard_normal((B, L.D_IN))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Td = torch.tensor(rng.standard_normal((B, n * r)), dtype=torch.float32, device="cuda")
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    lr = 3e-3
+    for t in range(1, 5):
+        p0, m0, v0 = host(p), host(m), host(v)
+        _, g = s32.mlp_train_step(p, m, v, t, n, r, Xd, Td, lr, want_grad=True)
+        p_ref, m_ref, v_ref = L.adam_step(p0, host(g), m0, v0, t, lr)
+        dp = host(p) - p0
+        print("adam step", t, "max |dp|", float(np.abs(dp).max()), flush=True)
+        assert np.allclose(host(m), m_ref, rtol=1e-5, atol=1e-9)
+        assert np.allclose(host(v), v_ref, rtol=1e-5, atol=1e-12)
+        # the step itself (p is float32: compare the increments)
+        assert np.allclose(dp, p_ref - p0, rtol=1e-3, atol=2e-7)
 
 
 def test_learned_start_decode_matches_oracle(s64):

@@ -20,13 +20,17 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def smx():
     from paper_1703_06303_amd.wlra import Solver
-    return Solver("mixed")
+    s = Solver("mixed")
+    yield s
+    s.close()
 
 
 @pytest.fixture(scope="module")
 def s32():
     from paper_1703_06303_amd.wlra import Solver
-    return Solver("fp32")
+    s = Solver("fp32")
+    yield s
+    s.close()
 
 
 def _w(inst):

@@ -18,13 +18,17 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def s64():
     from paper_1703_06303_amd.wlra import Solver
-    return Solver("fp64")
+    s = Solver("fp64")
+    yield s
+    s.close()
 
 
 @pytest.fixture(scope="module")
 def s32():
     from paper_1703_06303_amd.wlra import Solver
-    return Solver("fp32")
+    s = Solver("fp32")
+    yield s
+    s.close()
 
 
 def _oracle(inst, tol, sweeps):
@@ -123,16 +127,19 @@ def test_ragged_shapes_fp64(s64, h, w, n, k, r, const):
 
 
 @pytest.mark.parametrize("h,w,n,k,r,const", [(20, 30, 620, 50, 62, True), (16, 16, 300, 20, 40, False)])
-def test_one_workgroup_eigen_step_for_large_n2(s64, monkeypatch, h, w, n, k, r, const):
+def test_one_workgroup_eigen_step_for_large_n2(h, w, n, k, r, const):
     """The one-workgroup eigen kernel also serves n2 >= 256 when the
-    cooperative launch is refused; WLRA_EIG_ONE_WG forces that path (with a
-    staged block narrower than 16 columns at n2 = 570)."""
-    monkeypatch.setenv("WLRA_EIG_ONE_WG", "1")
+    cooperative launch is refused; the handle option WLRA_OPT_EIG_ONE_WG
+    forces that path (with a staged block narrower than 16 columns at
+    n2 = 570)."""
+    from paper_1703_06303_amd import wlra
     wspec = ("const", 7.5) if const else ("loguniform", 0.0, 2.5)
     inst = video.make_instance(h, w, n, k, r, 2, fg="bernoulli", fg_p=0.1, fg_lo=0.5, fg_hi=1.0,
                                noise=0.05, w1=wspec, seed=2000 + h * w + n + k)
     ref = _oracle(inst, 0.0, 3)
-    X1, X2, res = gpu_solve(s64, inst, 0.0, 3)
+    with wlra.Solver("fp64") as s1:
+        s1.set_option(wlra.OPT_EIG_ONE_WG, 1)
+        X1, X2, res = gpu_solve(s1, inst, 0.0, 3)
     print("one-workgroup eigen step", (h * w, n, k, r), res, flush=True)
     assert res["rc"] in (0, 1)
     assert rel(np.hstack([X1, X2]), ref.X) <= 1e-10

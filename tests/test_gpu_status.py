@@ -1,0 +1,54 @@
+"""Device-side failure flags reach the caller as statuses (through the C ABI).
+
+Both conditions are forced from the host, so every kernel still runs to its
+normal end: a round limit of one for the eigen step, and weights so small
+that W1^2 is far below the rounding of C C^T in FP32, which makes a pivot of
+the per-row Cholesky factorisation non-positive (the systems
+diag(W1(i,:)^2) + C C^T of the X1 update, below eq. (9), are SPD only in
+exact arithmetic).
+"""
+import numpy as np
+import pytest
+
+from gen import video
+
+from .gpu_util import gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+
+def test_eigen_round_limit_reports_inexact():
+    from paper_1703_06303_amd import wlra
+    inst = video.config1()
+    with wlra.Solver("fp64") as s:
+        _, _, ok = gpu_solve(s, inst, 0.0, 2)
+        s.set_option(wlra.OPT_EIG_MAXIT, 1)
+        X1, X2, res = gpu_solve(s, inst, 0.0, 2)
+        s.set_option(wlra.OPT_EIG_MAXIT, 60)
+        _, _, back = gpu_solve(s, inst, 0.0, 2)
+    print("eigen round limit", ok, res, back, flush=True)
+    assert ok["rc"] == wlra.MAX_SWEEPS
+    assert res["rc"] == wlra.INEXACT and res["status"] == wlra.INEXACT
+    assert res["sweeps"] == 2 and np.all(np.isfinite(X1)) and np.all(np.isfinite(X2))
+    assert back["rc"] == wlra.MAX_SWEEPS
+
+
+def test_option_range_checks():
+    from paper_1703_06303_amd import wlra
+    with wlra.Solver("fp32") as s:
+        for opt, val in ((wlra.OPT_EIG_MAXIT, 0), (wlra.OPT_EIG_MAXIT, 100001),
+                         (wlra.OPT_EIG_ONE_WG, 2), (99, 1)):
+            with pytest.raises(wlra.WlraError) as e:
+                s.set_option(opt, val)
+            assert e.value.code == wlra.E_ARG
+
+
+def test_row_solve_pivot_reports_error():
+    from paper_1703_06303_amd import wlra
+    # n - k = 2, so C C^T (10 x 10) has rank 2; W1 = 1e-12 everywhere
+    inst = video.make_instance(8, 10, 12, 10, 11, 2, fg="blobs", noise=0.02,
+                               w1=("const", 1e-12), seed=5, dtype=np.float32)
+    with wlra.Solver("fp32") as s:
+        _, _, res = gpu_solve(s, inst, 0.0, 1, dense_w=True)
+    print("row solve pivot", res, flush=True)
+    assert res["rc"] == wlra.E_ROWSOLVE and res["status"] == wlra.E_ROWSOLVE

@@ -1,0 +1,82 @@
+"""Per-sweep Error_p (Section 4.1) and the sweep count against the FP64
+oracle, through the C ABI.
+
+The GPU reports Error_p = ||X_p - X_{p-1}||_F of its own iterates.  In FP32
+those iterates differ from the oracle's by rounding; the parity bar on X is
+1e-5 (relative), and what the tests below see is far smaller, so the
+relative change Error_p / ||X_{p-1}||_F must agree with the oracle's to
+1e-3 of itself plus an absolute 1e-7 (FP32 rounding of iterates whose own
+difference from the oracle is a few 1e-8), and the stopping sweep must be the
+oracle's wherever the threshold falls between two sweeps' changes with room
+to spare.
+Shapes: the FP32 workload (m = 19200, n = 200, k = 20, r = 25, l = r - k = 5)
+and a shape with l = 12 > 8 (the change pass's wide template), in FP32 and in
+mixed precision.
+"""
+import numpy as np
+import pytest
+
+from gen import video
+from oracle import swlr as O
+
+from .gpu_util import gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+REL_RTOL, REL_ATOL = 1e-3, 1e-7
+
+
+def _check_rel(gpu_rel, ref_rel, what):
+    for p, (g, o) in enumerate(zip(gpu_rel, ref_rel), start=1):
+        print(what, "sweep", p, "gpu", g, "oracle", o, flush=True)
+        assert abs(g - o) <= REL_RTOL * o + REL_ATOL, (what, p, g, o)
+
+
+def _gpu_rel(res):
+    """Error_p for p = 1..sweeps from the GPU's trace (the tests divide it by
+    the oracle's ||X_{p-1}||_F, which the trace does not hold)."""
+    return res["trace_err"][1:res["sweeps"] + 1]
+
+
+def _l12():
+    return video.make_instance(40, 48, 120, 10, 22, 3, fg="blobs", w1=("loguniform", 1.0, 4.0),
+                               seed=123, dtype=np.float32)
+
+
+@pytest.mark.parametrize("which,tol", [("config2", 1e-7), ("l12", 1e-6)])
+def test_fp32_error_trace_and_sweeps(which, tol):
+    from paper_1703_06303_amd import wlra
+    inst = video.config2() if which == "config2" else _l12()
+    ref = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=tol, max_sweeps=100, X1_0=inst.X1_0)
+    with wlra.Solver("fp32") as s:
+        _, _, res = gpu_solve(s, inst, tol, 100, want_trace=True, want_x2=False)
+    print(which, "fp32", res["sweeps"], "oracle", ref.sweeps, flush=True)
+    nrm = [e / r for e, r in zip(ref.err, ref.rel)]        # ||X_{p-1}||_F of the oracle
+    g_rel = [e / q for e, q in zip(_gpu_rel(res), nrm)]
+    _check_rel(g_rel, ref.rel, which + " fp32")
+    assert res["rc"] == 0 and res["sweeps"] == ref.sweeps
+    assert res["rel_change"] == pytest.approx(ref.rel[-1], rel=REL_RTOL, abs=REL_ATOL)
+
+
+def test_mixed_error_trace_and_sweeps():
+    """Mixed precision: the BF16 phase's changes against Algorithm 1 on
+    [A1, bf16(A2)] (the oracle's first phase), and the refinement sweep's
+    change against Algorithm 1 on A from the phase's X1."""
+    from paper_1703_06303_amd import wlra
+    inst = _l12()
+    tol = 1e-7
+    Ab = inst.A.copy()
+    Ab[:, inst.k:] = O.round_bf16(inst.A[:, inst.k:])
+    first = O.swlr(Ab, inst.W1, inst.k, inst.r, tol=max(tol, O.MIXED_TOL), max_sweeps=99,
+                   X1_0=inst.X1_0)
+    ref = O.swlr_mixed(inst.A, inst.W1, inst.k, inst.r, tol=tol, max_sweeps=100, X1_0=inst.X1_0)
+    with wlra.Solver("mixed") as s:
+        _, _, res = gpu_solve(s, inst, tol, 100, want_trace=True, want_x2=False)
+    P = first.sweeps
+    print("mixed sweeps", res["sweeps"], "oracle phase 1", P, "total", ref.sweeps, flush=True)
+    assert res["rc"] == 0 and res["sweeps"] == ref.sweeps == P + 1
+    tr = res["trace_err"]
+    nrm1 = [e / r for e, r in zip(first.err, first.rel)]
+    _check_rel([e / q for e, q in zip(tr[1:P + 1], nrm1)], first.rel, "mixed phase 1")
+    nrm2 = ref.err[0] / ref.rel[0]
+    _check_rel([tr[P + 1] / nrm2], ref.rel, "mixed refinement")

@@ -90,6 +90,36 @@ def test_adam_first_step_is_signed_learning_rate():
     assert np.allclose(p1, -0.01 * g / (np.abs(g) + L.ADAM_EPS), rtol=1e-12)
 
 
+def test_adam_constant_gradient_steps_by_learning_rate():
+    """With the same gradient g at every step, the bias-corrected moments are
+    m_hat = g and v_hat = g^2 at every t (m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2), so each step moves p by -lr g / (|g| + eps).  A
+    dropped b1 m or b2 v term, or a wrong power in a bias correction, breaks
+    this from t = 2 on."""
+    g = np.array([3.0, -2e-3, 0.5, -7.0])
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    step = -0.01 * g / (np.abs(g) + L.ADAM_EPS)
+    for t in range(1, 8):
+        p, m, v = L.adam_step(p, g, m, v, t, 0.01)
+        assert np.allclose(p, t * step, rtol=1e-12, atol=0)
+        assert np.allclose(m, (1 - L.BETA1 ** t) * g, rtol=1e-12)
+        assert np.allclose(v, (1 - L.BETA2 ** t) * g * g, rtol=1e-12)
+
+
+def test_adam_alternating_gradient_second_step():
+    """Gradients g then -g.  By hand: m_2 = b1 (1 - b1) g - (1 - b1) g
+    = -(1 - b1)^2 g, so m_hat_2 = -(1 - b1) g / (1 + b1); v_2 = (1 - b2)(b2 + 1) g^2
+    = (1 - b2^2) g^2, so v_hat_2 = g^2.  The second step is therefore
+    +lr (1 - b1) / (1 + b1) g / (|g| + eps): with b1 = 0.9 it is 1/19 of the
+    first step's size and points the other way."""
+    g = np.array([2.0, -0.25])
+    p1, m, v = L.adam_step(np.zeros(2), g, np.zeros(2), np.zeros(2), 1, 0.1)
+    p2, m, v = L.adam_step(p1, -g, m, v, 2, 0.1)
+    unit = g / (np.abs(g) + L.ADAM_EPS)
+    assert np.allclose(p1, -0.1 * unit, rtol=1e-12)
+    assert np.allclose(p2 - p1, 0.1 * (0.1 / 1.9) * unit, rtol=1e-12)
+
+
 def test_target_basis_contains_the_solution_rows():
     inst = video.small(m_hw=(10, 12), n=20, k=4, r=7, seed=21, w1=("loguniform", 0.5, 3.0))
     res = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=0.0, max_sweeps=3, X1_0=inst.X1_0)
