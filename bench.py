@@ -1,33 +1,45 @@
 #!/usr/bin/env python3
 """Throughput of the sWLR solve (Dutta & Li, arXiv 1703.06303) on one MI355X.
 
-One step = one complete solve of problem (5) with Algorithm 1 from a random
-start, on a seeded synthetic video matrix resident in HBM (default: 120 x 160
-frames, m = 19200, n = 200, rank-3 background, 10% 8x8 blob foreground,
+One step = one complete solve of problem (5) with Algorithm 1, on a seeded
+synthetic video matrix resident in HBM (default workload: 120 x 160 frames,
+m = 19200, n = 200, rank-3 background, 10% 8x8 blob foreground,
 N(0, 0.02^2) noise, k = 20 background frames with W1 = 10**U(1, 4), r = 25,
 FP32 storage).  Every solve's objective is checked against F*, the FP64
 oracle's converged objective (or the closed form for a constant W1), at
 relative 1e-6.
 
 Schedules timed side by side (`variants` in the output):
-  plain          FP32 (FP64 for config1), the Section 4.1 rule with tol 1e-7
-  plain_tol1e-5  the same with tol 1e-5 (where the mixed phase stops)
+  plain_tol<t>   FP32 from the library's random start, the Section 4.1 rule
+                 with tol t for t in 1e-7 (the paper's threshold, also
+                 reported as "plain"), 1e-6, 1e-5, 1e-4, 1e-3
   mixed          A2 staged in BF16, sweeps to 1e-5, then one exact sweep
   a1+mixed       the same from X1_0 = A1
-  learned+mixed  the same from the learned warm start (config2): the network
-                 is first trained on GPU solves of --learn-train clips of the
-                 same generator (disjoint seeds) and compared with the random
-                 and A1 starts on --learn-heldout held-out clips
-                 (`learned_start` in the output)
+  learned+mixed  the same from the learned warm start: the network is trained
+                 on GPU solves of --learn-train clips of the same generator
+                 (disjoint seeds), or loaded from --learn-weights, and
+                 compared with the random and A1 starts on --learn-heldout
+                 held-out clips (`learned_start` in the output)
 `value` is the headline schedule's solves/s (learned+mixed when built, else
-mixed) and `vs_plain` its ratio to the plain schedule.
-`--workload config4` times the batched workload instead (64 clips of uneven
-shape per wlra_solve_batched call).
+mixed).  `vs_plain` divides it by the fastest plain FP32 schedule whose every
+solve meets 1e-6 (`vs_plain_schedule` names it): the comparison at equal
+final objective.
 
-Prints one JSON line (see the keys below).  `roofline` is for the kernel with
-the largest device time, from HIP events bracketing each launch on the
-library's stream in a profiled repeat of the timed steps.  `cpu_baseline` is
-the FP64 oracle (NumPy/LAPACK) on the host cores, on a bounded sample.
+The default run also times, as sub-objects of the same line:
+  config3  240 x 320 frames, m = 76800, n = 600, k = 50, r = 60, W1 = 1e3
+           (plain FP32, mixed, A1 + mixed), against the closed form
+  config4  64 clips of uneven shape (m in {4800, 19200, 76800}, n in
+           [100, 400], k in [5, 40], r = k + [2, 8], W1 log-uniform), one
+           wlra_solve_batched call per step on four lanes (FP32 and mixed):
+           solves/s, p50/p99 per-solve latency, and the HBM rate of the
+           streaming kernels (working set above the 256 MB MALL)
+Other workloads (`--workload`): config1, config3, config4 alone, frames
+(solve time against the number of frames, GPU vs oracle).
+
+Prints one JSON line.  `roofline` is for the kernel with the largest device
+time, from HIP events bracketing each launch on the library's stream in a
+profiled repeat of the timed steps.  `cpu_baseline` is the FP64 oracle
+(NumPy/LAPACK) on the host cores, on a bounded sample.
 """
 import argparse
 import json
@@ -41,6 +53,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+METRIC = "WLRA solves/s to rel. objective 1e-6 vs FP64 oracle; learned+mixed vs plain"
+PLAIN_TOLS = (1e-7, 1e-6, 1e-5, 1e-4, 1e-3)
+STREAMING = ("update", "gram_X1A2", "change", "gram_A2", "gram_X1X1", "validate")
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by
 # the same counters read for a plain copy of known size (reads x2.0, writes
@@ -51,6 +66,10 @@ TRAFFIC = {
     ("eig", "config2", "mixed"): (595867, ("k_eig.hip", "eig_small.h", "launch.h", "common.h"),
                                   "0f5ed553bd32245c669c0148bae03fe2a22dc347e8294e90cf1fc0834c713e3d"),
 }
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def measured_traffic(kernel, workload_name, precision):
@@ -70,7 +89,7 @@ def measured_traffic(kernel, workload_name, precision):
 
 
 def workload(name):
-    """(instance, storage precision of the plain solve, F* source)."""
+    """(instance, storage precision of the plain solve)."""
     from gen import video
     if name == "config2":
         return video.config2(), "fp32"
@@ -81,28 +100,24 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def reference_objective(inst, name):
-    """F* of the workload: the FP64 oracle converged far below the paper's
-    threshold, or the closed form when W1 is constant (problem (5) with
-    eq. (2): F* = sum of sigma_i(A S)^2, i > r, S = diag(w..w, 1..1))."""
+def reference_objective(inst):
+    """F* of the workload: the closed form when W1 is constant
+    (problem (5) with eq. (2): F* = sum of sigma_i(A S)^2, i > r,
+    S = diag(w..w, 1..1)), else the FP64 oracle converged far below the
+    paper's threshold."""
     import numpy as np
     from oracle import swlr as O
-    if inst.W1 is None and inst.m * inst.n > 5_000_000:
-        s = np.ones(inst.n)
-        s[:inst.k] = inst.w1_const
-        sv = np.linalg.svd(inst.A * s, compute_uv=False)
-        return float(np.sum(sv[inst.r:] ** 2)), "closed form H_r(A S) S^-1"
-    w = inst.W1 if inst.W1 is not None else inst.w1_const
-    ref = O.swlr(inst.A, w, inst.k, inst.r, tol=1e-13, max_sweeps=500, X1_0=inst.X1_0)
+    if inst.W1 is None:
+        _, f = O.closed_form_column_weights(inst.A, np.full(inst.k, inst.w1_const), inst.k, inst.r)
+        return f, "closed form H_r(A S) S^-1"
+    ref = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=1e-13, max_sweeps=500, X1_0=inst.X1_0)
     return ref.F[-1], f"FP64 oracle at tol 1e-13 ({ref.sweeps} sweeps)"
 
 
-# Schedules compared at equal final objective.  "plain" is Algorithm 1 with
-# the paper's threshold; "plain_tol1e-5" stops where the mixed phase stops;
-# "mixed" stages A2 in BF16 and ends with one exact sweep.
 def variants(plain_prec, learned=False):
-    v = {"plain": dict(precision=plain_prec, tol=1e-7, init="random"),
-         "plain_tol1e-5": dict(precision=plain_prec, tol=1e-5, init="random")}
+    v = {}
+    for t in PLAIN_TOLS:
+        v[f"plain_tol{t:.0e}"] = dict(precision=plain_prec, tol=t, init="random", plain=True)
     if plain_prec == "fp32":
         v["mixed"] = dict(precision="mixed", tol=1e-7, init="random")
         v["a1+mixed"] = dict(precision="mixed", tol=1e-7, init="a1")
@@ -111,70 +126,58 @@ def variants(plain_prec, learned=False):
     return v
 
 
-def train_learned(pool, args, log):
+def train_learned(pool, args):
     """Train the warm-start network on GPU solves of config-2 clips (training
-    seeds), then compare the random, A1 and learned starts on held-out seeds."""
+    seeds), or load trained weights, then compare the random, A1 and learned
+    starts on held-out seeds."""
     import numpy as np
+    import torch
     from gen import video
     from paper_1703_06303_amd import warmstart as WS
     from paper_1703_06303_amd import wlra
-    s = wlra.Solver("fp32")
-    tr = [video.config5_seed(i) for i in range(args.learn_train)]
-    X, T, info, t_data = WS.build_dataset(s, pool, tr)
-    log(f"# warm start: {len(tr)} training solves in {t_data:.1f} s")
-    t0 = time.perf_counter()
-    params, hist = WS.train(s, X, T, 200, 25, epochs=args.learn_epochs, batch=128, lr=1e-3)
-    t_train = time.perf_counter() - t0
-    log(f"# warm start: {args.learn_epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3f} -> "
-        f"{hist[-1]:.3f}")
-    ho = [video.config5_seed(i, heldout=True) for i in range(args.learn_heldout)]
-    ev = WS.evaluate(s, pool, params, ho)
-    Fr = np.array([x[2] for x in ev["random"]])
-    held = {}
-    for init, v in ev.items():
-        sw = np.array([x[0] for x in v])
-        ms = np.array([x[1] for x in v])
-        F = np.array([x[2] for x in v])
-        held[init] = {"sweeps_mean": float(sw.mean()), "sweeps_max": int(sw.max()),
-                      "solve_ms_mean": float(ms.mean()),
-                      "converged": int(sum(x[3] == 0 for x in v)),
-                      "max_rel_objective_vs_random_start": float(np.max(np.abs(F - Fr) / Fr))}
-    report = {"train_instances": len(tr), "train_data_s": t_data, "epochs": args.learn_epochs,
-              "train_s": t_train, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
-              "heldout_instances": len(ho), "heldout": held,
-              "training_solves_converged": int(sum(x[1] == 0 for x in info))}
+    report = {}
+    with wlra.Solver("fp32") as s:
+        if args.learn_weights and os.path.exists(args.learn_weights):
+            w = np.fromfile(args.learn_weights, dtype=np.float32)
+            if w.size != wlra.mlp_param_count(200, 25):
+                raise SystemExit(f"{args.learn_weights}: {w.size} floats, expected "
+                                 f"{wlra.mlp_param_count(200, 25)}")
+            params = torch.from_numpy(w).cuda()
+            meta = args.learn_weights + ".json"
+            report["weights"] = os.path.relpath(args.learn_weights, ROOT)
+            if os.path.exists(meta):
+                with open(meta) as f:
+                    report["training"] = json.load(f)
+            log(f"# warm start: weights loaded from {args.learn_weights}")
+        else:
+            tr = [video.config5_seed(i) for i in range(args.learn_train)]
+            X, T, info, t_data = WS.build_dataset(s, pool, tr)
+            log(f"# warm start: {len(tr)} training solves in {t_data:.1f} s")
+            t0 = time.perf_counter()
+            params, hist = WS.train(s, X, T, 200, 25, epochs=args.learn_epochs, batch=128, lr=1e-3)
+            t_train = time.perf_counter() - t0
+            log(f"# warm start: {args.learn_epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3f} "
+                f"-> {hist[-1]:.3f}")
+            report.update({"train_instances": len(tr), "train_data_s": t_data,
+                           "epochs": args.learn_epochs, "train_s": t_train,
+                           "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+                           "training_solves_converged": int(sum(x[1] == 0 for x in info))})
+        ho = [video.config5_seed(i, heldout=True) for i in range(args.learn_heldout)]
+        ev = WS.evaluate(s, pool, params, ho)
+    report["heldout_instances"] = len(ho)
+    report["heldout"] = WS.summarize(ev)
     return params, report
 
 
-def kernel_work(name, inst, res_list, elt, elt_a2, launches):
-    """Algorithmic bytes and flops of one launch of kernel `name` (`launches`
-    of it ran over the solves in res_list)."""
-    m, n, k, r = inst.m, inst.n, inst.k, inst.r
-    n2, l = n - k, r - k
-    if name == "update":
-        bytes_ = m * k * elt + m * n2 * elt_a2 + 2 * m * k * elt
-        flops = 2 * m * n * k + 2 * m * k * k
-        return bytes_, flops, "hbm"
-    if name == "gram_X1A2":
-        return m * k * elt + m * n2 * elt_a2, 2 * m * k * n2, "hbm"
-    if name == "gram_A2":
-        return m * n2 * elt_a2, m * n2 * n2, "fp64"
-    if name == "change":
-        # a2 [V_p dV] per row, then the K x K form (K = 2l + 2k) per row
-        return m * n2 * elt_a2 + 2 * m * k * elt, m * (4 * l * n2 + (2 * l + 2 * k) ** 2), "hbm"
-    if name == "eig":
-        mv = sum(x["eig_matvecs"] for x in res_list)
-        return 0, 2.0 * n2 * n2 * mv / max(launches, 1), "fp64"
-    return 0, 0, "latency"
-
-
 def cpu_baseline(inst, sample_solves, tol):
-    import numpy as np
+    """The oracle (FP64 NumPy/LAPACK) on the host: `sample_solves` full solves
+    with the BLAS threads it uses by default, and one solve on one thread."""
     from oracle import swlr as O
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     w = inst.W1 if inst.W1 is not None else inst.w1_const
     t0 = time.perf_counter()
@@ -183,89 +186,262 @@ def cpu_baseline(inst, sample_solves, tol):
         res = O.swlr(inst.A, w, inst.k, inst.r, tol=tol, max_sweeps=200, X1_0=inst.X1_0)
         sweeps.append(res.sweeps)
     dt = time.perf_counter() - t0
-    return {"value": sample_solves / dt, "unit": "solves/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{sample_solves} full solves of the same workload with the paper's "
-                      f"schedule (tol {tol}, {sweeps} sweeps), FP64 NumPy/LAPACK, {dt:.1f} s"}
+    out = {"value": sample_solves / dt, "unit": "solves/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": f"{sample_solves} full solves of the same workload with the paper's "
+                     f"schedule (tol {tol}, {sweeps} sweeps), FP64 NumPy/LAPACK, {dt:.1f} s",
+           "os_cpu_count": os.cpu_count(), "blas_threads": int(threads)}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            O.swlr(inst.A, w, inst.k, inst.r, tol=tol, max_sweeps=200, X1_0=inst.X1_0)
+            d1 = time.perf_counter() - t0
+        out["one_thread"] = {"value": 1.0 / d1, "unit": "solves/s", "seconds_per_solve": d1}
+    return out
 
 
-def run_batched(args):
-    """Batched workload: 64 seeded clips of uneven shape solved by one
-    wlra_solve_batched call per step, all inputs resident in HBM.  Compared:
-    one lane (instances one after another) vs four lanes, FP32 and mixed."""
+def roofline_of(name, launches, ms, nbytes, flops, res_list, n2):
+    """Roofline entry of one kernel kind from its profiled totals."""
+    avg_s = ms / launches / 1e3
+    if name == "eig":
+        mv = sum(x["eig_matvecs"] for x in res_list)
+        fl = 2.0 * n2 * n2 * mv / launches
+        roof = {"bound": "alu", "achieved": fl / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    elif nbytes > 0:
+        roof = {"bound": "hbm", "achieved": nbytes / launches / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": 0.0, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    return roof
+
+
+def time_schedules(inst, specs, fstar, steps, warmup, inputs, model=None, tag=""):
+    """Time every schedule: `steps` solves after `warmup` untimed ones."""
+    import numpy as np
+    import torch
+    from paper_1703_06303_amd import wlra
+    out = {}
+    for name, spec in specs.items():
+        with wlra.Solver(spec["precision"]) as solver:
+            solver.reserve(inst.m, inst.n, inst.k, inst.r)
+
+            def run(step):
+                A, W1 = inputs(spec["precision"])
+                return solver.solve(A, inst.k, inst.r, W1=W1, w1_const=inst.w1_const or 1.0,
+                                    tol=spec["tol"], max_sweeps=200, init=spec["init"],
+                                    seed=1000 + step,
+                                    model=model if spec["init"] == "learned" else None)[2]
+            for i in range(warmup):
+                run(i)
+            torch.cuda.synchronize()
+            results = []
+            t0 = time.perf_counter()
+            for i in range(steps):
+                results.append(run(i))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        objs = np.array([r["objective"] for r in results])
+        relF = np.abs(objs - fstar) / fstar
+        ok = int(np.sum((relF <= 1e-6) & (np.array([r["status"] for r in results]) == 0)))
+        sw = np.array([r["sweeps"] for r in results])
+        out[name] = {"solves_per_s": steps / dt, "ms_per_solve": 1e3 * dt / steps,
+                     "sweeps_per_solve": float(sw.mean()), "sweeps_per_s": float(sw.sum() / dt),
+                     "solves_meeting_1e-6": f"{ok}/{steps}", "all_meet_1e-6": ok == steps,
+                     "max_rel_objective_err": float(relF.max()), "precision": spec["precision"],
+                     "tol": spec["tol"], "init": spec["init"]}
+        log(f"# {tag}{name}: {out[name]['solves_per_s']:.1f} solves/s, "
+            f"{out[name]['sweeps_per_solve']:.1f} sweeps, {ok}/{steps} meet 1e-6")
+    return out
+
+
+def best_plain(out):
+    """Fastest plain FP32 schedule whose every solve meets 1e-6."""
+    ok = [(v["solves_per_s"], k) for k, v in out.items() if k.startswith("plain_tol")
+          and v["all_meet_1e-6"]]
+    return max(ok)[1] if ok else None
+
+
+def device_inputs(inst):
+    import torch
+    from paper_1703_06303_amd import wlra
+    dev = torch.device("cuda", 0)
+    tensors = {}
+
+    def inputs(prec):
+        tdt = torch.float64 if prec == "fp64" else torch.float32
+        if tdt not in tensors:
+            A = wlra.colmajor(torch.tensor(inst.A, dtype=tdt, device=dev))
+            W1 = (wlra.colmajor(torch.tensor(inst.W1, dtype=tdt, device=dev))
+                  if inst.W1 is not None else None)
+            tensors[tdt] = (A, W1)
+        return tensors[tdt]
+    return inputs
+
+
+def run_config3(steps, warmup):
+    """Sub-object: the mixed-precision workload (constant W1, closed-form F*)."""
+    from gen import video
+    t0 = time.perf_counter()
+    inst = video.config3()
+    fstar, fsrc = reference_objective(inst)
+    log(f"# config3: instance and F* in {time.perf_counter() - t0:.1f} s")
+    specs = {"plain_tol1e-07": dict(precision="fp32", tol=1e-7, init="random"),
+             "plain_tol1e-05": dict(precision="fp32", tol=1e-5, init="random"),
+             "mixed": dict(precision="mixed", tol=1e-7, init="random"),
+             "a1+mixed": dict(precision="mixed", tol=1e-7, init="a1")}
+    out = time_schedules(inst, specs, fstar, steps, warmup, device_inputs(inst), tag="config3 ")
+    bp = best_plain(out)
+    return {"workload": f"config3: m={inst.m} (240x320) n={inst.n} k={inst.k} r={inst.r}, "
+                        "W1 = 1e3", "reference_objective": {"value": fstar, "source": fsrc},
+            "variants": out, "vs_plain_schedule": bp,
+            "mixed_vs_plain": (out["mixed"]["solves_per_s"] / out[bp]["solves_per_s"]
+                               if bp else None)}
+
+
+def _gen_c4(args_):
+    from gen import video
+    import numpy as np
+    i, shape = args_
+    inst = video.config4_instance(i, shape)
+    return i, inst.A.astype(np.float32), inst.W1.astype(np.float32), inst.k, inst.r
+
+
+def run_config4(pool, steps, warmup, lanes=4, precisions=("fp32", "mixed"), one_lane=False):
+    """Sub-object: 64 clips per wlra_solve_batched call, inputs resident in
+    HBM; F* per clip from tests/golden/config4_fstar.json (FP64 oracle)."""
     import numpy as np
     import torch
     from gen import video
     from paper_1703_06303_amd import wlra
     shapes = video.config4_shapes()
-    gold_path = os.path.join(ROOT, "tests", "golden", "config4_fstar.json")
-    fstar = {}
-    if os.path.exists(gold_path):
-        with open(gold_path) as f:
-            fstar = {d["i"]: d["fstar"] for d in json.load(f)["instances"]}
+    with open(os.path.join(ROOT, "tests", "golden", "config4_fstar.json")) as f:
+        fstar = {d["i"]: d["fstar"] for d in json.load(f)["instances"]}
     t0 = time.perf_counter()
-    insts = [video.config4_instance(i, sh) for i, sh in enumerate(shapes)]
-    print(f"# generated {len(insts)} instances in {time.perf_counter() - t0:.1f} s",
-          file=sys.stderr, flush=True)
+    jobs = list(enumerate(shapes))
+    gen = pool.map(_gen_c4, jobs, chunksize=2) if pool is not None else map(_gen_c4, jobs)
     dev = torch.device("cuda", 0)
-    A = [wlra.colmajor(torch.tensor(x.A, dtype=torch.float32, device=dev)) for x in insts]
-    W = [wlra.colmajor(torch.tensor(x.W1, dtype=torch.float32, device=dev)) for x in insts]
-    X1 = [wlra.colmajor(torch.empty((x.m, x.k), dtype=torch.float32, device=dev)) for x in insts]
+    A, W, X1, KR = {}, {}, {}, {}
+    for i, a, w, k, r in gen:
+        A[i] = wlra.colmajor(torch.from_numpy(a).to(dev))
+        W[i] = wlra.colmajor(torch.from_numpy(w).to(dev))
+        X1[i] = wlra.colmajor(torch.empty((a.shape[0], k), dtype=torch.float32, device=dev))
+        KR[i] = (k, r)
+    idx = sorted(A)
+    ws_bytes = sum(A[i].numel() * 4 + W[i].numel() * 4 for i in idx)
+    log(f"# config4: {len(idx)} clips generated and moved in {time.perf_counter() - t0:.1f} s "
+        f"({ws_bytes / 1e9:.2f} GB of A and W1)")
 
     def problems(step):
-        return [wlra.make_problem(A[i], x.k, x.r, W1=W[i], tol=1e-7, max_sweeps=200,
+        return [wlra.make_problem(A[i], KR[i][0], KR[i][1], W1=W[i], tol=1e-7, max_sweeps=200,
                                   init="random", seed=1000 * step + i, X1_out=X1[i])
-                for i, x in enumerate(insts)]
+                for i in idx]
 
+    runs = [(p, lanes) for p in precisions]
+    if one_lane:
+        runs = [("fp32", 1)] + runs
     out = {}
-    for name, prec, lanes in (("fp32_1lane", "fp32", 1), ("fp32_4lanes", "fp32", 4),
-                              ("mixed_4lanes", "mixed", 4)):
-        solver = wlra.Solver(prec)
-        solver.set_batch_lanes(lanes)
-        for w in range(max(1, args.warmup)):
-            solver.solve_batched(problems(100 + w))
-        torch.cuda.synchronize()
-        allres = []
-        t0 = time.perf_counter()
-        for st in range(args.steps):
-            allres.append(solver.solve_batched(problems(st)))
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+    for prec, nl in runs:
+        name = f"{prec}_{nl}lane{'s' if nl > 1 else ''}"
+        with wlra.Solver(prec) as solver:
+            solver.set_batch_lanes(nl)
+            for w in range(max(1, warmup)):
+                solver.solve_batched(problems(100 + w))
+            torch.cuda.synchronize()
+            allres = []
+            t0 = time.perf_counter()
+            for st in range(steps):
+                allres.append(solver.solve_batched(problems(st)))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        with wlra.Solver(prec, profile=True) as ps:
+            ps.set_batch_lanes(nl)
+            ps.solve_batched(problems(0))
+            torch.cuda.synchronize()
+            prof = ps.profile(work=True)
         ms = np.array([r["ms"] for rs in allres for r in rs])
         sweeps = np.array([r["sweeps"] for rs in allres for r in rs])
-        ok = errs = 0
-        worst = 0.0
+        ok, worst = 0, 0.0
         for rs in allres:
-            for i, r in enumerate(rs):
-                if i in fstar:
-                    e = abs(r["objective"] - fstar[i]) / fstar[i]
-                    worst = max(worst, e)
-                    ok += int(e <= 1e-6 and r["status"] == 0)
-                    errs += 1
-        nsolve = len(insts) * args.steps
-        out[name] = {"solves_per_s": nsolve / dt, "batch_ms": 1e3 * dt / args.steps,
+            for j, r in enumerate(rs):
+                e = abs(r["objective"] - fstar[idx[j]]) / fstar[idx[j]]
+                worst = max(worst, e)
+                ok += int(e <= 1e-6 and r["status"] == 0)
+        nsolve = len(idx) * steps
+        hbm = {}
+        for kname in STREAMING:
+            if kname in prof and prof[kname][2] > 0:
+                lc, kms, kb, kf = prof[kname]
+                hbm[kname] = {"GB_per_s": kb / (kms / 1e3) / 1e9,
+                              "frac_of_hbm_peak": kb / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                              "ms_per_batch": kms, "launches": lc}
+        tot = sum(v[1] for v in prof.values())
+        out[name] = {"solves_per_s": nsolve / dt, "batch_ms": 1e3 * dt / steps,
                      "p50_solve_ms": float(np.percentile(ms, 50)),
                      "p99_solve_ms": float(np.percentile(ms, 99)),
                      "sweeps_per_solve": float(sweeps.mean()),
                      "sweeps_per_s": float(sweeps.sum() / dt),
-                     "solves_meeting_1e-6": f"{ok}/{errs}" if errs else "no reference",
-                     "max_rel_objective_err": worst if errs else None,
-                     "precision": prec, "lanes": lanes}
-        print(f"# {name}: {out[name]}", file=sys.stderr, flush=True)
-        del solver
-    head = out["mixed_4lanes"]
-    line = {
-        "metric": "WLRA solves/s to rel. objective 1e-6 vs FP64 oracle; learned+mixed vs plain",
-        "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": head["batch_ms"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
-        "config": {"workload": "config4: 64 clips, m in {4800, 19200, 76800}, n in [100, 400], "
-                               "k in [5, 40], r = k + [2, 8], W1 log-uniform; one "
-                               "wlra_solve_batched call per step",
-                   "instances": len(insts), "variant": "mixed_4lanes"},
-        "vs_plain": head["solves_per_s"] / out["fp32_1lane"]["solves_per_s"],
-        "variants": out,
-    }
+                     "solves_meeting_1e-6": f"{ok}/{nsolve}", "max_rel_objective_err": worst,
+                     "precision": prec, "lanes": nl, "streaming_hbm": hbm,
+                     "kernel_share": {k_: v[1] / tot for k_, v in
+                                      sorted(prof.items(), key=lambda kv: -kv[1][1])[:6]}}
+        log(f"# config4 {name}: {out[name]['solves_per_s']:.1f} solves/s, p50 "
+            f"{out[name]['p50_solve_ms']:.1f} ms, p99 {out[name]['p99_solve_ms']:.1f} ms, "
+            f"{ok}/{nsolve} meet 1e-6")
+    return {"workload": "config4: 64 clips, m in {4800, 19200, 76800}, n in [100, 400], "
+                        "k in [5, 40], r = k + [2, 8], W1 log-uniform; one wlra_solve_batched "
+                        "call per step", "instances": len(idx),
+            "working_set_bytes": ws_bytes, "variants": out}
+
+
+def run_frames(args):
+    """Solve time against the number of frames n at a fixed frame size
+    (the analogue of the paper's Fig. 3(c)): GPU FP32 vs the FP64 oracle on
+    the same clip and start, each point parity-checked (F within 1e-6 of the
+    oracle's converged F)."""
+    import numpy as np
+    import torch
+    from gen import video
+    from oracle import swlr as O
+    from paper_1703_06303_amd import wlra
+    k, r = 15, 16
+    rows = []
+    for n in args.frames:
+        inst = video.make_instance(120, 160, n, k, r, 3, fg="blobs", w1=("loguniform", 1.0, 4.0),
+                                   seed=video.BASE_SEED + 7000 + n, dtype=np.float32)
+        t0 = time.perf_counter()
+        ref = O.swlr(inst.A, inst.W1, k, r, tol=1e-7, max_sweeps=200, X1_0=inst.X1_0)
+        t_cpu = time.perf_counter() - t0
+        fs = O.swlr(inst.A, inst.W1, k, r, tol=1e-12, max_sweeps=500, X1_0=ref.X1).F[-1]
+        inputs = device_inputs(inst)
+        A, W1 = inputs("fp32")
+        X0 = wlra.colmajor(torch.tensor(inst.X1_0, dtype=torch.float32, device="cuda"))
+        with wlra.Solver("fp32") as s:
+            s.reserve(inst.m, inst.n, k, r)
+            for _ in range(2):
+                s.solve(A, k, r, W1=W1, tol=1e-7, init="given", X1_init=X0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, _, res = s.solve(A, k, r, W1=W1, tol=1e-7, init="given", X1_init=X0)
+            torch.cuda.synchronize()
+            t_gpu = (time.perf_counter() - t0) / args.steps
+        e = abs(res["objective"] - fs) / fs
+        rows.append({"n": n, "gpu_ms": 1e3 * t_gpu, "oracle_ms": 1e3 * t_cpu,
+                     "gpu_sweeps": res["sweeps"], "oracle_sweeps": ref.sweeps,
+                     "rel_objective_err": e, "meets_1e-6": bool(e <= 1e-6 and res["status"] == 0)})
+        log(f"# frames n={n}: GPU {1e3 * t_gpu:.2f} ms ({res['sweeps']} sweeps), oracle "
+            f"{1e3 * t_cpu:.0f} ms ({ref.sweeps} sweeps), relF {e:.1e}")
+    ok = sum(r_["meets_1e-6"] for r_ in rows)
+    line = {"metric": "sWLR solve time vs number of frames (GPU FP32 vs FP64 oracle)",
+            "value": rows[-1]["gpu_ms"], "unit": "ms per solve at the largest n", "n_gpus": 1,
+            "steps": args.steps, "warmup": 2, "ms_per_step": rows[-1]["gpu_ms"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"frames: 120x160 frames (m=19200), n in {list(args.frames)}, "
+                                   f"k={k}, r={r}, W1 log-uniform; paper's rule tol 1e-7"},
+            "points_meeting_1e-6": f"{ok}/{len(rows)}", "points": rows}
     print(json.dumps(line), flush=True)
 
 
@@ -274,13 +450,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="config2",
+                    choices=("config1", "config2", "config3", "config4", "frames"))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="config2 only: skip the config3 and config4 sub-objects")
     ap.add_argument("--cpu-solves", type=int, default=6)
     ap.add_argument("--learn-train", type=int, default=1024,
                     help="training clips for the warm-start network (0: no learned start)")
     ap.add_argument("--learn-epochs", type=int, default=200)
     ap.add_argument("--learn-heldout", type=int, default=48)
+    ap.add_argument("--learn-weights", default="",
+                    help="raw float32 network weights to load instead of training")
+    ap.add_argument("--frames", type=int, nargs="+", default=[50, 100, 200, 300, 400, 500, 600])
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -288,10 +470,13 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
-    # instance generation for the warm-start network runs in worker processes
-    # forked here, before this process touches the GPU
+    # host generation (warm-start clips, batched clips) runs in worker
+    # processes forked here, before this process touches the GPU
     pool = None
-    if args.workload == "config2" and args.learn_train > 0 and args.calib_copy == 0:
+    wants_pool = (args.calib_copy == 0 and
+                  ((args.workload == "config2" and (args.learn_train > 0 or not args.no_extra))
+                   or args.workload == "config4"))
+    if wants_pool:
         from paper_1703_06303_amd import warmstart as WS
         pool = WS.make_pool(12)
 
@@ -310,106 +495,69 @@ def main():
         return
     from paper_1703_06303_amd import wlra
 
-    if args.workload == "config4":
-        run_batched(args)
+    if args.workload == "frames":
+        run_frames(args)
         return
+    if args.workload == "config4":
+        sub = run_config4(pool, args.steps, args.warmup, one_lane=True)
+        head = sub["variants"]["mixed_4lanes"]
+        line = {"metric": METRIC, "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["batch_ms"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "bf16+f32", "data": "synthetic",
+                "config": {"workload": sub["workload"], "instances": sub["instances"],
+                           "variant": "mixed_4lanes"},
+                "vs_plain": head["solves_per_s"] / sub["variants"]["fp32_4lanes"]["solves_per_s"],
+                "variants": sub["variants"]}
+        print(json.dumps(line), flush=True)
+        return
+
     inst, plain_prec = workload(args.workload)
     t0 = time.perf_counter()
-    fstar, fsrc = reference_objective(inst, args.workload)
-    print(f"# F* = {fstar!r} from {fsrc} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
-          flush=True)
-
-    dev = torch.device("cuda", 0)
-    tensors = {}
-
-    def inputs(prec):
-        tdt = torch.float64 if prec == "fp64" else torch.float32
-        if tdt not in tensors:
-            A = wlra.colmajor(torch.tensor(inst.A, dtype=tdt, device=dev))
-            W1 = (wlra.colmajor(torch.tensor(inst.W1, dtype=tdt, device=dev))
-                  if inst.W1 is not None else None)
-            tensors[tdt] = (A, W1)
-        return tensors[tdt]
+    fstar, fsrc = reference_objective(inst)
+    log(f"# F* = {fstar!r} from {fsrc} ({time.perf_counter() - t0:.1f} s)")
+    inputs = device_inputs(inst)
 
     learned_params, learned_report = None, None
-    if pool is not None:
-        learned_params, learned_report = train_learned(
-            pool, args, lambda msg: print(msg, file=sys.stderr, flush=True))
+    if args.workload == "config2" and (args.learn_train > 0 or args.learn_weights):
+        learned_params, learned_report = train_learned(pool, args)
 
-    def run(solver, spec, step):
-        A, W1 = inputs(spec["precision"])
-        return solver.solve(A, inst.k, inst.r, W1=W1, w1_const=inst.w1_const or 1.0,
-                            tol=spec["tol"], max_sweeps=200, init=spec["init"], seed=1000 + step,
-                            model=learned_params if spec["init"] == "learned" else None)
-
-    out = {}
     specs = variants(plain_prec, learned_params is not None)
-    for name, spec in specs.items():
-        solver = wlra.Solver(spec["precision"])
-        solver.reserve(inst.m, inst.n, inst.k, inst.r)
-        for i in range(args.warmup):
-            run(solver, spec, i)
-        torch.cuda.synchronize()
-        results = []
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            results.append(run(solver, spec, i)[2])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        objs = np.array([r["objective"] for r in results])
-        relF = np.abs(objs - fstar) / fstar
-        ok = int(np.sum((relF <= 1e-6) & (np.array([r["status"] for r in results]) == 0)))
-        sw = np.array([r["sweeps"] for r in results])
-        out[name] = {"solves_per_s": args.steps / dt, "ms_per_solve": 1e3 * dt / args.steps,
-                     "sweeps_per_solve": float(sw.mean()), "sweeps_per_s": float(sw.sum() / dt),
-                     "solves_meeting_1e-6": f"{ok}/{args.steps}",
-                     "max_rel_objective_err": float(relF.max()), "precision": spec["precision"],
-                     "tol": spec["tol"], "init": spec["init"], "_dt": dt, "_ok": ok}
-        print(f"# {name}: {out[name]['solves_per_s']:.1f} solves/s, "
-              f"{out[name]['sweeps_per_solve']:.1f} sweeps, {ok}/{args.steps} meet 1e-6",
-              file=sys.stderr, flush=True)
-
+    out = time_schedules(inst, specs, fstar, args.steps, args.warmup, inputs,
+                         model=learned_params)
     # the headline schedule is the metric's (learned start + mixed precision)
-    # when it is built for the workload; the plain paper schedule is the
-    # comparison
-    head = next(h for h in ("learned+mixed", "mixed", "plain") if h in out)
+    # when it is built for the workload
+    head = next(h for h in ("learned+mixed", "mixed", "plain_tol1e-07") if h in out)
     hv = out[head]
     spec = specs[head]
+    bp = best_plain(out)
 
     # profiled repeat of the headline steps: per-kernel device time from events
-    psolver = wlra.Solver(spec["precision"], profile=True)
-    psolver.reserve(inst.m, inst.n, inst.k, inst.r)
-    run(psolver, spec, 0)
-    psolver.profile(reset=True)
-    presults = []
-    for i in range(args.steps):
-        r_ = run(psolver, spec, i)[2]
-        presults.append(r_)
-    torch.cuda.synchronize()
-    prof = psolver.profile()
+    with wlra.Solver(spec["precision"], profile=True) as psolver:
+        psolver.reserve(inst.m, inst.n, inst.k, inst.r)
+
+        def prun(step):
+            A, W1 = inputs(spec["precision"])
+            return psolver.solve(A, inst.k, inst.r, W1=W1, w1_const=inst.w1_const or 1.0,
+                                 tol=spec["tol"], max_sweeps=200, init=spec["init"],
+                                 seed=1000 + step, model=learned_params)[2]
+        prun(0)
+        psolver.profile(reset=True)
+        presults = [prun(i) for i in range(args.steps)]
+        torch.cuda.synchronize()
+        prof = psolver.profile(work=True)
     total_ms = sum(v[1] for v in prof.values())
-    dname, (dlaunch, dms) = max(prof.items(), key=lambda kv: kv[1][1])
-    avg_s = dms / dlaunch / 1e3
-    elt = 8 if spec["precision"] == "fp64" else 4
-    elt_a2 = 2 if spec["precision"] == "mixed" else elt
-    bytes_, flops, bound = kernel_work(dname, inst, presults, elt, elt_a2, dlaunch)
-    if bound == "hbm":
-        roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s"}
-    elif bound == "fp64":
-        roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "alu", "achieved": 0.0, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    dname, (dlaunch, dms, dbytes, dflops) = max(prof.items(), key=lambda kv: kv[1][1])
+    roof = roofline_of(dname, dlaunch, dms, dbytes, dflops, presults, inst.n - inst.k)
     roof["traffic"] = measured_traffic(dname, args.workload, spec["precision"])
     roof["kernel"] = dname
     roof["launches"] = dlaunch
-    roof["avg_launch_us"] = avg_s * 1e6
+    roof["avg_launch_us"] = dms / dlaunch * 1e3
     roof["share_of_device_time"] = dms / total_ms if total_ms else None
 
+    start = {"learned": "learned start", "a1": "A1 start", "random": "random start"}[spec["init"]]
     line = {
-        "metric": "WLRA solves/s to rel. objective 1e-6 vs FP64 oracle; learned+mixed vs plain",
+        "metric": METRIC,
         "value": hv["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
@@ -422,20 +570,24 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "bf16+f32"}[spec["precision"]],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: m={inst.m} ({inst.frame_hw[0]}x{inst.frame_hw[1]}) "
-                               f"n={inst.n} k={inst.k} r={inst.r}, {head} schedule, random start",
+                               f"n={inst.n} k={inst.k} r={inst.r}, {head} schedule, {start}",
                    "m": inst.m, "n": inst.n, "k": inst.k, "r": inst.r, "variant": head},
-        "vs_plain": hv["solves_per_s"] / out["plain"]["solves_per_s"],
+        "vs_plain": hv["solves_per_s"] / out[bp]["solves_per_s"] if bp else None,
+        "vs_plain_schedule": bp,
         "solves_meeting_1e-6": hv["solves_meeting_1e-6"],
         "max_rel_objective_err": hv["max_rel_objective_err"],
         "reference_objective": {"value": fstar, "source": fsrc},
-        "variants": {k_: {kk: vv for kk, vv in v.items() if not kk.startswith("_")}
-                     for k_, v in out.items()},
+        "variants": out,
         "learned_start": learned_report,
         "roofline": roof,
         "kernel_ms_per_solve": {k_: v[1] / args.steps for k_, v in sorted(prof.items())},
     }
+    if args.workload == "config2" and not args.no_extra:
+        line["config3"] = run_config3(5, 1)
+        line["config4"] = run_config4(pool, 2, 1)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, args.cpu_solves, 1e-7)
+    torch.cuda.synchronize()
     print(json.dumps(line), flush=True)
 
 

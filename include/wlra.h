@@ -162,6 +162,11 @@ typedef struct {
   char name[24];           /* kernel name                                       */
   int64_t launches;        /* launches since create or the last reset           */
   double ms;               /* summed device time between the bracketing events  */
+  double bytes;            /* summed algorithmic HBM bytes of those launches
+                              (each operand read or written once; 0 for the
+                              small steps, whose data stay in cache)           */
+  double flops;            /* summed algorithmic flops of those launches (0
+                              where not tallied)                               */
 } wlra_kstat;
 
 /* Create a handle bound to `device` and `hip_stream` (a hipStream_t; NULL is

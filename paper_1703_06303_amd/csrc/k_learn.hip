@@ -665,4 +665,5 @@ void launch_zero(hipStream_t s, int64_t count, T *out) {
   template void launch_zero<T>(hipStream_t, int64_t, T *);
 INST_L(float)
 INST_L(double)
+template void launch_zero<int>(hipStream_t, int64_t, int *);
 

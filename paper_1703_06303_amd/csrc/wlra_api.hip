@@ -43,6 +43,7 @@ static const char *kKernelNames[KK_COUNT] = {
 struct ProfEvent {
   int kind;
   hipEvent_t e0, e1;
+  double bytes, flops;  // algorithmic HBM bytes and flops of the launch
 };
 
 struct wlra_ctx {
@@ -70,6 +71,8 @@ struct wlra_ctx {
   std::vector<ProfEvent> pending;
   int64_t launches[KK_COUNT] = {};
   double ms[KK_COUNT] = {};
+  double bytes[KK_COUNT] = {};
+  double flops[KK_COUNT] = {};
 };
 
 static hipEvent_t prof_event(wlra_ctx *h) {
@@ -90,6 +93,8 @@ static void prof_collect(wlra_ctx *h) {
     if (hipEventElapsedTime(&t, pe.e0, pe.e1) == hipSuccess) {
       h->ms[pe.kind] += t;
       h->launches[pe.kind] += 1;
+      h->bytes[pe.kind] += pe.bytes;
+      h->flops[pe.kind] += pe.flops;
     }
     h->pool.push_back(pe.e0);
     h->pool.push_back(pe.e1);
@@ -97,11 +102,12 @@ static void prof_collect(wlra_ctx *h) {
   h->pending.clear();
 }
 
-// Run `stmt` (one kernel launch) between two events when profiling.
-#define PROF(h, kind, stmt)                                        \
+// Run `stmt` (one kernel launch) between two events when profiling, and
+// tally the launch's algorithmic bytes and flops.
+#define PROFW(h, kind, nbytes, nflops, stmt)                       \
   do {                                                             \
     if ((h)->flags & WLRA_FLAG_PROFILE) {                          \
-      ProfEvent pe{kind, prof_event(h), prof_event(h)};            \
+      ProfEvent pe{kind, prof_event(h), prof_event(h), (double)(nbytes), (double)(nflops)}; \
       if (pe.e0 && pe.e1) hipEventRecord(pe.e0, (h)->stream);       \
       stmt;                                                        \
       if (pe.e0 && pe.e1) {                                        \
@@ -112,6 +118,7 @@ static void prof_collect(wlra_ctx *h) {
       stmt;                                                        \
     }                                                              \
   } while (0)
+#define PROF(h, kind, stmt) PROFW(h, kind, 0, 0, stmt)
 
 namespace {
 
@@ -285,6 +292,13 @@ int ensure_ws(wlra_ctx *h, size_t bytes) {
   return WLRA_OK;
 }
 
+size_t workspace_bytes(const wlra_problem &p, int precision) {
+  const Sizes z = make_sizes(p.m, p.n, p.k, p.r, precision == WLRA_FP64 ? 8 : 4,
+                             precision == WLRA_MIXED_BF16,
+                             p.k > 0 && p.init == WLRA_INIT_LEARNED);
+  return make_layout(z, nullptr, nullptr).total;
+}
+
 int check_problem(const wlra_problem *p, int precision) {
   if (p == nullptr) return WLRA_E_ARG;
   if (precision < WLRA_FP64 || precision > WLRA_MIXED_BF16) return WLRA_E_ARG;
@@ -314,15 +328,15 @@ int check_problem(const wlra_problem *p, int precision) {
     if ((x) != hipSuccess) return WLRA_E_HIP; \
   } while (0)
 
+// One solve.  ws: a workspace of at least make_layout(...).total bytes
+// (the handle's).
 template <typename T>
-int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
+int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) {
   const bool mixed = (h->precision == WLRA_MIXED_BF16);
   const bool learned = (pr->k > 0 && pr->init == WLRA_INIT_LEARNED);
   const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T), mixed, learned);
-  int rc = ensure_ws(h, make_layout(z, nullptr, nullptr).total);
-  if (rc != WLRA_OK) return rc;
   Ptrs P;
-  make_layout(z, &P, h->ws);
+  make_layout(z, &P, ws);
   hipStream_t s = h->stream;
   const int64_t m = z.m, k = z.k, n2 = z.n2, l = z.l, b = z.b;
   const T *A = static_cast<const T *>(pr->A);
@@ -332,7 +346,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   const double wc = constw ? pr->w1_const : 0.0;
 
   HIPCHK(hipEventRecord(h->ev0, s));
-  HIPCHK(hipMemsetAsync(P.flags, 0, 64, s));
+  launch_zero<int>(s, 16, P.flags);  // a fill kernel, no memset node
   SmallState &sh = *h->st_host;
   memset(&sh, 0, sizeof(SmallState));
   // Mixed precision runs the sweeps on the BF16 copy of A2 with a looser
@@ -346,8 +360,12 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   sh.eig_floor = mixed ? std::max(eig_tol, MIXED_EIG_TOL) : eig_tol;
   HIPCHK(hipMemcpyAsync(P.st, &sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
 
-  PROF(h, KK_VALIDATE,
-       launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags, P.Ab));
+  // algorithmic bytes per launch of the streaming kernels (each operand read
+  // or written once): element sizes of the storage type and of A2's copy
+  const double es = (double)sizeof(T), es2 = mixed ? 2.0 : es;
+  const double md = (double)m, kd = (double)k, n2d = (double)n2;
+  PROFW(h, KK_VALIDATE, md * (double)pr->n * es + (W1 ? md * kd * es : 0.0) + (mixed ? md * n2d * 2.0 : 0.0), 0,
+        launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags, P.Ab));
   T *X1c = static_cast<T *>(P.X1[0]);
   const bool need_init = (k > 0);
   int *lflag = nullptr;  // learned start: the random start is its fallback
@@ -402,13 +420,13 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   auto gram_A2 = [&](bool on_bf16) {
     if constexpr (std::is_same<T, float>::value) {
       if (on_bf16) {
-        PROF(h, KK_GRAM,
+        PROFW(h, KK_GRAM, md * n2d * 2.0, md * n2d * n2d,
              (launch_tsgemm<bf16s, bf16s>(s, m, P.Ab, m, (int)n2, P.Ab, m, (int)n2, 1,
                                           z.splits_ga, z.rows_ga, P.part, P.GA, nullptr)));
         return;
       }
     }
-    PROF(h, KK_GRAM,
+    PROFW(h, KK_GRAM, md * n2d * es, md * n2d * n2d,
          (launch_tsgemm<T, T>(s, m, A2, pr->lda, (int)n2, A2, pr->lda, (int)n2, 1, z.splits_ga,
                               z.rows_ga, P.part, P.GA, nullptr)));
   };
@@ -416,13 +434,13 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   auto gram_X1A2 = [&](const T *X1, bool on_bf16) {
     if constexpr (std::is_same<T, float>::value) {
       if (on_bf16) {
-        PROF(h, KK_XTA,
+        PROFW(h, KK_XTA, md * (kd * es + n2d * 2.0), 2.0 * md * kd * n2d,
              (launch_tsgemm<float, bf16s>(s, m, X1, m, (int)k, P.Ab, m, (int)n2, 0, z.splits_p,
                                           z.rows_p, P.part, P.P, nullptr)));
         return;
       }
     }
-    PROF(h, KK_XTA,
+    PROFW(h, KK_XTA, md * (kd + n2d) * es, 2.0 * md * kd * n2d,
          (launch_tsgemm<T, T>(s, m, X1, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p, z.rows_p,
                               P.part, P.P, nullptr)));
   };
@@ -433,7 +451,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
   int nparts = 0;
   if (k > 0) {
     gram_X1A2(X1c, on_bf16);
-    PROF(h, KK_XTX,
+    PROFW(h, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
          (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_g1, z.rows_g1,
                               P.part, P.G1, nullptr)));
     PROF(h, KK_F1, launch_f1<T>(s, m, (int)k, A, pr->lda, W1, pr->ldw, wc, X1c, P.upd_part,
@@ -478,7 +496,8 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
            launch_chgprep(s, (int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1],
                           P.Zd[p & 1], P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, z.splits_kg, z.rows_kg,
                           P.part, P.st));
-      PROF(h, KK_CHANGE,
+      PROFW(h, KK_CHANGE, md * (n2d * (on_bf16 ? 2.0 : es) + 2.0 * kd * es),
+            md * (4.0 * (double)l * n2d + (2.0 * (double)l + 2.0 * kd) * (2.0 * (double)l + 2.0 * kd)),
            launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda,
                                on_bf16 ? P.Ab : nullptr, m, X1c,
                                static_cast<const T *>(P.X1[cur ^ 1]), P.Hb, P.Rh, P.chg_part,
@@ -523,9 +542,15 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res) {
     ua.A2b = on_bf16 ? P.Ab : nullptr;
     ua.ldb = m;
     ua.flags = P.flags;
-    PROF(h, KK_UPDATE, launch_update<T>(s, ua));
+    // reads A1, A2, X1_p (and W1), writes X1_{p+1}; the product
+    // [A1 A2 X1] [-S; Z; T] and, for a matrix W1, the per-row SPD solves
+    PROFW(h, KK_UPDATE,
+          md * (n2d * (on_bf16 ? 2.0 : es) + (3.0 + (constw ? 0.0 : 1.0)) * kd * es),
+          2.0 * md * ((double)pr->n + kd) * kd +
+              (constw ? 0.0 : md * (kd * kd * kd / 3.0 + 2.0 * kd * kd)),
+          launch_update<T>(s, ua));
     gram_X1A2(X1n, on_bf16);
-    PROF(h, KK_XTX,
+    PROFW(h, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
          (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_g1, z.rows_g1,
                               P.part, P.G1, nullptr)));
     nparts = z.nwg_upd;
@@ -654,10 +679,10 @@ int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res) {
     return rc;
   }
   if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
-  if (h->precision == WLRA_FP64)
-    rc = solve_impl<double>(h, prob, res);
-  else
-    rc = solve_impl<float>(h, prob, res);
+  rc = ensure_ws(h, workspace_bytes(*prob, h->precision));
+  if (rc == WLRA_OK)
+    rc = (h->precision == WLRA_FP64) ? solve_impl<double>(h, prob, res, h->ws)
+                                     : solve_impl<float>(h, prob, res, h->ws);
   if (rc < 0 && res) res->status = rc;
   return rc;
 }
@@ -706,13 +731,6 @@ int ensure_lanes(wlra_ctx *h, int want) {
     h->lanes.push_back(sub);
   }
   return WLRA_OK;
-}
-
-size_t workspace_bytes(const wlra_problem &p, int precision) {
-  const Sizes z = make_sizes(p.m, p.n, p.k, p.r, precision == WLRA_FP64 ? 8 : 4,
-                             precision == WLRA_MIXED_BF16,
-                             p.k > 0 && p.init == WLRA_INIT_LEARNED);
-  return make_layout(z, nullptr, nullptr).total;
 }
 
 }  // namespace
@@ -783,8 +801,12 @@ int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs, 
     for (int kk = 0; kk < KK_COUNT; ++kk) {
       h->ms[kk] += L->ms[kk];
       h->launches[kk] += L->launches[kk];
+      h->bytes[kk] += L->bytes[kk];
+      h->flops[kk] += L->flops[kk];
       L->ms[kk] = 0.0;
       L->launches[kk] = 0;
+      L->bytes[kk] = 0.0;
+      L->flops[kk] = 0.0;
     }
   }
   (void)hipEventDestroy(ev);
@@ -988,6 +1010,8 @@ int wlra_profile(wlra_handle h, int32_t max, wlra_kstat *out, int32_t reset) {
       strncpy(out[n].name, kKernelNames[i], sizeof(out[n].name) - 1);
       out[n].launches = h->launches[i];
       out[n].ms = h->ms[i];
+      out[n].bytes = h->bytes[i];
+      out[n].flops = h->flops[i];
     }
     ++n;
   }
@@ -995,6 +1019,8 @@ int wlra_profile(wlra_handle h, int32_t max, wlra_kstat *out, int32_t reset) {
     for (int i = 0; i < KK_COUNT; ++i) {
       h->launches[i] = 0;
       h->ms[i] = 0.0;
+      h->bytes[i] = 0.0;
+      h->flops[i] = 0.0;
     }
   return n;
 }

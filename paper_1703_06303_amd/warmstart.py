@@ -111,3 +111,21 @@ def evaluate(solver, pool, params, seeds, k=20, r=25, tol=1e-7, inits=("random",
                                      model=params if init == "learned" else None)
             out[init].append((res["sweeps"], res["ms"], res["objective"], res["status"]))
     return out
+
+
+def summarize(ev):
+    """Mean, p99 and maximum sweeps and solve times per start, and the
+    largest relative objective difference to the random start's solves."""
+    Fr = np.array([x[2] for x in ev["random"]]) if "random" in ev else None
+    out = {}
+    for init, v in ev.items():
+        sw = np.array([x[0] for x in v])
+        ms = np.array([x[1] for x in v])
+        F = np.array([x[2] for x in v])
+        out[init] = {"sweeps_mean": float(sw.mean()), "sweeps_p99": float(np.percentile(sw, 99)),
+                     "sweeps_max": int(sw.max()), "solve_ms_mean": float(ms.mean()),
+                     "solve_ms_p99": float(np.percentile(ms, 99)),
+                     "converged": int(sum(x[3] == 0 for x in v))}
+        if Fr is not None:
+            out[init]["max_rel_objective_vs_random_start"] = float(np.max(np.abs(F - Fr) / Fr))
+    return out

@@ -54,7 +54,8 @@ class Result(ctypes.Structure):
 
 
 class KStat(ctypes.Structure):
-    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("ms", ctypes.c_double)]
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 FLAG_PROFILE = 1
@@ -206,12 +207,17 @@ class Solver:
         except Exception:
             pass
 
-    def profile(self, reset=False):
-        """Per-kernel totals {name: (launches, ms)} of a profiling handle."""
+    def profile(self, reset=False, work=False):
+        """Per-kernel totals {name: (launches, ms)} of a profiling handle;
+        with work=True {name: (launches, ms, bytes, flops)} (algorithmic
+        totals of those launches)."""
         buf = (KStat * 32)()
         n = self.lib.wlra_profile(self.h, 32, buf, 1 if reset else 0)
         if n < 0:
             raise WlraError(n)
+        if work:
+            return {buf[i].name.decode(): (buf[i].launches, buf[i].ms, buf[i].bytes, buf[i].flops)
+                    for i in range(min(n, 32))}
         return {buf[i].name.decode(): (buf[i].launches, buf[i].ms) for i in range(min(n, 32))}
 
     def reserve(self, m, n, k, r):
@@ -221,18 +227,22 @@ class Solver:
 
     def solve(self, A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init="random",
               seed=0, X1_init=None, want_x2=False, want_trace=False, eig_tol=0.0, raise_on_error=True,
-              model=None, want_factors=False):
+              model=None, want_factors=False, out=None):
         """Solve problem (5).  A, W1, X1_init: column-major device tensors of
         the handle's dtype; model: float32 device tensor of network parameters
         (init="learned").  Returns (X1, X2 or None, result dict); with
         want_factors the dict holds "factors" = (R, C, V, theta) as float64
-        device tensors."""
+        device tensors.  out = (X1, X2 or None) passes preallocated outputs."""
         import torch
         m, n = A.shape
         fac = (torch.empty(factors_size(n, k, r), dtype=torch.float64, device=A.device)
                if want_factors else None)
-        X1 = colmajor(torch.empty((m, k), dtype=self.dtype, device=A.device))
-        X2 = colmajor(torch.empty((m, n - k), dtype=self.dtype, device=A.device)) if want_x2 else None
+        if out is not None:
+            X1, X2 = out
+        else:
+            X1 = colmajor(torch.empty((m, k), dtype=self.dtype, device=A.device))
+            X2 = (colmajor(torch.empty((m, n - k), dtype=self.dtype, device=A.device))
+                  if want_x2 else None)
         tr = (ctypes.c_double * (2 * (max_sweeps + 1)))() if want_trace else None
         p = make_problem(A, k, r, W1=W1, w1_const=w1_const, tol=tol, max_sweeps=max_sweeps,
                          init=init, seed=seed, X1_init=X1_init, X1_out=X1, X2_out=X2,
@@ -242,17 +252,17 @@ class Solver:
         rc = self.lib.wlra_solve(self.h, ctypes.byref(p), ctypes.byref(res))
         if rc < 0 and raise_on_error:
             raise WlraError(rc)
-        out = res.as_dict()
-        out["rc"] = rc
+        info = res.as_dict()
+        info["rc"] = rc
         if tr is not None:
-            out["trace_F"] = list(tr[:max_sweeps + 1])
-            out["trace_err"] = list(tr[max_sweeps + 1:])
+            info["trace_F"] = list(tr[:max_sweeps + 1])
+            info["trace_err"] = list(tr[max_sweeps + 1:])
         if fac is not None:
             n2, l = n - k, r - k
             o1, o2, o3 = k * k, k * k + k * n2, k * k + k * n2 + n2 * l
-            out["factors"] = (fac[:o1].view(k, k).t(), fac[o1:o2].view(n2, k).t(),
-                              fac[o2:o3].view(l, n2).t(), fac[o3:])
-        return X1, X2, out
+            info["factors"] = (fac[:o1].view(k, k).t(), fac[o1:o2].view(n2, k).t(),
+                               fac[o2:o3].view(l, n2).t(), fac[o3:])
+        return X1, X2, info
 
     # -- learned warm start -------------------------------------------------
     def _chk(self, rc):
