@@ -20,6 +20,8 @@ Model (all draws from NumPy's PCG64 stream for the given seed):
                            least a fraction p of the frame is covered; values
                            U[lo, hi] per pixel
   noise       iid N(0, sigma^2) on every entry, A1 included
+  fg          the foreground's support (1 where a foreground value was added;
+              derived after the draws, so it changes no other value)
   W1          a constant, or iid 10**U(a, b) per entry
   X1_0        iid N(0, 1), m x k, from the stream at seed + 1
 """
@@ -45,6 +47,7 @@ class Instance:
     frame_hw: tuple
     seed: int
     meta: dict = field(default_factory=dict)
+    fg: np.ndarray | None = None   # uint8 m x n: 1 where foreground was added
 
     @property
     def m(self) -> int:
@@ -106,6 +109,8 @@ def make_instance(h, w, n, k, r, rho, fg="blobs", fg_p=0.10, fg_lo=0.3, fg_hi=1.
     else:
         raise ValueError(fg)
     A[:, k:] += F
+    fgmask = np.zeros((m, n), dtype=np.uint8, order="F")
+    fgmask[:, k:] = F != 0
     A += noise * rng.standard_normal((m, n))
     if w1[0] == "const":
         W1, wc = None, float(w1[1])
@@ -120,7 +125,8 @@ def make_instance(h, w, n, k, r, rho, fg="blobs", fg_p=0.10, fg_lo=0.3, fg_hi=1.
         W1 = np.asfortranarray(W1.astype(dtype).astype(np.float64))
     X1_0 = np.asfortranarray(X1_0.astype(dtype).astype(np.float64))
     return Instance(A=A, k=k, r=r, W1=W1, w1_const=wc, X1_0=X1_0, frame_hw=(h, w),
-                    seed=seed, meta=dict(rho=rho, fg=fg, fg_p=fg_p, noise=noise, w1=w1))
+                    seed=seed, meta=dict(rho=rho, fg=fg, fg_p=fg_p, noise=noise, w1=w1),
+                    fg=fgmask)
 
 
 # -- the five workloads -------------------------------------------------------
@@ -174,6 +180,13 @@ def config4_instance(i, shape, dtype=np.float32) -> Instance:
 def config5_seed(i, heldout=False) -> int:
     """Disjoint seed ranges for warm-start training and held-out evaluation."""
     return BASE_SEED + (6_000_000 if heldout else 5_000_000) + 2 * i
+
+
+def column_weights(n2, seed, lo=0.5, hi=2.0):
+    """Weights w2 (n2 entries, 10**U(log10 lo, log10 hi)) for the variant of
+    the problem with one weight per column of the unweighted block."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), size=n2)
 
 
 def small(m_hw=(6, 8), n=12, k=3, r=5, rho=2, w1=("loguniform", 0.0, 2.0), fg="bernoulli",

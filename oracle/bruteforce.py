@@ -12,11 +12,15 @@ import numpy as np
 from scipy.optimize import minimize
 
 
-def brute_force(A, W1, k, r, starts=200, seed=0, gtol=1e-14, maxiter=20000):
+def brute_force(A, W1, k, r, starts=200, seed=0, gtol=1e-14, maxiter=20000, w2=None):
+    """w2: optional weights of the columns of the second block (eq. (6) with
+    W2(i, j) = w2_j); default 1."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     W = np.ones((m, n))
     W[:, :k] = W1
+    if w2 is not None:
+        W[:, k:] = np.asarray(w2, dtype=np.float64)[None, :]
     W2 = W * W
     rng = np.random.Generator(np.random.PCG64(seed))
 

@@ -24,6 +24,9 @@ Functions and the passage each follows:
   swlr_mixed                the reduced-precision schedule: Algorithm 1 on
                             [A1, bf16(A2)] to a looser threshold, then one
                             sweep of Algorithm 1 on A itself
+  objective_colweights,     eq. (6) with W2(i, j) = w2_j (one weight per
+  swlr_colweights           column of the unweighted block), reduced to
+                            problem (5) by scaling the columns of A2
 
 Readings taken where the paper is loose (all listed in the design notes):
   * X_p = [X1_p, X1_p C_p + D_p] uses the C_p, D_p computed from X1_p; on
@@ -264,6 +267,39 @@ def swlr_mixed(A, W1, k, r, tol=1e-7, max_sweeps=200, X1_0=None, mixed_tol=MIXED
     second.status = first.status
     second.F = first.F + second.F
     return second
+
+
+def objective_colweights(A, W1, w2, X, k):
+    """Eq. (6) with W = [W1, 1 w2^T]: ||(A1 - X1) o W1||_F^2 +
+    ||(A2 - X2) diag(w2)||_F^2."""
+    A = np.asarray(A, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    w2 = np.asarray(w2, dtype=np.float64)
+    f1 = np.sum(((A[:, :k] - X[:, :k]) * W1) ** 2)
+    f2 = np.sum(((A[:, k:] - X[:, k:]) * w2) ** 2)
+    return float(f1 + f2)
+
+
+def swlr_colweights(A, W1, w2, k, r, tol=1e-7, max_sweeps=200, X1_0=None):
+    """Eq. (6) restricted to weights that are constant down each column of
+    the second block, W2(i, j) = w2_j > 0.  With D2 = diag(w2),
+    ||(A2 - X2) D2|| = ||A2 D2 - X2 D2|| and rank([X1, X2 D2]) = rank([X1, X2])
+    (D2 is invertible), so (X1, X2) solves it exactly when (X1, X2 D2) solves
+    problem (5) for [A1, A2 D2].  Algorithm 1 runs on that problem; its
+    iterates, Error_p and the stopping rule are those of the reduced problem,
+    and X2 is returned unscaled (X2 D2 D2^-1).  F is the eq. (6) objective,
+    which equals the reduced problem's."""
+    A = np.asarray(A, dtype=np.float64)
+    w2 = np.asarray(w2, dtype=np.float64).reshape(-1)
+    if w2.shape != (A.shape[1] - k,):
+        raise OracleError(E_ARG, "w2 must have n - k entries")
+    if not np.all(np.isfinite(w2)) or not np.all(w2 > 0):
+        raise OracleError(E_WEIGHT, "w2 entries must be finite and > 0")
+    As = A.copy()
+    As[:, k:] = A[:, k:] * w2
+    res = swlr(As, W1, k, r, tol=tol, max_sweeps=max_sweeps, X1_0=X1_0)
+    res.X2 = res.X2 / w2
+    return res
 
 
 def stationarity_residual(A, W1, k, X1, C, D):
