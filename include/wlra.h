@@ -206,7 +206,9 @@ enum wlra_option {
                                60)                                           */
   WLRA_OPT_EIG_ONE_WG = 2   /* 1: the one-workgroup eigen kernel for every
                                n - k (default 0: a cooperative multi-workgroup
-                               kernel for n - k >= 256)                      */
+                               kernel for n - k >= 256 in wlra_solve; the
+                               lanes of wlra_solve_batched always use the
+                               one-workgroup kernel)                          */
 };
 
 /* Set a handle option; WLRA_E_ARG for an unknown option or a value out of

@@ -249,16 +249,19 @@ __global__ __launch_bounds__(256) void k_subspace_loss(int n, int r, int batch,
   }
 }
 
-// Adam (Kingma & Ba): bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.
+// Adam (Kingma & Ba): bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.  The
+// complements c1 = 1 - beta1 and c2 = 1 - beta2 come from the host, formed in
+// double and rounded once: 1.f - 0.999f would be off by 1.3e-5 relative.
 __global__ __launch_bounds__(256) void k_adam(int64_t P, float *__restrict__ p,
                                               const float *__restrict__ g, float *__restrict__ m,
-                                              float *__restrict__ v, float lr, float b1, float b2,
-                                              float eps, float bc1, float bc2) {
+                                              float *__restrict__ v, float lr, float b1, float c1,
+                                              float b2, float c2, float eps, float bc1,
+                                              float bc2) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < P;
        e += (int64_t)gridDim.x * blockDim.x) {
     const float gg = g[e];
-    const float mm = b1 * m[e] + (1.f - b1) * gg;
-    const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+    const float mm = b1 * m[e] + c1 * gg;
+    const float vv = b2 * v[e] + c2 * gg * gg;
     m[e] = mm;
     v[e] = vv;
     p[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
@@ -641,9 +644,9 @@ void launch_subspace_loss(hipStream_t s, int n, int r, int batch, const float *y
 }
 
 void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, float *v, float lr,
-                 float b1, float b2, float eps, float bc1, float bc2) {
-  hipLaunchKernelGGL(k_adam, dim3(grid_for(P, 4096)), dim3(256), 0, s, P, p, g, m, v, lr, b1, b2,
-                     eps, bc1, bc2);
+                 double b1, double b2, float eps, float bc1, float bc2) {
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(P, 4096)), dim3(256), 0, s, P, p, g, m, v, lr,
+                     (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), eps, bc1, bc2);
 }
 
 template <typename T>

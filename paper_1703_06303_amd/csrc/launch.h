@@ -132,7 +132,7 @@ void launch_colsum(hipStream_t s, int M, int N, const float *A, float *out);
 void launch_subspace_loss(hipStream_t s, int n, int r, int batch, const float *y, const float *T,
                           double lam, float *gy, double *loss_part, int *flags);
 void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, float *v, float lr,
-                 float b1, float b2, float eps, float bc1, float bc2);
+                 double b1, double b2, float eps, float bc1, float bc2);
 template <typename T>
 void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, T *Gt, T *Tt, T *St,
                     int *flags);

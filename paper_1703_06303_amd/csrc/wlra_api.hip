@@ -509,7 +509,9 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
     prof_collect(h);
     if (pr->trace && p <= pr->max_sweeps) {
       pr->trace[p] = sh.F;
-      pr->trace[pr->max_sweeps + 1 + p] = sh.err;
+      // the exact re-evaluation of X_p after the mixed phase runs no change
+      // pass: Error_p stays the BF16 phase's
+      if (!reeval) pr->trace[pr->max_sweeps + 1 + p] = sh.err;
     }
     reeval = false;
     if (sh.done && on_bf16) {
@@ -701,7 +703,9 @@ int wlra_set_option(wlra_handle h, int32_t option, int64_t value) {
     default:
       return WLRA_E_ARG;
   }
-  for (wlra_ctx *L : h->lanes) wlra_set_option(L, option, value);
+  // batch lanes keep the one-workgroup eigen kernel (see ensure_lanes)
+  for (wlra_ctx *L : h->lanes)
+    if (option != WLRA_OPT_EIG_ONE_WG) wlra_set_option(L, option, value);
   return WLRA_OK;
 }
 
@@ -727,7 +731,11 @@ int ensure_lanes(wlra_ctx *h, int want) {
     }
     sub->owns_stream = true;
     sub->eig_maxit = h->eig_maxit;
-    sub->eig_one_wg = h->eig_one_wg;
+    // No cooperative launches on the lanes: a process that had run the
+    // cooperative eigen kernel on four concurrent lane streams ended with a
+    // segmentation fault at exit (cause not shown).  Each lane's eigen step
+    // runs in one workgroup, which leaves the other CUs to the other lanes.
+    sub->eig_one_wg = 1;
     h->lanes.push_back(sub);
   }
   return WLRA_OK;
@@ -985,7 +993,7 @@ int wlra_mlp_train_step(wlra_handle h, float *params, float *adam_m, float *adam
     HIPCHK(hipMemcpyAsync(grad_out, g, (size_t)P * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (step > 0) {
     const double b1c = 1.0 - pow(0.9, step), b2c = 1.0 - pow(0.999, step);
-    launch_adam(s, P, params, g, adam_m, adam_v, (float)lr, 0.9f, 0.999f, 1e-8f, (float)b1c,
+    launch_adam(s, P, params, g, adam_m, adam_v, (float)lr, 0.9, 0.999, 1e-8f, (float)b1c,
                 (float)b2c);
   }
   std::vector<double> lh((size_t)B);

@@ -24,12 +24,18 @@ from .gpu_util import gpu_solve
 pytestmark = pytest.mark.gpu
 
 REL_RTOL, REL_ATOL = 1e-3, 1e-7
+# The BF16 phase of mixed precision stops its eigen steps at a residual of
+# 1e-7 ||A2^T A2||_F (the schedule's stated reading), where the oracle takes
+# an exact SVD: D_p differs from H_{r-k} at that level, and the phase's
+# Error_p (1e-5 .. 1e-1 relative) may differ from the oracle's by 1e-2 of
+# itself.  The stopping sweep must still be the oracle's.
+MIXED_RTOL = 1e-2
 
 
-def _check_rel(gpu_rel, ref_rel, what):
+def _check_rel(gpu_rel, ref_rel, what, rtol=REL_RTOL):
     for p, (g, o) in enumerate(zip(gpu_rel, ref_rel), start=1):
         print(what, "sweep", p, "gpu", g, "oracle", o, flush=True)
-        assert abs(g - o) <= REL_RTOL * o + REL_ATOL, (what, p, g, o)
+        assert abs(g - o) <= rtol * o + REL_ATOL, (what, p, g, o)
 
 
 def _gpu_rel(res):
@@ -77,6 +83,7 @@ def test_mixed_error_trace_and_sweeps():
     assert res["rc"] == 0 and res["sweeps"] == ref.sweeps == P + 1
     tr = res["trace_err"]
     nrm1 = [e / r for e, r in zip(first.err, first.rel)]
-    _check_rel([e / q for e, q in zip(tr[1:P + 1], nrm1)], first.rel, "mixed phase 1")
+    _check_rel([e / q for e, q in zip(tr[1:P + 1], nrm1)], first.rel, "mixed phase 1",
+               rtol=MIXED_RTOL)
     nrm2 = ref.err[0] / ref.rel[0]
     _check_rel([tr[P + 1] / nrm2], ref.rel, "mixed refinement")
