@@ -57,8 +57,10 @@ enum wlra_status {
                              pivot <= 0 in the storage precision (it is SPD in
                              exact arithmetic; this happens when W1^2 is below
                              the rounding of C C^T)                          */
-  WLRA_E_EIG = -9         /* the eigen step for H_{r-k} could not
+  WLRA_E_EIG = -9,        /* the eigen step for H_{r-k} could not
                              orthonormalise its block                        */
+  WLRA_E_SCRATCH = -10    /* wlra_solve_noalloc: the problem needs more
+                             workspace than WLRA_NOALLOC_SCRATCH_BYTES        */
 };
 
 /* Arithmetic of a handle.  The storage type of A, W1, X1_init, X1_out and
@@ -183,6 +185,25 @@ int wlra_reserve(wlra_handle h, int64_t m, int64_t n, int64_t k, int64_t r);
  * result is on the host.  Writes X1_out (and X2_out when given) with the
  * returned X_p.  Inputs are only read. */
 int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as wlra_solve, with the same kernels and results, but its workspace
+ * is a fixed per-device array of WLRA_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library (set up by wlra_create for the handle's device and held until the
+ * process ends) instead of the handle's growable workspace.  The call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * Returns WLRA_E_SCRATCH, before any device work, when the problem needs a
+ * larger workspace than the array holds (the size wlra_solve would grow the
+ * handle's workspace to: about 12 MB for a 19200 x 200 FP32 problem with
+ * k = 20, r = 25, and 19 MB in mixed precision, which fit; about 61 MB for
+ * a 76800 x 600 one, which does not), and
+ * WLRA_E_ARG for a handle created with WLRA_FLAG_PROFILE.  Every call on a
+ * device shares that device's array and leaves its contents behind: calls
+ * that overlap in time on one device (two streams, two threads, two handles)
+ * race and must be ordered by the caller. */
+#define WLRA_NOALLOC_SCRATCH_BYTES (32ll << 20)
+int wlra_solve_noalloc(wlra_handle h, const wlra_problem *prob, wlra_result *res);
 
 /* Solve `count` independent instances of problem (5) (uneven m, n, k, r
  * allowed; each one as wlra_solve would).  The instances run concurrently on

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <type_traits>
@@ -30,6 +31,34 @@
 #define MIXED_EIG_TOL 1e-7
 #define WLRA_BATCH_LANES_DEFAULT 4
 #define WLRA_BATCH_LANES_MAX 16
+
+// Workspace of wlra_solve_noalloc (for callers that cannot allocate): one
+// copy of this array per device, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: it uses the device
+// address that hipGetSymbolAddress returned for that device (kept in
+// g_scratch_dev, set up by wlra_create with the device current).
+#define WLRA_NOALLOC_MAX_DEVICES 64
+static __device__ __align__(256) char scratch[WLRA_NOALLOC_SCRATCH_BYTES];
+static void *g_scratch_dev[WLRA_NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Look up (once per device, with `device` current) the address of `scratch`.
+static void scratch_setup(int device) {
+  if (device < 0 || device >= WLRA_NOALLOC_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device] != nullptr) return;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr != nullptr)
+    g_scratch_dev[device] = ptr;
+  else
+    (void)hipGetLastError();  // wlra_solve_noalloc reports WLRA_E_HIP
+}
+
+static void *scratch_ptr(int device) {
+  if (device < 0 || device >= WLRA_NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[device];
+}
 
 enum KernelKind {
   KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_XTX, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
@@ -629,6 +658,7 @@ const char *wlra_strerror(int status) {
     case WLRA_INEXACT: return "eigen step of the returned sweep stopped at its round limit";
     case WLRA_E_ROWSOLVE: return "per-row system of the X1 update not positive definite in the storage precision";
     case WLRA_E_EIG: return "eigen step could not orthonormalise its block";
+    case WLRA_E_SCRATCH: return "problem needs more workspace than the no-allocation scratch holds";
     default: return "unknown status";
   }
 }
@@ -652,6 +682,7 @@ int wlra_create(wlra_handle *out, int device, void *hip_stream, int precision, u
   wlra_ctx *h = new (std::nothrow) wlra_ctx();
   if (h == nullptr) return WLRA_E_NOMEM;
   h->device = device;
+  scratch_setup(device);
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->precision = precision;
   h->flags = flags;
@@ -685,6 +716,26 @@ int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res) {
   if (rc == WLRA_OK)
     rc = (h->precision == WLRA_FP64) ? solve_impl<double>(h, prob, res, h->ws)
                                      : solve_impl<float>(h, prob, res, h->ws);
+  if (rc < 0 && res) res->status = rc;
+  return rc;
+}
+
+int wlra_solve_noalloc(wlra_handle h, const wlra_problem *prob, wlra_result *res) {
+  if (h == nullptr) return WLRA_E_ARG;
+  // a profiling handle records its events into a growing host list
+  if (h->flags & WLRA_FLAG_PROFILE) return WLRA_E_ARG;
+  int rc = check_problem(prob, h->precision);
+  if (rc == WLRA_OK && workspace_bytes(*prob, h->precision) > (size_t)WLRA_NOALLOC_SCRATCH_BYTES)
+    rc = WLRA_E_SCRATCH;
+  if (rc != WLRA_OK) {
+    if (res) { memset(res, 0, sizeof(*res)); res->status = rc; }
+    return rc;
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
+  char *ws = static_cast<char *>(scratch_ptr(h->device));
+  if (ws == nullptr) return WLRA_E_HIP;
+  rc = (h->precision == WLRA_FP64) ? solve_impl<double>(h, prob, res, ws)
+                                   : solve_impl<float>(h, prob, res, ws);
   if (rc < 0 && res) res->status = rc;
   return rc;
 }

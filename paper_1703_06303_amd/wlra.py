@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "libwlra.so")
 
 OK, MAX_SWEEPS, INEXACT = 0, 1, 2
 E_ARG, E_WEIGHT, E_NONFINITE, E_RANK, E_NOMEM, E_HIP, E_NODEVICE = -1, -2, -3, -4, -5, -6, -7
-E_ROWSOLVE, E_EIG = -8, -9
+E_ROWSOLVE, E_EIG, E_SCRATCH = -8, -9, -10
+NOALLOC_SCRATCH_BYTES = 32 << 20
 OPT_EIG_MAXIT, OPT_EIG_ONE_WG = 1, 2
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 INIT_RANDOM, INIT_GIVEN, INIT_A1, INIT_LEARNED = 0, 1, 2, 3
@@ -60,7 +61,8 @@ class KStat(ctypes.Structure):
 
 FLAG_PROFILE = 1
 
-SYMBOLS = ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
+SYMBOLS = ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_noalloc",
+           "wlra_solve_batched",
            "wlra_set_batch_lanes", "wlra_set_option", "wlra_destroy", "wlra_profile",
            "wlra_validate",
            "wlra_strerror", "wlra_version", "wlra_mlp_param_count", "wlra_mlp_init",
@@ -81,6 +83,8 @@ def load(path: str = LIB_PATH):
                                 ctypes.c_int, ctypes.c_uint32]
     lib.wlra_reserve.argtypes = [ctypes.c_void_p] + [ctypes.c_int64] * 4
     lib.wlra_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Result)]
+    lib.wlra_solve_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
+                                       ctypes.POINTER(Result)]
     lib.wlra_solve_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
                                        ctypes.POINTER(Result)]
     lib.wlra_set_batch_lanes.argtypes = [ctypes.c_void_p, ctypes.c_int32]
@@ -102,7 +106,8 @@ def load(path: str = LIB_PATH):
                                         ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
     for name in ("wlra_mlp_init", "wlra_sketch", "wlra_mlp_forward", "wlra_mlp_train_step"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_batched",
+    for name in ("wlra_create", "wlra_reserve", "wlra_solve", "wlra_solve_noalloc",
+                 "wlra_solve_batched",
                  "wlra_set_batch_lanes", "wlra_set_option", "wlra_destroy", "wlra_profile",
                  "wlra_validate",
                  "wlra_version"):
@@ -227,12 +232,14 @@ class Solver:
 
     def solve(self, A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init="random",
               seed=0, X1_init=None, want_x2=False, want_trace=False, eig_tol=0.0, raise_on_error=True,
-              model=None, want_factors=False, out=None):
+              model=None, want_factors=False, out=None, noalloc=False):
         """Solve problem (5).  A, W1, X1_init: column-major device tensors of
         the handle's dtype; model: float32 device tensor of network parameters
         (init="learned").  Returns (X1, X2 or None, result dict); with
         want_factors the dict holds "factors" = (R, C, V, theta) as float64
-        device tensors.  out = (X1, X2 or None) passes preallocated outputs."""
+        device tensors.  out = (X1, X2 or None) passes preallocated outputs.
+        noalloc=True calls wlra_solve_noalloc (the library's fixed scratch
+        instead of the handle's workspace)."""
         import torch
         m, n = A.shape
         fac = (torch.empty(factors_size(n, k, r), dtype=torch.float64, device=A.device)
@@ -249,7 +256,8 @@ class Solver:
                          trace=ctypes.cast(tr, ctypes.POINTER(ctypes.c_double)) if tr is not None else None,
                          eig_tol=eig_tol, model=model, factors_out=fac)
         res = Result()
-        rc = self.lib.wlra_solve(self.h, ctypes.byref(p), ctypes.byref(res))
+        entry = self.lib.wlra_solve_noalloc if noalloc else self.lib.wlra_solve
+        rc = entry(self.h, ctypes.byref(p), ctypes.byref(res))
         if rc < 0 and raise_on_error:
             raise WlraError(rc)
         info = res.as_dict()
@@ -300,6 +308,10 @@ class Solver:
                                           _ptr(g))
         self._chk(rc)
         return loss.value, g
+
+    def solve_noalloc(self, A, k, r, **kw):
+        """solve(..., noalloc=True): wlra_solve_noalloc."""
+        return self.solve(A, k, r, noalloc=True, **kw)
 
     def set_option(self, option, value):
         rc = self.lib.wlra_set_option(self.h, int(option), int(value))

@@ -26,7 +26,7 @@ def test_exports_every_declared_symbol():
 
 def test_version_and_strerror():
     assert wlra.load().wlra_version() >= 100
-    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8, -9):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10):
         assert wlra.strerror(code) != "unknown status"
 
 
