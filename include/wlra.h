@@ -135,6 +135,35 @@ typedef struct {
                               singular vectors of P_perp A2) and their squared
                               singular values (r-k), all column-major double:
                               X2_p = X1_p C + (A2 - X1_p C) V V^T               */
+  /* ---- extensions around problem (5) (zero-filled: not used) ---- */
+  const void *W2;          /* device, n - k entries of the storage type, or
+                              NULL: one weight per column of the unweighted
+                              block, eq. (6) with W2(i, j) = W2[j - k] > 0 and
+                              finite (else WLRA_E_WEIGHT).  Column scaling
+                              reduces it to problem (5) for [A1, A2 diag(W2)]
+                              with X2 diag(W2) in place of X2 (same rank, same
+                              objective); the validation pass stages that
+                              matrix once in the workspace (m n extra
+                              elements) and the sweeps run on it.  X2_out and
+                              the mask are of the original problem; objective,
+                              Error_p, the trace and factors_out are those of
+                              the scaled problem (the objective is the same)  */
+  uint8_t *mask_out;       /* device m x n bytes, column-major, optional: 1
+                              where |A(i, j) - X(i, j)| > mask_tau for the
+                              returned X_p, else 0 -- the foreground left by
+                              the background estimate X (Section 4).  Decided
+                              in the storage precision                        */
+  int64_t ldm;             /* >= m when mask_out != NULL                        */
+  double mask_tau;         /* >= 0 and finite when mask_out != NULL            */
+  const double *V_init;    /* device, optional: v0_rows x (r - k) column-major
+                              (ld ldv0) start of the first eigen step's block
+                              for H_{r-k}, such as V from factors_out of a
+                              solve on the same frames minus the newest ones;
+                              rows v0_rows .. n - k - 1 start at zero.  Only
+                              the eigen iteration's start changes, not what
+                              it converges to                                 */
+  int64_t ldv0;            /* >= v0_rows when V_init != NULL                    */
+  int64_t v0_rows;         /* 1 <= v0_rows <= n - k when V_init != NULL         */
 } wlra_problem;
 
 typedef struct {

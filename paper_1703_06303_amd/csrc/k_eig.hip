@@ -454,7 +454,7 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
   const double floor_ = st->eig_floor;
   const double maxamp = 1e6;
   Blk<RES> W = F0;
-  if (st->eig_first) {
+  if (st->eig_first == 1) {
     // Start from the columns of M with the largest diagonal entries (the
     // frames whose residual energy is largest, on which the leading
     // eigenvectors concentrate), plus a small deterministic perturbation
@@ -495,7 +495,8 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
     for (int e = t; e < n2 * b; e += ET) Y.at(s, e) = a.Y[e];
   }
   __syncthreads();
-  // a warm start is the previous sweep's Ritz block, orthonormal already
+  // a warm start is the previous sweep's Ritz block, orthonormal already; a
+  // cold start or a given start (eig_first 2) is orthonormalised first
   if (st->eig_first) blk_orth<RES>(s, cx, Y, b, Y, 0, a.flags);
   blk_op<RES>(s, cx, Y, b, W);
   blk_gram<RES>(s, cx, Y, b, W, b, s.H);
@@ -624,6 +625,29 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
     eig_body<false>(s, a, cx, Blk<false>{a.Y}, Blk<false>{a.F0}, Blk<false>{a.F1},
                     Blk<false>{a.F2});
   }
+}
+
+// Start block of the first eigen step from a given V (v0 x l, ld ldv):
+// Y(i, q) = V(i, q) for i < v0 and q < l, zero for the other rows, and the
+// b - l guard columns small pseudo-random vectors that keep the block of full
+// rank (the eigen step orthonormalises it).
+__global__ __launch_bounds__(256) void k_eig_seed(int n2, int l, int b, const double *V,
+                                                  int64_t ldv, int v0, double *Y) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n2 * b; e += gridDim.x * 256) {
+    const int i = e % n2, q = e / n2;
+    double v;
+    if (q < l)
+      v = (i < v0) ? V[i + (int64_t)q * ldv] : 0.0;
+    else
+      v = hash_unit((uint32_t)i, (uint32_t)q) / sqrt((double)n2);
+    Y[e] = v;
+  }
+}
+
+void launch_eig_seed(hipStream_t s, int n2, int l, int b, const double *V, int64_t ldv, int v0,
+                     double *Y) {
+  const int grid = std::max(1, std::min(64, (n2 * b + 255) / 256));
+  hipLaunchKernelGGL(k_eig_seed, dim3(grid), dim3(256), 0, s, n2, l, b, V, ldv, v0, Y);
 }
 
 void launch_eig(hipStream_t s, const SmallArgs &a) {

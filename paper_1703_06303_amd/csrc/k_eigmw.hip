@@ -352,8 +352,8 @@ __global__ __launch_bounds__(MW_T) void k_eig_mw(SmallArgs a) {
   double *Y = a.Y, *F0 = a.F0, *F1 = a.F1, *F2 = a.F2;
   double *W = F0;
   const int nr = c.r1 - c.r0;
-  const bool first = st->eig_first != 0;
-  if (first) {
+  const bool first = st->eig_first != 0;  // 2: a given start block in Y
+  if (st->eig_first == 1) {
     // start from the columns of M with the largest diagonal entries
     if (t < 64) {
       for (int q = 0; q < b; ++q) {

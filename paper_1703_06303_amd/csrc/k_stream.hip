@@ -26,16 +26,28 @@ __device__ __forceinline__ T a_elem(const T *__restrict__ A, int64_t lda,
 // (W1)_ij > 0).  flags |= DEV_BAD_A / DEV_BAD_W.  When A2b is given, the
 // same read also stages A2 in BF16 (m x (n - k), leading dimension m) for the
 // mixed-precision sweeps.
+// Column weights of the unweighted block (eq. (6) with W2(i, j) = w2_j): the
+// same read writes As = [A1, A2 diag(w2)] (m x n, leading dimension m), the
+// matrix of the equivalent problem (5) that the sweeps then run on, and the
+// BF16 copy is taken of the scaled columns; a w2_j that is not > 0 and
+// finite sets DEV_BAD_W.
 template <typename T>
 __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, const T *__restrict__ A,
                                                   int64_t lda, int64_t k, const T *__restrict__ W1,
-                                                  int64_t ldw, int *flags, bf16s *__restrict__ A2b) {
+                                                  int64_t ldw, int *flags, bf16s *__restrict__ A2b,
+                                                  const T *__restrict__ W2, T *__restrict__ As) {
   int bad_a = 0, bad_w = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+    const T sc = (W2 != nullptr && j >= k) ? W2[j - k] : T(1);
+    if (W2 != nullptr && j >= k && !(sc > T(0) && isfinite(sc))) bad_w = 1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
-      const T v = A[i + j * lda];
+      T v = A[i + j * lda];
       if (!isfinite(v)) bad_a = 1;
+      if (W2 != nullptr) {
+        v *= sc;
+        As[i + j * m] = v;
+      }
       if (A2b != nullptr && j >= k) A2b[i + (j - k) * m] = bf16_rne((float)v);
       if (W1 != nullptr && j < k) {
         const T w = W1[i + j * ldw];
@@ -590,15 +602,22 @@ __global__ __launch_bounds__(64) void k_rowsolve_lds(
 }
 
 // ---------------------------------------------------------------------------
-// Dense output X2 = X1 C + D = a2 V V^T + x1 Z^T row by row (one row per
-// lane): u = a2_i V, then x2_ij = u . V(j,:) + x1_i . Z(j,:).
-// Vr is n2 x l row-major, Zt n2 x k row-major (same as k_update).
+// Output pass over the rows of the returned X_p.  Dense X2 = X1 C + D =
+// a2 V V^T + x1 Z^T row by row (one row per lane): u = a2_i V, then
+// x2_ij = u . V(j,:) + x1_i . Z(j,:).  Vr is n2 x l row-major, Zt n2 x k
+// row-major (same as k_update).  X2 is written when given.
+// Column weights (w2 given): the rows are those of the scaled problem, so
+// x2_ij is divided by w2_j on the way out, and the residual of entry (i, j)
+// is |a2s_ij - x2s_ij| / w2_j.
+// Foreground mask (mask given): byte (i, j) is 1 where |A(i, j) - X(i, j)| >
+// tau, else 0, for all n columns (A1 - X1 included), decided in T.
 template <typename T, int KMAX, int LMAX>
 __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
                                            const T *__restrict__ A, int64_t lda,
                                            const T *__restrict__ X1, const T *__restrict__ Zt,
                                            const T *__restrict__ Vr, T *__restrict__ X2,
-                                           int64_t ldx2) {
+                                           int64_t ldx2, const T *__restrict__ w2,
+                                           uint8_t *__restrict__ mask, int64_t ldm, T tau) {
   const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const bool act = i < m;
   const int64_t ir = act ? i : (m - 1);
@@ -616,6 +635,11 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
   }
 #pragma unroll
   for (int c = 0; c < KMAX; ++c) x[c] = (c < k) ? X1[ir + (int64_t)c * m] : T(0);
+  if (mask != nullptr && act) {
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c)
+      if (c < k) mask[i + (int64_t)c * ldm] = fabs(A[i + (int64_t)c * lda] - x[c]) > tau ? 1 : 0;
+  }
   for (int j = 0; j < n2; ++j) {
     const T *vr = Vr + (int64_t)j * l;
     const T *zr = Zt + (int64_t)j * k;
@@ -626,7 +650,12 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
 #pragma unroll
     for (int c = 0; c < KMAX; ++c)
       if (c < k) acc = fma(x[c], zr[c], acc);
-    if (act) X2[i + (int64_t)j * ldx2] = acc;
+    const T sc = w2 != nullptr ? w2[j] : T(1);
+    if (act && X2 != nullptr) X2[i + (int64_t)j * ldx2] = w2 != nullptr ? acc / sc : acc;
+    if (act && mask != nullptr) {
+      const T res = fabs(A2[i + (int64_t)j * lda] - acc);
+      mask[i + (int64_t)(k + j) * ldm] = (w2 != nullptr ? res / sc : res) > tau ? 1 : 0;
+    }
   }
 }
 
@@ -941,9 +970,10 @@ __global__ __launch_bounds__(256) void k_copy_out(int64_t m, int64_t k, const T 
 
 template <typename T>
 void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t lda, int64_t k,
-                     const T *W1, int64_t ldw, int *flags, bf16s *A2b) {
+                     const T *W1, int64_t ldw, int *flags, bf16s *A2b, const T *W2, T *As) {
   dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)std::min<int64_t>(n, 1024));
-  hipLaunchKernelGGL(k_validate<T>, grid, dim3(256), 0, s, m, n, A, lda, k, W1, ldw, flags, A2b);
+  hipLaunchKernelGGL(k_validate<T>, grid, dim3(256), 0, s, m, n, A, lda, k, W1, ldw, flags, A2b,
+                     W2, As);
 }
 
 template <typename T>
@@ -1063,23 +1093,27 @@ void launch_update(hipStream_t s, const UpdateArgs<T> &a) {
 
 template <typename T, int KMAX>
 static void launch_x2_k(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-                        const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2) {
+                        const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2, const T *w2,
+                        uint8_t *mask, int64_t ldm, T tau) {
   const unsigned grid = (unsigned)((m + 63) / 64);
   if (l <= 8)
     hipLaunchKernelGGL((k_x2<T, KMAX, 8>), dim3(grid), dim3(64), 0, s, m, k, n2, l, A, lda, X1, Zt,
-                       Vr, X2, ldx2);
+                       Vr, X2, ldx2, w2, mask, ldm, tau);
   else
     hipLaunchKernelGGL((k_x2<T, KMAX, WLRA_BMAX>), dim3(grid), dim3(64), 0, s, m, k, n2, l, A, lda,
-                       X1, Zt, Vr, X2, ldx2);
+                       X1, Zt, Vr, X2, ldx2, w2, mask, ldm, tau);
 }
 
 template <typename T>
 void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-               const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2) {
-  if (k <= 8) launch_x2_k<T, 8>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2);
-  else if (k <= 16) launch_x2_k<T, 16>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2);
-  else if (k <= 32) launch_x2_k<T, 32>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2);
-  else launch_x2_k<T, 64>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2);
+               const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2, const T *w2,
+               uint8_t *mask, int64_t ldm, T tau) {
+  if (k <= 8) launch_x2_k<T, 8>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2, w2, mask, ldm, tau);
+  else if (k <= 16)
+    launch_x2_k<T, 16>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2, w2, mask, ldm, tau);
+  else if (k <= 32)
+    launch_x2_k<T, 32>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2, w2, mask, ldm, tau);
+  else launch_x2_k<T, 64>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2, w2, mask, ldm, tau);
 }
 
 void launch_chgprep(hipStream_t s, int n2, int k, int l, const double *Vp, const double *Vq,
@@ -1139,7 +1173,7 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
 
 #define INST(T)                                                                                   \
   template void launch_validate<T>(hipStream_t, int64_t, int64_t, const T *, int64_t, int64_t,    \
-                                   const T *, int64_t, int *, bf16s *);                           \
+                                   const T *, int64_t, int *, bf16s *, const T *, T *);           \
   template void launch_init_x1<T>(hipStream_t, int64_t, int64_t, int, uint64_t, const T *,        \
                                   int64_t, T *, int *, const int *);                              \
   template void launch_tsgemm<T, T>(hipStream_t, int64_t, const T *, int64_t, int, const T *,     \
@@ -1150,7 +1184,8 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
   template void launch_update<T>(hipStream_t, const UpdateArgs<T> &);                             \
   template UpdatePlan update_plan<T>(int, bool);                                                 \
   template void launch_x2<T>(hipStream_t, int64_t, int, int, int, const T *, int64_t, const T *,  \
-                             const T *, const T *, T *, int64_t);                                 \
+                             const T *, const T *, T *, int64_t, const T *, uint8_t *, int64_t,  \
+                             T);                                                                  \
   template void launch_copy_out<T>(hipStream_t, int64_t, int64_t, const T *, T *, int64_t);     \
   template void launch_change_qr<T>(hipStream_t, int64_t, int, int, int, const T *, int64_t,      \
                                     const bf16s *, int64_t, const T *, const T *, const double *, \

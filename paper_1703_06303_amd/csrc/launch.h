@@ -31,7 +31,8 @@ struct UpdateArgs {
 
 template <typename T>
 void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t lda, int64_t k,
-                     const T *W1, int64_t ldw, int *flags, bf16s *A2b);
+                     const T *W1, int64_t ldw, int *flags, bf16s *A2b, const T *W2 = nullptr,
+                     T *As = nullptr);
 template <typename T>
 void launch_init_x1(hipStream_t s, int64_t m, int64_t k, int mode, uint64_t seed, const T *src,
                     int64_t lds, T *X1, int *flags, const int *gate = nullptr);
@@ -53,7 +54,8 @@ template <typename T>
 UpdatePlan update_plan(int k, bool constw);
 template <typename T>
 void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-               const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2);
+               const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2, const T *w2,
+               uint8_t *mask, int64_t ldm, T tau);
 template <typename T>
 void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, int64_t ld);
 
@@ -131,6 +133,8 @@ void launch_gemm(hipStream_t s, int mode, int M, int N, int K, const float *A, i
 void launch_colsum(hipStream_t s, int M, int N, const float *A, float *out);
 void launch_subspace_loss(hipStream_t s, int n, int r, int batch, const float *y, const float *T,
                           double lam, float *gy, double *loss_part, int *flags);
+void launch_eig_seed(hipStream_t s, int n2, int l, int b, const double *V, int64_t ldv, int v0,
+                     double *Y);
 void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, float *v, float lr,
                  double b1, double b2, float eps, float bc1, float bc2);
 template <typename T>

@@ -170,6 +170,7 @@ struct Sizes {
   size_t elt;
   bool mixed;
   bool learned;
+  bool colw;  // column weights of the unweighted block: A staged scaled
   int splits_l1;  // Om^T A of the learned start's sketch
   int64_t rows_l1;
   int splits_kg;  // H^T H of the change pass (n2 rows)
@@ -185,6 +186,7 @@ struct Ptrs {
   double *Zd[2], *Vd[2];
   void *Gt, *Tt, *St, *Vr, *Zx, *Eb;
   bf16s *Ab;  // mixed precision: BF16 copy of A2 (m x n2), else NULL
+  void *As;   // column weights: [A1, A2 diag(W2)] (m x n), else NULL
   double *Hb, *Rh;  // change pass: aligned basis [V_p dV Z_p dZ] and its Gram
   double *epart;    // multi-workgroup eigen kernel: partial Grams
   // learned warm start (NULL unless the start is learned)
@@ -207,10 +209,11 @@ int choose_splits(int64_t m, int tiles, int64_t *rows) {
 }
 
 Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mixed,
-                 bool learned = false) {
+                 bool learned = false, bool colw = false) {
   Sizes z;
   z.mixed = mixed;
   z.learned = learned;
+  z.colw = colw;
   z.m = m; z.n = n; z.k = k; z.r = r; z.n2 = n - k; z.l = r - k;
   z.b = z.l > 0 ? std::min<int64_t>(z.n2, z.l + EIG_GUARD) : 0;
   const int tga = (int)(((z.n2 + 31) / 32) * ((z.n2 + 31) / 32 + 1) / 2);
@@ -280,6 +283,7 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.st, sizeof(SmallState)},
       {(void **)&p.flags, 64},
       {(void **)&p.Ab, z.mixed ? (size_t)(m * n2) * sizeof(bf16s) : 0},
+      {&p.As, z.colw ? (size_t)(m * z.n) * z.elt : 0},
       {(void **)&p.Hb, (size_t)(n2 * (2 * l + 2 * k)) * d},
       {(void **)&p.Rh, (size_t)((2 * l + 2 * k) * (2 * l + 2 * k)) * d},
       {(void **)&p.epart,
@@ -324,7 +328,8 @@ int ensure_ws(wlra_ctx *h, size_t bytes) {
 size_t workspace_bytes(const wlra_problem &p, int precision) {
   const Sizes z = make_sizes(p.m, p.n, p.k, p.r, precision == WLRA_FP64 ? 8 : 4,
                              precision == WLRA_MIXED_BF16,
-                             p.k > 0 && p.init == WLRA_INIT_LEARNED);
+                             p.k > 0 && p.init == WLRA_INIT_LEARNED,
+                             p.W2 != nullptr && p.n > p.k);
   return make_layout(z, nullptr, nullptr).total;
 }
 
@@ -349,6 +354,11 @@ int check_problem(const wlra_problem *p, int precision) {
     return WLRA_E_ARG;
   if (k > 0 && p->init == WLRA_INIT_GIVEN && (p->X1_init == nullptr || p->ldx0 < m)) return WLRA_E_ARG;
   if (!(p->tol == p->tol)) return WLRA_E_ARG;
+  if (p->mask_out != nullptr && (p->ldm < m || !(p->mask_tau >= 0 && isfinite(p->mask_tau))))
+    return WLRA_E_ARG;
+  if (p->V_init != nullptr && l > 0 &&
+      (p->v0_rows < 1 || p->v0_rows > n2 || p->ldv0 < p->v0_rows))
+    return WLRA_E_ARG;
   return WLRA_OK;
 }
 
@@ -363,13 +373,18 @@ template <typename T>
 int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) {
   const bool mixed = (h->precision == WLRA_MIXED_BF16);
   const bool learned = (pr->k > 0 && pr->init == WLRA_INIT_LEARNED);
-  const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T), mixed, learned);
+  const bool colw = (pr->W2 != nullptr && pr->n > pr->k);
+  const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T), mixed, learned, colw);
   Ptrs P;
   make_layout(z, &P, ws);
   hipStream_t s = h->stream;
   const int64_t m = z.m, k = z.k, n2 = z.n2, l = z.l, b = z.b;
-  const T *A = static_cast<const T *>(pr->A);
-  const T *A2 = A + k * pr->lda;
+  // with column weights every pass after validation reads the staged
+  // [A1, A2 diag(W2)] (leading dimension m) in place of A
+  const T *A = colw ? static_cast<const T *>(P.As) : static_cast<const T *>(pr->A);
+  const int64_t lda = colw ? m : pr->lda;
+  const T *A2 = A + k * lda;
+  const T *W2 = colw ? static_cast<const T *>(pr->W2) : nullptr;
   const T *W1 = (k > 0) ? static_cast<const T *>(pr->W1) : nullptr;
   const bool constw = (k > 0 && W1 == nullptr);
   const double wc = constw ? pr->w1_const : 0.0;
@@ -384,6 +399,11 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
   sh.tol = (mixed && pr->tol > 0) ? std::max(pr->tol, MIXED_TOL) : pr->tol;
   sh.max_sweeps = mixed ? std::max(max_sweeps - 1, 0) : max_sweeps;
   sh.eig_first = 1;
+  if (pr->V_init != nullptr && l > 0) {
+    // the first eigen step starts from the given block (orthonormalised there)
+    launch_eig_seed(s, (int)n2, (int)l, (int)b, pr->V_init, pr->ldv0, (int)pr->v0_rows, P.Y);
+    sh.eig_first = 2;
+  }
   const double eig_tol = pr->eig_tol > 0 ? pr->eig_tol
                          : (h->precision == WLRA_FP64 ? 64.0 * 2.220446049250313e-16 : 1e-10);
   sh.eig_floor = mixed ? std::max(eig_tol, MIXED_EIG_TOL) : eig_tol;
@@ -394,7 +414,8 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
   const double es = (double)sizeof(T), es2 = mixed ? 2.0 : es;
   const double md = (double)m, kd = (double)k, n2d = (double)n2;
   PROFW(h, KK_VALIDATE, md * (double)pr->n * es + (W1 ? md * kd * es : 0.0) + (mixed ? md * n2d * 2.0 : 0.0), 0,
-        launch_validate<T>(s, m, pr->n, A, pr->lda, k, W1, pr->ldw, P.flags, P.Ab));
+        launch_validate<T>(s, m, pr->n, static_cast<const T *>(pr->A), pr->lda, k, W1, pr->ldw,
+                           P.flags, P.Ab, W2, static_cast<T *>(P.As)));
   T *X1c = static_cast<T *>(P.X1[0]);
   const bool need_init = (k > 0);
   int *lflag = nullptr;  // learned start: the random start is its fallback
@@ -415,7 +436,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
     auto seq = [&]() {
       launch_gauss_fill<T>(s, m * LEARN_SK_ROWS, LEARN_SEED_OMEGA, 1.0, Om);
       launch_gauss_fill<T>(s, n * LEARN_SK_COLS, LEARN_SEED_PSI, 1.0, Ps);
-      launch_tsgemm<T, T>(s, m, Om, m, LEARN_SK_ROWS, A, pr->lda, (int)n, 0, z.splits_l1,
+      launch_tsgemm<T, T>(s, m, Om, m, LEARN_SK_ROWS, A, lda, (int)n, 0, z.splits_l1,
                           z.rows_l1, P.lpart, P.P1, nullptr);
       launch_sketch_finish<T>(s, (int)n, P.P1, Ps, P.sk);
       launch_gemm(s, 0, 1, LEARN_HID, LEARN_D_IN, P.sk, LEARN_D_IN, W1m, LEARN_D_IN, P.lh1,
@@ -427,7 +448,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
       launch_ldecode<T>(s, (int)n, (int)k, (int)z.r, P.yv, Gt, Tt, St, lflag);
       launch_zero<T>(s, m * k, X1z);
       UpdateArgs<T> ua{};
-      ua.m = m; ua.k = (int)k; ua.n = (int)n; ua.A = A; ua.lda = pr->lda; ua.W1 = W1;
+      ua.m = m; ua.k = (int)k; ua.n = (int)n; ua.A = A; ua.lda = lda; ua.W1 = W1;
       ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1z; ua.X1n = X1c;
       ua.Gt = Gt; ua.Tt = Tt; ua.St = St; ua.part = P.upd_part; ua.st = P.st;
       ua.Eb = static_cast<T *>(P.Eb);
@@ -441,7 +462,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
   if (need_init) {
     const int mode = (pr->init == WLRA_INIT_RANDOM || pr->init == WLRA_INIT_LEARNED) ? 0 : 1;
     const T *src = pr->init == WLRA_INIT_GIVEN ? static_cast<const T *>(pr->X1_init) : A;
-    const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : pr->lda;
+    const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : lda;
     PROF(h, KK_INIT, launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags, lflag));
   }
   // One-time Gram of the unweighted block: A2^T A2 (of the BF16 copy in
@@ -456,7 +477,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
       }
     }
     PROFW(h, KK_GRAM, md * n2d * es, md * n2d * n2d,
-         (launch_tsgemm<T, T>(s, m, A2, pr->lda, (int)n2, A2, pr->lda, (int)n2, 1, z.splits_ga,
+         (launch_tsgemm<T, T>(s, m, A2, lda, (int)n2, A2, lda, (int)n2, 1, z.splits_ga,
                               z.rows_ga, P.part, P.GA, nullptr)));
   };
   // X1^T A2 (k x n2) for the coefficients of the next small step.
@@ -470,7 +491,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
       }
     }
     PROFW(h, KK_XTA, md * (kd + n2d) * es, 2.0 * md * kd * n2d,
-         (launch_tsgemm<T, T>(s, m, X1, m, (int)k, A2, pr->lda, (int)n2, 0, z.splits_p, z.rows_p,
+         (launch_tsgemm<T, T>(s, m, X1, m, (int)k, A2, lda, (int)n2, 0, z.splits_p, z.rows_p,
                               P.part, P.P, nullptr)));
   };
   bool on_bf16 = mixed;  // A2 products on the BF16 copy (mixed phase)
@@ -483,7 +504,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
     PROFW(h, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
          (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_g1, z.rows_g1,
                               P.part, P.G1, nullptr)));
-    PROF(h, KK_F1, launch_f1<T>(s, m, (int)k, A, pr->lda, W1, pr->ldw, wc, X1c, P.upd_part,
+    PROF(h, KK_F1, launch_f1<T>(s, m, (int)k, A, lda, W1, pr->ldw, wc, X1c, P.upd_part,
                                 z.nwg_f1));
     nparts = z.nwg_f1;
   }
@@ -527,7 +548,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
                           P.part, P.st));
       PROFW(h, KK_CHANGE, md * (n2d * (on_bf16 ? 2.0 : es) + 2.0 * kd * es),
             md * (4.0 * (double)l * n2d + (2.0 * (double)l + 2.0 * kd) * (2.0 * (double)l + 2.0 * kd)),
-           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda,
+           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, lda,
                                on_bf16 ? P.Ab : nullptr, m, X1c,
                                static_cast<const T *>(P.X1[cur ^ 1]), P.Hb, P.Rh, P.chg_part,
                                P.st));
@@ -566,7 +587,7 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
     // X1_{p+1} from X1_p (Algorithm 1 steps 7-9), then the sums for p+1.
     T *X1n = static_cast<T *>(P.X1[cur ^ 1]);
     UpdateArgs<T> ua{};
-    ua.m = m; ua.k = (int)k; ua.n = (int)pr->n; ua.A = A; ua.lda = pr->lda; ua.W1 = W1;
+    ua.m = m; ua.k = (int)k; ua.n = (int)pr->n; ua.A = A; ua.lda = lda; ua.W1 = W1;
     ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1c; ua.X1n = X1n;
     ua.Gt = so.Gt; ua.Tt = so.Tt; ua.St = so.St; ua.part = P.upd_part; ua.st = P.st;
     ua.Eb = static_cast<T *>(P.Eb);
@@ -612,10 +633,11 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
                             hipMemcpyDeviceToDevice, s));
     }
   }
-  if (pr->X2_out != nullptr)
+  if (pr->X2_out != nullptr || pr->mask_out != nullptr)
     PROF(h, KK_X2,
-         launch_x2<T>(s, m, (int)k, (int)n2, (int)l, A, pr->lda, X1c, so.Zx, so.Vr,
-                      static_cast<T *>(pr->X2_out), pr->ldx2));
+         launch_x2<T>(s, m, (int)k, (int)n2, (int)l, A, lda, X1c, so.Zx, so.Vr,
+                      static_cast<T *>(pr->X2_out), pr->ldx2, W2, pr->mask_out, pr->ldm,
+                      (T)pr->mask_tau));
   HIPCHK(hipEventRecord(h->ev1, s));
   HIPCHK(hipEventSynchronize(h->ev1));
   prof_collect(h);

@@ -39,6 +39,9 @@ class Problem(ctypes.Structure):
         ("eig_tol", ctypes.c_double),
         ("model", ctypes.c_void_p),
         ("factors_out", ctypes.c_void_p),
+        ("W2", ctypes.c_void_p),
+        ("mask_out", ctypes.c_void_p), ("ldm", ctypes.c_int64), ("mask_tau", ctypes.c_double),
+        ("V_init", ctypes.c_void_p), ("ldv0", ctypes.c_int64), ("v0_rows", ctypes.c_int64),
     ]
 
 
@@ -150,8 +153,11 @@ def factors_size(n, k, r):
 
 def make_problem(A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init="random",
                  seed=0, X1_init=None, X1_out=None, X2_out=None, trace=None, eig_tol=0.0,
-                 model=None, factors_out=None):
-    """Fill a Problem from tensors (column-major device tensors or None)."""
+                 model=None, factors_out=None, W2=None, mask_out=None, mask_tau=0.0,
+                 V_init=None):
+    """Fill a Problem from tensors (column-major device tensors or None).
+    W2: n - k column weights (1-D); mask_out: m x n uint8; V_init: a
+    v0_rows x (r - k) float64 start block of the eigen step."""
     m, n = A.shape
     p = Problem()
     p.m, p.n, p.k, p.r = m, n, k, r
@@ -173,6 +179,14 @@ def make_problem(A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init=
     p.eig_tol = float(eig_tol)
     p.model = _ptr(model)
     p.factors_out = _ptr(factors_out)
+    p.W2 = _ptr(W2)
+    p.mask_out = _ptr(mask_out)
+    p.ldm = mask_out.stride(1) if (mask_out is not None and n > 1) else m
+    p.mask_tau = float(mask_tau)
+    p.V_init = _ptr(V_init)
+    if V_init is not None:
+        p.v0_rows = V_init.shape[0]
+        p.ldv0 = V_init.stride(1) if V_init.shape[1] > 1 else V_init.shape[0]
     return p
 
 
@@ -232,14 +246,18 @@ class Solver:
 
     def solve(self, A, k, r, W1=None, w1_const=0.0, tol=1e-7, max_sweeps=200, init="random",
               seed=0, X1_init=None, want_x2=False, want_trace=False, eig_tol=0.0, raise_on_error=True,
-              model=None, want_factors=False, out=None, noalloc=False):
+              model=None, want_factors=False, out=None, noalloc=False, W2=None, mask_tau=None,
+              V_init=None):
         """Solve problem (5).  A, W1, X1_init: column-major device tensors of
         the handle's dtype; model: float32 device tensor of network parameters
         (init="learned").  Returns (X1, X2 or None, result dict); with
         want_factors the dict holds "factors" = (R, C, V, theta) as float64
         device tensors.  out = (X1, X2 or None) passes preallocated outputs.
         noalloc=True calls wlra_solve_noalloc (the library's fixed scratch
-        instead of the handle's workspace)."""
+        instead of the handle's workspace).  W2: n - k column weights (device,
+        handle dtype); mask_tau: also return info["mask"], the m x n uint8
+        mask |A - X| > mask_tau; V_init: float64 device start block of the
+        eigen step (rows x (r - k), column-major)."""
         import torch
         m, n = A.shape
         fac = (torch.empty(factors_size(n, k, r), dtype=torch.float64, device=A.device)
@@ -251,10 +269,15 @@ class Solver:
             X2 = (colmajor(torch.empty((m, n - k), dtype=self.dtype, device=A.device))
                   if want_x2 else None)
         tr = (ctypes.c_double * (2 * (max_sweeps + 1)))() if want_trace else None
+        mask = (torch.empty((n, m), dtype=torch.uint8, device=A.device).t()
+                if mask_tau is not None else None)
+        if V_init is not None:
+            V_init = colmajor(V_init.to(torch.float64))
         p = make_problem(A, k, r, W1=W1, w1_const=w1_const, tol=tol, max_sweeps=max_sweeps,
                          init=init, seed=seed, X1_init=X1_init, X1_out=X1, X2_out=X2,
                          trace=ctypes.cast(tr, ctypes.POINTER(ctypes.c_double)) if tr is not None else None,
-                         eig_tol=eig_tol, model=model, factors_out=fac)
+                         eig_tol=eig_tol, model=model, factors_out=fac, W2=W2, mask_out=mask,
+                         mask_tau=mask_tau if mask_tau is not None else 0.0, V_init=V_init)
         res = Result()
         entry = self.lib.wlra_solve_noalloc if noalloc else self.lib.wlra_solve
         rc = entry(self.h, ctypes.byref(p), ctypes.byref(res))
@@ -265,6 +288,8 @@ class Solver:
         if tr is not None:
             info["trace_F"] = list(tr[:max_sweeps + 1])
             info["trace_err"] = list(tr[max_sweeps + 1:])
+        if mask is not None:
+            info["mask"] = mask
         if fac is not None:
             n2, l = n - k, r - k
             o1, o2, o3 = k * k, k * k + k * n2, k * k + k * n2 + n2 * l

@@ -57,6 +57,15 @@ def _prob(**kw):
     ({"init": 1, "X1_init": 0}, False),     # given start without a matrix
     ({"init": 1, "X1_init": 1, "ldx0": 100}, True),
     ({"X2_out": 1, "ldx2": 10}, False),
+    ({"mask_out": 1, "ldm": 100, "mask_tau": 0.3}, True),
+    ({"mask_out": 1, "ldm": 99, "mask_tau": 0.3}, False),      # ldm < m
+    ({"mask_out": 1, "ldm": 100, "mask_tau": -0.1}, False),    # negative threshold
+    ({"mask_out": 1, "ldm": 100, "mask_tau": float("nan")}, False),
+    ({"V_init": 1, "v0_rows": 15, "ldv0": 15}, True),          # n - k = 15 rows
+    ({"V_init": 1, "v0_rows": 16, "ldv0": 16}, False),         # more rows than n - k
+    ({"V_init": 1, "v0_rows": 0, "ldv0": 1}, False),
+    ({"V_init": 1, "v0_rows": 10, "ldv0": 9}, False),          # ldv0 < v0_rows
+    ({"W2": 1}, True),                                         # weights are checked on the device
 ])
 def test_validate(kw, ok):
     rc = wlra.validate(_prob(**kw), wlra.FP32)
