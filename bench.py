@@ -33,6 +33,8 @@ The default run also times, as sub-objects of the same line:
            wlra_solve_batched call per step on four lanes (FP32 and mixed):
            solves/s, p50/p99 per-solve latency, and the HBM rate of the
            streaming kernels (working set above the 256 MB MALL)
+  extensions  column weights of the unweighted block, the foreground mask
+           and appended frames warm-started from the previous solve
 Other workloads (`--workload`): config1, config3, config4 alone, frames
 (solve time against the number of frames, GPU vs oracle).
 
@@ -395,6 +397,108 @@ def run_config4(pool, steps, warmup, lanes=4, precisions=("fp32", "mixed"), one_
             "working_set_bytes": ws_bytes, "variants": out}
 
 
+def run_extensions(steps, warmup):
+    """Sub-object: the solve's extensions on the 19200 x 200 workload (FP32).
+      colweights  eq. (6) with one weight per column of the unweighted block
+                  (w2 = 10**U(log10 0.5, log10 2)): solves/s and the objective
+                  against the oracle's column-scaled Algorithm 1 converged
+      foreground  the mask |A - X| > tau (tau 0.25) of the returned iterate,
+                  written by the output pass: its cost per solve and its
+                  counts against the generator's foreground support
+      appended    frames arriving 20 at a time (n = 100, 120, .., 200): each
+                  solve warm-started from the previous X1 and V, against
+                  cold solves from the A1 start (ms and sweeps per append;
+                  objective of the last against the oracle)"""
+    import numpy as np
+    import torch
+    from gen import video
+    from oracle import foreground as FG
+    from oracle import swlr as O
+    from paper_1703_06303_amd import wlra
+    out = {}
+    inst = video.config2()
+    k, r = inst.k, inst.r
+    inputs = device_inputs(inst)
+    A, W1 = inputs("fp32")
+    # column weights
+    w2 = video.column_weights(inst.n - k, seed=6).astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    fs = O.swlr_colweights(inst.A, inst.W1, w2, k, r, tol=1e-13, max_sweeps=500,
+                           X1_0=inst.X1_0).F[-1]
+    log(f"# extensions: column-weight F* in {time.perf_counter() - t0:.1f} s")
+    W2 = torch.tensor(w2, dtype=torch.float32, device="cuda")
+    with wlra.Solver("fp32") as s:
+        def cw(i):
+            return s.solve(A, k, r, W1=W1, tol=1e-7, init="random", seed=1000 + i, W2=W2)[2]
+        for i in range(warmup):
+            cw(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [cw(i) for i in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    relF = max(abs(x["objective"] - fs) / fs for x in res)
+    out["colweights"] = {"solves_per_s": steps / dt, "ms_per_solve": 1e3 * dt / steps,
+                         "sweeps_per_solve": float(np.mean([x["sweeps"] for x in res])),
+                         "max_rel_objective_err": relF,
+                         "solves_meeting_1e-6": f"{sum(abs(x['objective'] - fs) / fs <= 1e-6 for x in res)}/{steps}"}
+    # foreground mask
+    with wlra.Solver("fp32", profile=True) as s:
+        for i in range(warmup + steps):
+            if i == warmup:
+                s.profile(reset=True)
+            _, _, rs = s.solve(A, k, r, W1=W1, tol=1e-7, init="random", seed=2000 + i,
+                               mask_tau=0.25)
+        torch.cuda.synchronize()
+        prof = s.profile()
+    mask = rs["mask"].cpu().numpy()
+    tp, fp, fn, tn = FG.mask_counts(mask, inst.fg)
+    out["foreground"] = {"tau": 0.25, "output_pass_ms": prof.get("x2_out", (0, 0.0))[1] / steps,
+                         "TP": tp, "FP": fp, "FN": fn, "TN": tn,
+                         "precision": tp / max(tp + fp, 1), "recall": tp / max(tp + fn, 1)}
+    # appended frames
+    ns = list(range(100, inst.n + 1, 20))
+    Af = torch.tensor(inst.A, dtype=torch.float32, device="cuda")
+    W1d = W1
+    warm, cold = [], []
+    with wlra.Solver("fp32") as s:
+        for rep in range(2):   # the first pass warms up
+            X1p, Vp = None, None
+            for n_t in ns:
+                At = wlra.colmajor(Af[:, :n_t])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if X1p is None:
+                    X1, _, rw = s.solve(At, k, r, W1=W1d, tol=1e-7, init="a1", want_factors=True)
+                else:
+                    X1, _, rw = s.solve(At, k, r, W1=W1d, tol=1e-7, init="given", X1_init=X1p,
+                                        V_init=Vp, want_factors=True)
+                torch.cuda.synchronize()
+                tw = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                _, _, rc = s.solve(At, k, r, W1=W1d, tol=1e-7, init="a1")
+                torch.cuda.synchronize()
+                tc = time.perf_counter() - t0
+                X1p, Vp = X1, rw["factors"][2]
+                if rep == 1:
+                    warm.append((n_t, 1e3 * tw, rw["sweeps"], rw["objective"]))
+                    cold.append((n_t, 1e3 * tc, rc["sweeps"], rc["objective"]))
+    fl = O.swlr(inst.A, inst.W1, k, r, tol=1e-13, max_sweeps=500, X1_0=inst.X1_0).F[-1]
+    out["appended"] = {
+        "frames": ns,
+        "warm_ms": [w[1] for w in warm], "warm_sweeps": [w[2] for w in warm],
+        "cold_a1_ms": [c[1] for c in cold], "cold_a1_sweeps": [c[2] for c in cold],
+        "warm_ms_per_append": float(np.mean([w[1] for w in warm[1:]])),
+        "cold_ms_per_append": float(np.mean([c[1] for c in cold[1:]])),
+        "last_rel_objective_err_warm": abs(warm[-1][3] - fl) / fl,
+        "last_rel_objective_err_cold": abs(cold[-1][3] - fl) / fl}
+    log(f"# extensions: colweights {out['colweights']['solves_per_s']:.1f} solves/s; mask "
+        f"precision {out['foreground']['precision']:.3f} recall {out['foreground']['recall']:.3f}; "
+        f"appended {out['appended']['warm_ms_per_append']:.2f} vs "
+        f"{out['appended']['cold_ms_per_append']:.2f} ms")
+    return out
+
+
 def run_frames(args):
     """Solve time against the number of frames n at a fixed frame size
     (the analogue of the paper's Fig. 3(c)): GPU FP32 vs the FP64 oracle on
@@ -585,6 +689,7 @@ def main():
     if args.workload == "config2" and not args.no_extra:
         line["config3"] = run_config3(5, 1)
         line["config4"] = run_config4(pool, 2, 1)
+        line["extensions"] = run_extensions(10, 2)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, args.cpu_solves, 1e-7)
     torch.cuda.synchronize()
