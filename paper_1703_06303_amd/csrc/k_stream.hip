@@ -390,6 +390,242 @@ __global__ __launch_bounds__(UPD_T) void k_update(
 }
 
 // ---------------------------------------------------------------------------
+// Row update for float storage, tiled: E = [A1 A2 X1] [-S; Z; T] for 128
+// rows per workgroup (four wavefronts of 32 rows, each two 16-row MFMA tiles
+// by KP output columns).  The inner index runs in chunks of 32 columns: the
+// chunk of A (128 rows x 32 columns) is read with 16-byte loads (a column's
+// 128 rows are 512 contiguous bytes, so every load of a wavefront covers two
+// whole columns), staged in LDS, and the next chunk's loads are issued before
+// the current chunk is multiplied.
+//  * float segments (A1, A2 in float, X1): LDS [column][row], products on
+//    v_mfma_f32_16x16x4f32, the 32 rows of B = [-S; Z; T] of the chunk in
+//    LDS too;
+//  * the BF16 copy of A2 (mixed precision): the chunk is transposed into LDS
+//    [row][column] as it is stored, and multiplied on v_mfma_f32_16x16x32_bf16
+//    against Z split into two BF16 terms, Z ~ Zh + Zl (|Z - Zh - Zl| <=
+//    2^-17 |Z|), so the product of the BF16 data with Z loses no more than
+//    the FP32 products do; Zh and Zl are stored [column][row] with rows
+//    padded to n2p (a multiple of 32, zero rows and columns beyond).
+// The epilogue is the one of k_update: for a constant W1 the panel already
+// holds K^-1 and X1' = A1 + E is written with the objective and change
+// partials (one pair per 64 rows); otherwise E goes to the per-row solve.
+// Requires m % 8 == 0, lda % 4 == 0 and 16-byte aligned A, X1 (checked by the
+// launcher).
+#define UT_T 256
+#define UT_R 128
+#define UT_KC 32
+#define UT_SLD (UT_R + 16)  // floats per staged column of A
+#define UT_BKS 40           // bf16 per staged row of the BF16 chunk (32 + pad)
+typedef __bf16 ut_bf8 __attribute__((ext_vector_type(8)));
+typedef float ut_f4 __attribute__((ext_vector_type(4)));
+
+template <int KMAX, bool CONSTW, bool A2BF>
+__global__ __launch_bounds__(UT_T) void k_update_t(
+    int64_t m, int k, int n, const float *__restrict__ A, int64_t lda,
+    const bf16s *__restrict__ A2b, int64_t ldb, const float *__restrict__ W1, int64_t ldw,
+    float wc, const float *__restrict__ X1o, float *__restrict__ X1n,
+    const float *__restrict__ Gt, const float *__restrict__ Tt, const bf16s *__restrict__ Zh,
+    const bf16s *__restrict__ Zl, int n2p, double *__restrict__ part, float *__restrict__ Eb,
+    const SmallState *__restrict__ st) {
+  if (st->done) return;
+  constexpr int KP = upd_kp<KMAX>(), NT = KP / 16, KPL = KP + 16;
+  constexpr int SM1 = UT_KC * UT_SLD + UT_KC * KPL, SM2 = UT_R * (KP + 1);
+  __shared__ __align__(16) float smem[SM1 > SM2 ? SM1 : SM2];
+  float *sA = smem;                       // [32][UT_SLD] float chunk
+  float *sB = smem + UT_KC * UT_SLD;      // [32][KPL] rows of B
+  bf16s *sAb = reinterpret_cast<bf16s *>(smem);  // [128][UT_BKS] BF16 chunk
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * UT_R;
+  const int n2 = n - k;
+  ut_f4 acc[2][NT];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = ut_f4{0.f, 0.f, 0.f, 0.f};
+
+  // float segment: nj columns of src (ld), rows of B from brow0 (k per row)
+  auto fseg = [&](const float *src, int64_t ld, int nj, const float *brow0) {
+    if (nj <= 0) return;
+    // thread t stages rows 4 (t % 32) .. + 3 of columns t / 32 + 8 p
+    const int q = t & 31, cq = t >> 5;
+    const int64_t g = min(r0 / 4 + q, m / 4 - 1);  // clamped 4-row group
+    float4 ra[4];
+    float rb[UT_KC * KP / UT_T];
+#define UT_FLOAD(J0)                                                                \
+  do {                                                                              \
+    _Pragma("unroll") for (int p = 0; p < 4; ++p) {                                 \
+      const int jc = min((J0) + cq + 8 * p, nj - 1);                                \
+      ra[p] = *reinterpret_cast<const float4 *>(src + 4 * g + (int64_t)jc * ld);    \
+    }                                                                               \
+    _Pragma("unroll") for (int u = 0; u < UT_KC * KP / UT_T; ++u) {                 \
+      const int e = t + u * UT_T, jr = e / KP, c = e - jr * KP;                     \
+      const int jj = min((J0) + jr, nj - 1);                                        \
+      const float v = brow0[(int64_t)jj * k + min(c, k - 1)];                       \
+      rb[u] = ((J0) + jr < nj && c < k) ? v : 0.f;                                  \
+    }                                                                               \
+  } while (0)
+    UT_FLOAD(0);
+    for (int j0 = 0; j0 < nj; j0 += UT_KC) {
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        *reinterpret_cast<float4 *>(sA + (cq + 8 * p) * UT_SLD + 4 * q) = ra[p];
+#pragma unroll
+      for (int u = 0; u < UT_KC * KP / UT_T; ++u) {
+        const int e = t + u * UT_T, jr = e / KP, c = e - jr * KP;
+        sB[jr * KPL + c] = rb[u];
+      }
+      __syncthreads();
+      if (j0 + UT_KC < nj) UT_FLOAD(j0 + UT_KC);
+      const int nk = min(UT_KC, nj - j0);
+#pragma unroll
+      for (int kk = 0; kk < UT_KC / 4; ++kk) {
+        if (4 * kk < nk) {
+          const float a0 = sA[(4 * kk + lg) * UT_SLD + 32 * w + li];
+          const float a1 = sA[(4 * kk + lg) * UT_SLD + 32 * w + 16 + li];
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) {
+            const float b = sB[(4 * kk + lg) * KPL + 16 * ct + li];
+            acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][ct], 0, 0, 0);
+            acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][ct], 0, 0, 0);
+          }
+        }
+      }
+    }
+  };
+  // BF16 segment: the n2 columns of A2b against Zh + Zl
+  auto bseg = [&]() {
+    if (n2 <= 0) return;
+    // thread t stages rows 8 (t % 16) .. + 7 of columns t / 16 + 16 p
+    const int q = t & 15, cq = t >> 4;
+    const int64_t g = min(r0 / 8 + q, m / 8 - 1);  // clamped 8-row group
+    uint4 ra[2];
+#define UT_BLOAD(J0)                                                                \
+  do {                                                                              \
+    _Pragma("unroll") for (int p = 0; p < 2; ++p) {                                 \
+      const int jc = min((J0) + cq + 16 * p, n2 - 1);                               \
+      ra[p] = *reinterpret_cast<const uint4 *>(A2b + 8 * g + (int64_t)jc * ldb);    \
+    }                                                                               \
+  } while (0)
+    UT_BLOAD(0);
+    for (int j0 = 0; j0 < n2; j0 += UT_KC) {
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int col = cq + 16 * p;
+        const uint32_t w0 = ra[p].x, w1 = ra[p].y, w2 = ra[p].z, w3 = ra[p].w;
+        bf16s *d = sAb + (8 * q) * UT_BKS + col;
+        d[0 * UT_BKS] = bf16s{(uint16_t)(w0 & 0xffffu)};
+        d[1 * UT_BKS] = bf16s{(uint16_t)(w0 >> 16)};
+        d[2 * UT_BKS] = bf16s{(uint16_t)(w1 & 0xffffu)};
+        d[3 * UT_BKS] = bf16s{(uint16_t)(w1 >> 16)};
+        d[4 * UT_BKS] = bf16s{(uint16_t)(w2 & 0xffffu)};
+        d[5 * UT_BKS] = bf16s{(uint16_t)(w2 >> 16)};
+        d[6 * UT_BKS] = bf16s{(uint16_t)(w3 & 0xffffu)};
+        d[7 * UT_BKS] = bf16s{(uint16_t)(w3 >> 16)};
+      }
+      __syncthreads();
+      if (j0 + UT_KC < n2) UT_BLOAD(j0 + UT_KC);
+      // columns j0 + 32 .. of the chunk past n2 meet zero rows of Zh, Zl
+      const ut_bf8 a0 = *reinterpret_cast<const ut_bf8 *>(sAb + (32 * w + li) * UT_BKS + 8 * lg);
+      const ut_bf8 a1 =
+          *reinterpret_cast<const ut_bf8 *>(sAb + (32 * w + 16 + li) * UT_BKS + 8 * lg);
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        const int64_t zo = (int64_t)(16 * ct + li) * n2p + j0 + 8 * lg;
+        const ut_bf8 bh = *reinterpret_cast<const ut_bf8 *>(Zh + zo);
+        const ut_bf8 bl = *reinterpret_cast<const ut_bf8 *>(Zl + zo);
+        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bh, acc[0][ct], 0, 0, 0);
+        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bh, acc[1][ct], 0, 0, 0);
+        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bl, acc[0][ct], 0, 0, 0);
+        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bl, acc[1][ct], 0, 0, 0);
+      }
+    }
+  };
+  fseg(A, lda, k, Gt);
+  if constexpr (A2BF)
+    bseg();
+  else
+    fseg(A + (int64_t)k * lda, lda, n2, Gt + (int64_t)k * k);
+  fseg(X1o, m, k, Tt);
+
+  // E tile to LDS (rows of the workgroup x KP), then one row per thread
+  __syncthreads();
+  float *sE = smem;  // [128][KP + 1]
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        sE[(32 * w + 16 * rt + 4 * lg + v) * (KP + 1) + 16 * ct + li] = acc[rt][ct][v];
+  __syncthreads();
+  if (t >= UT_R) return;
+  const int64_t i = r0 + t;
+  const bool act = i < m;
+  const float *er = sE + t * (KP + 1);
+  if (!CONSTW) {
+    if (act)
+      for (int c = 0; c < k; ++c) Eb[i + (int64_t)c * m] = er[c];
+    return;
+  }
+  // eight columns at a time: their reads in flight together, few registers
+  double f1 = 0.0, dx = 0.0;
+  const int64_t ic = act ? i : (m - 1);
+  for (int c0 = 0; c0 < k; c0 += 8) {
+    float av[8], xo[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int cc = min(c0 + u, k - 1);
+      av[u] = A[ic + (int64_t)cc * lda];
+      xo[u] = X1o[ic + (int64_t)cc * m];
+    }
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < k) {
+          const float x = av[u] + er[c0 + u];
+          X1n[i + (int64_t)(c0 + u) * m] = x;
+          const double d = (double)av[u] - (double)x;
+          f1 += d * d * (double)wc * (double)wc;
+          const double dd = (double)x - (double)xo[u];
+          dx += dd * dd;
+        }
+    }
+  }
+  f1 = wave_sum(f1);
+  dx = wave_sum(dx);
+  // one (f1, dx) pair per 64 rows, as k_update writes them
+  const int64_t pidx = 2 * (int64_t)blockIdx.x + (t >> 6);
+  if (lane == 0 && pidx * 64 < m) {
+    part[2 * pidx] = f1;
+    part[2 * pidx + 1] = dx;
+  }
+}
+
+#undef UT_FLOAD
+#undef UT_BLOAD
+
+// Zh + Zl ~ Z (rows k .. n - 1 of the panel Gt = [-S; Z], k per row) in BF16,
+// stored [column c][row j] with rows padded to n2p and columns to kp (zeros).
+__global__ __launch_bounds__(256) void k_panel_bf16(int n2, int k, int kp, int n2p,
+                                                     const float *__restrict__ Gt,
+                                                     bf16s *__restrict__ Zh,
+                                                     bf16s *__restrict__ Zl,
+                                                     const SmallState *__restrict__ st) {
+  if (st->done) return;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < kp * n2p; e += gridDim.x * 256) {
+    const int c = e / n2p, j = e - c * n2p;
+    const float z = (c < k && j < n2) ? Gt[(int64_t)(k + j) * k + c] : 0.f;
+    const bf16s h = bf16_rne(z);
+    Zh[e] = h;
+    Zl[e] = bf16_rne(z - to_f(h));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Per-row solve of the X1 update: x1_i' = a1_i + e_i (diag(w_i^2) + S)^-1,
 // one row per lane.  Register version: the lower Cholesky factor of the
 // row's k x k matrix lives in registers (all indices compile-time after
@@ -1031,9 +1267,38 @@ static void launch_update_kernel(hipStream_t s, const UpdateArgs<T> &a, const TA
                      a.Tt, a.St, a.part, a.Eb, pl.grows, a.st);
 }
 
+// The tiled kernel's requirements: 8-row groups, 16-byte aligned columns.
+template <typename T>
+static bool update_tiled_ok(const UpdateArgs<T> &a) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    auto al = [](const void *p) { return ((uintptr_t)p & 15u) == 0; };
+    if (a.m % 8 != 0 || a.lda % 4 != 0 || !al(a.A) || !al(a.X1o)) return false;
+    if (a.A2b != nullptr && (a.ldb % 8 != 0 || !al(a.A2b) || !a.Zh || !a.Zl || a.n2p % 32 != 0))
+      return false;
+    return true;
+  }
+}
+
+template <int KMAX, bool CONSTW, bool A2BF>
+static void launch_update_tiled(hipStream_t s, const UpdateArgs<float> &a) {
+  const unsigned grid = (unsigned)((a.m + UT_R - 1) / UT_R);
+  hipLaunchKernelGGL((k_update_t<KMAX, CONSTW, A2BF>), dim3(grid), dim3(UT_T), 0, s, a.m, a.k,
+                     a.n, a.A, a.lda, a.A2b, a.ldb, a.W1, a.ldw, a.wc, a.X1o, a.X1n, a.Gt, a.Tt,
+                     a.Zh, a.Zl, a.n2p, a.part, a.Eb, a.st);
+}
+
 template <typename T, int KMAX, bool CONSTW>
 static void launch_update_a2(hipStream_t s, const UpdateArgs<T> &a, const UpdatePlan &pl) {
   if constexpr (std::is_same<T, float>::value) {
+    if (update_tiled_ok(a)) {
+      if (a.A2b != nullptr)
+        launch_update_tiled<KMAX, CONSTW, true>(s, a);
+      else
+        launch_update_tiled<KMAX, CONSTW, false>(s, a);
+      return;
+    }
     if (a.A2b != nullptr) {
       launch_update_kernel<T, KMAX, CONSTW, bf16s>(s, a, a.A2b, a.ldb, pl);
       return;
@@ -1077,6 +1342,15 @@ static void launch_update_k(hipStream_t s, const UpdateArgs<T> &a) {
     hipLaunchKernelGGL((k_rowsolve_lds<T, KMAX>), dim3(grid), dim3(64), shm, s, a.m, a.k, a.A,
                        a.lda, a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, pl.nl, a.st, a.flags);
   }
+}
+
+int update_panel_kp(int k) { return ((k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64) + 15) / 16 * 16; }
+
+void launch_panel_bf16(hipStream_t s, int n2, int k, int n2p, const float *Gt, bf16s *Zh,
+                       bf16s *Zl, const SmallState *st) {
+  const int kp = update_panel_kp(k);
+  const int grid = std::max(1, std::min(256, (kp * n2p + 255) / 256));
+  hipLaunchKernelGGL(k_panel_bf16, dim3(grid), dim3(256), 0, s, n2, k, kp, n2p, Gt, Zh, Zl, st);
 }
 
 template <typename T>

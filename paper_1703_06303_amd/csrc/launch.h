@@ -24,6 +24,8 @@ struct UpdateArgs {
   T *Eb;                   // m x k right-hand sides of the per-row solve
   const bf16s *A2b;        // mixed precision: A2 in BF16 (ld ldb); NULL: A2 = A + k lda
   int64_t ldb;
+  const bf16s *Zh, *Zl;    // with A2b: Z ~ Zh + Zl in BF16, [column][row], rows padded to n2p
+  int n2p;
   double *part;
   const SmallState *st;
   int *flags;
@@ -52,6 +54,12 @@ struct UpdatePlan {
 };
 template <typename T>
 UpdatePlan update_plan(int k, bool constw);
+// Output columns of the row update's tiles for k (16, 32 or 64): the column
+// count of the BF16 panel Zh, Zl.
+int update_panel_kp(int k);
+// Zh + Zl ~ Z from the panel Gt = [-S; Z] (float), for the BF16 row update.
+void launch_panel_bf16(hipStream_t s, int n2, int k, int n2p, const float *Gt, bf16s *Zh,
+                       bf16s *Zl, const SmallState *st);
 template <typename T>
 void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
                const T *X1, const T *Zt, const T *Vr, T *X2, int64_t ldx2, const T *w2,

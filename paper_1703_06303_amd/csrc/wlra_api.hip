@@ -186,6 +186,7 @@ struct Ptrs {
   double *Zd[2], *Vd[2];
   void *Gt, *Tt, *St, *Vr, *Zx, *Eb;
   bf16s *Ab;  // mixed precision: BF16 copy of A2 (m x n2), else NULL
+  bf16s *Zh, *Zl;  // mixed precision: the row update's panel Z in two BF16 terms
   void *As;   // column weights: [A1, A2 diag(W2)] (m x n), else NULL
   double *Hb, *Rh;  // change pass: aligned basis [V_p dV Z_p dZ] and its Gram
   double *epart;    // multi-workgroup eigen kernel: partial Grams
@@ -236,6 +237,9 @@ Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mi
   return z;
 }
 
+// Rows of the BF16 panel: n2 padded to the row update's chunk of 32.
+inline int64_t panel_rows(int64_t n2) { return (std::max<int64_t>(n2, 1) + 31) / 32 * 32; }
+
 // Device workspace of one solve, in allocation order (256-byte aligned).
 Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
   Layout L{};
@@ -283,6 +287,8 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.st, sizeof(SmallState)},
       {(void **)&p.flags, 64},
       {(void **)&p.Ab, z.mixed ? (size_t)(m * n2) * sizeof(bf16s) : 0},
+      {(void **)&p.Zh, z.mixed ? (size_t)update_panel_kp((int)kk) * panel_rows(n2) * sizeof(bf16s) : 0},
+      {(void **)&p.Zl, z.mixed ? (size_t)update_panel_kp((int)kk) * panel_rows(n2) * sizeof(bf16s) : 0},
       {&p.As, z.colw ? (size_t)(m * z.n) * z.elt : 0},
       {(void **)&p.Hb, (size_t)(n2 * (2 * l + 2 * k)) * d},
       {(void **)&p.Rh, (size_t)((2 * l + 2 * k) * (2 * l + 2 * k)) * d},
@@ -541,6 +547,12 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
       PROF(h, KK_EIG, launch_eig(s, sa));
     }
     PROF(h, KK_POST, launch_post<T>(s, sa, so));
+    if constexpr (std::is_same<T, float>::value) {
+      // BF16 phase: Z ~ Zh + Zl for the row update's BF16 products
+      if (on_bf16 && k > 0)
+        PROF(h, KK_POST, launch_panel_bf16(s, (int)n2, (int)k, (int)panel_rows(n2), so.Gt,
+                                           P.Zh, P.Zl, P.st));
+    }
     if (p > 0 && !reeval) {
       PROF(h, KK_CHGQR,
            launch_chgprep(s, (int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1],
@@ -593,6 +605,9 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
     ua.Eb = static_cast<T *>(P.Eb);
     ua.A2b = on_bf16 ? P.Ab : nullptr;
     ua.ldb = m;
+    ua.Zh = on_bf16 ? P.Zh : nullptr;
+    ua.Zl = on_bf16 ? P.Zl : nullptr;
+    ua.n2p = (int)panel_rows(n2);
     ua.flags = P.flags;
     // reads A1, A2, X1_p (and W1), writes X1_{p+1}; the product
     // [A1 A2 X1] [-S; Z; T] and, for a matrix W1, the per-row SPD solves
