@@ -30,9 +30,10 @@ The default run also times, as sub-objects of the same line:
            (plain FP32, mixed, A1 + mixed), against the closed form
   config4  64 clips of uneven shape (m in {4800, 19200, 76800}, n in
            [100, 400], k in [5, 40], r = k + [2, 8], W1 log-uniform), one
-           wlra_solve_batched call per step on four lanes (FP32 and mixed):
-           solves/s, p50/p99 per-solve latency, and the HBM rate of the
-           streaming kernels (working set above the 256 MB MALL)
+           wlra_solve_batched call per step (FP32 and mixed, four streams):
+           solves/s, p50/p99 per-solve latency (from the batch's start to
+           each clip's result), and the HBM rate of the streaming kernels
+           (working set above the 256 MB MALL)
   extensions  column weights of the unweighted block, the foreground mask
            and appended frames warm-started from the previous solve
 Other workloads (`--workload`): config1, config3, config4 alone, frames
@@ -153,10 +154,11 @@ def train_learned(pool, args):
             log(f"# warm start: weights loaded from {args.learn_weights}")
         else:
             tr = [video.config5_seed(i) for i in range(args.learn_train)]
-            X, T, info, t_data = WS.build_dataset(s, pool, tr)
+            X, T, info, t_data = WS.build_dataset(s, pool, tr, log=lambda m_: log("# warm start: " + m_))
             log(f"# warm start: {len(tr)} training solves in {t_data:.1f} s")
             t0 = time.perf_counter()
-            params, hist = WS.train(s, X, T, 200, 25, epochs=args.learn_epochs, batch=128, lr=1e-3)
+            params, hist = WS.train(s, X, T, 200, 25, epochs=args.learn_epochs, batch=128, lr=1e-3,
+                                    log=(lambda m_: log("# warm start: " + m_)) if len(tr) > 4096 else None)
             t_train = time.perf_counter() - t0
             log(f"# warm start: {args.learn_epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3f} "
                 f"-> {hist[-1]:.3f}")
@@ -164,8 +166,14 @@ def train_learned(pool, args):
                            "epochs": args.learn_epochs, "train_s": t_train,
                            "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
                            "training_solves_converged": int(sum(x[1] == 0 for x in info))})
+            if args.save_weights:
+                os.makedirs(os.path.dirname(os.path.abspath(args.save_weights)), exist_ok=True)
+                params.detach().cpu().numpy().astype(np.float32).tofile(args.save_weights)
+                with open(args.save_weights + ".json", "w") as f:
+                    json.dump({k_: v for k_, v in report.items()}, f, indent=1)
+                log(f"# warm start: weights written to {args.save_weights}")
         ho = [video.config5_seed(i, heldout=True) for i in range(args.learn_heldout)]
-        ev = WS.evaluate(s, pool, params, ho)
+        ev = WS.evaluate(s, pool, params, ho, log=lambda m_: log("# warm start: " + m_))
     report["heldout_instances"] = len(ho)
     report["heldout"] = WS.summarize(ev)
     return params, report
@@ -345,7 +353,7 @@ def run_config4(pool, steps, warmup, lanes=4, precisions=("fp32", "mixed"), one_
         runs = [("fp32", 1)] + runs
     out = {}
     for prec, nl in runs:
-        name = f"{prec}_{nl}lane{'s' if nl > 1 else ''}"
+        name = f"{prec}_{nl}stream{'s' if nl > 1 else ''}"
         with wlra.Solver(prec) as solver:
             solver.set_batch_lanes(nl)
             for w in range(max(1, warmup)):
@@ -385,7 +393,7 @@ def run_config4(pool, steps, warmup, lanes=4, precisions=("fp32", "mixed"), one_
                      "sweeps_per_solve": float(sweeps.mean()),
                      "sweeps_per_s": float(sweeps.sum() / dt),
                      "solves_meeting_1e-6": f"{ok}/{nsolve}", "max_rel_objective_err": worst,
-                     "precision": prec, "lanes": nl, "streaming_hbm": hbm,
+                     "precision": prec, "streams": nl, "streaming_hbm": hbm,
                      "kernel_share": {k_: v[1] / tot for k_, v in
                                       sorted(prof.items(), key=lambda kv: -kv[1][1])[:6]}}
         log(f"# config4 {name}: {out[name]['solves_per_s']:.1f} solves/s, p50 "
@@ -555,7 +563,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="config2",
-                    choices=("config1", "config2", "config3", "config4", "frames"))
+                    choices=("config1", "config2", "config3", "config4", "frames", "learn"))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="config2 only: skip the config3 and config4 sub-objects")
@@ -564,12 +572,20 @@ def main():
                     help="training clips for the warm-start network (0: no learned start)")
     ap.add_argument("--learn-epochs", type=int, default=200)
     ap.add_argument("--learn-heldout", type=int, default=48)
-    ap.add_argument("--learn-weights", default="",
-                    help="raw float32 network weights to load instead of training")
+    ap.add_argument("--save-weights", default="",
+                    help="write the trained network's parameters (raw float32) here")
+    ap.add_argument("--learn-weights", default=None,
+                    help="raw float32 network weights to load instead of training (default: "
+                         "the committed weights trained on 20000 clips; the learn workload "
+                         "trains unless this is given)")
     ap.add_argument("--frames", type=int, nargs="+", default=[50, 100, 200, 300, 400, 500, 600])
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.learn_weights is None:
+        args.learn_weights = ("" if args.workload == "learn" else
+                              os.path.join(ROOT, "paper_1703_06303_amd", "weights",
+                                           "warmstart_config2.f32"))
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -579,7 +595,7 @@ def main():
     pool = None
     wants_pool = (args.calib_copy == 0 and
                   ((args.workload == "config2" and (args.learn_train > 0 or not args.no_extra))
-                   or args.workload == "config4"))
+                   or args.workload in ("config4", "learn")))
     if wants_pool:
         from paper_1703_06303_amd import warmstart as WS
         pool = WS.make_pool(12)
@@ -602,16 +618,23 @@ def main():
     if args.workload == "frames":
         run_frames(args)
         return
+    if args.workload == "learn":
+        # train (or load) the warm-start network and compare the random, A1
+        # and learned starts on the held-out clips; no schedule timing
+        _, rep = train_learned(pool, args)
+        print(json.dumps({"metric": "learned warm start: held-out sweeps and solve time",
+                          "learned_start": rep}), flush=True)
+        return
     if args.workload == "config4":
         sub = run_config4(pool, args.steps, args.warmup, one_lane=True)
-        head = sub["variants"]["mixed_4lanes"]
+        head = sub["variants"]["mixed_4streams"]
         line = {"metric": METRIC, "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
                 "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["batch_ms"],
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                 "dtype": "bf16+f32", "data": "synthetic",
                 "config": {"workload": sub["workload"], "instances": sub["instances"],
-                           "variant": "mixed_4lanes"},
-                "vs_plain": head["solves_per_s"] / sub["variants"]["fp32_4lanes"]["solves_per_s"],
+                           "variant": "mixed_4streams"},
+                "vs_plain": head["solves_per_s"] / sub["variants"]["fp32_4streams"]["solves_per_s"],
                 "variants": sub["variants"]}
         print(json.dumps(line), flush=True)
         return

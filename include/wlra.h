@@ -235,16 +235,24 @@ int wlra_solve(wlra_handle h, const wlra_problem *prob, wlra_result *res);
 int wlra_solve_noalloc(wlra_handle h, const wlra_problem *prob, wlra_result *res);
 
 /* Solve `count` independent instances of problem (5) (uneven m, n, k, r
- * allowed; each one as wlra_solve would).  The instances run concurrently on
- * the handle's batch lanes: each lane is an internal stream with its own
- * workspace, driven by its own host thread, and takes the largest remaining
- * instance (by m * n) whenever it is free.  The lanes start after the work
- * already queued on the handle's stream, and that stream waits for all of
- * them before later work.  Blocks until every result is on the host.
+ * allowed; each one as wlra_solve would, with the one-workgroup eigen
+ * kernel for every n - k).  The instances advance in lockstep, one sweep per
+ * round: the single-workgroup small steps of every active instance (the
+ * coefficients, M, the eigen step, the post step, the change pass's basis
+ * and the stopping decision) run as one launch each with one workgroup per
+ * instance, the streaming passes of each instance go to the batch streams
+ * (the handle's stream and wlra_set_batch_lanes - 1 more, round robin), and
+ * one read-back of all sweep states per round decides which instances go
+ * on.  The batch starts after the work already queued on the handle's
+ * stream, and that stream waits for all of it before later work.  Blocks
+ * until every result is on the host.  The batch workspace (the sum of the
+ * instances' workspaces) is grown before the first kernel of the call.
  * Returns WLRA_E_ARG if any instance fails the argument checks (nothing is
- * run), a negative status if the lanes cannot be set up, else 0; the status
- * of each instance is in res[i].status (res[i].ms is its own time on its
- * lane).  Instances must not share output buffers. */
+ * run), a negative status if the batch cannot be set up, else 0; the status
+ * of each instance is in res[i].status, and res[i].ms is the time from the
+ * start of the batch to the round in which that instance's last sweep was
+ * decided (its outputs are written at the end of the batch).  Instances
+ * must not share output buffers. */
 int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs,
                        wlra_result *res);
 
@@ -256,17 +264,26 @@ enum wlra_option {
                                60)                                           */
   WLRA_OPT_EIG_ONE_WG = 2   /* 1: the one-workgroup eigen kernel for every
                                n - k (default 0: a cooperative multi-workgroup
-                               kernel for n - k >= 256 in wlra_solve; the
-                               lanes of wlra_solve_batched always use the
-                               one-workgroup kernel)                          */
+                               kernel for n - k >= 256 in wlra_solve;
+                               wlra_solve_batched always uses the
+                               one-workgroup kernel)                          */,
+  WLRA_OPT_AUTOTUNE = 3     /* 1 (default): the first solve of each shape
+                               (m, n - k, k, precision) on the handle times
+                               the tall-skinny products X1^T A2 and A2^T A2 at
+                               4 workgroup counts (512 .. 4096) on its own
+                               operands and keeps the fastest for later
+                               solves of that shape (the row sums then run
+                               in that split's order: results are
+                               reproducible per handle); 0: the default
+                               count (2048)                                  */
 };
 
 /* Set a handle option; WLRA_E_ARG for an unknown option or a value out of
  * range. */
 int wlra_set_option(wlra_handle h, int32_t option, int64_t value);
 
-/* Number of batch lanes used by wlra_solve_batched (1..16, default 4; 1 runs
- * the instances one after another on the handle's stream). */
+/* Number of streams used by wlra_solve_batched for the instances' streaming
+ * passes (1..16, default 4; 1: the handle's stream only). */
 int wlra_set_batch_lanes(wlra_handle h, int32_t lanes);
 
 int wlra_destroy(wlra_handle h);

@@ -601,7 +601,7 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
   }
 }
 
-__global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
+__device__ __forceinline__ void eig_kernel_body(const SmallArgs &a) {
   if (a.st->done) return;
   __shared__ EigLDS s;
   const int n2 = a.n2, b = a.b, t = threadIdx.x;
@@ -625,6 +625,15 @@ __global__ __launch_bounds__(ET) void k_eig(SmallArgs a) {
     eig_body<false>(s, a, cx, Blk<false>{a.Y}, Blk<false>{a.F0}, Blk<false>{a.F1},
                     Blk<false>{a.F2});
   }
+}
+__global__ __launch_bounds__(ET) void k_eig(SmallArgs a) { eig_kernel_body(a); }
+// one workgroup per instance of a batch
+__global__ __launch_bounds__(ET) void k_eig_b(const SmallArgs *__restrict__ av) {
+  eig_kernel_body(av[blockIdx.x]);
+}
+
+void launch_eig_b(hipStream_t s, int count, const SmallArgs *av) {
+  if (count > 0) hipLaunchKernelGGL(k_eig_b, dim3(count), dim3(ET), 0, s, av);
 }
 
 // Start block of the first eigen step from a given V (v0 x l, ld ldv):

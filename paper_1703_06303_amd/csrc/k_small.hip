@@ -44,7 +44,7 @@ __global__ __launch_bounds__(1024) void k_gastats(int n2, const double *__restri
 // column held in registers (k <= KMAX) and R read from LDS (every thread
 // reads the same entry at once).
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
+__device__ __forceinline__ void coef_body(const SmallArgs &a) {
   SmallState *st = a.st;
   if (st->done) return;
   __shared__ double sR[64 * 64];
@@ -174,12 +174,19 @@ __global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
     st->trG1 = tr;
   }
 }
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_coef(SmallArgs a) { coef_body<KMAX>(a); }
+// one workgroup per instance of a batch (blockIdx.x = instance)
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_coef_b(const SmallArgs *__restrict__ av) {
+  coef_body<KMAX>(av[blockIdx.x]);
+}
 
 // -----------------------------------------------------------------------------
 // M in the fragment-major layout of the eigen step (padding entries zero).
-__global__ __launch_bounds__(256) void k_formM(int n2, int k, const double *__restrict__ GA,
-                                               const double *__restrict__ B,
-                                               double *__restrict__ M, const SmallState *st) {
+__device__ __forceinline__ void formM_body(int n2, int k, const double *__restrict__ GA,
+                                           const double *__restrict__ B, double *__restrict__ M,
+                                           const SmallState *st) {
   if (st->done) return;
   const int64_t total = mf_size(n2);
   for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
@@ -195,6 +202,16 @@ __global__ __launch_bounds__(256) void k_formM(int n2, int k, const double *__re
     }
     M[f] = v;
   }
+}
+__global__ __launch_bounds__(256) void k_formM(int n2, int k, const double *__restrict__ GA,
+                                               const double *__restrict__ B,
+                                               double *__restrict__ M, const SmallState *st) {
+  formM_body(n2, k, GA, B, M, st);
+}
+// batch: blockIdx.y = instance
+__global__ __launch_bounds__(256) void k_formM_b(const SmallArgs *__restrict__ av) {
+  const SmallArgs &a = av[blockIdx.y];
+  formM_body(a.n2, a.k, a.GA, a.B, a.M, a.st);
 }
 
 // -----------------------------------------------------------------------------
@@ -233,7 +250,7 @@ __device__ int small_chol64(double *K, int k, int *fail) {
 
 #define POST_CH 7680
 template <typename T>
-__global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
+__device__ __forceinline__ void post_body(const SmallArgs &a, const SmallOut<T> &o) {
   SmallState *st = a.st;
   if (st->done) return;
   __shared__ double sC[POST_CH];     // C chunk, k x cw (ld k)
@@ -395,6 +412,13 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
       st->gap = sqrt(fmax(a.theta[l - 1], 0.0)) - sqrt(fmax(a.theta[l], 0.0));
   }
 }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) { post_body<T>(a, o); }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_post_b(const SmallArgs *__restrict__ av,
+                                                 const SmallOut<T> *__restrict__ ov) {
+  post_body<T>(av[blockIdx.x], ov[blockIdx.x]);
+}
 
 // The n2-row part of the small step, one workgroup per PZ_R rows j: the
 // row-major copy of V, Z = (I - V V^T) C^T = C^T - V (CV)^T (kept in double
@@ -403,7 +427,7 @@ __global__ __launch_bounds__(1024) void k_post(SmallArgs a, SmallOut<T> o) {
 // K^-1 are staged in LDS; every product has k or l terms.
 #define PZ_R 16
 template <typename T>
-__global__ __launch_bounds__(256) void k_postz(SmallArgs a, SmallOut<T> o) {
+__device__ __forceinline__ void postz_body(const SmallArgs &a, const SmallOut<T> &o, int bx) {
   SmallState *st = a.st;
   if (st->done) return;
   __shared__ double sCV[64 * 32];
@@ -411,7 +435,7 @@ __global__ __launch_bounds__(256) void k_postz(SmallArgs a, SmallOut<T> o) {
   __shared__ double sVr[PZ_R * 32];
   __shared__ double sZ[PZ_R * 65];
   const int k = a.k, n2 = a.n2, l = a.l, t = threadIdx.x;
-  const int j0 = blockIdx.x * PZ_R, nr = min(PZ_R, n2 - j0);
+  const int j0 = bx * PZ_R, nr = min(PZ_R, n2 - j0);
   const double *CV = a.scratch;
   const double *Ki = a.scratch + 64 * 32 + 2 * 64 * 64;
   const bool constw = a.wconst > 0;
@@ -446,13 +470,25 @@ __global__ __launch_bounds__(256) void k_postz(SmallArgs a, SmallOut<T> o) {
     o.Gt[(int64_t)k * k + (int64_t)j * k + c] = (T)v;
   }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_postz(SmallArgs a, SmallOut<T> o) {
+  postz_body<T>(a, o, blockIdx.x);
+}
+// batch: blockIdx.y = instance; blocks past an instance's n2 rows exit
+template <typename T>
+__global__ __launch_bounds__(256) void k_postz_b(const SmallArgs *__restrict__ av,
+                                                 const SmallOut<T> *__restrict__ ov) {
+  const SmallArgs &a = av[blockIdx.y];
+  if ((int)blockIdx.x * PZ_R >= a.n2) return;
+  postz_body<T>(a, ov[blockIdx.y], blockIdx.x);
+}
 
 // Error_p and the stopping rule of Section 4.1:
 //   Error_p = ||X_p - X_{p-1}||_F,  stop when Error_p < tol or
 //   Error_p / ||X_{p-1}||_F < tol, or when p = max_sweeps.
 // ||X1_p - X1_{p-1}||^2 comes from the row update (dx1), ||X2_p - X2_{p-1}||^2
 // from the row pass k_change_q (partials in chg_part).
-__global__ __launch_bounds__(256) void k_decide(SmallArgs a) {
+__device__ __forceinline__ void decide_body(const SmallArgs &a) {
   SmallState *st = a.st;
   if (st->done) return;
   __shared__ double red[4];
@@ -483,6 +519,20 @@ __global__ __launch_bounds__(256) void k_decide(SmallArgs a) {
     st->have_prev = 1;
     if (!done) st->sweep += 1;
   }
+}
+__global__ __launch_bounds__(256) void k_decide(SmallArgs a) { decide_body(a); }
+// batch: then every instance's state is copied to stall[i] (one read-back)
+__global__ __launch_bounds__(256) void k_decide_b(const SmallArgs *__restrict__ av,
+                                                  SmallState *__restrict__ stall) {
+  const SmallArgs &a = av[blockIdx.x];
+  decide_body(a);
+  __syncthreads();
+  if (threadIdx.x == 0) __threadfence();
+  __syncthreads();
+  const int nw = (int)(sizeof(SmallState) / sizeof(int32_t));
+  const int32_t *src = reinterpret_cast<const int32_t *>(a.st);
+  int32_t *dst = reinterpret_cast<int32_t *>(stall + blockIdx.x);
+  for (int e = threadIdx.x; e < nw; e += 256) dst[e] = src[e];
 }
 
 // -----------------------------------------------------------------------------
@@ -515,3 +565,40 @@ void launch_post(hipStream_t s, const SmallArgs &a, const SmallOut<T> &o) {
 }
 template void launch_post<float>(hipStream_t, const SmallArgs &, const SmallOut<float> &);
 template void launch_post<double>(hipStream_t, const SmallArgs &, const SmallOut<double> &);
+
+// Batched launches: `count` instances whose argument blocks are consecutive
+// in device memory (av); kmax: the common k class of the instances (8, 16,
+// 32 or 64) for the coefficient kernel; n2max, the largest n2.
+void launch_coef_b(hipStream_t s, int kmax, int count, const SmallArgs *av) {
+  if (count <= 0) return;
+  if (kmax <= 8) hipLaunchKernelGGL(k_coef_b<8>, dim3(count), dim3(256), 0, s, av);
+  else if (kmax <= 16) hipLaunchKernelGGL(k_coef_b<16>, dim3(count), dim3(256), 0, s, av);
+  else if (kmax <= 32) hipLaunchKernelGGL(k_coef_b<32>, dim3(count), dim3(256), 0, s, av);
+  else hipLaunchKernelGGL(k_coef_b<64>, dim3(count), dim3(256), 0, s, av);
+}
+
+void launch_formM_b(hipStream_t s, int count, int n2max, const SmallArgs *av) {
+  if (count <= 0) return;
+  const int64_t total = mf_size(n2max);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 256));
+  hipLaunchKernelGGL(k_formM_b, dim3(g, count), dim3(256), 0, s, av);
+}
+
+template <typename T>
+void launch_post_b(hipStream_t s, int count, int n2max, const SmallArgs *av,
+                   const SmallOut<T> *ov) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_post_b<T>, dim3(count), dim3(1024), 0, s, av, ov);
+  if (n2max > 0)
+    hipLaunchKernelGGL(k_postz_b<T>, dim3((n2max + PZ_R - 1) / PZ_R, count), dim3(256), 0, s, av,
+                       ov);
+}
+template void launch_post_b<float>(hipStream_t, int, int, const SmallArgs *,
+                                   const SmallOut<float> *);
+template void launch_post_b<double>(hipStream_t, int, int, const SmallArgs *,
+                                    const SmallOut<double> *);
+
+void launch_decide_b(hipStream_t s, int count, const SmallArgs *av, SmallState *stall) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_decide_b, dim3(count), dim3(256), 0, s, av, stall);
+}

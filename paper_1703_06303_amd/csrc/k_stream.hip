@@ -7,6 +7,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "launch.h"
 
 // Element (i, j) of [A1 A2] as T.  A2 is either part of A (A + k lda, same
 // type) or a separate copy in BF16 (mixed precision).
@@ -610,11 +611,10 @@ __global__ __launch_bounds__(UT_T) void k_update_t(
 
 // Zh + Zl ~ Z (rows k .. n - 1 of the panel Gt = [-S; Z], k per row) in BF16,
 // stored [column c][row j] with rows padded to n2p and columns to kp (zeros).
-__global__ __launch_bounds__(256) void k_panel_bf16(int n2, int k, int kp, int n2p,
-                                                     const float *__restrict__ Gt,
-                                                     bf16s *__restrict__ Zh,
-                                                     bf16s *__restrict__ Zl,
-                                                     const SmallState *__restrict__ st) {
+__device__ __forceinline__ void panel_body(int n2, int k, int kp, int n2p,
+                                           const float *__restrict__ Gt, bf16s *__restrict__ Zh,
+                                           bf16s *__restrict__ Zl,
+                                           const SmallState *__restrict__ st) {
   if (st->done) return;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < kp * n2p; e += gridDim.x * 256) {
     const int c = e / n2p, j = e - c * n2p;
@@ -623,6 +623,18 @@ __global__ __launch_bounds__(256) void k_panel_bf16(int n2, int k, int kp, int n
     Zh[e] = h;
     Zl[e] = bf16_rne(z - to_f(h));
   }
+}
+__global__ __launch_bounds__(256) void k_panel_bf16(int n2, int k, int kp, int n2p,
+                                                     const float *__restrict__ Gt,
+                                                     bf16s *__restrict__ Zh,
+                                                     bf16s *__restrict__ Zl,
+                                                     const SmallState *__restrict__ st) {
+  panel_body(n2, k, kp, n2p, Gt, Zh, Zl, st);
+}
+// batch: blockIdx.y = instance
+__global__ __launch_bounds__(256) void k_panel_bf16_b(const PanelArgs *__restrict__ av) {
+  const PanelArgs &a = av[blockIdx.y];
+  panel_body(a.n2, a.k, a.kp, a.n2p, a.Gt, a.Zh, a.Zl, a.st);
 }
 
 // ---------------------------------------------------------------------------
@@ -917,13 +929,13 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
 #define QR_T 512
 #define CHG_NW 8    // wavefronts per workgroup of the change row pass
 #define CHG_GLD 65  // leading dimension of g in LDS (padded against bank conflicts)
-__global__ __launch_bounds__(QR_T) void k_chgprep(int n2, int k, int l,
-                                                  const double *__restrict__ Vp,
-                                                  const double *__restrict__ Vq,
-                                                  const double *__restrict__ Zp,
-                                                  const double *__restrict__ Zq,
-                                                  double *__restrict__ Hb, double *__restrict__ Kg,
-                                                  const SmallState *__restrict__ st) {
+__device__ __forceinline__ void chgprep_body(int n2, int k, int l,
+                                             const double *__restrict__ Vp,
+                                             const double *__restrict__ Vq,
+                                             const double *__restrict__ Zp,
+                                             const double *__restrict__ Zq,
+                                             double *__restrict__ Hb, double *__restrict__ Kg,
+                                             const SmallState *__restrict__ st) {
   if (st->done || !st->have_prev) return;
   __shared__ double X[WLRA_BMAX * WLRA_BMAX];
   __shared__ double E[WLRA_BMAX * WLRA_BMAX];
@@ -1035,6 +1047,20 @@ __global__ __launch_bounds__(QR_T) void k_chgprep(int n2, int k, int l,
   }
   (void)nrm;
   (void)Kg;
+}
+__global__ __launch_bounds__(QR_T) void k_chgprep(int n2, int k, int l,
+                                                  const double *__restrict__ Vp,
+                                                  const double *__restrict__ Vq,
+                                                  const double *__restrict__ Zp,
+                                                  const double *__restrict__ Zq,
+                                                  double *__restrict__ Hb, double *__restrict__ Kg,
+                                                  const SmallState *__restrict__ st) {
+  chgprep_body(n2, k, l, Vp, Vq, Zp, Zq, Hb, Kg, st);
+}
+// one workgroup per instance of a batch
+__global__ __launch_bounds__(QR_T) void k_chgprep_b(const ChgArgs *__restrict__ av) {
+  const ChgArgs &c = av[blockIdx.x];
+  chgprep_body(c.n2, c.k, c.l, c.Vp, c.Vq, c.Zp, c.Zq, c.Hb, c.Kg, c.st);
 }
 
 // Row pass: u_p = a2 V_p and u_d = a2 dV (wavefronts split the n2 columns,
@@ -1353,6 +1379,10 @@ void launch_panel_bf16(hipStream_t s, int n2, int k, int n2p, const float *Gt, b
   hipLaunchKernelGGL(k_panel_bf16, dim3(grid), dim3(256), 0, s, n2, k, kp, n2p, Gt, Zh, Zl, st);
 }
 
+void launch_panel_bf16_b(hipStream_t s, int count, const PanelArgs *av) {
+  if (count > 0) hipLaunchKernelGGL(k_panel_bf16_b, dim3(64, count), dim3(256), 0, s, av);
+}
+
 template <typename T>
 void launch_update(hipStream_t s, const UpdateArgs<T> &a) {
   // refuse to launch with a missing operand (the kernels have no null checks)
@@ -1388,6 +1418,18 @@ void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64
   else if (k <= 32)
     launch_x2_k<T, 32>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2, w2, mask, ldm, tau);
   else launch_x2_k<T, 64>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2, w2, mask, ldm, tau);
+}
+
+// The Gram Kg = H^T H of the change pass alone (after a batched k_chgprep).
+void launch_chgprep_gram(hipStream_t s, int n2, int k, int l, double *Hb, double *Kg, int splits,
+                         int64_t rows_per_split, double *part, const SmallState *st) {
+  const int K = 2 * l + 2 * k;
+  launch_tsgemm<double, double>(s, n2, Hb, n2, K, Hb, n2, K, 1, splits, rows_per_split, part, Kg,
+                                &st->done);
+}
+
+void launch_chgprep_b(hipStream_t s, int count, const ChgArgs *av) {
+  if (count > 0) hipLaunchKernelGGL(k_chgprep_b, dim3(count), dim3(QR_T), 0, s, av);
 }
 
 void launch_chgprep(hipStream_t s, int n2, int k, int l, const double *Vp, const double *Vq,

@@ -117,6 +117,36 @@ struct SmallOut {
   T *Zx;                 // plain Z = (I - V V^T) C^T for the dense X2 output
 };
 
+// Arguments of the change pass's small step (k_chgprep), one per instance
+// of a batch.
+struct ChgArgs {
+  int n2, k, l;
+  const double *Vp, *Vq, *Zp, *Zq;
+  double *Hb, *Kg;
+  const SmallState *st;
+};
+
+// Batched small steps: one launch for `count` instances whose argument
+// blocks are consecutive in device memory.
+void launch_coef_b(hipStream_t s, int kmax, int count, const SmallArgs *av);
+void launch_formM_b(hipStream_t s, int count, int n2max, const SmallArgs *av);
+void launch_eig_b(hipStream_t s, int count, const SmallArgs *av);
+template <typename T>
+void launch_post_b(hipStream_t s, int count, int n2max, const SmallArgs *av, const SmallOut<T> *ov);
+void launch_decide_b(hipStream_t s, int count, const SmallArgs *av, SmallState *stall);
+void launch_chgprep_b(hipStream_t s, int count, const ChgArgs *av);
+// The BF16 panel of one instance of a batch (k_panel_bf16).
+struct PanelArgs {
+  int n2, k, kp, n2p;
+  const float *Gt;
+  bf16s *Zh, *Zl;
+  const SmallState *st;
+};
+void launch_panel_bf16_b(hipStream_t s, int count, const PanelArgs *av);
+void launch_chgprep_gram(hipStream_t s, int n2, int k, int l, double *Hb, double *Kg, int splits,
+                         int64_t rows_per_split, double *part, const SmallState *st);
+
+
 void launch_coef(hipStream_t s, const SmallArgs &a);
 void launch_formM(hipStream_t s, const SmallArgs &a);
 void launch_eig(hipStream_t s, const SmallArgs &a);

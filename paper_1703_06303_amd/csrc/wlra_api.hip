@@ -7,10 +7,10 @@
 #include <string.h>
 
 #include <algorithm>
-#include <atomic>
+#include <array>
+#include <map>
 #include <mutex>
 #include <new>
-#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -77,10 +77,16 @@ struct ProfEvent {
 
 struct wlra_ctx {
   int device = 0;
-  // batched solves: sub-handles, each on its own stream with its own
-  // workspace, driven by one host thread each (created on first use)
+  // batched solves: streams used by wlra_solve_batched (the handle's and extra ones)
   int batch_lanes = WLRA_BATCH_LANES_DEFAULT;
-  std::vector<wlra_ctx *> lanes;
+  // batch engine: streams besides the handle's, events, workspace slices
+  // and pinned argument/state blocks (grown at the start of a batch call)
+  std::vector<hipStream_t> bstreams;
+  std::vector<hipEvent_t> bjoin, bdone;
+  char *bws = nullptr;
+  size_t bws_bytes = 0;
+  char *bhost = nullptr;
+  size_t bhost_bytes = 0;
   bool owns_stream = false;
   hipStream_t stream = nullptr;
   int precision = 0;
@@ -88,6 +94,11 @@ struct wlra_ctx {
   // options (wlra_set_option)
   int eig_maxit = EIG_MAXIT;
   int eig_one_wg = 0;
+  // autotuner (WLRA_OPT_AUTOTUNE): workgroup targets of the tall-skinny
+  // products per (m, n2, k, element size, BF16 copy), measured once
+  int autotune = 1;
+  std::map<std::array<int64_t, 5>, std::pair<int, int>> tune;
+  hipEvent_t tev0 = nullptr, tev1 = nullptr;
   char *ws = nullptr;
   size_t ws_bytes = 0;
   char *lws = nullptr;  // learned warm start: sketch and training buffers
@@ -148,6 +159,21 @@ static void prof_collect(wlra_ctx *h) {
     }                                                              \
   } while (0)
 #define PROF(h, kind, stmt) PROFW(h, kind, 0, 0, stmt)
+// The same on a given stream (events recorded on `strm`).
+#define PROFWS(h, strm, kind, nbytes, nflops, stmt)                \
+  do {                                                             \
+    if ((h)->flags & WLRA_FLAG_PROFILE) {                          \
+      ProfEvent pe{kind, prof_event(h), prof_event(h), (double)(nbytes), (double)(nflops)}; \
+      if (pe.e0 && pe.e1) hipEventRecord(pe.e0, (strm));           \
+      stmt;                                                        \
+      if (pe.e0 && pe.e1) {                                        \
+        hipEventRecord(pe.e1, (strm));                             \
+        (h)->pending.push_back(pe);                                \
+      }                                                            \
+    } else {                                                       \
+      stmt;                                                        \
+    }                                                              \
+  } while (0)
 
 namespace {
 
@@ -166,6 +192,8 @@ struct Sizes {
   int64_t m, n, k, r, n2, l, b;
   int splits_ga, splits_p;
   int64_t rows_ga, rows_p;
+  int tiles_ga, tiles_p;          // output tiles of A2^T A2 and X1^T A2
+  int splits_ga_max, splits_p_max;  // at the largest autotuner target
   int nwg_upd, nwg_f1;
   size_t elt;
   bool mixed;
@@ -198,10 +226,12 @@ struct Ptrs {
   int *flags;
 };
 
-// Row splits of a tall-skinny product: about 2048 workgroups in all (eight
-// per CU, so that each walks few row chunks), at least 256 rows each.
-int choose_splits(int64_t m, int tiles, int64_t *rows) {
-  int s = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles, (m + 255) / 256));
+// Row splits of a tall-skinny product: about `target` workgroups in all
+// (2048 by default: eight per CU, so that each walks few row chunks), at
+// least 256 rows each.  The autotuner picks the target per shape.
+#define TUNE_TARGET_MAX 4096
+int choose_splits(int64_t m, int tiles, int64_t *rows, int target = 2048) {
+  int s = (int)std::max<int64_t>(1, std::min<int64_t>((target + tiles - 1) / tiles, (m + 255) / 256));
   int64_t r = (m + s - 1) / s;
   r = (r + 31) / 32 * 32;
   s = (int)((m + r - 1) / r);
@@ -218,9 +248,16 @@ Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mi
   z.m = m; z.n = n; z.k = k; z.r = r; z.n2 = n - k; z.l = r - k;
   z.b = z.l > 0 ? std::min<int64_t>(z.n2, z.l + EIG_GUARD) : 0;
   const int tga = (int)(((z.n2 + 31) / 32) * ((z.n2 + 31) / 32 + 1) / 2);
-  z.splits_ga = choose_splits(m, std::max(1, tga), &z.rows_ga);
+  z.tiles_ga = std::max(1, tga);
+  z.splits_ga = choose_splits(m, z.tiles_ga, &z.rows_ga);
   const int tp = (int)(((std::max<int64_t>(k, 1) + 31) / 32) * ((z.n2 + 31) / 32));
-  z.splits_p = choose_splits(m, std::max(1, tp), &z.rows_p);
+  z.tiles_p = std::max(1, tp);
+  z.splits_p = choose_splits(m, z.tiles_p, &z.rows_p);
+  {
+    int64_t rr;
+    z.splits_ga_max = std::max(z.splits_ga, choose_splits(m, z.tiles_ga, &rr, TUNE_TARGET_MAX));
+    z.splits_p_max = std::max(z.splits_p, choose_splits(m, z.tiles_p, &rr, TUNE_TARGET_MAX));
+  }
   {
     const int tk1 = (int)((std::max<int64_t>(k, 1) + 31) / 32);
     z.splits_g1 = choose_splits(m, tk1 * tk1, &z.rows_g1);
@@ -249,8 +286,8 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
   const int64_t kk = std::max<int64_t>(k, 1), ll = std::max<int64_t>(l, 1);
   const int64_t Kc = 2 * l + 2 * k;
   const size_t part = std::max<size_t>(
-      std::max<size_t>((size_t)z.splits_ga * n2 * n2,
-                       (size_t)z.splits_p * std::max<int64_t>(kk * n2, kk * kk)),
+      std::max<size_t>((size_t)z.splits_ga_max * n2 * n2,
+                       (size_t)z.splits_p_max * std::max<int64_t>(kk * n2, kk * kk)),
       std::max<size_t>((size_t)z.splits_kg * Kc * Kc, (size_t)z.splits_g1 * kk * kk));
   struct Item { void **dst; size_t bytes; };
   Ptrs p{};
@@ -373,230 +410,413 @@ int check_problem(const wlra_problem *p, int precision) {
     if ((x) != hipSuccess) return WLRA_E_HIP; \
   } while (0)
 
-// One solve.  ws: a workspace of at least make_layout(...).total bytes
-// (the handle's).
+// Batch resources, grown before a batch's first kernel (never during its
+// sweeps): `ns - 1` extra streams (default priority) and their join events.
+int ensure_batch_streams(wlra_ctx *h, int ns) {
+  while ((int)h->bstreams.size() < ns - 1) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return WLRA_E_HIP;
+    h->bstreams.push_back(st);
+  }
+  while ((int)h->bjoin.size() < ns) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return WLRA_E_HIP;
+    h->bjoin.push_back(e);
+  }
+  return WLRA_OK;
+}
+
+int ensure_batch_ws(wlra_ctx *h, size_t bytes) {
+  if (bytes <= h->bws_bytes) return WLRA_OK;
+  if (h->bws) {
+    if (hipDeviceSynchronize() != hipSuccess) return WLRA_E_HIP;
+    (void)hipFree(h->bws);
+    h->bws = nullptr;
+    h->bws_bytes = 0;
+  }
+  const size_t want = bytes + bytes / 8;
+  if (hipMalloc(&h->bws, want) != hipSuccess) {
+    h->bws = nullptr;
+    return WLRA_E_NOMEM;
+  }
+  h->bws_bytes = want;
+  return WLRA_OK;
+}
+
+// Pinned host blocks of a batch and one completion event per instance.
+int ensure_batch_host(wlra_ctx *h, size_t bytes, int count) {
+  if (bytes > h->bhost_bytes) {
+    if (h->bhost) {
+      if (hipDeviceSynchronize() != hipSuccess) return WLRA_E_HIP;
+      (void)hipHostFree(h->bhost);
+      h->bhost = nullptr;
+      h->bhost_bytes = 0;
+    }
+    if (hipHostMalloc((void **)&h->bhost, bytes, hipHostMallocDefault) != hipSuccess) {
+      h->bhost = nullptr;
+      return WLRA_E_NOMEM;
+    }
+    h->bhost_bytes = bytes;
+  }
+  while ((int)h->bdone.size() < count) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return WLRA_E_HIP;
+    h->bdone.push_back(e);
+  }
+  return WLRA_OK;
+}
+
+// Per-instance state of one solve of Algorithm 1 and the steps that enqueue
+// its kernels.  A single solve (wlra_solve) drives one Run from the host,
+// reading the sweep state once per sweep; the batch engine
+// (wlra_solve_batched) drives many Runs in lockstep, with the single-workgroup
+// small steps of all of them in one launch each.
 template <typename T>
-int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) {
-  const bool mixed = (h->precision == WLRA_MIXED_BF16);
-  const bool learned = (pr->k > 0 && pr->init == WLRA_INIT_LEARNED);
-  const bool colw = (pr->W2 != nullptr && pr->n > pr->k);
-  const Sizes z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T), mixed, learned, colw);
-  Ptrs P;
-  make_layout(z, &P, ws);
-  hipStream_t s = h->stream;
-  const int64_t m = z.m, k = z.k, n2 = z.n2, l = z.l, b = z.b;
-  // with column weights every pass after validation reads the staged
-  // [A1, A2 diag(W2)] (leading dimension m) in place of A
-  const T *A = colw ? static_cast<const T *>(P.As) : static_cast<const T *>(pr->A);
-  const int64_t lda = colw ? m : pr->lda;
-  const T *A2 = A + k * lda;
-  const T *W2 = colw ? static_cast<const T *>(pr->W2) : nullptr;
-  const T *W1 = (k > 0) ? static_cast<const T *>(pr->W1) : nullptr;
-  const bool constw = (k > 0 && W1 == nullptr);
-  const double wc = constw ? pr->w1_const : 0.0;
+struct Run {
+  wlra_ctx *h = nullptr;
+  const wlra_problem *pr = nullptr;
+  wlra_result *res = nullptr;
+  hipStream_t s = nullptr;     // stream of this instance's own launches
+  SmallState *sh = nullptr;    // host copy of the sweep state (pinned)
+  bool mixed = false, learned = false, colw = false, constw = false;
+  Sizes z{};
+  Ptrs P{};
+  int64_t m = 0, k = 0, n2 = 0, l = 0, b = 0, lda = 0;
+  const T *A = nullptr, *A2 = nullptr, *W1 = nullptr, *W2 = nullptr;
+  double wc = 0.0, eig_tol = 0.0, es = 0.0, md = 0.0, kd = 0.0, n2d = 0.0;
+  T *X1c = nullptr;
+  int cur = 0, nparts = 0, p = 0, max_sweeps = 0, mixed_status = 0, rc_tune = 0;
+  bool may_tune = true;  // false: no new autotuner entries (nothing allocates)
+  bool on_bf16 = false, reeval = false;
+  SmallArgs sa{};
+  SmallOut<T> so{};
 
-  HIPCHK(hipEventRecord(h->ev0, s));
-  launch_zero<int>(s, 16, P.flags);  // a fill kernel, no memset node
-  SmallState &sh = *h->st_host;
-  memset(&sh, 0, sizeof(SmallState));
-  // Mixed precision runs the sweeps on the BF16 copy of A2 with a looser
-  // threshold and one sweep fewer, then refines in exact arithmetic.
-  const int max_sweeps = (k > 0) ? pr->max_sweeps : 0;
-  sh.tol = (mixed && pr->tol > 0) ? std::max(pr->tol, MIXED_TOL) : pr->tol;
-  sh.max_sweeps = mixed ? std::max(max_sweeps - 1, 0) : max_sweeps;
-  sh.eig_first = 1;
-  if (pr->V_init != nullptr && l > 0) {
-    // the first eigen step starts from the given block (orthonormalised there)
-    launch_eig_seed(s, (int)n2, (int)l, (int)b, pr->V_init, pr->ldv0, (int)pr->v0_rows, P.Y);
-    sh.eig_first = 2;
-  }
-  const double eig_tol = pr->eig_tol > 0 ? pr->eig_tol
-                         : (h->precision == WLRA_FP64 ? 64.0 * 2.220446049250313e-16 : 1e-10);
-  sh.eig_floor = mixed ? std::max(eig_tol, MIXED_EIG_TOL) : eig_tol;
-  HIPCHK(hipMemcpyAsync(P.st, &sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
+  // Validation, start, the one-time Gram and the sums of sweep 0.  Returns
+  // a negative status on a launch failure.
+  int begin(wlra_ctx *h_, const wlra_problem *pr_, wlra_result *res_, char *ws, hipStream_t s_,
+            SmallState *sh_) {
+    h = h_; pr = pr_; res = res_; s = s_; sh = sh_;
+    mixed = (h->precision == WLRA_MIXED_BF16);
+    learned = (pr->k > 0 && pr->init == WLRA_INIT_LEARNED);
+    colw = (pr->W2 != nullptr && pr->n > pr->k);
+    z = make_sizes(pr->m, pr->n, pr->k, pr->r, sizeof(T), mixed, learned, colw);
+    make_layout(z, &P, ws);
+    m = z.m; k = z.k; n2 = z.n2; l = z.l; b = z.b;
+    // with column weights every pass after validation reads the staged
+    // [A1, A2 diag(W2)] (leading dimension m) in place of A
+    A = colw ? static_cast<const T *>(P.As) : static_cast<const T *>(pr->A);
+    lda = colw ? m : pr->lda;
+    A2 = A + k * lda;
+    W2 = colw ? static_cast<const T *>(pr->W2) : nullptr;
+    W1 = (k > 0) ? static_cast<const T *>(pr->W1) : nullptr;
+    constw = (k > 0 && W1 == nullptr);
+    wc = constw ? pr->w1_const : 0.0;
+    es = (double)sizeof(T); md = (double)m; kd = (double)k; n2d = (double)n2;
 
-  // algorithmic bytes per launch of the streaming kernels (each operand read
-  // or written once): element sizes of the storage type and of A2's copy
-  const double es = (double)sizeof(T), es2 = mixed ? 2.0 : es;
-  const double md = (double)m, kd = (double)k, n2d = (double)n2;
-  PROFW(h, KK_VALIDATE, md * (double)pr->n * es + (W1 ? md * kd * es : 0.0) + (mixed ? md * n2d * 2.0 : 0.0), 0,
-        launch_validate<T>(s, m, pr->n, static_cast<const T *>(pr->A), pr->lda, k, W1, pr->ldw,
-                           P.flags, P.Ab, W2, static_cast<T *>(P.As)));
-  T *X1c = static_cast<T *>(P.X1[0]);
-  const bool need_init = (k > 0);
-  int *lflag = nullptr;  // learned start: the random start is its fallback
-  if (learned) {
-    // Y = network(sketch of A), the predicted row basis; X1_0 is the
-    // per-row weighted least-squares fit in span(Y^T): k_ldecode forms the
-    // row update's operands, the row-update kernels solve the k x k systems.
-    const int64_t n = pr->n;
-    const float *W1m = pr->model, *b1 = W1m + LEARN_HID * LEARN_D_IN;
-    const float *W2m = b1 + LEARN_HID, *b2 = W2m + LEARN_HID * LEARN_HID;
-    const float *W3m = b2 + LEARN_HID, *b3 = W3m + n * z.r * LEARN_HID;
-    T *Om = static_cast<T *>(P.Om), *Ps = static_cast<T *>(P.Ps);
-    T *Gt = static_cast<T *>(P.Gt), *Tt = static_cast<T *>(P.Tt), *St = static_cast<T *>(P.St);
-    T *X1z = static_cast<T *>(P.X1[1]);
-    // the decode's failures (k_ldecode, or a per-row solve) go to a flag
-    // word of their own, which gates the random start that replaces it
-    lflag = P.flags + 1;
-    auto seq = [&]() {
-      launch_gauss_fill<T>(s, m * LEARN_SK_ROWS, LEARN_SEED_OMEGA, 1.0, Om);
-      launch_gauss_fill<T>(s, n * LEARN_SK_COLS, LEARN_SEED_PSI, 1.0, Ps);
-      launch_tsgemm<T, T>(s, m, Om, m, LEARN_SK_ROWS, A, lda, (int)n, 0, z.splits_l1,
-                          z.rows_l1, P.lpart, P.P1, nullptr);
-      launch_sketch_finish<T>(s, (int)n, P.P1, Ps, P.sk);
-      launch_gemm(s, 0, 1, LEARN_HID, LEARN_D_IN, P.sk, LEARN_D_IN, W1m, LEARN_D_IN, P.lh1,
-                  LEARN_HID, b1, 1, nullptr, 0);
-      launch_gemm(s, 0, 1, LEARN_HID, LEARN_HID, P.lh1, LEARN_HID, W2m, LEARN_HID, P.lh2,
-                  LEARN_HID, b2, 1, nullptr, 0);
-      launch_gemm(s, 0, 1, (int)(n * z.r), LEARN_HID, P.lh2, LEARN_HID, W3m, LEARN_HID, P.yv,
-                  (int)(n * z.r), b3, 0, nullptr, 0);
-      launch_ldecode<T>(s, (int)n, (int)k, (int)z.r, P.yv, Gt, Tt, St, lflag);
-      launch_zero<T>(s, m * k, X1z);
-      UpdateArgs<T> ua{};
-      ua.m = m; ua.k = (int)k; ua.n = (int)n; ua.A = A; ua.lda = lda; ua.W1 = W1;
-      ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1z; ua.X1n = X1c;
-      ua.Gt = Gt; ua.Tt = Tt; ua.St = St; ua.part = P.upd_part; ua.st = P.st;
-      ua.Eb = static_cast<T *>(P.Eb);
-      ua.A2b = nullptr;
-      ua.ldb = m;
-      ua.flags = lflag;
-      launch_update<T>(s, ua);
-    };
-    PROF(h, KK_LEARN, seq());
+    launch_zero<int>(s, 16, P.flags);  // a fill kernel, no memset node
+    memset(sh, 0, sizeof(SmallState));
+    // Mixed precision runs the sweeps on the BF16 copy of A2 with a looser
+    // threshold and one sweep fewer, then refines in exact arithmetic.
+    max_sweeps = (k > 0) ? pr->max_sweeps : 0;
+    sh->tol = (mixed && pr->tol > 0) ? std::max(pr->tol, MIXED_TOL) : pr->tol;
+    sh->max_sweeps = mixed ? std::max(max_sweeps - 1, 0) : max_sweeps;
+    sh->eig_first = 1;
+    if (pr->V_init != nullptr && l > 0) {
+      // the first eigen step starts from the given block (orthonormalised there)
+      launch_eig_seed(s, (int)n2, (int)l, (int)b, pr->V_init, pr->ldv0, (int)pr->v0_rows, P.Y);
+      sh->eig_first = 2;
+    }
+    eig_tol = pr->eig_tol > 0 ? pr->eig_tol
+                              : (h->precision == WLRA_FP64 ? 64.0 * 2.220446049250313e-16 : 1e-10);
+    sh->eig_floor = mixed ? std::max(eig_tol, MIXED_EIG_TOL) : eig_tol;
+    HIPCHK(hipMemcpyAsync(P.st, sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
+
+    // algorithmic bytes per launch of the streaming kernels (each operand
+    // read or written once)
+    PROFWS(h, s, KK_VALIDATE,
+           md * (double)pr->n * es + (W1 ? md * kd * es : 0.0) + (mixed ? md * n2d * 2.0 : 0.0), 0,
+           launch_validate<T>(s, m, pr->n, static_cast<const T *>(pr->A), pr->lda, k, W1, pr->ldw,
+                              P.flags, P.Ab, W2, static_cast<T *>(P.As)));
+    X1c = static_cast<T *>(P.X1[0]);
+    int *lflag = nullptr;  // learned start: the random start is its fallback
+    if (learned) {
+      // Y = network(sketch of A), the predicted row basis; X1_0 is the
+      // per-row weighted least-squares fit in span(Y^T): k_ldecode forms the
+      // row update's operands, the row-update kernels solve the k x k systems.
+      const int64_t n = pr->n;
+      const float *W1m = pr->model, *b1 = W1m + LEARN_HID * LEARN_D_IN;
+      const float *W2m = b1 + LEARN_HID, *b2 = W2m + LEARN_HID * LEARN_HID;
+      const float *W3m = b2 + LEARN_HID, *b3 = W3m + n * z.r * LEARN_HID;
+      T *Om = static_cast<T *>(P.Om), *Ps = static_cast<T *>(P.Ps);
+      T *Gt = static_cast<T *>(P.Gt), *Tt = static_cast<T *>(P.Tt), *St = static_cast<T *>(P.St);
+      T *X1z = static_cast<T *>(P.X1[1]);
+      // the decode's failures (k_ldecode, or a per-row solve) go to a flag
+      // word of their own, which gates the random start that replaces it
+      lflag = P.flags + 1;
+      auto seq = [&]() {
+        launch_gauss_fill<T>(s, m * LEARN_SK_ROWS, LEARN_SEED_OMEGA, 1.0, Om);
+        launch_gauss_fill<T>(s, n * LEARN_SK_COLS, LEARN_SEED_PSI, 1.0, Ps);
+        launch_tsgemm<T, T>(s, m, Om, m, LEARN_SK_ROWS, A, lda, (int)n, 0, z.splits_l1,
+                            z.rows_l1, P.lpart, P.P1, nullptr);
+        launch_sketch_finish<T>(s, (int)n, P.P1, Ps, P.sk);
+        launch_gemm(s, 0, 1, LEARN_HID, LEARN_D_IN, P.sk, LEARN_D_IN, W1m, LEARN_D_IN, P.lh1,
+                    LEARN_HID, b1, 1, nullptr, 0);
+        launch_gemm(s, 0, 1, LEARN_HID, LEARN_HID, P.lh1, LEARN_HID, W2m, LEARN_HID, P.lh2,
+                    LEARN_HID, b2, 1, nullptr, 0);
+        launch_gemm(s, 0, 1, (int)(n * z.r), LEARN_HID, P.lh2, LEARN_HID, W3m, LEARN_HID, P.yv,
+                    (int)(n * z.r), b3, 0, nullptr, 0);
+        launch_ldecode<T>(s, (int)n, (int)k, (int)z.r, P.yv, Gt, Tt, St, lflag);
+        launch_zero<T>(s, m * k, X1z);
+        UpdateArgs<T> ua{};
+        ua.m = m; ua.k = (int)k; ua.n = (int)n; ua.A = A; ua.lda = lda; ua.W1 = W1;
+        ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1z; ua.X1n = X1c;
+        ua.Gt = Gt; ua.Tt = Tt; ua.St = St; ua.part = P.upd_part; ua.st = P.st;
+        ua.Eb = static_cast<T *>(P.Eb);
+        ua.A2b = nullptr;
+        ua.ldb = m;
+        ua.flags = lflag;
+        launch_update<T>(s, ua);
+      };
+      PROFWS(h, s, KK_LEARN, 0, 0, seq());
+    }
+    if (k > 0) {
+      const int mode = (pr->init == WLRA_INIT_RANDOM || pr->init == WLRA_INIT_LEARNED) ? 0 : 1;
+      const T *src = pr->init == WLRA_INIT_GIVEN ? static_cast<const T *>(pr->X1_init) : A;
+      const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : lda;
+      PROFWS(h, s, KK_INIT, 0, 0,
+             launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags, lflag));
+    }
+    on_bf16 = mixed;  // A2 products on the BF16 copy (mixed phase)
+    rc_tune = tune_products();
+    if (rc_tune != WLRA_OK) return rc_tune;
+    gram_A2(on_bf16);
+    // eig_floor is relative to ||A2^T A2||_F; k_gastats scales it.
+    PROFWS(h, s, KK_GAST, 0, 0, launch_gastats(s, (int)n2, P.GA, P.st));
+    if (k > 0) {
+      gram_X1A2(X1c, on_bf16);
+      PROFWS(h, s, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
+             (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_g1,
+                                  z.rows_g1, P.part, P.G1, nullptr)));
+      PROFWS(h, s, KK_F1, 0, 0,
+             launch_f1<T>(s, m, (int)k, A, lda, W1, pr->ldw, wc, X1c, P.upd_part, z.nwg_f1));
+      nparts = z.nwg_f1;
+    }
+    sa = SmallArgs{};
+    sa.k = (int)k; sa.n2 = (int)n2; sa.l = (int)l; sa.b = (int)b;
+    sa.G1 = P.G1; sa.P = P.P; sa.GA = P.GA;
+    sa.R = P.R; sa.B = P.B; sa.C = P.C; sa.M = P.M;
+    sa.Y = P.Y; sa.Wb = P.Wb; sa.F0 = P.F0; sa.F1 = P.F1; sa.F2 = P.F2; sa.theta = P.theta;
+    sa.scratch = P.scratch; sa.st = P.st; sa.flags = P.flags; sa.wconst = constw ? wc : 0.0;
+    sa.eig_maxit = h->eig_maxit; sa.eig_deg = EIG_DEG;
+    sa.eig_one_wg = h->eig_one_wg;
+    sa.epart = P.epart;
+    sa.upd_part = P.upd_part; sa.chg_part = P.chg_part; sa.nchg = z.nwg_upd;
+    so = SmallOut<T>{static_cast<T *>(P.Gt), static_cast<T *>(P.Tt), static_cast<T *>(P.St),
+                     static_cast<T *>(P.Vr), static_cast<T *>(P.Zx)};
+    cur = 0;
+    p = 0;
+    reeval = false;
+    mixed_status = 0;
+    return WLRA_OK;
   }
-  if (need_init) {
-    const int mode = (pr->init == WLRA_INIT_RANDOM || pr->init == WLRA_INIT_LEARNED) ? 0 : 1;
-    const T *src = pr->init == WLRA_INIT_GIVEN ? static_cast<const T *>(pr->X1_init) : A;
-    const int64_t lds = pr->init == WLRA_INIT_GIVEN ? pr->ldx0 : lda;
-    PROF(h, KK_INIT, launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags, lflag));
+
+  // Autotuner: the workgroup target (512 .. 4096) of the X1^T A2 product
+  // and of the A2^T A2 Gram, each timed once per shape on this instance's own
+  // operands (the products' results are overwritten by the solve), then
+  // reused for every later solve of that shape on the handle.  Different
+  // targets sum the rows in different orders, so results are reproducible
+  // per handle.
+  int tune_products() {
+    if (!h->autotune || n2 == 0) return WLRA_OK;
+    const std::array<int64_t, 5> key{m, n2, k, (int64_t)sizeof(T), on_bf16 ? 1 : 0};
+    auto it = h->tune.find(key);
+    int tp = 0, tg = 0;
+    if (it != h->tune.end()) {
+      tp = it->second.first;
+      tg = it->second.second;
+    } else {
+      if (!may_tune) return WLRA_OK;
+      static const int cand[4] = {512, 1024, 2048, TUNE_TARGET_MAX};
+      float best_p = 1e30f, best_g = 1e30f;
+      for (int c : cand) {
+        int64_t rp, rg;
+        const int sp = choose_splits(m, z.tiles_p, &rp, c);
+        const int sg = choose_splits(m, z.tiles_ga, &rg, c);
+        float tms_p = 0.f, tms_g = 0.f;
+        if (k > 0) {
+          auto xta = [&]() {
+            if constexpr (std::is_same<T, float>::value) {
+              if (on_bf16) {
+                launch_tsgemm<float, bf16s>(s, m, X1c, m, (int)k, P.Ab, m, (int)n2, 0, sp, rp,
+                                            P.part, P.P, nullptr);
+                return;
+              }
+            }
+            launch_tsgemm<T, T>(s, m, X1c, m, (int)k, A2, lda, (int)n2, 0, sp, rp, P.part, P.P,
+                                nullptr);
+          };
+          xta();
+          HIPCHK(hipEventRecord(h->tev0, s));
+          for (int rep = 0; rep < 3; ++rep) xta();
+          HIPCHK(hipEventRecord(h->tev1, s));
+          HIPCHK(hipEventSynchronize(h->tev1));
+          HIPCHK(hipEventElapsedTime(&tms_p, h->tev0, h->tev1));
+          if (tms_p < best_p) { best_p = tms_p; tp = c; }
+        }
+        auto gram = [&]() {
+          if constexpr (std::is_same<T, float>::value) {
+            if (on_bf16) {
+              launch_tsgemm<bf16s, bf16s>(s, m, P.Ab, m, (int)n2, P.Ab, m, (int)n2, 1, sg, rg,
+                                          P.part, P.GA, nullptr);
+              return;
+            }
+          }
+          launch_tsgemm<T, T>(s, m, A2, lda, (int)n2, A2, lda, (int)n2, 1, sg, rg, P.part, P.GA,
+                              nullptr);
+        };
+        gram();
+        HIPCHK(hipEventRecord(h->tev0, s));
+        gram();
+        HIPCHK(hipEventRecord(h->tev1, s));
+        HIPCHK(hipEventSynchronize(h->tev1));
+        HIPCHK(hipEventElapsedTime(&tms_g, h->tev0, h->tev1));
+        if (tms_g < best_g) { best_g = tms_g; tg = c; }
+      }
+      h->tune[key] = {tp, tg};
+    }
+    if (tp > 0) z.splits_p = choose_splits(m, z.tiles_p, &z.rows_p, tp);
+    if (tg > 0) z.splits_ga = choose_splits(m, z.tiles_ga, &z.rows_ga, tg);
+    return WLRA_OK;
   }
+
+  // Input checks of the validation pass (after a synchronisation).
+  static int input_status(int dflags) {
+    if (dflags & DEV_BAD_W) return WLRA_E_WEIGHT;
+    if (dflags & DEV_BAD_A) return WLRA_E_NONFINITE;
+    return WLRA_OK;
+  }
+
   // One-time Gram of the unweighted block: A2^T A2 (of the BF16 copy in
   // mixed precision, so that M = G_A - B^T B stays consistent).
-  auto gram_A2 = [&](bool on_bf16) {
+  void gram_A2(bool bf) {
     if constexpr (std::is_same<T, float>::value) {
-      if (on_bf16) {
-        PROFW(h, KK_GRAM, md * n2d * 2.0, md * n2d * n2d,
-             (launch_tsgemm<bf16s, bf16s>(s, m, P.Ab, m, (int)n2, P.Ab, m, (int)n2, 1,
-                                          z.splits_ga, z.rows_ga, P.part, P.GA, nullptr)));
+      if (bf) {
+        PROFWS(h, s, KK_GRAM, md * n2d * 2.0, md * n2d * n2d,
+               (launch_tsgemm<bf16s, bf16s>(s, m, P.Ab, m, (int)n2, P.Ab, m, (int)n2, 1,
+                                            z.splits_ga, z.rows_ga, P.part, P.GA, nullptr)));
         return;
       }
     }
-    PROFW(h, KK_GRAM, md * n2d * es, md * n2d * n2d,
-         (launch_tsgemm<T, T>(s, m, A2, lda, (int)n2, A2, lda, (int)n2, 1, z.splits_ga,
-                              z.rows_ga, P.part, P.GA, nullptr)));
-  };
-  // X1^T A2 (k x n2) for the coefficients of the next small step.
-  auto gram_X1A2 = [&](const T *X1, bool on_bf16) {
-    if constexpr (std::is_same<T, float>::value) {
-      if (on_bf16) {
-        PROFW(h, KK_XTA, md * (kd * es + n2d * 2.0), 2.0 * md * kd * n2d,
-             (launch_tsgemm<float, bf16s>(s, m, X1, m, (int)k, P.Ab, m, (int)n2, 0, z.splits_p,
-                                          z.rows_p, P.part, P.P, nullptr)));
-        return;
-      }
-    }
-    PROFW(h, KK_XTA, md * (kd + n2d) * es, 2.0 * md * kd * n2d,
-         (launch_tsgemm<T, T>(s, m, X1, m, (int)k, A2, lda, (int)n2, 0, z.splits_p, z.rows_p,
-                              P.part, P.P, nullptr)));
-  };
-  bool on_bf16 = mixed;  // A2 products on the BF16 copy (mixed phase)
-  gram_A2(on_bf16);
-  // eig_floor is relative to ||A2^T A2||_F; k_gastats scales it.
-  PROF(h, KK_GAST, launch_gastats(s, (int)n2, P.GA, P.st));
-  int nparts = 0;
-  if (k > 0) {
-    gram_X1A2(X1c, on_bf16);
-    PROFW(h, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
-         (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_g1, z.rows_g1,
-                              P.part, P.G1, nullptr)));
-    PROF(h, KK_F1, launch_f1<T>(s, m, (int)k, A, lda, W1, pr->ldw, wc, X1c, P.upd_part,
-                                z.nwg_f1));
-    nparts = z.nwg_f1;
+    PROFWS(h, s, KK_GRAM, md * n2d * es, md * n2d * n2d,
+           (launch_tsgemm<T, T>(s, m, A2, lda, (int)n2, A2, lda, (int)n2, 1, z.splits_ga,
+                                z.rows_ga, P.part, P.GA, nullptr)));
   }
-  HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (*h->flags_host & DEV_BAD_W) return WLRA_E_WEIGHT;
-  if (*h->flags_host & DEV_BAD_A) return WLRA_E_NONFINITE;
+  // X1^T A2 (k x n2) for the coefficients of the next small step.
+  void gram_X1A2(const T *X1, bool bf) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (bf) {
+        PROFWS(h, s, KK_XTA, md * (kd * es + n2d * 2.0), 2.0 * md * kd * n2d,
+               (launch_tsgemm<float, bf16s>(s, m, X1, m, (int)k, P.Ab, m, (int)n2, 0,
+                                            z.splits_p, z.rows_p, P.part, P.P, nullptr)));
+        return;
+      }
+    }
+    PROFWS(h, s, KK_XTA, md * (kd + n2d) * es, 2.0 * md * kd * n2d,
+           (launch_tsgemm<T, T>(s, m, X1, m, (int)k, A2, lda, (int)n2, 0, z.splits_p, z.rows_p,
+                                P.part, P.P, nullptr)));
+  }
 
-  SmallArgs sa{};
-  sa.k = (int)k; sa.n2 = (int)n2; sa.l = (int)l; sa.b = (int)b;
-  sa.G1 = P.G1; sa.P = P.P; sa.GA = P.GA;
-  sa.R = P.R; sa.B = P.B; sa.C = P.C; sa.M = P.M;
-  sa.Y = P.Y; sa.Wb = P.Wb; sa.F0 = P.F0; sa.F1 = P.F1; sa.F2 = P.F2; sa.theta = P.theta;
-  sa.scratch = P.scratch; sa.st = P.st; sa.flags = P.flags; sa.wconst = constw ? wc : 0.0;
-  sa.eig_maxit = h->eig_maxit; sa.eig_deg = EIG_DEG;
-  sa.eig_one_wg = h->eig_one_wg;
-  sa.epart = P.epart;
-  sa.upd_part = P.upd_part; sa.chg_part = P.chg_part; sa.nchg = z.nwg_upd;
-  SmallOut<T> so{static_cast<T *>(P.Gt), static_cast<T *>(P.Tt), static_cast<T *>(P.St),
-                 static_cast<T *>(P.Vr), static_cast<T *>(P.Zx)};
-
-  int cur = 0;
-  bool reeval = false;   // exact re-evaluation of X_p right after the mixed phase
-  int mixed_status = 0;
-  for (int p = 0;; ++p) {
-    // Small step for sweep p: R, B, C from the Grams of X1_p; the top r-k
-    // eigenpairs of (P^perp A2)^T (P^perp A2); Z, T, S and F(X_p).
+  // Arguments of sweep p's small step.
+  void small_args() {
     sa.nparts = nparts;
     sa.Zcur = P.Zd[p & 1];
     sa.Vcur = P.Vd[p & 1];
-    PROF(h, KK_COEF, launch_coef(s, sa));
+  }
+  // Small step for sweep p on this instance's stream: R, B, C from the Grams
+  // of X1_p; the top r-k eigenpairs of (P^perp A2)^T (P^perp A2); Z, T, S
+  // and F(X_p).
+  void small_single() {
+    PROFWS(h, s, KK_COEF, 0, 0, launch_coef(s, sa));
     if (l > 0) {
-      PROF(h, KK_FORMM, launch_formM(s, sa));
-      PROF(h, KK_EIG, launch_eig(s, sa));
+      PROFWS(h, s, KK_FORMM, 0, 0, launch_formM(s, sa));
+      PROFWS(h, s, KK_EIG, 0, 0, launch_eig(s, sa));
     }
-    PROF(h, KK_POST, launch_post<T>(s, sa, so));
+    PROFWS(h, s, KK_POST, 0, 0, launch_post<T>(s, sa, so));
+  }
+  // BF16 phase: Z ~ Zh + Zl for the row update's BF16 products.
+  void panel() {
     if constexpr (std::is_same<T, float>::value) {
-      // BF16 phase: Z ~ Zh + Zl for the row update's BF16 products
       if (on_bf16 && k > 0)
-        PROF(h, KK_POST, launch_panel_bf16(s, (int)n2, (int)k, (int)panel_rows(n2), so.Gt,
-                                           P.Zh, P.Zl, P.st));
+        PROFWS(h, s, KK_POST, 0, 0,
+               launch_panel_bf16(s, (int)n2, (int)k, (int)panel_rows(n2), so.Gt, P.Zh, P.Zl,
+                                 P.st));
     }
-    if (p > 0 && !reeval) {
-      PROF(h, KK_CHGQR,
-           launch_chgprep(s, (int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1],
-                          P.Zd[p & 1], P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, z.splits_kg, z.rows_kg,
-                          P.part, P.st));
-      PROFW(h, KK_CHANGE, md * (n2d * (on_bf16 ? 2.0 : es) + 2.0 * kd * es),
-            md * (4.0 * (double)l * n2d + (2.0 * (double)l + 2.0 * kd) * (2.0 * (double)l + 2.0 * kd)),
-           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, lda,
-                               on_bf16 ? P.Ab : nullptr, m, X1c,
-                               static_cast<const T *>(P.X1[cur ^ 1]), P.Hb, P.Rh, P.chg_part,
-                               P.st));
-    }
-    PROF(h, KK_DECIDE, launch_decide(s, sa));
-    HIPCHK(hipMemcpyAsync(h->st_host, P.st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    prof_collect(h);
+  }
+  bool panel_needed() const { return std::is_same<T, float>::value && on_bf16 && k > 0; }
+  PanelArgs panel_args() const {
+    return PanelArgs{(int)n2, (int)k, update_panel_kp((int)k), (int)panel_rows(n2),
+                     reinterpret_cast<const float *>(so.Gt), P.Zh, P.Zl, P.st};
+  }
+  bool change_needed() const { return p > 0 && !reeval; }
+  ChgArgs chg_args() const {
+    return ChgArgs{(int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1], P.Zd[p & 1],
+                   P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, P.st};
+  }
+  // Error_p: the aligned basis and its Gram (one workgroup + product), then
+  // the row pass.  batched_prep: the one-workgroup part ran in a batch launch.
+  void change(bool batched_prep) {
+    if (!batched_prep)
+      PROFWS(h, s, KK_CHGQR, 0, 0,
+             launch_chgprep(s, (int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1],
+                            P.Zd[p & 1], P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, z.splits_kg, z.rows_kg,
+                            P.part, P.st));
+    else
+      PROFWS(h, s, KK_CHGQR, 0, 0,
+             launch_chgprep_gram(s, (int)n2, (int)k, (int)l, P.Hb, P.Rh, z.splits_kg, z.rows_kg,
+                                 P.part, P.st));
+    PROFWS(h, s, KK_CHANGE, md * (n2d * (on_bf16 ? 2.0 : es) + 2.0 * kd * es),
+           md * (4.0 * (double)l * n2d +
+                 (2.0 * (double)l + 2.0 * kd) * (2.0 * (double)l + 2.0 * kd)),
+           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, lda, on_bf16 ? P.Ab : nullptr,
+                               m, X1c, static_cast<const T *>(P.X1[cur ^ 1]), P.Hb, P.Rh,
+                               P.chg_part, P.st));
+  }
+
+  // Host side of sweep p after its state is in *sh: the trace, and the end
+  // of the mixed phase.  Returns 1 when X_p is final, 2 when the mixed phase
+  // ended (X_p is re-evaluated in exact arithmetic by the next small step,
+  // whose sums are enqueued here), 0 when the X1 update follows.
+  int after_decide() {
     if (pr->trace && p <= pr->max_sweeps) {
-      pr->trace[p] = sh.F;
+      pr->trace[p] = sh->F;
       // the exact re-evaluation of X_p after the mixed phase runs no change
       // pass: Error_p stays the BF16 phase's
-      if (!reeval) pr->trace[pr->max_sweeps + 1 + p] = sh.err;
+      if (!reeval) pr->trace[pr->max_sweeps + 1 + p] = sh->err;
     }
     reeval = false;
-    if (sh.done && on_bf16) {
+    if (sh->done && on_bf16) {
       // End of the mixed phase at X1_p: switch to A2 itself (exact G_A and
       // X1_p^T A2), re-evaluate X_p without a change pass, then allow one
       // more X1 update (the refinement sweep) within max_sweeps.
-      mixed_status = sh.status;
+      mixed_status = sh->status;
       on_bf16 = false;
       reeval = true;
-      sh.done = 0;
-      sh.have_prev = 0;
-      sh.tol = pr->tol;
-      sh.max_sweeps = std::min(p + 1, max_sweeps);
-      sh.eig_floor = eig_tol;
-      HIPCHK(hipMemcpyAsync(P.st, &sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
+      sh->done = 0;
+      sh->have_prev = 0;
+      sh->tol = pr->tol;
+      sh->max_sweeps = std::min(p + 1, max_sweeps);
+      sh->eig_floor = eig_tol;
+      (void)hipMemcpyAsync(P.st, sh, sizeof(SmallState), hipMemcpyHostToDevice, s);
       gram_A2(false);
-      PROF(h, KK_GAST, launch_gastats(s, (int)n2, P.GA, P.st));
+      PROFWS(h, s, KK_GAST, 0, 0, launch_gastats(s, (int)n2, P.GA, P.st));
       if (k > 0) gram_X1A2(X1c, false);
-      --p;
-      continue;
+      return 2;
     }
-    if (sh.done) break;
-    // X1_{p+1} from X1_p (Algorithm 1 steps 7-9), then the sums for p+1.
+    return sh->done ? 1 : 0;
+  }
+
+  // X1_{p+1} from X1_p (Algorithm 1 steps 7-9), then the sums for p+1.
+  void update() {
     T *X1n = static_cast<T *>(P.X1[cur ^ 1]);
     UpdateArgs<T> ua{};
     ua.m = m; ua.k = (int)k; ua.n = (int)pr->n; ua.A = A; ua.lda = lda; ua.W1 = W1;
@@ -611,68 +831,326 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws) 
     ua.flags = P.flags;
     // reads A1, A2, X1_p (and W1), writes X1_{p+1}; the product
     // [A1 A2 X1] [-S; Z; T] and, for a matrix W1, the per-row SPD solves
-    PROFW(h, KK_UPDATE,
-          md * (n2d * (on_bf16 ? 2.0 : es) + (3.0 + (constw ? 0.0 : 1.0)) * kd * es),
-          2.0 * md * ((double)pr->n + kd) * kd +
-              (constw ? 0.0 : md * (kd * kd * kd / 3.0 + 2.0 * kd * kd)),
-          launch_update<T>(s, ua));
+    PROFWS(h, s, KK_UPDATE,
+           md * (n2d * (on_bf16 ? 2.0 : es) + (3.0 + (constw ? 0.0 : 1.0)) * kd * es),
+           2.0 * md * ((double)pr->n + kd) * kd +
+               (constw ? 0.0 : md * (kd * kd * kd / 3.0 + 2.0 * kd * kd)),
+           launch_update<T>(s, ua));
     gram_X1A2(X1n, on_bf16);
-    PROFW(h, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
-         (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_g1, z.rows_g1,
-                              P.part, P.G1, nullptr)));
+    PROFWS(h, s, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
+           (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_g1, z.rows_g1,
+                                P.part, P.G1, nullptr)));
     nparts = z.nwg_upd;
     cur ^= 1;
     X1c = X1n;
+    ++p;
   }
-  HIPCHK(hipMemcpyAsync(h->flags_host, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+
+  // Failure flags of the device (after a synchronisation).
+  static int device_status(int dflags) {
+    // a failed row solve first: a rank-deficient X1 can follow from it
+    if (dflags & DEV_ROWSOLVE) return WLRA_E_ROWSOLVE;
+    if (dflags & DEV_RANK) return WLRA_E_RANK;
+    if (dflags & DEV_EIG_ORTH) return WLRA_E_EIG;
+    return WLRA_OK;
+  }
+  // Outputs of the returned X_p.
+  int outputs() {
+    if (k > 0)
+      PROFWS(h, s, KK_COPY, 0, 0,
+             launch_copy_out<T>(s, m, k, X1c, static_cast<T *>(pr->X1_out), pr->ldx1));
+    if (pr->factors_out != nullptr) {
+      // R (k x k), C (k x n2), V (n2 x l), theta (l): the returned X_p's factors
+      double *f = pr->factors_out;
+      const size_t d = sizeof(double);
+      if (k > 0) {
+        HIPCHK(hipMemcpyAsync(f, P.R, (size_t)(k * k) * d, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(f + k * k, P.C, (size_t)(k * n2) * d, hipMemcpyDeviceToDevice, s));
+      }
+      if (l > 0) {
+        HIPCHK(hipMemcpyAsync(f + k * k + k * n2, P.Y, (size_t)(n2 * l) * d,
+                              hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(f + k * k + k * n2 + n2 * l, P.theta, (size_t)l * d,
+                              hipMemcpyDeviceToDevice, s));
+      }
+    }
+    if (pr->X2_out != nullptr || pr->mask_out != nullptr)
+      PROFWS(h, s, KK_X2, 0, 0,
+             launch_x2<T>(s, m, (int)k, (int)n2, (int)l, A, lda, X1c, so.Zx, so.Vr,
+                          static_cast<T *>(pr->X2_out), pr->ldx2, W2, pr->mask_out, pr->ldm,
+                          (T)pr->mask_tau));
+    return WLRA_OK;
+  }
+  // The result record (ms: the caller's measurement).
+  int result(float ms) {
+    int status = (k == 0) ? WLRA_OK : (mixed ? mixed_status : sh->status);
+    // the eigen step of the returned X_p's sweep (each step sets eig_fail)
+    if (sh->eig_fail) status = WLRA_INEXACT;
+    if (res) {
+      res->status = status;
+      res->sweeps = sh->sweep;
+      res->objective = sh->F;
+      res->abs_change = sh->err;
+      res->rel_change = sh->rel;
+      res->gap = sh->gap;
+      res->ms = ms;
+      res->eig_iters = sh->eig_iters;
+      res->eig_matvecs = sh->eig_matvecs;
+    }
+    return status;
+  }
+};
+
+// One solve.  ws: a workspace of at least make_layout(...).total bytes.
+template <typename T>
+int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws,
+               bool may_tune = true) {
+  hipStream_t s = h->stream;
+  HIPCHK(hipEventRecord(h->ev0, s));
+  Run<T> r;
+  r.may_tune = may_tune;
+  int rc = r.begin(h, pr, res, ws, s, h->st_host);
+  if (rc != WLRA_OK) return rc;
+  HIPCHK(hipMemcpyAsync(h->flags_host, r.P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const int dflags = *h->flags_host;
-  // a failed row solve first: a rank-deficient X1 can follow from it
-  if (dflags & DEV_ROWSOLVE) return WLRA_E_ROWSOLVE;
-  if (dflags & DEV_RANK) return WLRA_E_RANK;
-  if (dflags & DEV_EIG_ORTH) return WLRA_E_EIG;
-  if (k > 0)
-    PROF(h, KK_COPY, launch_copy_out<T>(s, m, k, X1c, static_cast<T *>(pr->X1_out), pr->ldx1));
-  if (pr->factors_out != nullptr) {
-    // R (k x k), C (k x n2), V (n2 x l), theta (l): the returned X_p's factors
-    double *f = pr->factors_out;
-    const size_t d = sizeof(double);
-    if (k > 0) {
-      HIPCHK(hipMemcpyAsync(f, P.R, (size_t)(k * k) * d, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(f + k * k, P.C, (size_t)(k * n2) * d, hipMemcpyDeviceToDevice, s));
-    }
-    if (l > 0) {
-      HIPCHK(hipMemcpyAsync(f + k * k + k * n2, P.Y, (size_t)(n2 * l) * d,
-                            hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(f + k * k + k * n2 + n2 * l, P.theta, (size_t)l * d,
-                            hipMemcpyDeviceToDevice, s));
-    }
+  rc = Run<T>::input_status(*h->flags_host);
+  if (rc != WLRA_OK) return rc;
+  for (;;) {
+    r.small_args();
+    r.small_single();
+    r.panel();
+    if (r.change_needed()) r.change(false);
+    PROFWS(h, s, KK_DECIDE, 0, 0, launch_decide(s, r.sa));
+    HIPCHK(hipMemcpyAsync(h->st_host, r.P.st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    prof_collect(h);
+    const int d = r.after_decide();
+    if (d == 1) break;
+    if (d == 2) continue;
+    r.update();
   }
-  if (pr->X2_out != nullptr || pr->mask_out != nullptr)
-    PROF(h, KK_X2,
-         launch_x2<T>(s, m, (int)k, (int)n2, (int)l, A, lda, X1c, so.Zx, so.Vr,
-                      static_cast<T *>(pr->X2_out), pr->ldx2, W2, pr->mask_out, pr->ldm,
-                      (T)pr->mask_tau));
+  HIPCHK(hipMemcpyAsync(h->flags_host, r.P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  rc = Run<T>::device_status(*h->flags_host);
+  if (rc != WLRA_OK) return rc;
+  rc = r.outputs();
+  if (rc != WLRA_OK) return rc;
   HIPCHK(hipEventRecord(h->ev1, s));
   HIPCHK(hipEventSynchronize(h->ev1));
   prof_collect(h);
   float ms = 0.f;
   hipEventElapsedTime(&ms, h->ev0, h->ev1);
-  int status = (k == 0) ? WLRA_OK : (mixed ? mixed_status : sh.status);
-  // the eigen step of the returned X_p's sweep (each step sets eig_fail)
-  if (sh.eig_fail) status = WLRA_INEXACT;
-  if (res) {
-    res->status = status;
-    res->sweeps = sh.sweep;
-    res->objective = sh.F;
-    res->abs_change = sh.err;
-    res->rel_change = sh.rel;
-    res->gap = sh.gap;
-    res->ms = ms;
-    res->eig_iters = sh.eig_iters;
-    res->eig_matvecs = sh.eig_matvecs;
+  return r.result(ms);
+}
+
+// ---------------------------------------------------------------------------
+// Batch engine (wlra_solve_batched): every instance is a Run with its own
+// workspace slice.  The instances advance one sweep per round in lockstep:
+// the single-workgroup small steps of all active instances (coefficients,
+// M, the eigen step, the post step, the change pass's basis, the decision)
+// run as one launch each, one workgroup per instance, so that a batch of
+// clips fills the device where one clip's small step uses one CU; the
+// streaming passes of each instance are enqueued on the batch streams
+// (round robin); one read-back of all sweep states per round drives the
+// host side (trace, end of the mixed phase, which instances update).
+template <typename T>
+int batch_impl(wlra_ctx *h, int count, const wlra_problem *probs, wlra_result *res) {
+  const int ns = std::max(1, std::min(h->batch_lanes, count));
+  int rc = ensure_batch_streams(h, ns);
+  if (rc != WLRA_OK) return rc;
+  std::vector<hipStream_t> strm(ns);
+  strm[0] = h->stream;
+  for (int j = 1; j < ns; ++j) strm[j] = h->bstreams[j - 1];
+  // workspace slices, argument blocks, state copies
+  std::vector<size_t> off(count);
+  size_t tot = 0;
+  for (int i = 0; i < count; ++i) {
+    off[i] = tot;
+    tot += (workspace_bytes(probs[i], h->precision) + 255) & ~(size_t)255;
   }
-  return status;
+  const size_t a_sa = ((size_t)count * sizeof(SmallArgs) + 255) & ~(size_t)255;
+  const size_t a_so = ((size_t)count * sizeof(SmallOut<T>) + 255) & ~(size_t)255;
+  const size_t a_ch = ((size_t)count * sizeof(ChgArgs) + 255) & ~(size_t)255;
+  const size_t a_st = ((size_t)count * sizeof(SmallState) + 255) & ~(size_t)255;
+  const size_t a_pa = ((size_t)count * sizeof(PanelArgs) + 255) & ~(size_t)255;
+  const size_t dev_bytes = tot + 2 * a_sa + a_so + a_ch + a_st + a_pa;
+  rc = ensure_batch_ws(h, dev_bytes);
+  if (rc != WLRA_OK) return rc;
+  const size_t host_bytes = 2 * a_sa + a_so + a_ch + 2 * a_st + a_pa + (size_t)count * sizeof(int);
+  rc = ensure_batch_host(h, host_bytes, count);
+  if (rc != WLRA_OK) return rc;
+  char *dws = h->bws;
+  SmallArgs *av_d = reinterpret_cast<SmallArgs *>(dws + tot);
+  SmallArgs *ae_d = reinterpret_cast<SmallArgs *>(dws + tot + a_sa);
+  SmallOut<T> *ov_d = reinterpret_cast<SmallOut<T> *>(dws + tot + 2 * a_sa);
+  ChgArgs *ch_d = reinterpret_cast<ChgArgs *>(dws + tot + 2 * a_sa + a_so);
+  SmallState *stall_d = reinterpret_cast<SmallState *>(dws + tot + 2 * a_sa + a_so + a_ch);
+  PanelArgs *pa_d = reinterpret_cast<PanelArgs *>(dws + tot + 2 * a_sa + a_so + a_ch + a_st);
+  char *hb = h->bhost;
+  SmallArgs *av_h = reinterpret_cast<SmallArgs *>(hb);
+  SmallArgs *ae_h = reinterpret_cast<SmallArgs *>(hb + a_sa);
+  SmallOut<T> *ov_h = reinterpret_cast<SmallOut<T> *>(hb + 2 * a_sa);
+  ChgArgs *ch_h = reinterpret_cast<ChgArgs *>(hb + 2 * a_sa + a_so);
+  SmallState *stall_h = reinterpret_cast<SmallState *>(hb + 2 * a_sa + a_so + a_ch);
+  SmallState *sh_h = reinterpret_cast<SmallState *>(hb + 2 * a_sa + a_so + a_ch + a_st);
+  PanelArgs *pa_h = reinterpret_cast<PanelArgs *>(hb + 2 * a_sa + a_so + a_ch + 2 * a_st);
+  int *flags_h = reinterpret_cast<int *>(hb + 2 * a_sa + a_so + a_ch + 2 * a_st + a_pa);
+
+  // ordering helpers: main waits for the other streams, or they for main
+  auto join = [&]() -> int {
+    for (int j = 1; j < ns; ++j) {
+      HIPCHK(hipEventRecord(h->bjoin[j], strm[j]));
+      HIPCHK(hipStreamWaitEvent(strm[0], h->bjoin[j], 0));
+    }
+    return WLRA_OK;
+  };
+  auto fork = [&]() -> int {
+    HIPCHK(hipEventRecord(h->bjoin[0], strm[0]));
+    for (int j = 1; j < ns; ++j) HIPCHK(hipStreamWaitEvent(strm[j], h->bjoin[0], 0));
+    return WLRA_OK;
+  };
+
+  HIPCHK(hipEventRecord(h->ev0, strm[0]));
+  rc = fork();
+  if (rc != WLRA_OK) return rc;
+  std::vector<Run<T>> runs(count);
+  std::vector<int> state(count, 0);  // 0 active, 1 finished, -1 failed
+  for (int i = 0; i < count; ++i) {
+    rc = runs[i].begin(h, &probs[i], &res[i], dws + off[i], strm[i % ns], &sh_h[i]);
+    if (rc != WLRA_OK) return rc;
+    HIPCHK(hipMemcpyAsync(&flags_h[i], runs[i].P.flags, sizeof(int), hipMemcpyDeviceToHost,
+                          runs[i].s));
+  }
+  for (int j = 0; j < ns; ++j) HIPCHK(hipStreamSynchronize(strm[j]));
+  prof_collect(h);
+  for (int i = 0; i < count; ++i) {
+    const int st = Run<T>::input_status(flags_h[i]);
+    if (st != WLRA_OK) {
+      memset(&res[i], 0, sizeof(wlra_result));
+      res[i].status = st;
+      state[i] = -1;
+    }
+  }
+  std::vector<int> order, eig_list, chg_list, pan_list;
+  for (;;) {
+    order.clear();
+    for (int i = 0; i < count; ++i)
+      if (state[i] == 0) order.push_back(i);
+    if (order.empty()) break;
+    // instances by coefficient class (the kernel's k bound), stable
+    auto kcls = [&](int i) { const int64_t k = probs[i].k; return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return kcls(a) < kcls(b); });
+    const int na = (int)order.size();
+    eig_list.clear();
+    chg_list.clear();
+    pan_list.clear();
+    int n2max = 0;
+    for (int q = 0; q < na; ++q) {
+      Run<T> &r = runs[order[q]];
+      r.small_args();
+      av_h[q] = r.sa;
+      ov_h[q] = r.so;
+      n2max = std::max(n2max, (int)r.n2);
+      if (r.l > 0) {
+        ae_h[eig_list.size()] = r.sa;
+        eig_list.push_back(order[q]);
+      }
+      if (r.change_needed()) {
+        ch_h[chg_list.size()] = r.chg_args();
+        chg_list.push_back(order[q]);
+      }
+      if (r.panel_needed()) {
+        pa_h[pan_list.size()] = r.panel_args();
+        pan_list.push_back(order[q]);
+      }
+    }
+    rc = join();
+    if (rc != WLRA_OK) return rc;
+    hipStream_t s0 = strm[0];
+    HIPCHK(hipMemcpyAsync(av_d, av_h, (size_t)na * sizeof(SmallArgs), hipMemcpyHostToDevice, s0));
+    HIPCHK(hipMemcpyAsync(ov_d, ov_h, (size_t)na * sizeof(SmallOut<T>), hipMemcpyHostToDevice, s0));
+    if (!eig_list.empty())
+      HIPCHK(hipMemcpyAsync(ae_d, ae_h, eig_list.size() * sizeof(SmallArgs),
+                            hipMemcpyHostToDevice, s0));
+    if (!chg_list.empty())
+      HIPCHK(hipMemcpyAsync(ch_d, ch_h, chg_list.size() * sizeof(ChgArgs),
+                            hipMemcpyHostToDevice, s0));
+    if (!pan_list.empty())
+      HIPCHK(hipMemcpyAsync(pa_d, pa_h, pan_list.size() * sizeof(PanelArgs),
+                            hipMemcpyHostToDevice, s0));
+    for (int q0 = 0; q0 < na;) {
+      int q1 = q0;
+      while (q1 < na && kcls(order[q1]) == kcls(order[q0])) ++q1;
+      PROFWS(h, s0, KK_COEF, 0, 0, launch_coef_b(s0, kcls(order[q0]), q1 - q0, av_d + q0));
+      q0 = q1;
+    }
+    if (!eig_list.empty()) {
+      int n2e = 0;
+      for (int i : eig_list) n2e = std::max(n2e, (int)runs[i].n2);
+      PROFWS(h, s0, KK_FORMM, 0, 0, launch_formM_b(s0, (int)eig_list.size(), n2e, ae_d));
+      PROFWS(h, s0, KK_EIG, 0, 0, launch_eig_b(s0, (int)eig_list.size(), ae_d));
+    }
+    PROFWS(h, s0, KK_POST, 0, 0, launch_post_b<T>(s0, na, n2max, av_d, ov_d));
+    if (!pan_list.empty())
+      PROFWS(h, s0, KK_POST, 0, 0, launch_panel_bf16_b(s0, (int)pan_list.size(), pa_d));
+    if (!chg_list.empty()) {
+      PROFWS(h, s0, KK_CHGQR, 0, 0, launch_chgprep_b(s0, (int)chg_list.size(), ch_d));
+      rc = fork();
+      if (rc != WLRA_OK) return rc;
+      for (int i : chg_list) runs[i].change(true);
+      rc = join();
+      if (rc != WLRA_OK) return rc;
+    }
+    PROFWS(h, s0, KK_DECIDE, 0, 0, launch_decide_b(s0, na, av_d, stall_d));
+    HIPCHK(hipMemcpyAsync(stall_h, stall_d, (size_t)na * sizeof(SmallState),
+                          hipMemcpyDeviceToHost, s0));
+    HIPCHK(hipStreamSynchronize(s0));
+    prof_collect(h);
+    rc = fork();
+    if (rc != WLRA_OK) return rc;
+    for (int q = 0; q < na; ++q) {
+      const int i = order[q];
+      Run<T> &r = runs[i];
+      *r.sh = stall_h[q];
+      const int d = r.after_decide();
+      if (d == 1) {
+        state[i] = 1;
+        // the instance's solve is complete on the device here (its outputs
+        // follow at the end of the batch)
+        HIPCHK(hipEventRecord(h->bdone[i], s0));
+        HIPCHK(hipMemcpyAsync(&flags_h[i], r.P.flags, sizeof(int), hipMemcpyDeviceToHost, r.s));
+      } else if (d == 0) {
+        r.update();
+      }
+    }
+  }
+  for (int j = 0; j < ns; ++j) HIPCHK(hipStreamSynchronize(strm[j]));
+  prof_collect(h);
+  // outputs of the finished instances, each timed from the batch's start to
+  // the end of its outputs on its stream
+  for (int i = 0; i < count; ++i) {
+    if (state[i] != 1) continue;
+    const int st = Run<T>::device_status(flags_h[i]);
+    if (st != WLRA_OK) {
+      memset(&res[i], 0, sizeof(wlra_result));
+      res[i].status = st;
+      state[i] = -1;
+      continue;
+    }
+    rc = runs[i].outputs();
+    if (rc != WLRA_OK) return rc;
+  }
+  rc = join();
+  if (rc != WLRA_OK) return rc;
+  for (int j = 0; j < ns; ++j) HIPCHK(hipStreamSynchronize(strm[j]));
+  prof_collect(h);
+  for (int i = 0; i < count; ++i) {
+    if (state[i] != 1) continue;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, h->ev0, h->bdone[i]);
+    runs[i].result(ms);
+  }
+  return WLRA_OK;
 }
 
 }  // namespace
@@ -725,7 +1203,8 @@ int wlra_create(wlra_handle *out, int device, void *hip_stream, int precision, u
   h->flags = flags;
   if (hipHostMalloc((void **)&h->st_host, sizeof(SmallState), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&h->flags_host, 64, hipHostMallocDefault) != hipSuccess ||
-      hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+      hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+      hipEventCreate(&h->tev0) != hipSuccess || hipEventCreate(&h->tev1) != hipSuccess) {
     wlra_destroy(h);
     return WLRA_E_HIP;
   }
@@ -771,8 +1250,9 @@ int wlra_solve_noalloc(wlra_handle h, const wlra_problem *prob, wlra_result *res
   if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
   char *ws = static_cast<char *>(scratch_ptr(h->device));
   if (ws == nullptr) return WLRA_E_HIP;
-  rc = (h->precision == WLRA_FP64) ? solve_impl<double>(h, prob, res, ws)
-                                   : solve_impl<float>(h, prob, res, ws);
+  // no new autotuner entries: inserting one would allocate host memory
+  rc = (h->precision == WLRA_FP64) ? solve_impl<double>(h, prob, res, ws, false)
+                                   : solve_impl<float>(h, prob, res, ws, false);
   if (rc < 0 && res) res->status = rc;
   return rc;
 }
@@ -788,12 +1268,13 @@ int wlra_set_option(wlra_handle h, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return WLRA_E_ARG;
       h->eig_one_wg = (int)value;
       break;
+    case WLRA_OPT_AUTOTUNE:
+      if (value != 0 && value != 1) return WLRA_E_ARG;
+      h->autotune = (int)value;
+      break;
     default:
       return WLRA_E_ARG;
   }
-  // batch lanes keep the one-workgroup eigen kernel (see ensure_lanes)
-  for (wlra_ctx *L : h->lanes)
-    if (option != WLRA_OPT_EIG_ONE_WG) wlra_set_option(L, option, value);
   return WLRA_OK;
 }
 
@@ -803,33 +1284,7 @@ int wlra_set_batch_lanes(wlra_handle h, int32_t lanes) {
   return WLRA_OK;
 }
 
-namespace {
 
-// Sub-handles for batched solves: one non-blocking stream (default priority)
-// and one workspace each.
-int ensure_lanes(wlra_ctx *h, int want) {
-  while ((int)h->lanes.size() < want) {
-    hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return WLRA_E_HIP;
-    wlra_ctx *sub = nullptr;
-    const int rc = wlra_create(&sub, h->device, st, h->precision, h->flags);
-    if (rc != WLRA_OK) {
-      (void)hipStreamDestroy(st);
-      return rc;
-    }
-    sub->owns_stream = true;
-    sub->eig_maxit = h->eig_maxit;
-    // No cooperative launches on the lanes: a process that had run the
-    // cooperative eigen kernel on four concurrent lane streams ended with a
-    // segmentation fault at exit (cause not shown).  Each lane's eigen step
-    // runs in one workgroup, which leaves the other CUs to the other lanes.
-    sub->eig_one_wg = 1;
-    h->lanes.push_back(sub);
-  }
-  return WLRA_OK;
-}
-
-}  // namespace
 
 int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs, wlra_result *res) {
   if (h == nullptr || count < 0 || (count > 0 && (probs == nullptr || res == nullptr)))
@@ -838,75 +1293,24 @@ int wlra_solve_batched(wlra_handle h, int32_t count, const wlra_problem *probs, 
     if (check_problem(&probs[i], h->precision) == WLRA_E_ARG) return WLRA_E_ARG;
   if (count == 0) return WLRA_OK;
   if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
-  const int nl = std::min<int>(count, h->batch_lanes);
-  if (nl <= 1) {
-    for (int i = 0; i < count; ++i) wlra_solve(h, &probs[i], &res[i]);
-    return WLRA_OK;
-  }
-  int rc = ensure_lanes(h, nl);
-  if (rc != WLRA_OK) return rc;
-  // Largest instances first (longest-processing-time order): the lanes take
-  // the next instance as they free up, so small clips fill in around big ones.
-  std::vector<int> order(count);
-  size_t ws_max = 0;
   for (int i = 0; i < count; ++i) {
-    order[i] = i;
-    ws_max = std::max(ws_max, workspace_bytes(probs[i], h->precision));
+    memset(&res[i], 0, sizeof(wlra_result));
+    const int rc = check_problem(&probs[i], h->precision);
+    res[i].status = rc;  // WLRA_E_WEIGHT (a bad constant weight) is per instance
   }
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return probs[a].m * probs[a].n > probs[b].m * probs[b].n;
-  });
-  // Grow every lane's workspace once, before any lane starts (a free while
-  // other lanes run would synchronise the device).
-  for (int j = 0; j < nl; ++j) {
-    wlra_ctx *L = h->lanes[j];
-    if (hipSetDevice(h->device) != hipSuccess) return WLRA_E_HIP;
-    rc = ensure_ws(L, ws_max);
-    if (rc != WLRA_OK) return rc;
-  }
-  // Order the lanes after the work already queued on the caller's stream.
-  hipEvent_t ev = nullptr;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return WLRA_E_HIP;
-  if (hipEventRecord(ev, h->stream) != hipSuccess) return WLRA_E_HIP;
-  for (int j = 0; j < nl; ++j)
-    if (hipStreamWaitEvent(h->lanes[j]->stream, ev, 0) != hipSuccess) return WLRA_E_HIP;
-  std::atomic<int> next{0};
-  auto work = [&](int j) {
-    wlra_ctx *L = h->lanes[j];
-    for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) {
-      const int i = order[q];
-      wlra_solve(L, &probs[i], &res[i]);
+  std::vector<wlra_problem> ok;
+  std::vector<int> idx;
+  for (int i = 0; i < count; ++i)
+    if (res[i].status == WLRA_OK) {
+      ok.push_back(probs[i]);
+      idx.push_back(i);
     }
-  };
-  std::vector<std::thread> th;
-  try {
-    for (int j = 1; j < nl; ++j) th.emplace_back(work, j);
-  } catch (...) {
-    // no more threads: the lanes already started share the remaining work
-  }
-  work(0);
-  for (auto &t : th) t.join();
-  // The caller's stream continues after every lane.
-  for (int j = 0; j < nl; ++j) {
-    wlra_ctx *L = h->lanes[j];
-    if (hipEventRecord(ev, L->stream) != hipSuccess ||
-        hipStreamWaitEvent(h->stream, ev, 0) != hipSuccess) {
-      (void)hipEventDestroy(ev);
-      return WLRA_E_HIP;
-    }
-    for (int kk = 0; kk < KK_COUNT; ++kk) {
-      h->ms[kk] += L->ms[kk];
-      h->launches[kk] += L->launches[kk];
-      h->bytes[kk] += L->bytes[kk];
-      h->flops[kk] += L->flops[kk];
-      L->ms[kk] = 0.0;
-      L->launches[kk] = 0;
-      L->bytes[kk] = 0.0;
-      L->flops[kk] = 0.0;
-    }
-  }
-  (void)hipEventDestroy(ev);
-  return WLRA_OK;
+  if (ok.empty()) return WLRA_OK;
+  std::vector<wlra_result> rr(ok.size());
+  const int rc = (h->precision == WLRA_FP64) ? batch_impl<double>(h, (int)ok.size(), ok.data(), rr.data())
+                                             : batch_impl<float>(h, (int)ok.size(), ok.data(), rr.data());
+  for (size_t q = 0; q < ok.size(); ++q) res[idx[q]] = rr[q];
+  return rc < 0 ? rc : WLRA_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1123,8 +1527,14 @@ int wlra_profile(wlra_handle h, int32_t max, wlra_kstat *out, int32_t reset) {
 
 int wlra_destroy(wlra_handle h) {
   if (h == nullptr) return WLRA_OK;
-  for (wlra_ctx *L : h->lanes) wlra_destroy(L);
-  h->lanes.clear();
+  for (hipStream_t st : h->bstreams)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t e : h->bjoin)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->bdone)
+    if (e) (void)hipEventDestroy(e);
+  if (h->bws) (void)hipFree(h->bws);
+  if (h->bhost) (void)hipHostFree(h->bhost);
   for (auto &pe : h->pending) {
     h->pool.push_back(pe.e0);
     h->pool.push_back(pe.e1);
@@ -1137,6 +1547,8 @@ int wlra_destroy(wlra_handle h) {
   if (h->flags_host) hipHostFree(h->flags_host);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  if (h->tev0) hipEventDestroy(h->tev0);
+  if (h->tev1) hipEventDestroy(h->tev1);
   if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return WLRA_OK;

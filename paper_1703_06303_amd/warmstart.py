@@ -52,9 +52,9 @@ def target_basis(C, V, k, r):
     return T.reshape(-1)
 
 
-def build_dataset(solver, pool, seeds, k=20, r=25, tol=1e-7):
+def build_dataset(solver, pool, seeds, k=20, r=25, tol=1e-7, log=None):
     """Sketches X (N x 512) and targets T (N x n r) of config-2 clips, from
-    GPU solves started at A1."""
+    GPU solves started at A1.  log(msg) is called every 500 clips."""
     import torch
     from . import wlra
     X, T, info = [], [], []
@@ -67,6 +67,8 @@ def build_dataset(solver, pool, seeds, k=20, r=25, tol=1e-7):
         R, C, V, th = res["factors"]
         T.append(target_basis(C, V, k, r))
         info.append((seed, res["status"], res["sweeps"], res["objective"]))
+        if log and len(info) % 500 == 0:
+            log(f"{len(info)} clips solved ({time.perf_counter() - t0:.0f} s)")
     return torch.stack(X), torch.stack(T), info, time.perf_counter() - t0
 
 
@@ -97,7 +99,8 @@ def train(solver, X, T, n, r, epochs=30, batch=128, lr=1e-3, seed=1, log=None):
     return params, hist
 
 
-def evaluate(solver, pool, params, seeds, k=20, r=25, tol=1e-7, inits=("random", "a1", "learned")):
+def evaluate(solver, pool, params, seeds, k=20, r=25, tol=1e-7, inits=("random", "a1", "learned"),
+             log=None):
     """Solve each held-out clip from each start; returns {init: [(sweeps,
     ms, objective, status)]}."""
     import torch
@@ -110,6 +113,8 @@ def evaluate(solver, pool, params, seeds, k=20, r=25, tol=1e-7, inits=("random",
             _, _, res = solver.solve(Ad, k, r, W1=Wd, tol=tol, init=init, seed=seed,
                                      model=params if init == "learned" else None)
             out[init].append((res["sweeps"], res["ms"], res["objective"], res["status"]))
+        if log and len(out[inits[0]]) % 250 == 0:
+            log(f"{len(out[inits[0]])} held-out clips evaluated")
     return out
 
 

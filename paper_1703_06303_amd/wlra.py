@@ -17,7 +17,7 @@ OK, MAX_SWEEPS, INEXACT = 0, 1, 2
 E_ARG, E_WEIGHT, E_NONFINITE, E_RANK, E_NOMEM, E_HIP, E_NODEVICE = -1, -2, -3, -4, -5, -6, -7
 E_ROWSOLVE, E_EIG, E_SCRATCH = -8, -9, -10
 NOALLOC_SCRATCH_BYTES = 32 << 20
-OPT_EIG_MAXIT, OPT_EIG_ONE_WG = 1, 2
+OPT_EIG_MAXIT, OPT_EIG_ONE_WG, OPT_AUTOTUNE = 1, 2, 3
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 INIT_RANDOM, INIT_GIVEN, INIT_A1, INIT_LEARNED = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16}

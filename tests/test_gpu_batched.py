@@ -1,9 +1,10 @@
 """Batched solves (wlra_solve_batched) on the GPU through the C ABI.
 
-A batch runs its instances concurrently on several lanes (streams with their
-own workspaces).  Each instance must come out exactly as a single solve of it
-would (the kernels are deterministic), match the FP64 oracle, and report its
-own status.
+A batch advances its instances in lockstep: the single-workgroup small steps
+of all of them run as one launch each, their streaming passes on several
+streams.  Each instance must come out exactly as a single solve of it would
+(the kernels are deterministic and the batch runs the same ones), match the
+FP64 oracle, and report its own status.
 """
 import numpy as np
 import pytest

@@ -37,7 +37,7 @@ def test_option_range_checks():
     from paper_1703_06303_amd import wlra
     with wlra.Solver("fp32") as s:
         for opt, val in ((wlra.OPT_EIG_MAXIT, 0), (wlra.OPT_EIG_MAXIT, 100001),
-                         (wlra.OPT_EIG_ONE_WG, 2), (99, 1)):
+                         (wlra.OPT_EIG_ONE_WG, 2), (wlra.OPT_AUTOTUNE, 2), (99, 1)):
             with pytest.raises(wlra.WlraError) as e:
                 s.set_option(opt, val)
             assert e.value.code == wlra.E_ARG
@@ -52,3 +52,32 @@ def test_row_solve_pivot_reports_error():
         _, _, res = gpu_solve(s, inst, 0.0, 1, dense_w=True)
     print("row solve pivot", res, flush=True)
     assert res["rc"] == wlra.E_ROWSOLVE and res["status"] == wlra.E_ROWSOLVE
+
+
+def test_autotuned_products_keep_parity():
+    """The autotuner (on by default) changes only the row splits of the
+    tall-skinny products: on the 19200 x 200 workload the solve with it on
+    and off reaches the oracle's iterate at equal sweeps within the FP32 bar,
+    a second solve on the same handle (tuned entry reused) repeats the first
+    bit for bit, and a converged solve meets F* within 1e-6."""
+    from oracle import swlr as O
+    from paper_1703_06303_amd import wlra
+    from .gpu_util import rel
+    inst = video.config2()
+    ref = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=0.0, max_sweeps=3, X1_0=inst.X1_0)
+    out = {}
+    for tune in (0, 1):
+        with wlra.Solver("fp32") as s:
+            s.set_option(wlra.OPT_AUTOTUNE, tune)
+            a = gpu_solve(s, inst, 0.0, 3)
+            b = gpu_solve(s, inst, 0.0, 3)
+            c = gpu_solve(s, inst, 1e-7, 200)
+        e = rel(np.hstack([a[0], a[1]]), ref.X)
+        print("autotune", tune, "relX", e, "F", c[2]["objective"], flush=True)
+        assert e <= 1e-5
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        out[tune] = c[2]
+    fs = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=1e-13, max_sweeps=500, X1_0=inst.X1_0).F[-1]
+    for tune in (0, 1):
+        assert out[tune]["rc"] == 0
+        assert abs(out[tune]["objective"] - fs) <= 1e-6 * fs
