@@ -647,8 +647,10 @@ __global__ __launch_bounds__(64) void k_rowsolve_reg(
     int64_t m, int k, const T *__restrict__ A, int64_t lda, const T *__restrict__ W1, int64_t ldw,
     const T *__restrict__ X1o, T *__restrict__ X1n, const T *__restrict__ Eb,
     const T *__restrict__ St, double *__restrict__ part, const SmallState *__restrict__ st,
-    int *flags) {
+    int *flags, const int *__restrict__ cgflag) {
   if (st->done) return;
+  // after the CG solve, only when it left rows unsolved in this sweep
+  if (cgflag != nullptr && *cgflag != st->sweep + 1) return;
   const int lane = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const bool act = i < m;
@@ -728,6 +730,132 @@ __global__ __launch_bounds__(64) void k_rowsolve_reg(
   if (bad) atomicOr(flags, DEV_ROWSOLVE);
 }
 
+// Per-row solves by preconditioned conjugate gradients (float storage): one
+// row per thread, K_i = diag(w_i^2) + S with S = C C^T shared (in LDS,
+// zero-padded to KP x KP, read by every lane at once), the Jacobi
+// preconditioner diag(K_i).  With P_i = diag(K_i), P_i^-1/2 K_i P_i^-1/2 =
+// I + E_i with ||E_i|| <= ||S|| / min w^2, so the iteration contracts fast
+// when the weights dominate C C^T (on the 19200 x 200 workload ||S|| = 17
+// against min w^2 = 100; rows where ||S||_F > min w^2 / 2 are not
+// attempted).  A row stops when ||r|| <= 2^-21 ||e||; a row still
+// above it after CG_MAXIT iterations marks the sweep in *cgflag (sweep + 1),
+// and the direct per-row Cholesky kernel launched after this one then
+// solves every row again.  Reads and epilogue as k_rowsolve_reg.
+#define CG_MAXIT 40
+template <int KP>
+__global__ __launch_bounds__(256) void k_rowsolve_cg(
+    int64_t m, int k, const float *__restrict__ A, int64_t lda, const float *__restrict__ W1,
+    int64_t ldw, const float *__restrict__ X1o, float *__restrict__ X1n,
+    const float *__restrict__ Eb, const float *__restrict__ St, double *__restrict__ part,
+    const SmallState *__restrict__ st, int *cgflag) {
+  if (st->done) return;
+  __shared__ __align__(16) float sS[KP * KP];
+  __shared__ double red[4];
+  const int t = threadIdx.x, lane = t & 63;
+  double s2 = 0.0;
+  for (int e2 = t; e2 < KP * KP; e2 += 256) {
+    const int r2 = e2 / KP, c2 = e2 - r2 * KP;
+    const float v = (r2 < k && c2 < k) ? St[r2 * k + c2] : 0.f;
+    sS[e2] = v;
+    s2 += (double)v * v;
+  }
+  // ||S||_F (>= ||S||_2): a row is left to the direct solve unless
+  // ||S||_F <= min w^2 / 2, which bounds the preconditioned matrix's
+  // eigenvalues to [1/2, 3/2]
+  const float snorm = (float)sqrt(block_sum(s2, red));
+  const int64_t i = (int64_t)blockIdx.x * 256 + t;
+  const bool act = i < m;
+  const int64_t ir = act ? i : (m - 1);
+  // x, r, p, q and w^2 per row in registers; the Jacobi preconditioner
+  // diag(K) = w^2 + diag(S) is re-read from LDS where it is needed (1 in the
+  // padding, where r stays 0)
+  float x[KP], r[KP], p[KP], q[KP], wq[KP];
+  auto dinv = [&](int c) { return 1.f / (wq[c] + sS[c * KP + c] + (c < k ? 0.f : 1.f)); };
+  float ee = 0.f;
+#pragma unroll
+  for (int c = 0; c < KP; ++c) {
+    const int cc = min(c, k - 1);
+    const float mf = (c < k) ? 1.f : 0.f;
+    r[c] = Eb[ir + (int64_t)cc * m] * mf;  // r = e - K x with x = 0
+    const float wv = W1[ir + (int64_t)cc * ldw];
+    wq[c] = wv * wv * mf;
+    x[c] = 0.f;
+    ee = fmaf(r[c], r[c], ee);
+  }
+  const float stop = ee * (1.f / 4398046511104.f);  // (2^-21)^2 ||e||^2
+  float rz = 0.f;
+#pragma unroll
+  for (int c = 0; c < KP; ++c) {
+    p[c] = r[c] * dinv(c);
+    rz = fmaf(r[c], p[c], rz);
+  }
+  float wmin = wq[0];
+#pragma unroll
+  for (int c = 1; c < KP; ++c)
+    if (c < k) wmin = fminf(wmin, wq[c]);
+  const bool handled = snorm <= 0.5f * wmin;
+  bool done_row = !(ee > 0.f) || !handled;
+  for (int it = 0; it < CG_MAXIT; ++it) {
+    if (__all(done_row)) break;
+    // q = K p = w^2 o p + S p; S row by row from LDS (a compiler barrier per
+    // row keeps its KP entries from being hoisted out of the iteration)
+    float pq = 0.f;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      __asm__ volatile("" ::: "memory");
+      float acc = wq[c] * p[c];
+#pragma unroll
+      for (int j4 = 0; j4 < KP; j4 += 4) {
+        const float4 sv = *reinterpret_cast<const float4 *>(sS + c * KP + j4);
+        acc = fmaf(sv.x, p[j4], acc);
+        acc = fmaf(sv.y, p[j4 + 1], acc);
+        acc = fmaf(sv.z, p[j4 + 2], acc);
+        acc = fmaf(sv.w, p[j4 + 3], acc);
+      }
+      q[c] = acc;
+      pq = fmaf(p[c], acc, pq);
+    }
+    const float alpha = (pq > 0.f && !done_row) ? rz / pq : 0.f;
+    float rr = 0.f, rzn = 0.f;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      x[c] = fmaf(alpha, p[c], x[c]);
+      r[c] = fmaf(-alpha, q[c], r[c]);
+      rr = fmaf(r[c], r[c], rr);
+      q[c] = r[c] * dinv(c);  // z = P^-1 r, in q's registers
+      rzn = fmaf(r[c], q[c], rzn);
+    }
+    if (!done_row && rr <= stop) done_row = true;
+    const float beta = (rz > 0.f && !done_row) ? rzn / rz : 0.f;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) p[c] = fmaf(beta, p[c], q[c]);
+    rz = rzn;
+  }
+  if (act && (!done_row || !handled)) atomicMax(cgflag, st->sweep + 1);
+  double f1 = 0.0, dx = 0.0;
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < KP; ++c)
+      if (c < k) {
+        const float a1 = A[i + (int64_t)c * lda];
+        const float xn = a1 + x[c];
+        X1n[i + (int64_t)c * m] = xn;
+        const double d = (double)a1 - (double)xn;
+        f1 += d * d * (double)wq[c];
+        const double dd = (double)xn - (double)X1o[i + (int64_t)c * m];
+        dx += dd * dd;
+      }
+  }
+  f1 = wave_sum(f1);
+  dx = wave_sum(dx);
+  // one (f1, dx) pair per 64 rows, as k_update writes them
+  const int64_t pidx = 4 * (int64_t)blockIdx.x + (t >> 6);
+  if (lane == 0 && pidx * 64 < m) {
+    part[2 * pidx] = f1;
+    part[2 * pidx + 1] = dx;
+  }
+}
+
 // LDS version for any k <= WLRA_KMAX: the factor of each lane's matrix is
 // lane-interleaved in LDS (element e of lane l at [e*nl + l]), `nl` lanes at
 // a time.
@@ -736,8 +864,9 @@ __global__ __launch_bounds__(64) void k_rowsolve_lds(
     int64_t m, int k, const T *__restrict__ A, int64_t lda, const T *__restrict__ W1, int64_t ldw,
     const T *__restrict__ X1o, T *__restrict__ X1n, const T *__restrict__ Eb,
     const T *__restrict__ St, double *__restrict__ part, int nl,
-    const SmallState *__restrict__ st, int *flags) {
+    const SmallState *__restrict__ st, int *flags, const int *__restrict__ cgflag) {
   if (st->done) return;
+  if (cgflag != nullptr && *cgflag != st->sweep + 1) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sS = reinterpret_cast<T *>(smem_raw);  // k x k
   T *sm = sS + k * k;
@@ -1334,16 +1463,33 @@ static void launch_update_a2(hipStream_t s, const UpdateArgs<T> &a, const Update
 }
 
 template <typename T>
-static void launch_rowsolve_reg(hipStream_t s, const UpdateArgs<T> &a, unsigned grid) {
+static void launch_rowsolve_reg(hipStream_t s, const UpdateArgs<T> &a, unsigned grid,
+                                const int *cgflag) {
   if (a.k <= 8)
     hipLaunchKernelGGL((k_rowsolve_reg<T, 8>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
-                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
+                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags, cgflag);
   else if (a.k <= 16)
     hipLaunchKernelGGL((k_rowsolve_reg<T, 16>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
-                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
+                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags, cgflag);
   else
     hipLaunchKernelGGL((k_rowsolve_reg<T, 24>), dim3(grid), dim3(64), 0, s, a.m, a.k, a.A, a.lda,
-                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags);
+                       a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, a.flags, cgflag);
+}
+
+// CG per-row solves (float, k <= 48); false when k is beyond them.
+static bool launch_rowsolve_cg(hipStream_t s, const UpdateArgs<float> &a, int *cgflag) {
+  const unsigned grid = (unsigned)((a.m + 255) / 256);
+#define RS_CG(KP)                                                                               \
+  hipLaunchKernelGGL((k_rowsolve_cg<KP>), dim3(grid), dim3(256), 0, s, a.m, a.k, a.A, a.lda,     \
+                     a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, a.st, cgflag)
+  if (a.k <= 16) RS_CG(16);
+  else if (a.k <= 24) RS_CG(24);
+  else if (a.k <= 32) RS_CG(32);
+  else if (a.k <= 40) RS_CG(40);
+  else if (a.k <= 48) RS_CG(48);
+  else return false;
+#undef RS_CG
+  return true;
 }
 
 template <typename T, int KMAX>
@@ -1355,10 +1501,16 @@ static void launch_update_k(hipStream_t s, const UpdateArgs<T> &a) {
     return;
   }
   launch_update_a2<T, KMAX, false>(s, a, pl);
+  // float: conjugate gradients per row, the direct solves below only for a
+  // sweep in which some row did not converge (a flag word of its own)
+  const int *cgflag = nullptr;
+  if constexpr (sizeof(T) == 4) {
+    if (a.flags != nullptr && launch_rowsolve_cg(s, a, a.flags + 2)) cgflag = a.flags + 2;
+  }
   // register-resident per-row solves for fp32 up to k = 24 (the fp64 factor would not fit)
   if constexpr (sizeof(T) == 4) {
     if (a.k <= 24) {
-      launch_rowsolve_reg<T>(s, a, grid);
+      launch_rowsolve_reg<T>(s, a, grid, cgflag);
       return;
     }
   }
@@ -1366,7 +1518,8 @@ static void launch_update_k(hipStream_t s, const UpdateArgs<T> &a) {
     const size_t shm = (size_t)a.k * a.k * sizeof(T) +
                        (size_t)(a.k * (a.k + 1) / 2 + 2 * a.k) * pl.nl * sizeof(T);
     hipLaunchKernelGGL((k_rowsolve_lds<T, KMAX>), dim3(grid), dim3(64), shm, s, a.m, a.k, a.A,
-                       a.lda, a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, pl.nl, a.st, a.flags);
+                       a.lda, a.W1, a.ldw, a.X1o, a.X1n, a.Eb, a.St, a.part, pl.nl, a.st, a.flags,
+                       cgflag);
   }
 }
 
