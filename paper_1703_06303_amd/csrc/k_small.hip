@@ -43,8 +43,13 @@ __global__ __launch_bounds__(1024) void k_gastats(int n2, const double *__restri
 // column of B, backward substitution with R gives the column of C, the
 // column held in registers (k <= KMAX) and R read from LDS (every thread
 // reads the same entry at once).
+// Several workgroups per instance when n2 > 256 (wg of nwg): each one
+// factors G1 (the same arithmetic in every workgroup) and solves its own
+// 256-column slice of P; workgroup 0 alone writes R and the sweep state, and
+// every workgroup writes its share of ||B||^2 to coef_part[wg] (summed in
+// order by k_post).
 template <int KMAX>
-__device__ __forceinline__ void coef_body(const SmallArgs &a) {
+__device__ __forceinline__ void coef_body(const SmallArgs &a, int wg, int nwg) {
   SmallState *st = a.st;
   if (st->done) return;
   __shared__ double sR[64 * 64];
@@ -60,8 +65,10 @@ __device__ __forceinline__ void coef_body(const SmallArgs &a) {
   f1 = block_sum(f1, red);
   dx = block_sum(dx, red);
   if (t == 0) {
-    st->f1 = f1;
-    st->dx1 = dx;
+    if (wg == 0) {
+      st->f1 = f1;
+      st->dx1 = dx;
+    }
     fail = 0;
   }
   {
@@ -116,18 +123,19 @@ __device__ __forceinline__ void coef_body(const SmallArgs &a) {
   }
   __syncthreads();
   if (fail) {
-    if (t == 0) {
+    if (t == 0 && wg == 0) {
       atomicOr(a.flags, DEV_RANK);
       st->done = 1;
     }
     return;
   }
-  for (int e = t; e < k * k; e += 256) {
-    const int r = e % k, c = e / k;
-    a.R[e] = (r <= c) ? sR[r + c * 64] : 0.0;
-  }
+  if (wg == 0)
+    for (int e = t; e < k * k; e += 256) {
+      const int r = e % k, c = e / k;
+      a.R[e] = (r <= c) ? sR[r + c * 64] : 0.0;
+    }
   double nb2 = 0.0;
-  for (int jj = t; k > 0 && jj < n2; jj += 256) {
+  for (int jj = wg * 256 + t; k > 0 && jj < n2; jj += nwg * 256) {
     const double *pc = a.P + (int64_t)jj * k;
     double x[KMAX];
 #pragma unroll
@@ -170,16 +178,23 @@ __device__ __forceinline__ void coef_body(const SmallArgs &a) {
   }
   nb2 = block_sum(nb2, red);
   if (t == 0) {
-    st->nB2 = nb2;
-    st->trG1 = tr;
+    a.coef_part[wg] = nb2;
+    if (wg == 0) st->trG1 = tr;
   }
 }
+// workgroups per instance of the coefficient step
+__host__ __device__ inline int coef_groups(int n2) { return n2 > 256 ? (n2 + 255) / 256 : 1; }
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_coef(SmallArgs a) { coef_body<KMAX>(a); }
-// one workgroup per instance of a batch (blockIdx.x = instance)
+__global__ __launch_bounds__(256) void k_coef(SmallArgs a) {
+  coef_body<KMAX>(a, blockIdx.x, gridDim.x);
+}
+// batch: blockIdx.y = instance; workgroups past an instance's count exit
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_coef_b(const SmallArgs *__restrict__ av) {
-  coef_body<KMAX>(av[blockIdx.x]);
+  const SmallArgs &a = av[blockIdx.y];
+  const int ng = coef_groups(a.n2);
+  if ((int)blockIdx.x >= ng) return;
+  coef_body<KMAX>(a, blockIdx.x, ng);
 }
 
 // -----------------------------------------------------------------------------
@@ -267,62 +282,48 @@ __device__ __forceinline__ void post_body(const SmallArgs &a, const SmallOut<T> 
   double *Ki = Tm + 64 * 64;             // K^-1, k x k (constant weight)
 
   // ---- CV = C V and S = C C^T ----------------------------------------------
-  const int ncv = k * l, nss = k * k, nout = ncv + nss;
-  double acc[6];
+  // on the FP64 matrix cores: 16 x 16 output tiles (S: ceil(k/16)^2, CV:
+  // ceil(k/16) x ceil(l/16)), one wavefront per tile, the inner index (the
+  // n2 columns of C) in k-steps of 4, eight steps' reads in flight at once;
+  // C (k x n2, ld k) and V (n2 x l, ld n2) are read from L2, clamped and
+  // masked by zero factors.
+  {
+    typedef double pd4 __attribute__((ext_vector_type(4)));
+    const int lane = t & 63, w = t >> 6, li = lane & 15, lk = lane >> 4;
+    const int tk = (k + 15) / 16, tl = (l + 15) / 16;
+    const int ntile = tk * tk + tk * tl;
+    for (int tile = w; tile < ntile; tile += 16) {
+      const bool isS = tile < tk * tk;
+      const int tt = isS ? tile : tile - tk * tk;
+      const int r0 = 16 * (tt % tk), c0 = 16 * (tt / tk);
+      const int ra = min(r0 + li, max(k - 1, 0));
+      const double ma = (r0 + li < k) ? 1.0 : 0.0;
+      const int cb = isS ? min(c0 + li, max(k - 1, 0)) : min(c0 + li, max(l - 1, 0));
+      const double mb = isS ? ((c0 + li < k) ? 1.0 : 0.0) : ((c0 + li < l) ? 1.0 : 0.0);
+      pd4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int j0 = 0; j0 < n2; j0 += 32) {
+        double av[8], bv[8];
 #pragma unroll
-  for (int u = 0; u < 6; ++u) acc[u] = 0.0;
-  const int cw = max(1, min(POST_CH / max(k, 1), 4096 / max(l, 1)));
-  for (int j0 = 0; j0 < n2; j0 += cw) {
-    const int nc = min(cw, n2 - j0);
-    __syncthreads();
-    // clamped reads, all in flight (nc k <= POST_CH, nc l <= 4096); no
-    // reads at all for k = 0 or l = 0
-    const int ncc = nc * k, nvv = nc * l;
-    if (ncc > 0) {
-      double cv[(POST_CH + 1023) / 1024];
-#pragma unroll
-      for (int u = 0; u < (POST_CH + 1023) / 1024; ++u)
-        cv[u] = a.C[(int64_t)j0 * k + min(t + 1024 * u, ncc - 1)];
-#pragma unroll
-      for (int u = 0; u < (POST_CH + 1023) / 1024; ++u)
-        if (t + 1024 * u < ncc) sC[t + 1024 * u] = cv[u];
-    }
-    if (nvv > 0) {
-      double vv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = min(t + 1024 * u, nvv - 1), jj = e / l, q = e - jj * l;
-        vv[u] = V[(j0 + jj) + (int64_t)q * n2];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (t + 1024 * u < nvv) sV[t + 1024 * u] = vv[u];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 6; ++u) {
-      const int o_ = t + 1024 * u;
-      if (o_ < nout) {
-        double s_ = acc[u];
-        if (o_ < ncv) {
-          const int c = o_ % k, q = o_ / k;
-          for (int jj = 0; jj < nc; ++jj) s_ = fma(sC[c + jj * k], sV[jj * l + q], s_);
-        } else {
-          const int e = o_ - ncv, c = e % k, d = e / k;
-          for (int jj = 0; jj < nc; ++jj) s_ = fma(sC[c + jj * k], sC[d + jj * k], s_);
+        for (int u = 0; u < 8; ++u) {
+          const int jj = j0 + 4 * u + lk, jc = min(jj, n2 - 1);
+          const double mj = (jj < n2) ? 1.0 : 0.0;
+          av[u] = a.C[(int64_t)jc * k + ra] * (ma * mj);
+          bv[u] = isS ? a.C[(int64_t)jc * k + cb] * mb : V[jc + (int64_t)cb * n2] * mb;
         }
-        acc[u] = s_;
-      }
-    }
-  }
 #pragma unroll
-  for (int u = 0; u < 6; ++u) {
-    const int o_ = t + 1024 * u;
-    if (o_ < ncv) {
-      CV[o_] = acc[u];
-      sK[o_] = acc[u];  // LDS copy of CV for T (k l <= 2048)
-    } else if (o_ < nout) {
-      S[o_ - ncv] = acc[u];
+        for (int u = 0; u < 8; ++u)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + lk + 4 * v, cc = c0 + li;  // output row lk + 4 v, column li
+        if (isS) {
+          if (rr < k && cc < k) S[rr + cc * k] = acc[v];
+        } else if (rr < k && cc < l) {
+          CV[rr + cc * k] = acc[v];
+          sK[rr + cc * k] = acc[v];  // LDS copy of CV for T (k l <= 2048)
+        }
+      }
     }
   }
   __syncthreads();
@@ -403,6 +404,10 @@ __device__ __forceinline__ void post_body(const SmallArgs &a, const SmallOut<T> 
     // eigenvalues of M, with ||P^perp A2||^2 = ||A2||^2 - ||B||^2.
     double sth = 0.0;
     for (int q = 0; q < l; ++q) sth += a.theta[q];
+    double nb2 = 0.0;  // ||B||^2 from the coefficient step's workgroups, in order
+    const int ng = coef_groups(a.n2);
+    for (int w = 0; w < ng; ++w) nb2 += a.coef_part[w];
+    st->nB2 = nb2;
     st->F = st->f1 + st->trGA - st->nB2 - sth;
     st->nrmX2sq = st->nB2 + sth;
     st->nrmX = sqrt(st->trG1 + st->nB2 + sth);
@@ -541,10 +546,11 @@ void launch_gastats(hipStream_t s, int n2, const double *GA, SmallState *st) {
 }
 
 void launch_coef(hipStream_t s, const SmallArgs &a) {
-  if (a.k <= 8) hipLaunchKernelGGL(k_coef<8>, dim3(1), dim3(256), 0, s, a);
-  else if (a.k <= 16) hipLaunchKernelGGL(k_coef<16>, dim3(1), dim3(256), 0, s, a);
-  else if (a.k <= 32) hipLaunchKernelGGL(k_coef<32>, dim3(1), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_coef<64>, dim3(1), dim3(256), 0, s, a);
+  const dim3 g(coef_groups(a.n2));
+  if (a.k <= 8) hipLaunchKernelGGL(k_coef<8>, g, dim3(256), 0, s, a);
+  else if (a.k <= 16) hipLaunchKernelGGL(k_coef<16>, g, dim3(256), 0, s, a);
+  else if (a.k <= 32) hipLaunchKernelGGL(k_coef<32>, g, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_coef<64>, g, dim3(256), 0, s, a);
 }
 
 void launch_formM(hipStream_t s, const SmallArgs &a) {
@@ -569,12 +575,13 @@ template void launch_post<double>(hipStream_t, const SmallArgs &, const SmallOut
 // Batched launches: `count` instances whose argument blocks are consecutive
 // in device memory (av); kmax: the common k class of the instances (8, 16,
 // 32 or 64) for the coefficient kernel; n2max, the largest n2.
-void launch_coef_b(hipStream_t s, int kmax, int count, const SmallArgs *av) {
+void launch_coef_b(hipStream_t s, int kmax, int count, int n2max, const SmallArgs *av) {
   if (count <= 0) return;
-  if (kmax <= 8) hipLaunchKernelGGL(k_coef_b<8>, dim3(count), dim3(256), 0, s, av);
-  else if (kmax <= 16) hipLaunchKernelGGL(k_coef_b<16>, dim3(count), dim3(256), 0, s, av);
-  else if (kmax <= 32) hipLaunchKernelGGL(k_coef_b<32>, dim3(count), dim3(256), 0, s, av);
-  else hipLaunchKernelGGL(k_coef_b<64>, dim3(count), dim3(256), 0, s, av);
+  const dim3 g(coef_groups(n2max), count);
+  if (kmax <= 8) hipLaunchKernelGGL(k_coef_b<8>, g, dim3(256), 0, s, av);
+  else if (kmax <= 16) hipLaunchKernelGGL(k_coef_b<16>, g, dim3(256), 0, s, av);
+  else if (kmax <= 32) hipLaunchKernelGGL(k_coef_b<32>, g, dim3(256), 0, s, av);
+  else hipLaunchKernelGGL(k_coef_b<64>, g, dim3(256), 0, s, av);
 }
 
 void launch_formM_b(hipStream_t s, int count, int n2max, const SmallArgs *av) {

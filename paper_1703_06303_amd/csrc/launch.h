@@ -108,6 +108,7 @@ struct SmallArgs {
   int eig_maxit, eig_deg;
   int eig_one_wg;          // 1: the one-workgroup eigen kernel for every n2
   double *epart;           // partial Grams of the multi-workgroup eigen kernel
+  double *coef_part;       // ||B||^2 per coefficient workgroup (WLRA_NMAX / 256 + 1)
 };
 
 template <typename T>
@@ -128,7 +129,7 @@ struct ChgArgs {
 
 // Batched small steps: one launch for `count` instances whose argument
 // blocks are consecutive in device memory.
-void launch_coef_b(hipStream_t s, int kmax, int count, const SmallArgs *av);
+void launch_coef_b(hipStream_t s, int kmax, int count, int n2max, const SmallArgs *av);
 void launch_formM_b(hipStream_t s, int count, int n2max, const SmallArgs *av);
 void launch_eig_b(hipStream_t s, int count, const SmallArgs *av);
 template <typename T>

@@ -218,6 +218,7 @@ struct Ptrs {
   void *As;   // column weights: [A1, A2 diag(W2)] (m x n), else NULL
   double *Hb, *Rh;  // change pass: aligned basis [V_p dV Z_p dZ] and its Gram
   double *epart;    // multi-workgroup eigen kernel: partial Grams
+  double *coef_part;  // ||B||^2 per workgroup of the coefficient step
   // learned warm start (NULL unless the start is learned)
   void *Om, *Ps;
   double *P1, *lpart;
@@ -328,6 +329,7 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {(void **)&p.Zl, z.mixed ? (size_t)update_panel_kp((int)kk) * panel_rows(n2) * sizeof(bf16s) : 0},
       {&p.As, z.colw ? (size_t)(m * z.n) * z.elt : 0},
       {(void **)&p.Hb, (size_t)(n2 * (2 * l + 2 * k)) * d},
+      {(void **)&p.coef_part, (size_t)(WLRA_NMAX / 256 + 1) * d},
       {(void **)&p.Rh, (size_t)((2 * l + 2 * k) * (2 * l + 2 * k)) * d},
       {(void **)&p.epart,
        (l > 0 && eig_mw_groups((int)n2) > 0)
@@ -610,6 +612,7 @@ struct Run {
     sa.eig_maxit = h->eig_maxit; sa.eig_deg = EIG_DEG;
     sa.eig_one_wg = h->eig_one_wg;
     sa.epart = P.epart;
+    sa.coef_part = P.coef_part;
     sa.upd_part = P.upd_part; sa.chg_part = P.chg_part; sa.nchg = z.nwg_upd;
     so = SmallOut<T>{static_cast<T *>(P.Gt), static_cast<T *>(P.Tt), static_cast<T *>(P.St),
                      static_cast<T *>(P.Vr), static_cast<T *>(P.Zx)};
@@ -1081,7 +1084,9 @@ int batch_impl(wlra_ctx *h, int count, const wlra_problem *probs, wlra_result *r
     for (int q0 = 0; q0 < na;) {
       int q1 = q0;
       while (q1 < na && kcls(order[q1]) == kcls(order[q0])) ++q1;
-      PROFWS(h, s0, KK_COEF, 0, 0, launch_coef_b(s0, kcls(order[q0]), q1 - q0, av_d + q0));
+      int n2c = 0;
+      for (int q = q0; q < q1; ++q) n2c = std::max(n2c, (int)runs[order[q]].n2);
+      PROFWS(h, s0, KK_COEF, 0, 0, launch_coef_b(s0, kcls(order[q0]), q1 - q0, n2c, av_d + q0));
       q0 = q1;
     }
     if (!eig_list.empty()) {
