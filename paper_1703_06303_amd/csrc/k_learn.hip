@@ -269,6 +269,101 @@ __global__ __launch_bounds__(256) void k_adam(int64_t P, float *__restrict__ p,
 }
 
 // ---------------------------------------------------------------------------
+// Lane `lane`'s value of x, in every lane.
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const long long v = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(v & 0xffffffffll), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Solve M X = B in place of B (M: SPD nn x nn, B: nn x cols, both in LDS
+// with leading dimension ld; nn <= LEARN_RMAX, nn + cols <= 64) by
+// Gauss-Jordan elimination without pivoting on wavefront 0, lane c holding
+// column c of [M B] in registers: per pivot j, column j is read from lane j
+// (v_readlane) and row j is divided by the pivot p, every other row losing
+// M[i][j] / p times it; no workgroup barriers between the steps.  On SPD
+// input the pivots are the Schur complements of the leading blocks (the
+// squared Cholesky pivots); one below 1e-13 of the largest diagonal entry
+// sets *bad and is replaced by 1.  M is left as it was.  Entered and left
+// with a barrier.
+__device__ __forceinline__ void ld_gj_solve(const double *M, double *B, int nn, int cols, int ld,
+                                            int *bad) {
+  constexpr int L = LEARN_RMAX;
+  const int t = threadIdx.x, nc = nn + cols;
+  if (t < 64) {
+    double dmax = 0.0;
+    for (int j = 0; j < nn; ++j) dmax = fmax(dmax, M[j + j * ld]);
+    const int c = min(t, max(nc - 1, 0));
+    // rows past nn are zero and stay zero: every step updates all L rows
+    // without a branch
+    double m[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const int ic = min(i, max(nn - 1, 0));
+      const double v = (c < nn) ? M[ic + c * ld] : B[ic + (c - nn) * ld];
+      m[i] = (i < nn) ? v : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      if (j < nn) {
+        double p = readlane_d(m[j], j);
+        if (!(p > 1e-13 * dmax)) {
+          if (t == 0) *bad = 1;
+          p = 1.0;
+        }
+        const double mj = m[j] / p;
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+          if (i != j) m[i] = fma(-readlane_d(m[i], j), mj, m[i]);
+        m[j] = mj;
+      }
+    }
+    if (t >= nn && t < nc) {
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+        if (i < nn) B[i + (t - nn) * ld] = m[i];
+    }
+  }
+  __syncthreads();
+}
+
+// epi(a, c, v) for every entry (a, c) of X Y (rows, cols <= 32, inner <=
+// LEARN_RMAX), operands in LDS with leading dimension ld, XT / YT reading
+// them transposed.  On the FP64 matrix cores: 16 x 16 output tiles dealt to
+// wavefronts [w0, w0 + nw) of the workgroup, the inner index in k-steps of 4
+// (every read issued before the first multiply); indices clamped, the
+// excess masked.  No barrier.
+template <bool XT, bool YT, typename Epi>
+__device__ __forceinline__ void ld_mm(const double *X, const double *Y, int rows, int cols,
+                                      int inner, int ld, int w0, int nw, Epi epi) {
+  typedef double pd4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6) - w0;
+  const int li = lane & 15, lk = lane >> 4, tr = (rows + 15) / 16, tc = (cols + 15) / 16;
+  if (w < 0 || w >= nw) return;
+  for (int tile = w; tile < tr * tc; tile += nw) {
+    const int r0 = 16 * (tile % tr), c0 = 16 * (tile / tr);
+    const int a = min(r0 + li, rows - 1), c = min(c0 + li, cols - 1);
+    double av[LEARN_RMAX / 4], bv[LEARN_RMAX / 4];
+#pragma unroll
+    for (int u = 0; u < LEARN_RMAX / 4; ++u) {
+      const int bi = 4 * u + lk, bc = min(bi, inner - 1);
+      const double x = XT ? X[bc + a * ld] : X[a + bc * ld];
+      av[u] = (bi < inner) ? x : 0.0;
+      bv[u] = YT ? Y[c + bc * ld] : Y[bc + c * ld];
+    }
+    pd4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < LEARN_RMAX / 4; ++u)
+      if (4 * u < inner) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ra = r0 + lk + 4 * v, cb = c0 + li;  // output row lk + 4 v, column li
+      if (ra < rows && cb < cols) epi(ra, cb, acc[v]);
+    }
+  }
+}
+
 // Decode of the predicted row basis Y (n x r, Y[j + n q], r <= LEARN_RMAX).
 // With the row space fixed, problem (5) separates over rows; row i of the
 // start is the weighted least-squares fit z_i Y^T.  Writing the rows of
@@ -284,280 +379,190 @@ __global__ __launch_bounds__(256) void k_adam(int64_t P, float *__restrict__ p,
 //                                  range(W^T) is the pseudo-inverse of W^T W)
 //   Q = F^T - P_b N^-1 P_b Gy F^T,   Z = Y2 Q,   S = F Gy Q (symmetrised).
 // Output as the row update's operands: Gt = [-S; Z] ((k + n2) x k,
-// row-major), St = S, Tt = 0.  One workgroup, all in double; Y is first
-// scaled to ||Y||_F^2 = r (the row space does not change).  A zero Y, a
+// row-major), St = S, Tt = 0.  One workgroup, all in double (Gy and Z on
+// the FP64 matrix cores, the two SPD inverses by ld_inverse); Y is scaled to
+// ||Y||_F^2 = r (the row space does not change).  A zero Y, a
 // pivot of Y1 Y1^T or N below 1e-13 of its largest diagonal entry, or a
 // non-finite result sets DEV_LEARN_FAIL.
-// Lower Cholesky in place of the SPD nn x nn matrix M (LDS, ld L, nn <= L
-// <= 64) by wavefront 0: one row per lane in registers, column j handed to
-// every lane through colbuf.  A pivot below 1e-13 of the largest diagonal
-// entry sets *bad (and is replaced by 1).  The strict upper triangle is
-// left as it was.
-template <int L>
-__device__ __forceinline__ void ld_chol_wave(double *M, int nn, double *colbuf, int *bad) {
-  const int i = threadIdx.x;
-  double dmax = 0.0;
-  for (int j = 0; j < nn; ++j) dmax = fmax(dmax, M[j + j * L]);
-  double a[L];
-#pragma unroll
-  for (int q = 0; q < L; ++q) a[q] = M[min(i, L - 1) + q * L];
-#pragma unroll
-  for (int j = 0; j < L; ++j) {
-    if (j < nn) {
-      double d = __shfl(a[j], j, 64);
-      if (!(d > 1e-13 * dmax)) {
-        if (i == 0) *bad = 1;
-        d = 1.0;
-      }
-      const double ljj = sqrt(d), inv = 1.0 / ljj;
-      a[j] = (i == j) ? ljj : a[j] * inv;
-      colbuf[i] = a[j];
-      wave_sync();
-#pragma unroll
-      for (int q = j + 1; q < L; ++q)
-        if (q < nn) a[q] = fma(-a[j], colbuf[q], a[q]);
-      wave_sync();
-    }
-  }
-  if (i < nn) {
-#pragma unroll
-    for (int q = 0; q < L; ++q)
-      if (q <= i && q < nn) M[i + q * L] = a[q];
-  }
-  wave_sync();
-}
-
-// X (nn x cols, ld L, cols <= 64) <- (Lm Lm^T)^-1 X with Lm from
-// ld_chol_wave, by wavefront 0: one column per lane in registers, Lm read
-// from LDS (the same element in every lane).
-template <int L>
-__device__ __forceinline__ void ld_solve_wave(const double *Lm, int nn, double *X, int cols) {
-  const int c = threadIdx.x;
-  if (c < cols) {
-    double x[L];
-#pragma unroll
-    for (int i = 0; i < L; ++i) x[i] = X[i + c * L];
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-      if (i < nn) {
-        double v = x[i];
-#pragma unroll
-        for (int q = 0; q < i; ++q) v = fma(-Lm[i + q * L], x[q], v);
-        x[i] = v / Lm[i + i * L];
-      }
-      asm volatile("" ::: "memory");  // keep each row's reads of Lm in place
-    }
-#pragma unroll
-    for (int i = L - 1; i >= 0; --i) {
-      if (i < nn) {
-        double v = x[i];
-#pragma unroll
-        for (int q = i + 1; q < L; ++q)
-          if (q < nn) v = fma(-Lm[q + i * L], x[q], v);
-        x[i] = v / Lm[i + i * L];
-      }
-      asm volatile("" ::: "memory");
-    }
-#pragma unroll
-    for (int i = 0; i < L; ++i)
-      if (i < nn) X[i + c * L] = x[i];
-  }
-}
-
 template <typename T>
-__global__ __launch_bounds__(256) void k_ldecode(int n, int k, int r, const float *__restrict__ yv,
-                                                 T *__restrict__ Gt, T *__restrict__ Tt,
-                                                 T *__restrict__ St, int *flags) {
-  constexpr int L = LEARN_RMAX, NT = 256;
-  // sA: Y1, later Gy; sB: Y1 Y1^T, later products; sT: temporaries
-  __shared__ double sA[L * L], sB[L * L], sF[L * L], sP[L * L], sN[L * L], sU[L * L], sT[L * L];
-  __shared__ double red[8];
+__global__ __launch_bounds__(1024) void k_ldecode(int n, int k, int r, const float *__restrict__ yv,
+                                                  T *__restrict__ Gt, T *__restrict__ Tt,
+                                                  T *__restrict__ St, int *flags) {
+  typedef double pd4 __attribute__((ext_vector_type(4)));
+  constexpr int L = LEARN_RMAX, LP = L + 1, NT = 1024, NW = NT / 64;  // LP odd: no bank conflicts
+  // Y2 is staged through sY in chunks of crow rows (float, column stride
+  // crow = 20 mod 64: the Gram's matrix-core reads are free of bank
+  // conflicts, those of Z at most two-way)
+  constexpr int YST = 16384;
+  __shared__ float sY[YST];
+  __shared__ double pool[8 * L * LP];
+  __shared__ double red[NW];
   __shared__ int bad;
+  // Y1 and Gy stay unscaled; the scale of Y (||Y||_F^2 = r) enters the
+  // products that read them
+  double *sY1 = pool, *sG = pool + L * LP, *sK = pool + 2 * L * LP, *sF = pool + 3 * L * LP;
+  double *sP = pool + 4 * L * LP, *sN = pool + 5 * L * LP, *sT = pool + 6 * L * LP;
+  double *sU = pool + 7 * L * LP;
+  double *park = sK;  // 16 partial Gram tiles (4096 doubles) before sK..sU are used
   const int t = threadIdx.x, n2 = n - k;
+  const int lane = t & 63, w = t >> 6, li = lane & 15, lk = lane >> 4;
+  const int crow = (((YST / r) - 20) & ~63) + 20;  // <= YST / r since r <= LEARN_RMAX
+  const int nchunk = (n2 + crow - 1) / crow;
   if (t == 0) bad = 0;
+  // rows [j0, j0 + cl) of Y2 to sY (coalesced, eight reads in flight)
+  auto stage = [&](int j0, int cl) {
+    for (int e0 = t; e0 < cl * r; e0 += 8 * NT) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(e0 + u * NT, cl * r - 1);
+        v[u] = yv[k + j0 + (e % cl) + (int64_t)n * (e / cl)];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * NT;
+        if (e < cl * r) sY[(e % cl) + (e / cl) * crow] = v[u];
+      }
+    }
+  };
+  // Y1 = Y[:k] to LDS; its squared entries towards ||Y||_F^2
   double ss = 0.0;
-  const int64_t ny = (int64_t)n * r;
-  for (int64_t e0 = t; e0 < ny; e0 += 8 * NT) {
-    float v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = yv[min(e0 + u * NT, ny - 1)];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (e0 + u * NT < ny) ss = fma((double)v[u], (double)v[u], ss);
+  for (int e = t; e < k * r; e += NT) {
+    const int a = e % k, q = e / k;
+    const double v = (double)yv[a + (int64_t)n * q];
+    sY1[a + q * LP] = v;
+    ss = fma(v, v, ss);
   }
-  ss = block_sum(ss, red);
+  // Gy = Y2^T Y2 on the FP64 matrix cores: 16 x 16 output tiles (r <= 32:
+  // at most 4), four wavefronts per tile taking every fourth group of 8
+  // k-steps (4 rows each); the partial tiles are added in a fixed order
+  {
+    const int tile = w & 3, part = w >> 2;
+    const int r0 = 16 * (tile & 1), c0 = 16 * (tile >> 1);
+    const bool act = r0 < r && c0 < r;
+    const int qa = min(r0 + li, r - 1), qb = min(c0 + li, r - 1);
+    const double ma = (r0 + li < r) ? 1.0 : 0.0, mb = (c0 + li < r) ? 1.0 : 0.0;
+    pd4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int j0 = ch * crow, cl = min(crow, n2 - j0);
+      if (ch > 0) __syncthreads();  // the previous chunk has been read
+      stage(j0, cl);
+      __syncthreads();
+      if (act) {
+        for (int s0 = 32 * part; s0 < cl; s0 += 128) {
+          double av[8], bv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int jj = s0 + 4 * u + lk, jc = min(jj, cl - 1);
+            const double mj = (jj < cl) ? ma : 0.0;
+            av[u] = (double)sY[jc + qa * crow] * mj;
+            bv[u] = (double)sY[jc + qb * crow] * mb;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) park[(part * 4 + tile) * 256 + (lk + 4 * v) * 16 + li] = acc[v];
+  }
+  ss = wave_sum(ss);
+  if (lane == 0) red[w] = ss;
+  __syncthreads();
+  {
+    const int tile = t >> 8, el = t & 255;  // output row el / 16, column el % 16
+    const int rr = 16 * (tile & 1) + el / 16, cc = 16 * (tile >> 1) + el % 16;
+    if (rr < r && cc < r)
+      sG[rr + cc * LP] = ((park[tile * 256 + el] + park[(4 + tile) * 256 + el]) +
+                          park[(8 + tile) * 256 + el]) + park[(12 + tile) * 256 + el];
+  }
+  __syncthreads();
+  ss = 0.0;
+  for (int i = 0; i < NW; ++i) ss += red[i];
+  for (int q = 0; q < r; ++q) ss += sG[q + q * LP];
   if (!(ss > 0.0) || !isfinite(ss)) {
     if (t == 0) atomicOr(flags, DEV_LEARN_FAIL);
     return;
   }
-  const double sc = sqrt((double)r / ss);
-  {
-    constexpr int EPT = L * L / NT;
-    float v[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = t + u * NT, a = min(e % L, k - 1), q = min(e / L, r - 1);
-      v[u] = yv[a + (int64_t)n * q];
-    }
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = t + u * NT;
-      sA[e] = ((e % L) < k && (e / L) < r) ? sc * (double)v[u] : 0.0;
-    }
-  }
+  const double sc = sqrt((double)r / ss), sc2 = (double)r / ss;
+  // K = Y1 Y1^T (scaled) and the right-hand side Y1 of F = K^-1 Y1
+  ld_mm<false, true>(sY1, sY1, k, k, r, LP, 0, 4, [&](int a, int c, double v) { sK[a + c * LP] = sc2 * v; });
+  for (int e = t; e < k * r; e += NT) sF[(e % k) + (e / k) * LP] = sc * sY1[(e % k) + (e / k) * LP];
   __syncthreads();
-  __shared__ double colbuf[64];
-  auto chol = [&](double *Mx, int nn) {
-    if (t < 64) ld_chol_wave<L>(Mx, nn, colbuf, &bad);
-    __syncthreads();
-  };
-  auto chol_solve = [&](const double *Lx, int nn, double *X, int cols) {
-    if (t < 64) ld_solve_wave<L>(Lx, nn, X, cols);
-    __syncthreads();
-  };
-  // Out (rows x cols) = X Y, inner dimension inner, all ld L
-  auto mm = [&](double *Out, const double *X, const double *Y, int rows, int cols, int inner) {
-    for (int e = t; e < rows * cols; e += NT) {
-      const int a = e % rows, c = e / rows;
-      double v = 0.0;
-      for (int b = 0; b < inner; ++b) v = fma(X[a + b * L], Y[b + c * L], v);
-      Out[a + c * L] = v;
-    }
-    __syncthreads();
-  };
-  // Y1 Y1^T: (a, b) = sum_q Y1[a, q] Y1[b, q]
-  for (int e = t; e < k * k; e += NT) {
-    const int a = e % k, b = e / k;
-    double v = 0.0;
-    for (int q = 0; q < r; ++q) v = fma(sA[a + q * L], sA[b + q * L], v);
-    sB[a + b * L] = v;
-  }
+  ld_gj_solve(sK, sF, k, r, LP, &bad);  // F (k x r)
+  // P_b = I - Y1^T F (r x r, symmetric) and Gy F^T (r x k)
+  ld_mm<true, false>(sY1, sF, r, r, k, LP, 0, 4, [&](int a, int c, double v) {
+    sP[a + c * LP] = ((a == c) ? 1.0 : 0.0) - sc * v;
+  });
+  ld_mm<false, true>(sG, sF, r, k, r, LP, 4, 4, [&](int a, int c, double v) { sU[a + c * LP] = sc2 * v; });
   __syncthreads();
-  chol(sB, k);
-  for (int e = t; e < L * L; e += NT) sF[e] = sA[e];
+  ld_mm<false, false>(sG, sP, r, r, r, LP, 0, 4, [&](int a, int c, double v) { sT[a + c * LP] = sc2 * v; });
+  ld_mm<false, false>(sP, sU, r, k, r, LP, 4, 4, [&](int a, int c, double v) { sK[a + c * LP] = v; });
   __syncthreads();
-  chol_solve(sB, k, sF, r);  // F = (Y1 Y1^T)^-1 Y1 (k x r)
-  // P_b = I - Y1^T F (r x r, symmetric)
-  for (int e = t; e < r * r; e += NT) {
-    const int q = e % r, q2 = e / r;
-    double v = (q == q2) ? 1.0 : 0.0;
-    for (int a = 0; a < k; ++a) v -= sA[a + q * L] * sF[a + q2 * L];
-    sP[q + q2 * L] = v;
-  }
+  // N = P_b (Gy P_b) + I - P_b; then N^-1 U with U = P_b Gy F^T (in sK)
+  ld_mm<false, false>(sP, sT, r, r, r, LP, 0, 4, [&](int a, int c, double v) {
+    sN[a + c * LP] = v + ((a == c) ? 1.0 : 0.0) - sP[a + c * LP];
+  });
   __syncthreads();
-  // Gy = Y2^T Y2 (r x r) over the n2 rows, staged through sN in chunks of
-  // rows; each thread keeps its entries in registers
-  {
-    constexpr int EPT = (L * L + NT - 1) / NT;
-    double acc[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) acc[u] = 0.0;
-    const int crow = (L * L) / r;  // rows per chunk
-    for (int j0 = 0; j0 < n2; j0 += crow) {
-      const int jl = min(crow, n2 - j0);
-      {
-        constexpr int SPT = L * L / NT;  // jl * r <= L * L
-        float v[SPT];
-#pragma unroll
-        for (int u = 0; u < SPT; ++u) {
-          const int e = min(t + u * NT, jl * r - 1), jr = e % jl, q = e / jl;
-          v[u] = yv[k + j0 + jr + (int64_t)n * q];
-        }
-#pragma unroll
-        for (int u = 0; u < SPT; ++u) {
-          const int e = t + u * NT;
-          if (e < jl * r) sN[(e % jl) + (e / jl) * crow] = sc * (double)v[u];
-        }
-      }
+  ld_gj_solve(sN, sK, r, k, LP, &bad);
+  // Q = F^T - P_b N^-1 U (r x k)
+  ld_mm<false, false>(sP, sK, r, k, r, LP, 0, 4, [&](int a, int c, double v) {
+    sT[a + c * LP] = sF[c + a * LP] - v;
+  });
+  __syncthreads();
+  ld_mm<false, false>(sG, sT, r, k, r, LP, 0, 4, [&](int a, int c, double v) { sU[a + c * LP] = sc2 * v; });
+  // Z = sc Y2 Q (n2 x k, row-major below S) on the FP64 matrix cores while
+  // wavefronts 0-3 form Gy Q: 16 x 16 tiles of each chunk dealt round-robin
+  // to wavefronts 4.., the r columns of Y2 as the inner index (at most 8
+  // k-steps, all reads issued first); a single chunk is still in sY from
+  // the Gram
+  int nb = 0;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int j0 = ch * crow, cl = min(crow, n2 - j0);
+    if (nchunk > 1) {
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < EPT; ++u) {
-        const int e = t + u * NT;
-        if (e < r * r) {
-          const int q = e % r, q2 = e / r;
-          double v = acc[u];
-          for (int jr = 0; jr < jl; ++jr) v = fma(sN[jr + q * crow], sN[jr + q2 * crow], v);
-          acc[u] = v;
-        }
-      }
+      stage(j0, cl);
       __syncthreads();
     }
+    const int nti = (cl + 15) / 16, ntj = (k + 15) / 16;
+    for (int tile = w - 4; tile >= 0 && tile < nti * ntj; tile += NW - 4) {
+      const int jt = 16 * (tile % nti), c0 = 16 * (tile / nti);
+      const int ja = min(jt + li, cl - 1), cb = min(c0 + li, k - 1);
+      const double mc = (c0 + li < k) ? 1.0 : 0.0;
+      double av[L / 4], bv[L / 4];
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = t + u * NT;
-      if (e < r * r) sA[(e % r) + (e / r) * L] = acc[u];  // sA = Gy from here on
+      for (int u = 0; u < L / 4; ++u) {
+        const int q = 4 * u + lk, qc = min(q, r - 1);
+        av[u] = (double)sY[ja + qc * crow];
+        bv[u] = (q < r) ? sT[qc + cb * LP] * mc : 0.0;
+      }
+      pd4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < L / 4; ++u)
+        if (4 * u < r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = jt + lk + 4 * v, c = c0 + li;
+        if (j < cl && c < k) {
+          const double z = sc * acc[v];
+          nb |= !isfinite(z);
+          Gt[(int64_t)(k + j0 + j) * k + c] = (T)z;
+        }
+      }
     }
-    __syncthreads();
   }
-  mm(sT, sA, sP, r, r, r);  // Gy P_b
-  // N = P_b (Gy P_b) + I - P_b
-  for (int e = t; e < r * r; e += NT) {
-    const int q = e % r, q2 = e / r;
-    double v = ((q == q2) ? 1.0 : 0.0) - sP[q + q2 * L];
-    for (int b = 0; b < r; ++b) v = fma(sP[q + b * L], sT[b + q2 * L], v);
-    sN[q + q2 * L] = v;
-  }
-  // Gy F^T (r x k): (q, c) = sum_b Gy[q, b] F[c, b]
-  for (int e = t; e < r * k; e += NT) {
-    const int q = e % r, c = e / r;
-    double v = 0.0;
-    for (int b = 0; b < r; ++b) v = fma(sA[q + b * L], sF[c + b * L], v);
-    sB[q + c * L] = v;
-  }
+  if (nb) bad = 1;
   __syncthreads();
-  mm(sU, sP, sB, r, k, r);  // U = P_b Gy F^T
-  chol(sN, r);
-  chol_solve(sN, r, sU, k);    // N^-1 U
-  // Q = F^T - P_b N^-1 U (r x k) in sT
-  for (int e = t; e < r * k; e += NT) {
-    const int q = e % r, c = e / r;
-    double v = sF[c + q * L];
-    for (int b = 0; b < r; ++b) v -= sP[q + b * L] * sU[b + c * L];
-    sT[q + c * L] = v;
-  }
-  __syncthreads();
-  mm(sB, sA, sT, r, k, r);  // Gy Q (r x k)
   // S = F (Gy Q), symmetrised; Gt's first k rows are -S; T = 0
+  ld_mm<false, false>(sF, sU, k, k, r, LP, 0, 4, [&](int a, int c, double v) { sP[a + c * LP] = v; });
+  __syncthreads();
   for (int e = t; e < k * k; e += NT) {
     const int a = e % k, c = e / k;
-    double v1 = 0.0, v2 = 0.0;
-    for (int b = 0; b < r; ++b) {
-      v1 = fma(sF[a + b * L], sB[b + c * L], v1);
-      v2 = fma(sF[c + b * L], sB[b + a * L], v2);
-    }
-    const double sv = 0.5 * (v1 + v2);
+    const double sv = 0.5 * (sP[a + c * LP] + sP[c + a * LP]);
     if (!isfinite(sv)) bad = 1;
     St[a * k + c] = (T)sv;
     Gt[a * k + c] = (T)(-sv);
     Tt[a * k + c] = T(0);
-  }
-  // Z = Y2 Q: one row per thread, the k entries in registers
-  for (int j = t; j < n2; j += NT) {
-    double z[L];
-#pragma unroll
-    for (int c = 0; c < L; ++c) z[c] = 0.0;
-    for (int q0 = 0; q0 < r; q0 += 8) {
-      float yq[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) yq[u] = yv[k + j + (int64_t)n * min(q0 + u, r - 1)];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (q0 + u < r) {
-          const double y = sc * (double)yq[u];
-#pragma unroll
-          for (int c = 0; c < L; ++c) z[c] = fma(y, sT[q0 + u + c * L], z[c]);
-        }
-        asm volatile("" ::: "memory");  // one row of Q's reads at a time
-      }
-    }
-    int nb = 0;
-#pragma unroll
-    for (int c = 0; c < L; ++c)
-      if (c < k) {
-        nb |= !isfinite(z[c]);
-        Gt[(int64_t)(k + j) * k + c] = (T)z[c];
-      }
-    if (nb) bad = 1;
   }
   __syncthreads();
   if (t == 0 && bad) atomicOr(flags, DEV_LEARN_FAIL);
@@ -652,7 +657,7 @@ void launch_adam(hipStream_t s, int64_t P, float *p, const float *g, float *m, f
 template <typename T>
 void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, T *Gt, T *Tt, T *St,
                     int *flags) {
-  hipLaunchKernelGGL(k_ldecode<T>, dim3(1), dim3(256), 0, s, n, k, r, yv, Gt, Tt, St, flags);
+  hipLaunchKernelGGL(k_ldecode<T>, dim3(1), dim3(1024), 0, s, n, k, r, yv, Gt, Tt, St, flags);
 }
 
 template <typename T>

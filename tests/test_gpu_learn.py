@@ -118,10 +118,16 @@ def test_adam_steps_match_oracle(s32):
         assert np.allclose(dp, p_ref - p0, rtol=1e-3, atol=2e-7)
 
 
-def test_learned_start_decode_matches_oracle(s64):
+@pytest.mark.parametrize("shape", [
+    dict(),                                           # r <= 16: one Gram tile
+    dict(m_hw=(12, 16), n=200, k=20, r=25),           # the learned-start workload's n, k, r
+    dict(m_hw=(8, 10), n=1000, k=10, r=32),           # Y2 staged in three chunks of rows
+], ids=["small", "n200_r25", "n1000_r32_chunked"])
+def test_learned_start_decode_matches_oracle(s64, shape):
     """With max_sweeps = 0 the returned X1 is the start X1_0 itself."""
     import torch
-    inst = _inst(seed=9)
+    inst = _inst(seed=9, **shape)
+    print("decode", inst.A.shape, inst.k, inst.r, flush=True)
     n, r, k = inst.n, inst.r, inst.k
     p = _params_gpu(n, r, 0)
     s64.mlp_init(p, n, r, 31)
