@@ -144,6 +144,33 @@ def test_learned_start_decode_matches_oracle(s64, shape):
     assert rel(np.hstack([X1s, X2s]), ref.X) <= 1e-9
 
 
+def test_learned_start_keeps_sketch_only_for_the_same_layout(s64):
+    """The Gaussian sketch matrices stay in the handle's workspace between
+    learned solves of one layout; a solve of another layout in between must
+    not leave a stale sketch behind (the start equals a fresh handle's)."""
+    from paper_1703_06303_amd.wlra import Solver
+    a = _inst(seed=21)
+    b = _inst(seed=22, m_hw=(16, 20), n=48, k=7, r=10)
+    pa = _params_gpu(a.n, a.r, 0)
+    s64.mlp_init(pa, a.n, a.r, 5)
+    pb = _params_gpu(b.n, b.r, 0)
+    s64.mlp_init(pb, b.n, b.r, 6)
+    with Solver("fp64") as fresh:
+        ref_a = gpu_solve(fresh, a, 0.0, 0, init="learned", want_x2=False, model=pa)[0]
+    with Solver("fp64") as fresh:
+        ref_b = gpu_solve(fresh, b, 0.0, 0, init="learned", want_x2=False, model=pb)[0]
+    # kept (a after a), dropped for another layout (b), dropped after a
+    # non-learned solve of a's shape (another layout too)
+    for step in ("a", "a", "b", "a", "random a", "a"):
+        if step == "random a":
+            gpu_solve(s64, a, 0.0, 2, init="random", seed=3)
+            continue
+        inst, p, ref = (a, pa, ref_a) if step == "a" else (b, pb, ref_b)
+        X1 = gpu_solve(s64, inst, 0.0, 0, init="learned", want_x2=False, model=p)[0]
+        # the handles' split choices may differ: equal up to rounding
+        assert rel(X1, ref) <= 1e-12, step
+
+
 def test_learned_start_falls_back_to_random(s64):
     """A network whose output is zero predicts no row space: the decode
     fails and the random start keyed by the same seed is used."""
