@@ -99,10 +99,12 @@ __device__ __forceinline__ void small_jacobi_reg(double *H, double *S, double *t
       for (int round = 0; round < per; ++round) {
         // partner of an index in this round's circle arrangement (nb is the
         // dummy of an odd nb)
+        // (i - 1 - round lies in (-per, per), pp - 1 + round in [0, 2 per))
         auto partner = [&](int i) {
-          const int pos = (i == 0) ? 0 : 1 + ((i - 1 - round) % per + per) % per;
-          const int pp = nbp - 1 - pos;
-          return (pp == 0) ? 0 : 1 + (pp - 1 + round) % per;
+          const int v = i - 1 - round;
+          const int pos = (i == 0) ? 0 : 1 + (v < 0 ? v + per : v);
+          const int pp = nbp - 1 - pos, w = pp - 1 + round;
+          return (pp == 0) ? 0 : 1 + (w >= per ? w - per : w);
         };
         const int px = partner(x), py = partner(y);
         const bool paired = px < nb && px != x;
@@ -196,9 +198,10 @@ __device__ __forceinline__ void small_jacobi_wave(double *H, double *S, double *
       if (!(off > 1e-28 * tot)) break;
       for (int round = 0; round < nbp - 1; ++round) {
         if (t < half) {
-          const int x0 = t, x1 = nbp - 1 - t;
-          int p = (x0 == 0) ? 0 : 1 + (x0 - 1 + round) % (nbp - 1);
-          int q = (x1 == 0) ? 0 : 1 + (x1 - 1 + round) % (nbp - 1);
+          const int x0 = t, x1 = nbp - 1 - t, per = nbp - 1;
+          const int w0 = x0 - 1 + round, w1 = x1 - 1 + round;  // in [0, 2 per)
+          int p = (x0 == 0) ? 0 : 1 + (w0 >= per ? w0 - per : w0);
+          int q = (x1 == 0) ? 0 : 1 + (w1 >= per ? w1 - per : w1);
           if (p > q) {
             const int tmp = p;
             p = q;

@@ -94,12 +94,17 @@ __device__ __forceinline__ void blk_gram(EigLDS &s, const EigCtx &cx, Blk<RES> X
 // of 8 k-steps, with an odd leading dimension, so that the loop needs no
 // clamps or masks and its LDS reads take immediate offsets.  When the
 // buffer holds fewer than 8 columns, lanes past them read a zero column.
+// epi(f, v) gives the value stored for entry f (row + column n2) of Out
+// from v = (M X)[f]; the filter's three-term recurrence runs there.
 typedef double eig_d4 __attribute__((ext_vector_type(4)));
 #define OP_KH 32   // k-steps of 4 per register batch of M
 #define OP_TPW 4   // row tiles per wave per round (4 waves per group: 16 tiles)
-template <bool RES>
+struct EpiCopy {
+  __device__ __forceinline__ double operator()(int, double v) const { return v; }
+};
+template <bool RES, typename Epi = EpiCopy>
 __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, int nc,
-                                       Blk<RES> Out) {
+                                       Blk<RES> Out, Epi epi = Epi()) {
   const int t = threadIdx.x, n2 = cx.n2;
   const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int li = lane & 15, lk = lane >> 4;
@@ -125,72 +130,85 @@ __device__ __forceinline__ void blk_op(EigLDS &s, const EigCtx &cx, Blk<RES> X, 
       s.pool[fbase + e] = (i < n2 && c < cw) ? Xc.at(s, i + c * n2) : 0.0;
     }
     __syncthreads();
+    // v_mfma_f64_4x4x4_4b_f64: four 4 x 4 blocks (rows 4b..4b+3) per
+    // instruction, one instruction per 4 columns.  Its A operand is the
+    // same fragment as the 16 x 16 x 4 one (lane l: row l % 16, k l / 16);
+    // B[k][j] sits at lane 16k + 4b + j and D[i][j] at lane 16i + 4b + j.
+    // Even and odd k-steps go to separate accumulators (four chains).
+    const double *xq0 = s.pool + fbase + 4 * ks0 + lk + min(li & 3, cwf) * xld;
+    const double *xq1 = s.pool + fbase + 4 * ks0 + lk + min(4 + (li & 3), cwf) * xld;
+    // M's fragments of k-steps [ks0 + kb, ks0 + kb + nk) of row tile rt
+    auto load_m = [&](double *a, int rt, int kb, int nk) __attribute__((always_inline)) {
+      const double2 *mt =
+          reinterpret_cast<const double2 *>(cx.M) + ((int64_t)rt * kq2 + ks0 / 2) * 64 + lane;
+#pragma unroll
+      for (int u0 = 0; u0 < OP_KH; u0 += 8) {
+        if (u0 < nk) {
+#pragma unroll
+          for (int u = u0; u < u0 + 8; u += 2) {
+            const double2 v = mt[(int64_t)((kb + u) >> 1) * 64];
+            a[u] = v.x;
+            a[u + 1] = v.y;
+          }
+        }
+      }
+    };
+    auto mul = [&](const double *a, int kb, int nk, double &c00, double &c01, double &c10,
+                   double &c11) __attribute__((always_inline)) {
+#pragma unroll
+      for (int u0 = 0; u0 < OP_KH; u0 += 8) {
+        if (u0 < nk) {
+          double b0[8], b1[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            b0[u] = xq0[4 * (kb + u0 + u)];
+            b1[u] = xq1[4 * (kb + u0 + u)];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; u += 2) {
+            c00 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u], b0[u], c00, 0, 0, 0);
+            c10 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u], b1[u], c10, 0, 0, 0);
+            c01 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u + 1], b0[u + 1], c01, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u + 1], b1[u + 1], c11, 0, 0, 0);
+          }
+        }
+      }
+    };
+    // group 1 writes its half of tile rt to Out, group 0 parks its half
+    auto emit = [&](int rt, int rp0, double d0, double d1) __attribute__((always_inline)) {
+      const int row_t = 4 * ((lane >> 2) & 3) + (lane >> 4), col = lane & 3;
+      if (grp == 0) {
+        part[(rt - rp0) * 256 + row_t * 16 + col] = d0;
+        part[(rt - rp0) * 256 + row_t * 16 + 4 + col] = d1;
+      } else {
+        const int row = rt * 16 + row_t;
+        if (row < n2) {
+          if (col < cw) Out.at(s, row + (c0 + col) * n2) = d0;
+          if (4 + col < cw) Out.at(s, row + (c0 + 4 + col) * n2) = d1;
+        }
+      }
+    };
     for (int rp0 = 0; rp0 < rtiles; rp0 += 4 * OP_TPW) {
 #pragma unroll 1
       for (int j = 0; j < OP_TPW; ++j) {
         const int rt = rp0 + wq + 4 * j;
         if (rt >= rtiles) break;
-        const double2 *mt =
-            reinterpret_cast<const double2 *>(cx.M) + ((int64_t)rt * kq2 + ks0 / 2) * 64 + lane;
-        // v_mfma_f64_4x4x4_4b_f64: four 4 x 4 blocks (rows 4b..4b+3) per
-        // instruction, one instruction per 4 columns.  Its A operand is the
-        // same fragment as the 16 x 16 x 4 one (lane l: row l % 16, k l / 16);
-        // B[k][j] sits at lane 16k + 4b + j and D[i][j] at lane 16i + 4b + j.
-        // Even and odd k-steps go to separate accumulators (four chains).
-        const double *xq0 = s.pool + fbase + 4 * ks0 + lk + min(li & 3, cwf) * xld;
-        const double *xq1 = s.pool + fbase + 4 * ks0 + lk + min(4 + (li & 3), cwf) * xld;
         double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
         for (int kb = 0; kb < ks1 - ks0; kb += OP_KH) {
           const int nk = min(OP_KH, ks1 - ks0 - kb);
           double a[OP_KH];
-#pragma unroll
-          for (int u0 = 0; u0 < OP_KH; u0 += 8) {
-            if (u0 < nk) {
-#pragma unroll
-              for (int u = u0; u < u0 + 8; u += 2) {
-                const double2 v = mt[(int64_t)((kb + u) >> 1) * 64];
-                a[u] = v.x;
-                a[u + 1] = v.y;
-              }
-            }
-          }
-#pragma unroll
-          for (int u0 = 0; u0 < OP_KH; u0 += 8) {
-            if (u0 < nk) {
-              double b0[8], b1[8];
-#pragma unroll
-              for (int u = 0; u < 8; ++u) {
-                b0[u] = xq0[4 * (kb + u0 + u)];
-                b1[u] = xq1[4 * (kb + u0 + u)];
-              }
-#pragma unroll
-              for (int u = 0; u < 8; u += 2) {
-                c00 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u], b0[u], c00, 0, 0, 0);
-                c10 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u], b1[u], c10, 0, 0, 0);
-                c01 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u + 1], b0[u + 1], c01, 0, 0, 0);
-                c11 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u0 + u + 1], b1[u + 1], c11, 0, 0, 0);
-              }
-            }
-          }
+          load_m(a, rt, kb, nk);
+          mul(a, kb, nk, c00, c01, c10, c11);
         }
-        const int row_t = 4 * ((lane >> 2) & 3) + (lane >> 4), col = lane & 3;
-        const double d0 = c00 + c01, d1 = c10 + c11;
-        if (grp == 0) {
-          part[(rt - rp0) * 256 + row_t * 16 + col] = d0;
-          part[(rt - rp0) * 256 + row_t * 16 + 4 + col] = d1;
-        } else {
-          const int row = rt * 16 + row_t;
-          if (row < n2) {
-            if (col < cw) Out.at(s, row + (c0 + col) * n2) = d0;
-            if (4 + col < cw) Out.at(s, row + (c0 + 4 + col) * n2) = d1;
-          }
-        }
+        emit(rt, rp0, c00 + c01, c10 + c11);
       }
       __syncthreads();
+      // Out = epi(group 1's half + group 0's half), a fixed order
       const int pr0 = rp0 * 16, prn = min(n2, (rp0 + 4 * OP_TPW) * 16) - pr0;
       for (int e = t; e < prn * cw; e += ET) {
         const int i = e % prn, c = e / prn;
-        Out.at(s, pr0 + i + (c0 + c) * n2) += part[(i >> 4) * 256 + (i & 15) * 16 + c];
+        const int f = pr0 + i + (c0 + c) * n2;
+        Out.at(s, f) = epi(f, Out.at(s, f) + part[(i >> 4) * 256 + (i & 15) * 16 + c]);
       }
       __syncthreads();
     }
@@ -343,8 +361,9 @@ __device__ __forceinline__ void blk_trsm(EigLDS &s, int n2, Blk<RES> X, int nb, 
 // is formed afresh for every eigen step and read by nothing else), walking
 // the fragment-major storage in order.  The
 // filter steps then multiply by the deflated matrix directly.  Reads go in
-// batches of 8 per thread, clamped to stay in bounds, so that they are in
+// batches of DF_U per thread, clamped to stay in bounds, so that they are in
 // flight together.
+#define DF_U 16
 template <bool RES>
 __device__ __forceinline__ void blk_deflate(EigLDS &s, const EigCtx &cx, Blk<RES> Y, int q0, int q1) {
   const int t = threadIdx.x, n2 = cx.n2;
@@ -354,14 +373,14 @@ __device__ __forceinline__ void blk_deflate(EigLDS &s, const EigCtx &cx, Blk<RES
   const int h = t & 1, lane = (t >> 1) & 63;
   const int ri = lane & 15, cj = 4 * h + (lane >> 4);
   double *M = cx.Mw;
-  for (int e0 = t; e0 < nn; e0 += 16 * ET) {
-    double v[16];
+  for (int e0 = t; e0 < nn; e0 += DF_U * ET) {
+    double v[DF_U];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = M[min(e0 + u * ET, nn - 1)];
+    for (int u = 0; u < DF_U; ++u) v[u] = M[min(e0 + u * ET, nn - 1)];
     const int T0 = e0 >> 7;
     int rt = T0 / kq2, q2 = T0 - rt * kq2;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < DF_U; ++u) {
       const int i = rt * 16 + ri, j = 8 * q2 + cj;
       if (e0 + u * ET < nn && i < n2 && j < n2)
         for (int a = q0; a < q1; ++a) v[u] -= s.th[a] * Y.at(s, i + a * n2) * Y.at(s, j + a * n2);
@@ -372,7 +391,7 @@ __device__ __forceinline__ void blk_deflate(EigLDS &s, const EigCtx &cx, Blk<RES
       }
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < DF_U; ++u)
       if (e0 + u * ET < nn) M[e0 + u * ET] = v[u];
   }
   __syncthreads();
@@ -554,16 +573,17 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
     Blk<RES> P0 = F0, P1 = F1, P2 = F2;
     for (int e = t; e < n2 * act; e += ET) P0.at(s, e) = Ya.at(s, e);
     __syncthreads();
-    blk_op<RES>(s, cx, P0, act, P1);
-    for (int e = t; e < n2 * act; e += ET) P1.at(s, e) = (P1.at(s, e) - e0 * P0.at(s, e)) * (s1 / h);
-    __syncthreads();
+    {
+      const double f1 = s1 / h;
+      blk_op<RES>(s, cx, P0, act, P1, [&](int f, double v) { return (v - e0 * P0.at(s, f)) * f1; });
+    }
     nmv += act * (d + 1);
     for (int j = 2; j <= d; ++j) {
       const double s2 = 1.0 / (tau - s1);
-      blk_op<RES>(s, cx, P1, act, P2);
-      for (int e = t; e < n2 * act; e += ET)
-        P2.at(s, e) = 2.0 * (s2 / h) * (P2.at(s, e) - e0 * P1.at(s, e)) - (s1 * s2) * P0.at(s, e);
-      __syncthreads();
+      const double f2 = 2.0 * (s2 / h), f0 = s1 * s2;
+      blk_op<RES>(s, cx, P1, act, P2, [&](int f, double v) {
+        return f2 * (v - e0 * P1.at(s, f)) - f0 * P0.at(s, f);
+      });
       const Blk<RES> tmp = P0;
       P0 = P1;
       P1 = P2;
