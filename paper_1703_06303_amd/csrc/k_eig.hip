@@ -97,7 +97,7 @@ __device__ __forceinline__ void blk_gram(EigLDS &s, const EigCtx &cx, Blk<RES> X
 // epi(f, v) gives the value stored for entry f (row + column n2) of Out
 // from v = (M X)[f]; the filter's three-term recurrence runs there.
 typedef double eig_d4 __attribute__((ext_vector_type(4)));
-#define OP_KH 32   // k-steps of 4 per register batch of M
+#define OP_KH 24   // k-steps of 4 per register batch of M
 #define OP_TPW 4   // row tiles per wave per round (4 waves per group: 16 tiles)
 struct EpiCopy {
   __device__ __forceinline__ double operator()(int, double v) const { return v; }
@@ -334,26 +334,101 @@ __device__ __forceinline__ void blk_rot(EigLDS &s, int n2, Blk<RES> X, int nb, c
   }
 }
 
-// X (n2 x nb) <- X R^-1 with R upper triangular in LDS: wavefront 0 forms
-// R^-1 (column c of R^-1 by back substitution on lane c), then blk_rot.
-template <bool RES>
-__device__ __forceinline__ void blk_trsm(EigLDS &s, int n2, Blk<RES> X, int nb, const double *R) {
+// The small steps of one CholeskyQR pass, from the Gram H of the nb columns
+// of X (nb x nb, ld B_): with D = diag(H), R'^T R' = D^-1/2 H D^-1/2 (plus
+// a diagonal shift of shift_coef ||D^-1/2 H D^-1/2||_F when shift_coef > 0),
+// R = R' D^1/2 and G = R^-1 (upper), so that X G is the orthonormal factor
+// of X.  For nb <= 8 all of it runs on wavefront 0 between two barriers,
+// the Gram entry (x, y) in lane x + nb y and column c of R^-1 in lane c;
+// larger blocks take the steps one by one.  Returns nonzero on a
+// non-positive pivot.
+__device__ __forceinline__ int cqr_small(EigLDS &s, int nb, double shift_coef) {
   const int t = threadIdx.x;
-  double *Ri = s.G;
+  if (nb > 8) {
+    for (int c = t; c < nb; c += ET) {
+      const double d = s.H[c + c * B_];
+      s.res[c] = d > 0 ? 1.0 / sqrt(d) : 1.0;  // a zero column is left to the shift
+    }
+    __syncthreads();
+    for (int e = t; e < nb * nb; e += ET) {
+      const int a2 = e % nb, c = e / nb;
+      s.H[a2 + c * B_] *= s.res[a2] * s.res[c];
+    }
+    __syncthreads();
+    double sh = 0.0;
+    if (shift_coef > 0.0) {
+      double fro = 0.0;
+      for (int e = 0; e < nb * nb; ++e) fro += s.H[(e % nb) + (e / nb) * B_] * s.H[(e % nb) + (e / nb) * B_];
+      sh = shift_coef * sqrt(fro);
+    }
+    if (blk_chol(s, s.H, nb, sh)) return 1;
+    for (int e = t; e < nb * nb; e += ET) {
+      const int a2 = e % nb, c = e / nb;
+      if (a2 <= c) s.H[a2 + c * B_] /= s.res[c];
+    }
+    __syncthreads();
+    double *Ri = s.G;
+    if (t < 64) {
+      for (int e = t; e < B_ * B_; e += 64) Ri[e] = 0.0;
+      wave_sync();
+      if (t < nb) {
+        const int c = t;
+        for (int a = c; a >= 0; --a) {
+          double v = (a == c) ? 1.0 : 0.0;
+          for (int q = a + 1; q <= c; ++q) v -= s.H[a + q * B_] * Ri[q + c * B_];
+          Ri[a + c * B_] = v / s.H[a + a * B_];
+        }
+      }
+    }
+    __syncthreads();
+    return 0;
+  }
   if (t < 64) {
-    for (int e = t; e < B_ * B_; e += 64) Ri[e] = 0.0;
+    const bool in = t < nb * nb;
+    const int x = in ? t % nb : 0, y = in ? t / nb : 0;
+    const double h = in ? s.H[x + y * B_] : 0.0;
+    const double dx = __shfl(h, x + x * nb, 64), dy = __shfl(h, y + y * nb, 64);
+    const double sx = dx > 0 ? 1.0 / sqrt(dx) : 1.0, sy = dy > 0 ? 1.0 / sqrt(dy) : 1.0;
+    double g = h * (sx * sy);
+    if (shift_coef > 0.0) {
+      const double fro = wave_sum(in ? g * g : 0.0);
+      if (in && x == y) g += shift_coef * sqrt(fro);
+    }
+    int bad = 0;
+    for (int j = 0; j < nb; ++j) {
+      double p = __shfl(g, j + j * nb, 64);
+      if (!(p > 0.0)) {
+        bad = 1;
+        p = 1.0;
+      }
+      const double rjj = sqrt(p);
+      if (in && x == j) g = (y == j) ? rjj : ((y > j) ? g / rjj : g);
+      const double rx = __shfl(g, j + x * nb, 64), ry = __shfl(g, j + y * nb, 64);
+      if (in && x > j && x <= y) g -= rx * ry;
+    }
+    // R = R' D^1/2 to LDS (upper triangle), then column t of R^-1 by back
+    // substitution in registers
+    if (in && x <= y) s.H[x + y * B_] = g / sy;
     wave_sync();
     if (t < nb) {
       const int c = t;
-      for (int a = c; a >= 0; --a) {
+      double ri[8];
+#pragma unroll
+      for (int a = 7; a >= 0; --a) {
         double v = (a == c) ? 1.0 : 0.0;
-        for (int q = a + 1; q <= c; ++q) v -= R[a + q * B_] * Ri[q + c * B_];
-        Ri[a + c * B_] = v / R[a + a * B_];
+#pragma unroll
+        for (int q = a + 1; q < 8; ++q)
+          if (q <= c) v = fma(-s.H[min(a, nb - 1) + min(q, nb - 1) * B_], ri[q], v);
+        ri[a] = (a <= c && a < nb) ? v / s.H[min(a, nb - 1) + min(a, nb - 1) * B_] : 0.0;
       }
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (a < nb) s.G[a + c * B_] = ri[a];
     }
+    if (t == 0) s.ints[0] = bad;
   }
   __syncthreads();
-  blk_rot<RES>(s, n2, X, nb, Ri);
+  return s.ints[0];
 }
 
 // Hotelling deflation of newly locked Ritz pairs, once per locking event:
@@ -427,40 +502,15 @@ __device__ __forceinline__ void blk_orth(EigLDS &s, const EigCtx &cx, Blk<RES> X
     // Gram, scaled to unit diagonal (D^-1/2 G D^-1/2 = R'^T R'), so that
     // X R^-1 = X D^-1/2 R'^-1: the normalisation costs no pass over X
     blk_gram<RES>(s, cx, X, nb, X, nb, s.H);
-    for (int c = t; c < nb; c += ET) {
-      const double d = s.H[c + c * B_];
-      s.res[c] = d > 0 ? 1.0 / sqrt(d) : 1.0;  // a zero column is left to the shift
-    }
-    __syncthreads();
-    for (int e = t; e < nb * nb; e += ET) {
-      const int a2 = e % nb, c = e / nb;
-      s.H[a2 + c * B_] *= s.res[a2] * s.res[c];
-    }
-    __syncthreads();
-    if (blk_chol(s, s.H, nb, 0.0)) {
+    if (cqr_small(s, nb, 0.0)) {
       blk_gram<RES>(s, cx, X, nb, X, nb, s.H);
-      for (int e = t; e < nb * nb; e += ET) {
-        const int a2 = e % nb, c = e / nb;
-        s.H[a2 + c * B_] *= s.res[a2] * s.res[c];
-      }
-      __syncthreads();
-      double fro = 0.0;
-      for (int e = 0; e < nb * nb; ++e) fro += s.H[(e % nb) + (e / nb) * B_] * s.H[(e % nb) + (e / nb) * B_];
-      const double sh = 11.0 * ((double)n2 * nb + (double)nb * (nb + 1)) * 2.220446049250313e-16 * sqrt(fro);
       shifted = 1;
-      if (blk_chol(s, s.H, nb, sh)) {
+      if (cqr_small(s, nb, 11.0 * ((double)n2 * nb + (double)nb * (nb + 1)) * 2.220446049250313e-16)) {
         if (t == 0) atomicOr(flags, DEV_EIG_ORTH);
         return;
       }
     }
-    // R = R' D^1/2 (column c of R' times d_c^1/2), so that X R^-1 is the
-    // orthonormal factor of X itself
-    for (int e = t; e < nb * nb; e += ET) {
-      const int a2 = e % nb, c = e / nb;
-      if (a2 <= c) s.H[a2 + c * B_] /= s.res[c];
-    }
-    __syncthreads();
-    blk_trsm<RES>(s, n2, X, nb, s.H);
+    blk_rot<RES>(s, n2, X, nb, s.G);  // X R^-1
   }
 }
 
