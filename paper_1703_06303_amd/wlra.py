@@ -134,6 +134,12 @@ def colmajor(t):
     return t.t().contiguous().t()
 
 
+def empty_colmajor(rows, cols, dtype, device):
+    """Uninitialised column-major rows x cols tensor (no copy kernel)."""
+    import torch
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
@@ -265,9 +271,8 @@ class Solver:
         if out is not None:
             X1, X2 = out
         else:
-            X1 = colmajor(torch.empty((m, k), dtype=self.dtype, device=A.device))
-            X2 = (colmajor(torch.empty((m, n - k), dtype=self.dtype, device=A.device))
-                  if want_x2 else None)
+            X1 = empty_colmajor(m, k, self.dtype, A.device)
+            X2 = empty_colmajor(m, n - k, self.dtype, A.device) if want_x2 else None
         tr = (ctypes.c_double * (2 * (max_sweeps + 1)))() if want_trace else None
         mask = (torch.empty((n, m), dtype=torch.uint8, device=A.device).t()
                 if mask_tau is not None else None)
