@@ -20,7 +20,7 @@
 
 #define WLRA_VERSION 200
 #define EIG_GUARD 3
-#define EIG_DEG 12
+#define EIG_DEG 20
 #define EIG_MAXIT 60
 // Mixed precision: the BF16 sweeps stop at max(tol, MIXED_TOL) before the
 // exact refinement sweep.  Their eigen steps stop at a residual of
