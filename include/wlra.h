@@ -32,8 +32,8 @@ extern "C" {
 #endif
 
 /* Status codes.  0, 1 and 2 mean a result is in the outputs; negative codes
- * mean the outputs are not written (or, for WLRA_E_ROWSOLVE and WLRA_E_EIG,
- * must not be used). */
+ * mean the outputs are not written (argument and input errors) or must not
+ * be used (WLRA_E_ROWSOLVE, WLRA_E_RANK, WLRA_E_EIG: the solve ran). */
 enum wlra_status {
   WLRA_OK = 0,            /* converged under the Section 4.1 rule             */
   WLRA_MAX_SWEEPS = 1,    /* max_sweeps X1 updates done; result is X_p        */

@@ -937,10 +937,9 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws,
   r.may_tune = may_tune;
   int rc = r.begin(h, pr, res, ws, s, h->st_host);
   if (rc != WLRA_OK) return rc;
-  HIPCHK(hipMemcpyAsync(h->flags_host, r.P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  rc = Run<T>::input_status(*h->flags_host);
-  if (rc != WLRA_OK) return rc;
+  // the input checks' flags come back with the first sweep's state (one
+  // synchronisation fewer; the sweep's kernels are harmless on bad input)
+  bool inputs_checked = false;
   for (;;) {
     r.small_args();
     r.small_single();
@@ -948,21 +947,29 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws,
     if (r.change_needed()) r.change(false);
     PROFWS(h, s, KK_DECIDE, 0, 0, launch_decide(s, r.sa));
     HIPCHK(hipMemcpyAsync(h->st_host, r.P.st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
+    if (!inputs_checked)
+      HIPCHK(hipMemcpyAsync(h->flags_host, r.P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (!inputs_checked) {
+      inputs_checked = true;
+      rc = Run<T>::input_status(*h->flags_host);
+      if (rc != WLRA_OK) return rc;
+    }
     prof_collect(h);
     const int d = r.after_decide();
     if (d == 1) break;
     if (d == 2) continue;
     r.update();
   }
-  HIPCHK(hipMemcpyAsync(h->flags_host, r.P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  rc = Run<T>::device_status(*h->flags_host);
-  if (rc != WLRA_OK) return rc;
+  // outputs, the device flags and the end event under one synchronisation;
+  // a failure status then means the outputs must not be used
   rc = r.outputs();
   if (rc != WLRA_OK) return rc;
+  HIPCHK(hipMemcpyAsync(h->flags_host, r.P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(h->ev1, s));
   HIPCHK(hipEventSynchronize(h->ev1));
+  rc = Run<T>::device_status(*h->flags_host);
+  if (rc != WLRA_OK) return rc;
   prof_collect(h);
   float ms = 0.f;
   hipEventElapsedTime(&ms, h->ev0, h->ev1);
