@@ -73,8 +73,8 @@ STREAMING = ("update", "gram_X1A2", "change", "gram_A2", "gram_X1X1", "validate"
 # byte-identical to the ones measured (SHA-256 of their concatenation, in the
 # order listed); otherwise traffic is reported as null.
 TRAFFIC = {
-    ("eig", "config2", "mixed"): (595867, ("k_eig.hip", "eig_small.h", "launch.h", "common.h"),
-                                  "0f5ed553bd32245c669c0148bae03fe2a22dc347e8294e90cf1fc0834c713e3d"),
+    ("eig", "config2", "mixed"): (647260, ("k_eig.hip", "eig_small.h", "launch.h", "common.h"),
+                                  "2ae3094f83181539d54bbf42f8f3326e65b5cb3f31975e1e54a988341134f807"),
 }
 
 
@@ -182,9 +182,10 @@ def train_learned(pool, args):
                     json.dump({k_: v for k_, v in report.items()}, f, indent=1)
                 log(f"# warm start: weights written to {args.save_weights}")
         ho = [video.config5_seed(i, heldout=True) for i in range(args.learn_heldout)]
-        ev = WS.evaluate(s, pool, params, ho, log=lambda m_: log("# warm start: " + m_))
+        ev = (WS.evaluate(s, pool, params, ho, log=lambda m_: log("# warm start: " + m_))
+              if ho else None)
     report["heldout_instances"] = len(ho)
-    report["heldout"] = WS.summarize(ev)
+    report["heldout"] = WS.summarize(ev) if ev else None
     return params, report
 
 
@@ -227,6 +228,10 @@ def roofline_of(name, launches, ms, nbytes, flops, res_list, n2):
         fl = 2.0 * n2 * n2 * mv / launches
         roof = {"bound": "alu", "achieved": fl / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
+        # the step runs in one workgroup: its share of the chip's FP64 rate
+        # (one CU of 256) for context
+        roof["peak_one_cu"] = FP64_PEAK_TFLOPS / 256
+        roof["frac_one_cu"] = roof["achieved"] / roof["peak_one_cu"]
     elif nbytes > 0:
         roof = {"bound": "hbm", "achieved": nbytes / launches / avg_s / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
