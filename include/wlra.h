@@ -71,17 +71,16 @@ typedef enum {
   WLRA_FP64 = 0,
   WLRA_FP32 = 1,
   WLRA_MIXED_BF16 = 2    /* float storage; the validation pass stages A2 in
-                            BF16 (round to nearest even) and the sweeps run on
-                            [A1, bf16(A2)] (Grams of A2 summed in double, the
-                            row update in float) until the Section 4.1 rule
-                            holds at max(tol, 1e-5) or max_sweeps - 1 updates;
-                            then A2^T A2 and X1^T A2 are formed from A2 itself,
-                            X_p is re-evaluated and one exact sweep (the
-                            refinement) gives the returned X_{p+1}.  The
-                            BF16 phase's eigen steps stop at a residual of
-                            max(eig_tol, 1e-7) ||A2^T A2||_F, the exact ones
-                            at eig_tol.  The status is that of the BF16
-                            phase.                                          */
+                            BF16 (round to nearest even).  The sweeps' X1
+                            updates take the product with A2 (step 7) from
+                            that copy on the BF16 matrix cores, with float
+                            accumulation; every other step (the Grams of A2
+                            and X1, the small steps, the change) uses A2
+                            itself.  This phase runs until the Section 4.1
+                            rule holds at max(tol, 1e-5) or max_sweeps - 1
+                            updates; then one exact sweep (the refinement)
+                            gives the returned X_{p+1}.  The status is that
+                            of the first phase.                             */
 } wlra_precision;
 
 /* Start X1_0 (Algorithm 1 leaves it open; Section 4.1 recommends a random

@@ -21,9 +21,9 @@ Functions and the passage each follows:
                             below eq. (9) and the stopping rule of Section 4.1
   round_bf16                BF16 rounding (IEEE binary32 truncated to 8 exponent
                             and 7 fraction bits, round to nearest even)
-  swlr_mixed                the reduced-precision schedule: Algorithm 1 on
-                            [A1, bf16(A2)] to a looser threshold, then one
-                            sweep of Algorithm 1 on A itself
+  swlr_mixed                the reduced-precision schedule: Algorithm 1 with
+                            step 7's A2 product on bf16(A2) to a looser
+                            threshold, then one exact sweep of Algorithm 1
   objective_colweights,     eq. (6) with W2(i, j) = w2_j (one weight per
   swlr_colweights           column of the unweighted block), reduced to
                             problem (5) by scaling the columns of A2
@@ -143,12 +143,18 @@ def _validate(A, W1, k, r):
             raise OracleError(E_WEIGHT, "W1 entries must be finite and > 0")
 
 
-def swlr(A, W1, k, r, tol=1e-7, max_sweeps=200, X1_0=None, row_chunk=4096):
+def swlr(A, W1, k, r, tol=1e-7, max_sweeps=200, X1_0=None, row_chunk=4096, A2_update=None):
     """Algorithm 1 (sWLR), literally, in float64.
 
     A: m x n; W1: m x k array or a scalar; X1_0: m x k start (the paper
     draws it at random; callers pass it so every implementation starts from
     the same point).  tol <= 0 runs exactly max_sweeps X1 updates.
+
+    A2_update (m x (n - k), optional; not in the paper): a stand-in for A2 in
+    step 7's product only.  Writing E_p = A1 o W1 o W1 + A2 Z + X1_p T with
+    Z = (I - V V^T) C_p^T and T = C_p V V^T C_p^T (D_p = P_perp A2 V V^T),
+    the term A2 Z takes A2_update instead: E_p gains (A2_update - A2) Z.
+    Every other step (QR, C_p, D_p, the objective and Error_p) uses A2.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
@@ -213,6 +219,11 @@ def swlr(A, W1, k, r, tol=1e-7, max_sweeps=200, X1_0=None, row_chunk=4096):
             return res
         # Step 7: E_p = A1 o W1 o W1 + (A2 - D_p) C_p^T.
         E = A1 * W1sq + (A2 - D) @ C.T
+        if A2_update is not None and ell > 0:
+            V = Vt[:ell].T
+            E = E + (A2_update - A2) @ (C.T - V @ (V.T @ C.T))
+        elif A2_update is not None:
+            E = E + (A2_update - A2) @ C.T
         S = C @ C.T
         # Steps 8-9: row i of X1_{p+1} = E(i,:) (diag(W1(i,:)^2) + C C^T)^{-1}.
         X1_new = np.empty_like(X1)
@@ -248,24 +259,24 @@ MIXED_TOL = 1e-5
 def swlr_mixed(A, W1, k, r, tol=1e-7, max_sweeps=200, X1_0=None, mixed_tol=MIXED_TOL):
     """Reduced-precision schedule, in float64 arithmetic.
 
-    Phase 1: Algorithm 1 on the perturbed matrix [A1, bf16(A2)] (A2 rounded
-    to BF16 from float32), stopping at max(tol, mixed_tol) (tol > 0) or
-    after max_sweeps - 1 X1 updates.  Phase 2: Algorithm 1 on A itself from
-    the X1 reached, for one more X1 update when max_sweeps allows it.  The
-    result is phase 2's X_p with sweeps = all X1 updates and the status of
-    phase 1."""
+    Phase 1: Algorithm 1 on A with step 7's product A2 Z taken with bf16(A2)
+    (A2 rounded to BF16 from float32; `swlr`'s A2_update), every other step
+    exact, stopping at max(tol, mixed_tol) (tol > 0) or after max_sweeps - 1
+    X1 updates.  Phase 2: Algorithm 1 on A from the X1 reached, for one more
+    X1 update when max_sweeps allows it.  The result is phase 2's X_p with
+    sweeps = all X1 updates and the status of phase 1."""
     A = np.asarray(A, dtype=np.float64)
     if k == 0:
         return swlr(A, W1, k, r, tol=tol, max_sweeps=max_sweeps, X1_0=X1_0)
-    Ab = A.copy()
-    Ab[:, k:] = round_bf16(A[:, k:])
+    A2b = round_bf16(A[:, k:])
     tol1 = max(tol, mixed_tol) if tol > 0 else tol
-    first = swlr(Ab, W1, k, r, tol=tol1, max_sweeps=max(max_sweeps - 1, 0), X1_0=X1_0)
+    first = swlr(A, W1, k, r, tol=tol1, max_sweeps=max(max_sweeps - 1, 0), X1_0=X1_0,
+                 A2_update=A2b)
     extra = min(first.sweeps + 1, max_sweeps) - first.sweeps
     second = swlr(A, W1, k, r, tol=0.0, max_sweeps=extra, X1_0=first.X1)
     second.sweeps = first.sweeps + extra
     second.status = first.status
-    second.F = first.F + second.F
+    second.F = first.F + second.F[1:]  # phase 2 re-evaluates X_p: F_p once
     return second
 
 

@@ -22,13 +22,11 @@
 #define EIG_GUARD 3
 #define EIG_DEG 20
 #define EIG_MAXIT 60
-// Mixed precision: the BF16 sweeps stop at max(tol, MIXED_TOL) before the
-// exact refinement sweep.  Their eigen steps stop at a residual of
-// MIXED_EIG_TOL * ||A2^T A2||_F: M is formed from BF16 data there (relative
-// rounding 2^-9), and the phase only has to bring the iterate change below
-// MIXED_TOL; the exact phase returns to the full eigen tolerance.
+// Mixed precision: the sweeps whose X1 update takes its A2 product from the
+// BF16 copy stop at max(tol, MIXED_TOL) before the exact refinement sweep.
+// Every small step (eigen step included, at the full tolerance) is exact, so
+// X_p at the end of that phase needs no re-evaluation.
 #define MIXED_TOL 1e-5
-#define MIXED_EIG_TOL 1e-7
 #define WLRA_BATCH_LANES_DEFAULT 4
 #define WLRA_BATCH_LANES_MAX 16
 
@@ -499,7 +497,7 @@ struct Run {
   T *X1c = nullptr;
   int cur = 0, nparts = 0, p = 0, max_sweeps = 0, mixed_status = 0, rc_tune = 0;
   bool may_tune = true;  // false: no new autotuner entries (nothing allocates)
-  bool on_bf16 = false, reeval = false;
+  bool on_bf16 = false;  // the X1 update's A2 product on the BF16 copy
   SmallArgs sa{};
   SmallOut<T> so{};
 
@@ -550,7 +548,7 @@ struct Run {
     }
     eig_tol = pr->eig_tol > 0 ? pr->eig_tol
                               : (h->precision == WLRA_FP64 ? 64.0 * 2.220446049250313e-16 : 1e-10);
-    sh->eig_floor = mixed ? std::max(eig_tol, MIXED_EIG_TOL) : eig_tol;
+    sh->eig_floor = eig_tol;
     HIPCHK(hipMemcpyAsync(P.st, sh, sizeof(SmallState), hipMemcpyHostToDevice, s));
 
     // algorithmic bytes per launch of the streaming kernels (each operand
@@ -611,14 +609,14 @@ struct Run {
       PROFWS(h, s, KK_INIT, 0, 0,
              launch_init_x1<T>(s, m, k, mode, pr->seed, src, lds, X1c, P.flags, lflag));
     }
-    on_bf16 = mixed;  // A2 products on the BF16 copy (mixed phase)
+    on_bf16 = mixed;  // the mixed phase: BF16 in the X1 update's A2 product only
     rc_tune = tune_products();
     if (rc_tune != WLRA_OK) return rc_tune;
-    gram_A2(on_bf16);
+    gram_A2();
     // eig_floor is relative to ||A2^T A2||_F; k_gastats scales it.
     PROFWS(h, s, KK_GAST, 0, 0, launch_gastats(s, (int)n2, P.GA, P.st));
     if (k > 0) {
-      gram_X1A2(X1c, on_bf16);
+      gram_X1A2(X1c);
       PROFWS(h, s, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
              (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_g1,
                                   z.rows_g1, P.part, P.G1, nullptr)));
@@ -641,7 +639,6 @@ struct Run {
                      static_cast<T *>(P.Vr), static_cast<T *>(P.Zx)};
     cur = 0;
     p = 0;
-    reeval = false;
     mixed_status = 0;
     return WLRA_OK;
   }
@@ -654,7 +651,7 @@ struct Run {
   // per handle.
   int tune_products() {
     if (!h->autotune || n2 == 0) return WLRA_OK;
-    const std::array<int64_t, 5> key{m, n2, k, (int64_t)sizeof(T), on_bf16 ? 1 : 0};
+    const std::array<int64_t, 5> key{m, n2, k, (int64_t)sizeof(T), 0};
     auto it = h->tune.find(key);
     int tp = 0, tg = 0;
     if (it != h->tune.end()) {
@@ -671,13 +668,6 @@ struct Run {
         float tms_p = 0.f, tms_g = 0.f;
         if (k > 0) {
           auto xta = [&]() {
-            if constexpr (std::is_same<T, float>::value) {
-              if (on_bf16) {
-                launch_tsgemm<float, bf16s>(s, m, X1c, m, (int)k, P.Ab, m, (int)n2, 0, sp, rp,
-                                            P.part, P.P, nullptr);
-                return;
-              }
-            }
             launch_tsgemm<T, T>(s, m, X1c, m, (int)k, A2, lda, (int)n2, 0, sp, rp, P.part, P.P,
                                 nullptr);
           };
@@ -690,13 +680,6 @@ struct Run {
           if (tms_p < best_p) { best_p = tms_p; tp = c; }
         }
         auto gram = [&]() {
-          if constexpr (std::is_same<T, float>::value) {
-            if (on_bf16) {
-              launch_tsgemm<bf16s, bf16s>(s, m, P.Ab, m, (int)n2, P.Ab, m, (int)n2, 1, sg, rg,
-                                          P.part, P.GA, nullptr);
-              return;
-            }
-          }
           launch_tsgemm<T, T>(s, m, A2, lda, (int)n2, A2, lda, (int)n2, 1, sg, rg, P.part, P.GA,
                               nullptr);
         };
@@ -722,31 +705,16 @@ struct Run {
     return WLRA_OK;
   }
 
-  // One-time Gram of the unweighted block: A2^T A2 (of the BF16 copy in
-  // mixed precision, so that M = G_A - B^T B stays consistent).
-  void gram_A2(bool bf) {
-    if constexpr (std::is_same<T, float>::value) {
-      if (bf) {
-        PROFWS(h, s, KK_GRAM, md * n2d * 2.0, md * n2d * n2d,
-               (launch_tsgemm<bf16s, bf16s>(s, m, P.Ab, m, (int)n2, P.Ab, m, (int)n2, 1,
-                                            z.splits_ga, z.rows_ga, P.part, P.GA, nullptr)));
-        return;
-      }
-    }
+  // One-time Gram of the unweighted block: A2^T A2 (always of A2 itself:
+  // M = G_A - B^T B subtracts two numbers of the size of the background
+  // energy, so both come from the same data in every precision).
+  void gram_A2() {
     PROFWS(h, s, KK_GRAM, md * n2d * es, md * n2d * n2d,
            (launch_tsgemm<T, T>(s, m, A2, lda, (int)n2, A2, lda, (int)n2, 1, z.splits_ga,
                                 z.rows_ga, P.part, P.GA, nullptr)));
   }
   // X1^T A2 (k x n2) for the coefficients of the next small step.
-  void gram_X1A2(const T *X1, bool bf) {
-    if constexpr (std::is_same<T, float>::value) {
-      if (bf) {
-        PROFWS(h, s, KK_XTA, md * (kd * es + n2d * 2.0), 2.0 * md * kd * n2d,
-               (launch_tsgemm<float, bf16s>(s, m, X1, m, (int)k, P.Ab, m, (int)n2, 0,
-                                            z.splits_p, z.rows_p, P.part, P.P, nullptr)));
-        return;
-      }
-    }
+  void gram_X1A2(const T *X1) {
     PROFWS(h, s, KK_XTA, md * (kd + n2d) * es, 2.0 * md * kd * n2d,
            (launch_tsgemm<T, T>(s, m, X1, m, (int)k, A2, lda, (int)n2, 0, z.splits_p, z.rows_p,
                                 P.part, P.P, nullptr)));
@@ -783,7 +751,7 @@ struct Run {
     return PanelArgs{(int)n2, (int)k, update_panel_kp((int)k), (int)panel_rows(n2),
                      reinterpret_cast<const float *>(so.Gt), P.Zh, P.Zl, P.st};
   }
-  bool change_needed() const { return p > 0 && !reeval; }
+  bool change_needed() const { return p > 0; }
   ChgArgs chg_args() const {
     return ChgArgs{(int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1], P.Zd[p & 1],
                    P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, P.st};
@@ -800,43 +768,35 @@ struct Run {
       PROFWS(h, s, KK_CHGQR, 0, 0,
              launch_chgprep_gram(s, (int)n2, (int)k, (int)l, P.Hb, P.Rh, z.splits_kg, z.rows_kg,
                                  P.part, P.st));
-    PROFWS(h, s, KK_CHANGE, md * (n2d * (on_bf16 ? 2.0 : es) + 2.0 * kd * es),
+    PROFWS(h, s, KK_CHANGE, md * (n2d * es + 2.0 * kd * es),
            md * (4.0 * (double)l * n2d +
                  (2.0 * (double)l + 2.0 * kd) * (2.0 * (double)l + 2.0 * kd)),
-           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, lda, on_bf16 ? P.Ab : nullptr,
+           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, lda, nullptr,
                                m, X1c, static_cast<const T *>(P.X1[cur ^ 1]), P.Hb, P.Rh,
                                P.chg_part, P.st));
   }
 
   // Host side of sweep p after its state is in *sh: the trace, and the end
-  // of the mixed phase.  Returns 1 when X_p is final, 2 when the mixed phase
-  // ended (X_p is re-evaluated in exact arithmetic by the next small step,
-  // whose sums are enqueued here), 0 when the X1 update follows.
+  // of the mixed phase.  Returns 1 when X_p is final, 0 when the X1 update
+  // follows.
   int after_decide() {
     if (pr->trace && p <= pr->max_sweeps) {
       pr->trace[p] = sh->F;
-      // the exact re-evaluation of X_p after the mixed phase runs no change
-      // pass: Error_p stays the BF16 phase's
-      if (!reeval) pr->trace[pr->max_sweeps + 1 + p] = sh->err;
+      pr->trace[pr->max_sweeps + 1 + p] = sh->err;
     }
-    reeval = false;
     if (sh->done && on_bf16) {
-      // End of the mixed phase at X1_p: switch to A2 itself (exact G_A and
-      // X1_p^T A2), re-evaluate X_p without a change pass, then allow one
-      // more X1 update (the refinement sweep) within max_sweeps.
+      // End of the mixed phase at X1_p.  Its small step was exact already
+      // (only the X1 updates used the BF16 copy), so one more X1 update in
+      // exact arithmetic (the refinement sweep) follows within max_sweeps.
       mixed_status = sh->status;
       on_bf16 = false;
-      reeval = true;
+      if (p >= max_sweeps) return 1;
       sh->done = 0;
-      sh->have_prev = 0;
+      sh->sweep = p + 1;  // the decision did not count the sweep it ended on
       sh->tol = pr->tol;
-      sh->max_sweeps = std::min(p + 1, max_sweeps);
-      sh->eig_floor = eig_tol;
+      sh->max_sweeps = p + 1;
       (void)hipMemcpyAsync(P.st, sh, sizeof(SmallState), hipMemcpyHostToDevice, s);
-      gram_A2(false);
-      PROFWS(h, s, KK_GAST, 0, 0, launch_gastats(s, (int)n2, P.GA, P.st));
-      if (k > 0) gram_X1A2(X1c, false);
-      return 2;
+      return 0;
     }
     return sh->done ? 1 : 0;
   }
@@ -862,7 +822,7 @@ struct Run {
            2.0 * md * ((double)pr->n + kd) * kd +
                (constw ? 0.0 : md * (kd * kd * kd / 3.0 + 2.0 * kd * kd)),
            launch_update<T>(s, ua));
-    gram_X1A2(X1n, on_bf16);
+    gram_X1A2(X1n);
     PROFWS(h, s, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
            (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_g1, z.rows_g1,
                                 P.part, P.G1, nullptr)));
@@ -958,7 +918,6 @@ int solve_impl(wlra_ctx *h, const wlra_problem *pr, wlra_result *res, char *ws,
     prof_collect(h);
     const int d = r.after_decide();
     if (d == 1) break;
-    if (d == 2) continue;
     r.update();
   }
   // outputs, the device flags and the end event under one synchronisation;

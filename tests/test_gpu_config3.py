@@ -6,8 +6,8 @@ pass with r - k = 10.
 Bars (the stated FP32 tolerance, 1e-5 relative Frobenius on X = [X1 X2]):
   * FP32 at the same start and number of sweeps as the FP64 oracle;
   * mixed precision at the same start and number of sweeps as the oracle's
-    mixed schedule (`swlr_mixed`: the same steps in float64 on
-    [A1, bf16(A2)], then one sweep on A);
+    mixed schedule (`swlr_mixed`: the same steps in float64, step 7's A2
+    product on bf16(A2), then one exact sweep);
   * a converged FP32 solve against the closed form: W1 is constant, so
     X* = H_r(A S) S^-1 with S = diag(w, .., w, 1, .., 1) (problem (5) and
     eq. (2)).

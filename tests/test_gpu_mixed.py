@@ -1,9 +1,10 @@
-"""GPU parity of the mixed-precision mode (A2 staged in BF16, then one exact
-refinement sweep), called through the C ABI.
+"""GPU parity of the mixed-precision mode (the X1 updates' A2 product on a
+BF16 copy, then one exact refinement sweep), called through the C ABI.
 
 Bars: at the same start and the same number of sweeps, X = [X1 X2] within
 1e-5 (relative Frobenius) of the oracle's mixed schedule (`swlr_mixed`: the
-same steps in float64 on [A1, bf16(A2)], then on A); and the objective of a
+same steps in float64 with step 7's A2 product on bf16(A2), then one exact
+sweep); and the objective of a
 converged mixed solve within 1e-6 (relative) of the converged FP64 optimum.
 """
 import numpy as np

@@ -278,9 +278,51 @@ def test_mixed_schedule_special_cases():
     assert mix.sweeps == 4 and _relerr(mix.X, ref.X) < 1e-12
 
 
+def test_update_stand_in_enters_step7_through_z_only():
+    """`swlr`'s A2_update replaces A2 in step 7's product A2 Z alone
+    (Z = (I - V V^T) C^T).  Equal to A2 it is the plain sweep.  A perturbation
+    G V^T along the sweep's right singular vectors leaves the update as it is
+    ((I - V V^T) annihilates it).  The update is affine in the stand-in.  And a
+    small perturbation that is orthogonal to col(X1), to the top left singular
+    vectors of P_perp A2 and to V leaves Q, C and D unchanged, so the update
+    equals the plain sweep of Algorithm 1 on [A1, A2 + perturbation] (this
+    fixes the sign of the correction)."""
+    inst = video.small(m_hw=(10, 12), n=30, k=4, r=7, rho=2, fg="blobs", seed=17,
+                       w1=("loguniform", 1.0, 3.0))
+    A, W1, k, r, X0 = inst.A, inst.W1, inst.k, inst.r, inst.X1_0
+    A2 = A[:, k:]
+    rng = np.random.default_rng(5)
+    one = dict(tol=0.0, max_sweeps=1, X1_0=X0)
+    base = O.swlr(A, W1, k, r, **one)
+    same = O.swlr(A, W1, k, r, A2_update=A2.copy(), **one)
+    assert np.array_equal(same.X1, base.X1)
+    V = O.swlr(A, W1, k, r, tol=0.0, max_sweeps=0, X1_0=X0).V
+    along = O.swlr(A, W1, k, r, A2_update=A2 + rng.standard_normal((A.shape[0], r - k)) @ V.T,
+                   **one)
+    assert _relerr(along.X1, base.X1) < 1e-12
+    dl = 1e-3 * rng.standard_normal(A2.shape)
+    x1 = O.swlr(A, W1, k, r, A2_update=A2 + dl, **one).X1
+    x2 = O.swlr(A, W1, k, r, A2_update=A2 + 2 * dl, **one).X1
+    assert _relerr(x2 - base.X1, 2 * (x1 - base.X1)) < 1e-9
+    Q, _ = np.linalg.qr(X0)
+    N = A2 - Q @ (Q.T @ A2)
+    U, sv, _ = np.linalg.svd(N, full_matrices=False)
+    Ul = U[:, :r - k]
+    Pl = np.eye(A.shape[0]) - Q @ Q.T - Ul @ Ul.T
+    Pr = np.eye(A2.shape[1]) - V @ V.T
+    dp = Pl @ rng.standard_normal(A2.shape) @ Pr
+    dp *= 1e-3 * sv[r - k - 1] / np.linalg.norm(dp, 2)
+    stand_in = O.swlr(A, W1, k, r, A2_update=A2 + dp, **one).X1
+    Ap = A.copy()
+    Ap[:, k:] = A2 + dp
+    plain = O.swlr(Ap, W1, k, r, **one).X1
+    assert _relerr(stand_in, plain) < 1e-10
+
+
 def test_mixed_schedule_meets_objective():
-    """BF16 sweeps to 1e-5 and one exact sweep land within 1e-6 of the
-    converged objective (the accuracy the schedule is meant for)."""
+    """Sweeps with the BF16 update product to 1e-5 and one exact sweep land
+    within 1e-6 of the converged objective (the accuracy the schedule is
+    meant for)."""
     inst = video.small(m_hw=(24, 32), n=60, k=8, r=11, rho=3, fg="blobs", seed=12,
                        w1=("loguniform", 1.0, 4.0))
     ref = O.swlr(inst.A, inst.W1, inst.k, inst.r, tol=1e-13, max_sweeps=500, X1_0=inst.X1_0)
