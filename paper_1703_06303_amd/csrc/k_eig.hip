@@ -310,7 +310,8 @@ __device__ __forceinline__ int blk_chol(EigLDS &s, double *G, int nb, double shi
 }
 
 // X (n2 x nb) <- X S (S nb x nb in LDS, ld B_).  Rows are copied to LDS
-// scratch in chunks, then each thread forms one output entry.
+// scratch in chunks, column-major (consecutive threads touch consecutive
+// words), then each thread forms one output entry.
 template <bool RES>
 __device__ __forceinline__ void blk_rot(EigLDS &s, int n2, Blk<RES> X, int nb, const double *S) {
   const int t = threadIdx.x;
@@ -321,13 +322,13 @@ __device__ __forceinline__ void blk_rot(EigLDS &s, int n2, Blk<RES> X, int nb, c
     const int nr = min(rows, n2 - r0);
     for (int e = t; e < nr * nb; e += ET) {
       const int i = e % nr, c = e / nr;
-      s.pool[tmp + i * nb + c] = X.at(s, r0 + i + c * n2);
+      s.pool[tmp + e] = X.at(s, r0 + i + c * n2);
     }
     __syncthreads();
     for (int e = t; e < nr * nb; e += ET) {
       const int i = e % nr, c = e / nr;
       double v = 0.0;
-      for (int a = 0; a < nb; ++a) v = fma(s.pool[tmp + i * nb + a], S[a + c * B_], v);
+      for (int a = 0; a < nb; ++a) v = fma(s.pool[tmp + i + a * nr], S[a + c * B_], v);
       X.at(s, r0 + i + c * n2) = v;
     }
     __syncthreads();

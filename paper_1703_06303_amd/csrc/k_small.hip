@@ -37,22 +37,35 @@ __global__ __launch_bounds__(1024) void k_gastats(int n2, const double *__restri
   }
 }
 
+// Lane `lane`'s x (lane uniform).
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const long long v = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(v & 0xffffffffll), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // -----------------------------------------------------------------------------
-// Cholesky of G1 = X1^T X1 by wavefront 0 (rank check on the pivots); then
-// one thread per column of P: forward substitution with R^T gives that
-// column of B, backward substitution with R gives the column of C, the
-// column held in registers (k <= KMAX) and R read from LDS (every thread
-// reads the same entry at once).
+// Cholesky of G1 = X1^T X1 by wavefront 0 (rank check on the pivots): lane c
+// holds column c in registers, and at step j the scaled row j of R goes
+// through LDS to every lane.  Then one thread per column of P: forward
+// substitution with R^T gives that column of B, backward substitution with
+// R gives the column of C, the column held in registers (k <= KMAX) and R
+// read from LDS (every thread reads the same entry at once).
 // Several workgroups per instance when n2 > 256 (wg of nwg): each one
 // factors G1 (the same arithmetic in every workgroup) and solves its own
 // 256-column slice of P; workgroup 0 alone writes R and the sweep state, and
 // every workgroup writes its share of ||B||^2 to coef_part[wg] (summed in
 // order by k_post).
+#define COEF_LD 65  // odd leading dimension: a lane per column hits distinct banks
 template <int KMAX>
 __device__ __forceinline__ void coef_body(const SmallArgs &a, int wg, int nwg) {
   SmallState *st = a.st;
   if (st->done) return;
-  __shared__ double sR[64 * 64];
+  constexpr int LD = COEF_LD;
+  __shared__ double sG[64 * LD];   // G1, then R (upper), column-major, ld LD
+  __shared__ double sR[64 * 64];   // R for the substitutions (ld 64: aligned pairs)
+  __shared__ double sRow[2][64];   // row j of R during the factorisation
   __shared__ double red[4];
   __shared__ int fail;
   const int k = a.k, n2 = a.n2, t = threadIdx.x;
@@ -84,43 +97,46 @@ __device__ __forceinline__ void coef_body(const SmallArgs &a, int wg, int nwg) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int e = t + 256 * u, r = e % 64, c = e / 64;
-      sR[e] = (r < k && c < k) ? gv[u] : 0.0;
+      sG[r + c * LD] = (r < k && c < k) ? gv[u] : 0.0;
     }
   }
   __syncthreads();
   double gmax = 0, tr = 0;
   for (int i = 0; i < k; ++i) {
-    gmax = fmax(gmax, sR[i + i * 64]);
-    tr += sR[i + i * 64];
+    gmax = fmax(gmax, sG[i + i * LD]);
+    tr += sG[i + i * LD];
   }
   // A pivot below k * eps * max diag(X1^T X1) means X1 is numerically
   // rank deficient (cond(X1) > 1 / sqrt(k eps)).
   const double thr = (double)k * 2.220446049250313e-16 * gmax;
   if (t < 64) {
-    for (int j = 0; j < k; ++j) {
-      if (t == 0) {
-        double p = sR[j + j * 64];
+    // Entries below the diagonal are updated too (they stay the symmetric
+    // Schur complement) and are discarded at the end; columns past k hold
+    // zeros, so their updates change nothing.
+    double g[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) g[i] = sG[i + t * LD];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      if (j < k) {
+        double p = readlane_d(g[j], j);
         if (!(p > thr)) {
-          fail = 1;
+          if (t == 0) fail = 1;
           p = gmax > 0 ? gmax : 1.0;
         }
-        sR[j + j * 64] = sqrt(p);
+        const double rjj = sqrt(p);
+        g[j] = (t == j) ? rjj : g[j] / rjj;
+        sRow[j & 1][t] = g[j];
+        wave_sync();
+#pragma unroll
+        for (int aa = j + 1; aa < KMAX; ++aa) g[aa] = fma(-sRow[j & 1][aa], g[j], g[aa]);
       }
-      wave_sync();
-      const double rjj = sR[j + j * 64];
-      for (int c = j + 1 + t; c < k; c += 64) sR[j + c * 64] /= rjj;
-      wave_sync();
-      const int rem = k - j - 1;
-      for (int e = t; e < rem * rem; e += 64) {
-        const int aa = j + 1 + e % rem, cc = j + 1 + e / rem;
-        if (aa <= cc) sR[aa + cc * 64] -= sR[j + aa * 64] * sR[j + cc * 64];
-      }
-      wave_sync();
     }
-    // the strict lower triangle is never read below; keep it zero
-    for (int e = t; e < k * k; e += 64)
-      if ((e % k) > (e / k)) sR[(e % k) + (e / k) * 64] = 0.0;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) sG[i + t * LD] = (i <= t) ? g[i] : 0.0;
   }
+  __syncthreads();
+  for (int e = t; e < 64 * 64; e += 256) sR[e] = sG[(e & 63) + (e >> 6) * LD];
   __syncthreads();
   if (fail) {
     if (t == 0 && wg == 0) {

@@ -98,8 +98,8 @@ __global__ __launch_bounds__(256) void k_init_x1(int64_t m, int64_t k, int mode,
 // Tall-skinny transposed product:  part[s] = X[rows of split s]^T Y[rows of s]
 // (k1 x k2, double), on the FP64 matrix cores.  A workgroup owns a 32 x 32
 // output tile; its four wavefronts own 16 x 16 quadrants and multiply with
-// v_mfma_f64_16x16x4f64 (products of the float or BF16 inputs are exact in
-// double, sums in double).  Row chunks of 32 are staged through LDS as double
+// v_mfma_f64_16x16x4f64 (products of float inputs are exact in double, sums
+// in double).  Row chunks of 32 are staged through LDS as double
 // (column-major, padded), the next chunk being loaded into registers while
 // the current one multiplies.  `sym` computes only the tiles on or above the
 // diagonal (X == Y).  Fragment layouts (lane l): A[l % 16][l / 16],
@@ -1052,12 +1052,19 @@ __global__ __launch_bounds__(64) void k_x2(int64_t m, int k, int n2, int l,
 //
 // k_chgprep (one workgroup): O by Newton-Schulz iteration from V_q^T V_p,
 // made exactly orthogonal by two-pass Gram-Schmidt (a column that vanishes
-// is replaced by the unit vector farthest from the span of the others), and
-// H column-major into Hb (n2 x K, K = 2l + 2k).  Kg = H^T H (K x K) is then
-// formed by the tall-skinny product kernel.
+// is replaced by the unit vector farthest from the span of the others), the
+// columns [V_p dV] of H column-major into Hb (n2 x 2l, what the row pass
+// reads) and Kg = H^T H (K x K, K = 2l + 2k, symmetric).  Rows of V_p, V_q,
+// Z_p and Z_q are read in chunks, contiguously, into LDS; both V_q^T V_p and
+// H^T H are summed over the chunks on v_mfma_f64_16x16x4f64 (16 x 16 output
+// tiles; for H^T H the tiles on or above the diagonal, a fixed set per
+// wavefront, mirrored when written).
 #define QR_T 512
 #define CHG_NW 8    // wavefronts per workgroup of the change row pass
 #define CHG_GLD 65  // leading dimension of g in LDS (padded against bank conflicts)
+#define CHP_LDS 16384  // doubles of LDS for the staged rows
+#define CHP_MAXT 10    // H^T H tiles per wavefront (78 tiles at K = 192)
+typedef double chp_d4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void chgprep_body(int n2, int k, int l,
                                              const double *__restrict__ Vp,
                                              const double *__restrict__ Vq,
@@ -1068,51 +1075,121 @@ __device__ __forceinline__ void chgprep_body(int n2, int k, int l,
   if (st->done || !st->have_prev) return;
   __shared__ double X[WLRA_BMAX * WLRA_BMAX];
   __shared__ double E[WLRA_BMAX * WLRA_BMAX];
-  __shared__ double red[QR_T / 64];
-  __shared__ double nrm[2];
+  __shared__ __align__(16) double sH[CHP_LDS];
   const int K = 2 * l + 2 * k, t = threadIdx.x;
-  const int lane = t & 63;
+  const int lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int B_ = WLRA_BMAX;
   if (l > 0) {
-    // X = V_q^T V_p: a wavefront per entry, lanes over the rows
-    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    for (int e = wv; e < l * l; e += QR_T / 64) {
-      const int a = e % l, b = e / l;
-      double sacc = 0.0;
-      for (int i = lane; i < n2; i += 64)
-        sacc = fma(Vq[(int64_t)i * l + a], Vp[(int64_t)i * l + b], sacc);
-      sacc = wave_sum(sacc);
-      if (lane == 0) X[a + b * B_] = sacc;
+    // X = V_q^T V_p: chunks of rows of V_q and V_p side by side in LDS;
+    // wavefront w multiplies every eighth k-step of 4 rows into its own
+    // partial tiles, which are summed in wavefront order at the end
+    const int TL = (l + 15) / 16;
+    const int ra = max(4, min((n2 + 3) & ~3, (CHP_LDS / (2 * l)) & ~3));
+    double *sQ = sH, *sP = sH + ra * l;
+    chp_d4 xa[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) xa[u][v] = chp_d4{0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < n2; i0 += ra) {
+      const int nr = min(ra, n2 - i0), ne = nr * l;
+      __syncthreads();
+      for (int e0 = t; e0 < ne; e0 += 4 * QR_T) {
+        double q4[4], p4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u * QR_T, ne - 1);
+          q4[u] = Vq[(int64_t)i0 * l + e];
+          p4[u] = Vp[(int64_t)i0 * l + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (e0 + u * QR_T < ne) {
+            sQ[e0 + u * QR_T] = q4[u];
+            sP[e0 + u * QR_T] = p4[u];
+          }
+      }
+      __syncthreads();
+      for (int ks = w; 4 * ks < nr; ks += QR_T / 64) {
+        const int i = 4 * ks + lk;
+        const bool ri = i < nr;
+        const int ic = ri ? i : nr - 1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (u < TL) {
+            const int aa = 16 * u + li;
+            const double av = (ri && aa < l) ? sQ[ic * l + min(aa, l - 1)] : 0.0;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+              if (v < TL) {
+                const int bb = 16 * v + li;
+                const double bv = (ri && bb < l) ? sP[ic * l + min(bb, l - 1)] : 0.0;
+                xa[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, xa[u][v], 0, 0, 0);
+              }
+            }
+          }
+        }
+      }
     }
     __syncthreads();
-    // Newton-Schulz: X <- X (3 I - X^T X) / 2 until X^T X = I to rounding
-    for (int it = 0; it < 60; ++it) {
-      double dev = 0.0;
-      for (int e = t; e < l * l; e += QR_T) {
-        const int a = e % l, b = e / l;
-        double sacc = 0.0;
-        for (int q = 0; q < l; ++q) sacc = fma(X[q + a * B_], X[q + b * B_], sacc);
-        E[a + b * B_] = sacc;
-        const double d = sacc - (a == b ? 1.0 : 0.0);
-        dev = fma(d, d, dev);
-      }
-      dev = block_sum(dev, red);  // includes the barrier before E is read
-      if (!(dev > 1e-28)) break;
-      double xn[2];
-      int cnt = 0;
-      for (int e = t; e < l * l; e += QR_T) {
-        const int a = e % l, b = e / l;
-        double sacc = 0.0;
-        for (int q = 0; q < l; ++q) sacc = fma(X[a + q * B_], (q == b ? 3.0 : 0.0) - E[q + b * B_], sacc);
-        xn[cnt++] = 0.5 * sacc;
-      }
-      __syncthreads();
-      cnt = 0;
-      for (int e = t; e < l * l; e += QR_T) X[(e % l) + (e / l) * B_] = xn[cnt++];
-      __syncthreads();
+    // partial tile (u, v) of wavefront w at sH + ((w * 2 + u) * 2 + v) * 256,
+    // entry (row, column) at row * 16 + column
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+        if (u < TL && v < TL)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            sH[((w * 2 + u) * 2 + v) * 256 + (lk + 4 * q) * 16 + li] = xa[u][v][q];
+    __syncthreads();
+    for (int e = t; e < l * l; e += QR_T) {
+      const int aa = e % l, bb = e / l, u = aa >> 4, v = bb >> 4;
+      double sacc = 0.0;
+      for (int ww = 0; ww < QR_T / 64; ++ww)
+        sacc += sH[((ww * 2 + u) * 2 + v) * 256 + (aa & 15) * 16 + (bb & 15)];
+      X[aa + bb * B_] = sacc;
     }
-    // two-pass Gram-Schmidt on the columns of X (wavefront 0)
+    __syncthreads();
+    // Newton-Schulz on wavefront 0: X <- X (3 I - X^T X) / 2 until X^T X = I
+    // to rounding (up to 16 entries of X per lane, l <= 32)
     if (t < 64) {
+      for (int it = 0; it < 60; ++it) {
+        double dev = 0.0;
+        for (int e = lane; e < l * l; e += 64) {
+          const int aa = e % l, bb = e / l;
+          double sacc = 0.0;
+          for (int q = 0; q < l; ++q) sacc = fma(X[q + aa * B_], X[q + bb * B_], sacc);
+          E[aa + bb * B_] = sacc;
+          const double d = sacc - (aa == bb ? 1.0 : 0.0);
+          dev = fma(d, d, dev);
+        }
+        dev = wave_sum(dev);
+        if (!(dev > 1e-28)) break;
+        wave_sync();
+        double xn[WLRA_BMAX * WLRA_BMAX / 64];
+#pragma unroll
+        for (int u = 0; u < WLRA_BMAX * WLRA_BMAX / 64; ++u) {
+          const int e = lane + 64 * u;
+          xn[u] = 0.0;
+          if (e < l * l) {
+            const int aa = e % l, bb = e / l;
+            double sacc = 0.0;
+            for (int q = 0; q < l; ++q)
+              sacc = fma(X[aa + q * B_], (q == bb ? 3.0 : 0.0) - E[q + bb * B_], sacc);
+            xn[u] = 0.5 * sacc;
+          }
+        }
+        wave_sync();
+#pragma unroll
+        for (int u = 0; u < WLRA_BMAX * WLRA_BMAX / 64; ++u) {
+          const int e = lane + 64 * u;
+          if (e < l * l) X[(e % l) + (e / l) * B_] = xn[u];
+        }
+        wave_sync();
+      }
+      // two-pass Gram-Schmidt on the columns of X
       for (int c = 0; c < l; ++c) {
         for (int pass = 0; pass < 2; ++pass) {
           for (int q = 0; q < c; ++q) {
@@ -1155,27 +1232,113 @@ __device__ __forceinline__ void chgprep_body(int n2, int k, int l,
     }
     __syncthreads();
   }
-  // H = [V_p, V_q O - V_p, Z_p, Z_q - Z_p], column-major n2 x K
-  for (int64_t e = t; e < (int64_t)n2 * K; e += QR_T) {
-    const int i = (int)(e % n2), c = (int)(e / n2);
-    double v;
-    if (c < l) {
-      v = Vp[(int64_t)i * l + c];
-    } else if (c < 2 * l) {
-      const int b = c - l;
-      double sacc = 0.0;
-      for (int a = 0; a < l; ++a) sacc = fma(Vq[(int64_t)i * l + a], X[a + b * B_], sacc);
-      v = sacc - Vp[(int64_t)i * l + b];
-    } else if (c < 2 * l + k) {
-      v = Zp[(int64_t)i * k + (c - 2 * l)];
-    } else {
-      const int b = c - 2 * l - k;
-      v = Zq[(int64_t)i * k + b] - Zp[(int64_t)i * k + b];
+  // H = [V_p, V_q O - V_p, Z_p, Z_q - Z_p] by chunks of rows: row i of the
+  // chunk at sH + i * hld (columns K .. K16 - 1 and rows past the chunk zero),
+  // the chunk's V_q rows after it
+  const int K16 = (K + 15) & ~15, T16 = K16 / 16, ntile = T16 * (T16 + 1) / 2;
+  const int hld = K16 + 16;  // 4 consecutive rows fall in distinct bank halves
+  const int rb = max(4, min((n2 + 3) & ~3, (CHP_LDS / (hld + l)) & ~3));
+  double *sVq = sH + rb * hld;
+  chp_d4 ka[CHP_MAXT];
+  int tr_[CHP_MAXT], tc_[CHP_MAXT];
+#pragma unroll
+  for (int u = 0; u < CHP_MAXT; ++u) {
+    ka[u] = chp_d4{0.0, 0.0, 0.0, 0.0};
+    // upper tile w + 8 u in row order: (0,0) (0,1) .. (0,T16-1) (1,1) ..
+    int tt = w + (QR_T / 64) * u, r = 0;
+    while (r < T16 && tt >= T16 - r) {
+      tt -= T16 - r;
+      ++r;
     }
-    Hb[e] = v;
+    tr_[u] = r;
+    tc_[u] = r + tt;
   }
-  (void)nrm;
-  (void)Kg;
+  for (int i0 = 0; i0 < n2; i0 += rb) {
+    const int nr = min(rb, n2 - i0), nr4 = (nr + 3) & ~3;
+    __syncthreads();
+    {
+      const int nv = nr * l, nz = nr * k;
+      // V_p into columns 0 .. l-1, V_q to its own block
+      for (int e0 = t; e0 < nv; e0 += 4 * QR_T) {
+        double p4[4], q4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u * QR_T, nv - 1);
+          p4[u] = Vp[(int64_t)i0 * l + e];
+          q4[u] = Vq[(int64_t)i0 * l + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * QR_T;
+          if (e < nv) {
+            sH[(e / l) * hld + (e % l)] = p4[u];
+            sVq[e] = q4[u];
+          }
+        }
+      }
+      // Z_p into columns 2l .. 2l+k-1, Z_q - Z_p into 2l+k .. K-1
+      for (int e0 = t; e0 < nz; e0 += 4 * QR_T) {
+        double p4[4], q4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u * QR_T, nz - 1);
+          p4[u] = Zp[(int64_t)i0 * k + e];
+          q4[u] = Zq[(int64_t)i0 * k + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * QR_T;
+          if (e < nz) {
+            const int i = e / k, c = e % k;
+            sH[i * hld + 2 * l + c] = p4[u];
+            sH[i * hld + 2 * l + k + c] = q4[u] - p4[u];
+          }
+        }
+      }
+      // zero padding: columns K .. K16-1 of the chunk's rows, rows nr .. nr4-1
+      const int padc = K16 - K;
+      for (int e = t; e < nr * padc; e += QR_T) sH[(e / padc) * hld + K + (e % padc)] = 0.0;
+      for (int e = t; e < (nr4 - nr) * K16; e += QR_T) sH[(nr + e / K16) * hld + (e % K16)] = 0.0;
+    }
+    __syncthreads();
+    // dV = V_q O - V_p into columns l .. 2l-1
+    for (int e = t; e < nr * l; e += QR_T) {
+      const int i = e / l, bb = e % l;
+      double sacc = 0.0;
+      for (int aa = 0; aa < l; ++aa) sacc = fma(sVq[i * l + aa], X[aa + bb * B_], sacc);
+      sH[i * hld + l + bb] = sacc - sH[i * hld + bb];
+    }
+    __syncthreads();
+    // columns [V_p dV] for the row pass
+    for (int e = t; e < nr * 2 * l; e += QR_T) {
+      const int c = e / nr, i = e - c * nr;
+      Hb[(int64_t)(i0 + i) + (int64_t)c * n2] = sH[i * hld + c];
+    }
+    // H^T H, this wavefront's tiles
+    for (int ks = 0; 4 * ks < nr4; ++ks) {
+      const double *row = sH + (4 * ks + lk) * hld + li;
+#pragma unroll
+      for (int u = 0; u < CHP_MAXT; ++u)
+        if (w + (QR_T / 64) * u < ntile)
+          ka[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * tr_[u]], row[16 * tc_[u]], ka[u],
+                                                      0, 0, 0);
+    }
+  }
+  // Kg, both triangles from the tiles on or above the diagonal (entries
+  // below the diagonal of a diagonal tile are taken from above it)
+#pragma unroll
+  for (int u = 0; u < CHP_MAXT; ++u) {
+    if (w + (QR_T / 64) * u < ntile) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * tr_[u] + lk + 4 * q, c = 16 * tc_[u] + li;
+        if (r < K && c < K && (tr_[u] < tc_[u] || r <= c)) {
+          Kg[r + (int64_t)c * K] = ka[u][q];
+          Kg[c + (int64_t)r * K] = ka[u][q];
+        }
+      }
+    }
+  }
 }
 __global__ __launch_bounds__(QR_T) void k_chgprep(int n2, int k, int l,
                                                   const double *__restrict__ Vp,
@@ -1199,9 +1362,9 @@ __global__ __launch_bounds__(QR_T) void k_chgprep_b(const ChgArgs *__restrict__ 
 // rows in 16 x 16 tiles on v_mfma_f64_16x16x4f64 (tiles on or above the
 // diagonal, split between the wavefronts), each tile contracted with the
 // matching block of Kg.  One partial per workgroup.
-template <typename T, int LMAX, typename TA2>
+template <typename T, int LMAX>
 __global__ __launch_bounds__(64 * CHG_NW) void k_change_q(
-    int64_t m, int k, int n2, int l, const TA2 *__restrict__ A2, int64_t lda,
+    int64_t m, int k, int n2, int l, const T *__restrict__ A2, int64_t lda,
     const T *__restrict__ X1p, const T *__restrict__ X1q, const double *__restrict__ Hb,
     const double *__restrict__ Kg, int stage_rows, double *__restrict__ part,
     const SmallState *__restrict__ st) {
@@ -1237,15 +1400,15 @@ __global__ __launch_bounds__(64 * CHG_NW) void k_change_q(
       }
       __syncthreads();
       const int j0 = c0 + w * len / CHG_NW, j1 = c0 + (w + 1) * len / CHG_NW;
-      // sixteen clamped column reads in flight, converted at the use
+      // sixteen clamped column reads in flight, widened at the use
       for (int j = j0; j < j1; j += 16) {
-        TA2 raw[16];
+        T raw[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) raw[u] = A2[ir + (int64_t)min(j + u, j1 - 1) * lda];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           if (j + u < j1) {
-            const double v = (double)to_f(raw[u]);
+            const double v = (double)raw[u];
             const double *rr = sR + (j + u - c0) * rw;
 #pragma unroll
             for (int q = 0; q < LMAX; ++q)
@@ -1573,30 +1736,18 @@ void launch_x2(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64
   else launch_x2_k<T, 64>(s, m, k, n2, l, A, lda, X1, Zt, Vr, X2, ldx2, w2, mask, ldm, tau);
 }
 
-// The Gram Kg = H^T H of the change pass alone (after a batched k_chgprep).
-void launch_chgprep_gram(hipStream_t s, int n2, int k, int l, double *Hb, double *Kg, int splits,
-                         int64_t rows_per_split, double *part, const SmallState *st) {
-  const int K = 2 * l + 2 * k;
-  launch_tsgemm<double, double>(s, n2, Hb, n2, K, Hb, n2, K, 1, splits, rows_per_split, part, Kg,
-                                &st->done);
-}
-
 void launch_chgprep_b(hipStream_t s, int count, const ChgArgs *av) {
   if (count > 0) hipLaunchKernelGGL(k_chgprep_b, dim3(count), dim3(QR_T), 0, s, av);
 }
 
 void launch_chgprep(hipStream_t s, int n2, int k, int l, const double *Vp, const double *Vq,
-                    const double *Zp, const double *Zq, double *Hb, double *Kg, int splits,
-                    int64_t rows_per_split, double *part, const SmallState *st) {
+                    const double *Zp, const double *Zq, double *Hb, double *Kg,
+                    const SmallState *st) {
   hipLaunchKernelGGL(k_chgprep, dim3(1), dim3(QR_T), 0, s, n2, k, l, Vp, Vq, Zp, Zq, Hb, Kg, st);
-  const int K = 2 * l + 2 * k;
-  // Kg = H^T H; skipped with the rest of the step once the solve is done
-  launch_tsgemm<double, double>(s, n2, Hb, n2, K, Hb, n2, K, 1, splits, rows_per_split, part, Kg,
-                                &st->done);
 }
 
-template <typename T, int LMAX, typename TA2>
-static void launch_change_qr_k(hipStream_t s, int64_t m, int k, int n2, int l, const TA2 *A2,
+template <typename T, int LMAX>
+static void launch_change_qr_k(hipStream_t s, int64_t m, int k, int n2, int l, const T *A2,
                                int64_t lda2, const T *X1p, const T *X1q, const double *Hb,
                                const double *Kg, double *part, const SmallState *st) {
   const unsigned grid = (unsigned)((m + 63) / 64);
@@ -1606,31 +1757,21 @@ static void launch_change_qr_k(hipStream_t s, int64_t m, int k, int n2, int l, c
   const size_t stage = (size_t)std::max(rows * 2 * l, ((K + 15) / 16) * 16 * CHG_GLD);
   const size_t shm = (stage + (size_t)2 * LMAX * 64) * sizeof(double);
   if (shm > 65536)
-    (void)hipFuncSetAttribute((const void *)k_change_q<T, LMAX, TA2>,
+    (void)hipFuncSetAttribute((const void *)k_change_q<T, LMAX>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_change_q<T, LMAX, TA2>), dim3(grid), dim3(64 * CHG_NW), shm, s, m, k,
+  hipLaunchKernelGGL((k_change_q<T, LMAX>), dim3(grid), dim3(64 * CHG_NW), shm, s, m, k,
                      n2, l, A2, lda2, X1p, X1q, Hb, Kg, rows, part, st);
 }
 
 template <typename T>
 void launch_change_qr(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-                      const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q,
-                      const double *Hb, const double *Kg, double *part, const SmallState *st) {
-  if constexpr (std::is_same<T, float>::value) {
-    if (A2b != nullptr) {
-      if (l <= 8)
-        launch_change_qr_k<T, 8, bf16s>(s, m, k, n2, l, A2b, ldb, X1p, X1q, Hb, Kg, part, st);
-      else
-        launch_change_qr_k<T, WLRA_BMAX, bf16s>(s, m, k, n2, l, A2b, ldb, X1p, X1q, Hb, Kg, part,
-                                                st);
-      return;
-    }
-  }
+                      const T *X1p, const T *X1q, const double *Hb, const double *Kg,
+                      double *part, const SmallState *st) {
   const T *A2 = A + (int64_t)k * lda;
   if (l <= 8)
-    launch_change_qr_k<T, 8, T>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
+    launch_change_qr_k<T, 8>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
   else
-    launch_change_qr_k<T, WLRA_BMAX, T>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
+    launch_change_qr_k<T, WLRA_BMAX>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
 }
 
 template <typename T>
@@ -1657,14 +1798,7 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
                              T);                                                                  \
   template void launch_copy_out<T>(hipStream_t, int64_t, int64_t, const T *, T *, int64_t);     \
   template void launch_change_qr<T>(hipStream_t, int64_t, int, int, int, const T *, int64_t,      \
-                                    const bf16s *, int64_t, const T *, const T *, const double *, \
-                                    const double *, double *, const SmallState *);
+                                    const T *, const T *, const double *, const double *,         \
+                                    double *, const SmallState *);
 INST(float)
 INST(double)
-// mixed precision: X1^T A2 and A2^T A2 with A2 in BF16
-template void launch_tsgemm<float, bf16s>(hipStream_t, int64_t, const float *, int64_t, int,
-                                          const bf16s *, int64_t, int, int, int, int64_t,
-                                          double *, double *, const int *);
-template void launch_tsgemm<bf16s, bf16s>(hipStream_t, int64_t, const bf16s *, int64_t, int,
-                                          const bf16s *, int64_t, int, int, int, int64_t,
-                                          double *, double *, const int *);

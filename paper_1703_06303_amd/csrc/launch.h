@@ -144,8 +144,6 @@ struct PanelArgs {
   const SmallState *st;
 };
 void launch_panel_bf16_b(hipStream_t s, int count, const PanelArgs *av);
-void launch_chgprep_gram(hipStream_t s, int n2, int k, int l, double *Hb, double *Kg, int splits,
-                         int64_t rows_per_split, double *part, const SmallState *st);
 
 
 void launch_coef(hipStream_t s, const SmallArgs &a);
@@ -182,11 +180,12 @@ void launch_ldecode(hipStream_t s, int n, int k, int r, const float *yv, T *Gt, 
 template <typename T>
 void launch_zero(hipStream_t s, int64_t count, T *out);
 
-// Error_p through a Gram of aligned factor differences (k_stream.hip).
+// Error_p through a Gram of aligned factor differences (k_stream.hip): the
+// aligned basis's columns [V_p dV] into Hb and its Gram Kg in one workgroup.
 void launch_chgprep(hipStream_t s, int n2, int k, int l, const double *Vp, const double *Vq,
-                    const double *Zp, const double *Zq, double *Hb, double *Kg, int splits,
-                    int64_t rows_per_split, double *part, const SmallState *st);
+                    const double *Zp, const double *Zq, double *Hb, double *Kg,
+                    const SmallState *st);
 template <typename T>
 void launch_change_qr(hipStream_t s, int64_t m, int k, int n2, int l, const T *A, int64_t lda,
-                      const bf16s *A2b, int64_t ldb, const T *X1p, const T *X1q,
-                      const double *Hb, const double *Kg, double *part, const SmallState *st);
+                      const T *X1p, const T *X1q, const double *Hb, const double *Kg,
+                      double *part, const SmallState *st);

@@ -208,8 +208,6 @@ struct Sizes {
   bool colw;  // column weights of the unweighted block: A staged scaled
   int splits_l1;  // Om^T A of the learned start's sketch
   int64_t rows_l1;
-  int splits_kg;  // H^T H of the change pass (n2 rows)
-  int64_t rows_kg;
   int splits_g1;  // X1^T X1
   int64_t rows_g1;
 };
@@ -271,11 +269,6 @@ Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mi
     z.splits_g1 = choose_splits(m, tk1 * tk1, &z.rows_g1);
   }
   z.splits_l1 = choose_splits(m, (int)((n + 31) / 32), &z.rows_l1);
-  {
-    const int K = (int)(2 * z.l + 2 * k), tk = (K + 31) / 32;
-    z.splits_kg = choose_splits(std::max<int64_t>(z.n2, 1), std::max(1, tk * (tk + 1) / 2),
-                                &z.rows_kg);
-  }
   z.nwg_upd = (int)((m + 63) / 64);
   z.nwg_f1 = 256;
   z.elt = elt;
@@ -292,11 +285,10 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
   const size_t d = sizeof(double);
   const int64_t m = z.m, k = z.k, n2 = z.n2, l = z.l;
   const int64_t kk = std::max<int64_t>(k, 1), ll = std::max<int64_t>(l, 1);
-  const int64_t Kc = 2 * l + 2 * k;
   const size_t part = std::max<size_t>(
       std::max<size_t>((size_t)z.splits_ga_max * n2 * n2,
                        (size_t)z.splits_p_max * std::max<int64_t>(kk * n2, kk * kk)),
-      std::max<size_t>((size_t)z.splits_kg * Kc * Kc, (size_t)z.splits_g1 * kk * kk));
+      (size_t)z.splits_g1 * kk * kk);
   struct Item { void **dst; size_t bytes; };
   Ptrs p{};
   Item items[] = {
@@ -756,24 +748,19 @@ struct Run {
     return ChgArgs{(int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1], P.Zd[p & 1],
                    P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, P.st};
   }
-  // Error_p: the aligned basis and its Gram (one workgroup + product), then
-  // the row pass.  batched_prep: the one-workgroup part ran in a batch launch.
+  // Error_p: the aligned basis and its Gram (one workgroup), then the row
+  // pass.  batched_prep: the one-workgroup part ran in a batch launch.
   void change(bool batched_prep) {
     if (!batched_prep)
       PROFWS(h, s, KK_CHGQR, 0, 0,
              launch_chgprep(s, (int)n2, (int)k, (int)l, P.Vd[p & 1], P.Vd[(p & 1) ^ 1],
-                            P.Zd[p & 1], P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, z.splits_kg, z.rows_kg,
-                            P.part, P.st));
-    else
-      PROFWS(h, s, KK_CHGQR, 0, 0,
-             launch_chgprep_gram(s, (int)n2, (int)k, (int)l, P.Hb, P.Rh, z.splits_kg, z.rows_kg,
-                                 P.part, P.st));
+                            P.Zd[p & 1], P.Zd[(p & 1) ^ 1], P.Hb, P.Rh, P.st));
     PROFWS(h, s, KK_CHANGE, md * (n2d * es + 2.0 * kd * es),
            md * (4.0 * (double)l * n2d +
                  (2.0 * (double)l + 2.0 * kd) * (2.0 * (double)l + 2.0 * kd)),
-           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, lda, nullptr,
-                               m, X1c, static_cast<const T *>(P.X1[cur ^ 1]), P.Hb, P.Rh,
-                               P.chg_part, P.st));
+           launch_change_qr<T>(s, m, (int)k, (int)n2, (int)l, A, lda, X1c,
+                               static_cast<const T *>(P.X1[cur ^ 1]), P.Hb, P.Rh, P.chg_part,
+                               P.st));
   }
 
   // Host side of sweep p after its state is in *sh: the trace, and the end
