@@ -6,6 +6,37 @@
 
 #include "common.h"
 
+// 1 / x and 1 / sqrt(x) to a few ulps: the hardware estimates (about 23
+// correct bits) refined by two Newton steps each.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// Rotation (c, s) of the symmetric 2 x 2 Schur decomposition that zeroes hpq
+// in [hpp hpq; hpq hqq]: tau = (hqq - hpp) / (2 hpq), t the root of
+// t^2 + 2 tau t - 1 = 0 of smaller magnitude, sign(tau) / (|tau| +
+// sqrt(1 + tau^2)), c = 1 / sqrt(1 + t^2), s = t c.  Reciprocals and square
+// roots go through rcp_nr / rsq_nr; for |tau| > 1e150 (tau^2 would
+// overflow) t = sign(tau) / (2 |tau|), and t = 0 past 1e300.
+__device__ __forceinline__ void jacobi_cs(double hpp, double hqq, double hpq, double &c,
+                                          double &sn) {
+  const double tau = (hqq - hpp) * rcp_nr(2.0 * hpq);
+  const double at = fabs(tau);
+  const double a = fma(tau, tau, 1.0);
+  const double den = at > 1e150 ? 2.0 * at : at + a * rsq_nr(a);
+  const double r = at < 1e300 ? rcp_nr(den) : 0.0;
+  const double tt = tau >= 0 ? r : -r;
+  c = rsq_nr(fma(tt, tt, 1.0));
+  sn = tt * c;
+}
+
 // Upper Cholesky in place of G (nb x nb, ld WLRA_BMAX) by wavefront 0, with an
 // optional diagonal shift.  Returns nonzero on a non-positive pivot.
 __device__ __forceinline__ int small_chol_reg(double *G, int nb, double shift, int *ints);
@@ -112,12 +143,7 @@ __device__ __forceinline__ void small_jacobi_reg(double *H, double *S, double *t
         const double hpp = __shfl(h, p + p * nb, 64), hqq = __shfl(h, q + q * nb, 64);
         const double hpq = __shfl(h, p + q * nb, 64);
         double c = 1.0, sn = 0.0;
-        if (paired && fabs(hpq) > 1e-300) {
-          const double tau = (hqq - hpp) / (2.0 * hpq);
-          const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          sn = tt * c;
-        }
+        if (paired && fabs(hpq) > 1e-300) jacobi_cs(hpp, hqq, hpq, c, sn);
         const double ax = paired ? c : 1.0, bx = paired ? ((x == p) ? -sn : sn) : 0.0;
         // lane y holds index y as its x (y < nb), so its coefficients are y's
         const double ay = __shfl(ax, y, 64), by = __shfl(bx, y, 64);
@@ -210,12 +236,7 @@ __device__ __forceinline__ void small_jacobi_wave(double *H, double *S, double *
           if (q < nb) {
             double c = 1.0, sn = 0.0;
             const double apq = Hc[p + q * L];
-            if (fabs(apq) > 1e-300) {
-              const double tau = (Hc[q + q * L] - Hc[p + p * L]) / (2.0 * apq);
-              const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-              c = 1.0 / sqrt(1.0 + tt * tt);
-              sn = tt * c;
-            }
+            if (fabs(apq) > 1e-300) jacobi_cs(Hc[p + p * L], Hc[q + q * L], apq, c, sn);
             al[p] = c;
             be[p] = -sn;
             pt[p] = q;
