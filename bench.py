@@ -13,7 +13,8 @@ Schedules timed side by side (`variants` in the output):
   plain_tol<t>   FP32 from the library's random start, the Section 4.1 rule
                  with tol t for t in 1e-7 (the paper's threshold, also
                  reported as "plain"), 1e-6, 1e-5, 1e-4, 1e-3
-  mixed          A2 staged in BF16, sweeps to max(tol, 1e-5), then one exact
+  mixed          A2 staged in BF16 for the X1 update's product with A2 (every
+                 other step exact), sweeps to max(tol, 1e-5), then one exact
                  sweep; tol 1e-7 (no suffix), 1e-4 and 1e-3 (mixed_tol<t>)
   a1+mixed       the same from X1_0 = A1
   learned+mixed  the same from the learned warm start: the network is trained
@@ -45,7 +46,9 @@ Other workloads (`--workload`): config1, config3, config4 alone, frames
 
 Prints one JSON line.  `roofline` is for the kernel with the largest device
 time, from HIP events bracketing each launch on the library's stream in a
-profiled repeat of the timed steps.  `cpu_baseline` is the FP64 oracle
+profiled repeat of the timed steps (for the eigen step also its share of the
+FP64 rate of the CUs it runs on: one, or one per 16 rows of M for the
+cooperative kernel).  `cpu_baseline` is the FP64 oracle
 (NumPy/LAPACK) on the host cores, on a bounded sample.
 """
 import argparse
@@ -228,10 +231,13 @@ def roofline_of(name, launches, ms, nbytes, flops, res_list, n2):
         fl = 2.0 * n2 * n2 * mv / launches
         roof = {"bound": "alu", "achieved": fl / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
-        # the step runs in one workgroup: its share of the chip's FP64 rate
-        # (one CU of 256) for context
-        roof["peak_one_cu"] = FP64_PEAK_TFLOPS / 256
-        roof["frac_one_cu"] = roof["achieved"] / roof["peak_one_cu"]
+        # the step runs in one workgroup for n - k < 256, else in one
+        # workgroup per 16 rows of M (cooperative): the share of the chip's
+        # FP64 rate that those CUs hold (of 256), for context
+        cus = 1 if n2 < 256 else (n2 + 15) // 16
+        roof["cus_used"] = cus
+        roof["peak_cus_used"] = FP64_PEAK_TFLOPS * cus / 256
+        roof["frac_cus_used"] = roof["achieved"] / roof["peak_cus_used"]
     elif nbytes > 0:
         roof = {"bound": "hbm", "achieved": nbytes / launches / avg_s / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
