@@ -42,6 +42,19 @@ __device__ __forceinline__ bf16s bf16_rne(float f) {
   return bf16s{(uint16_t)(u >> 16)};
 }
 
+// 1 / x and 1 / sqrt(x) to a few ulps: the hardware estimates (about 23
+// correct bits) refined by two Newton steps each.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
 // Per-solve device state shared by the small-step kernels (all double).
 // Index p below is the sweep of Algorithm 1: X_p = [X1_p, X1_p C_p + D_p].
 struct SmallState {

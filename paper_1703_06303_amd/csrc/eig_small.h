@@ -6,19 +6,6 @@
 
 #include "common.h"
 
-// 1 / x and 1 / sqrt(x) to a few ulps: the hardware estimates (about 23
-// correct bits) refined by two Newton steps each.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
-}
-
 // Rotation (c, s) of the symmetric 2 x 2 Schur decomposition that zeroes hpq
 // in [hpp hpq; hpq hqq]: tau = (hqq - hpp) / (2 hpq), t the root of
 // t^2 + 2 tau t - 1 = 0 of smaller magnitude, sign(tau) / (|tau| +

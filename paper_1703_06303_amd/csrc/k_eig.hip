@@ -389,7 +389,7 @@ __device__ __forceinline__ int cqr_small(EigLDS &s, int nb, double shift_coef) {
     const int x = in ? t % nb : 0, y = in ? t / nb : 0;
     const double h = in ? s.H[x + y * B_] : 0.0;
     const double dx = __shfl(h, x + x * nb, 64), dy = __shfl(h, y + y * nb, 64);
-    const double sx = dx > 0 ? 1.0 / sqrt(dx) : 1.0, sy = dy > 0 ? 1.0 / sqrt(dy) : 1.0;
+    const double sx = dx > 0 ? rsq_nr(dx) : 1.0, sy = dy > 0 ? rsq_nr(dy) : 1.0;
     double g = h * (sx * sy);
     if (shift_coef > 0.0) {
       const double fro = wave_sum(in ? g * g : 0.0);
@@ -402,8 +402,8 @@ __device__ __forceinline__ int cqr_small(EigLDS &s, int nb, double shift_coef) {
         bad = 1;
         p = 1.0;
       }
-      const double rjj = sqrt(p);
-      if (in && x == j) g = (y == j) ? rjj : ((y > j) ? g / rjj : g);
+      const double ir = rsq_nr(p), rjj = p * ir;
+      if (in && x == j) g = (y == j) ? rjj : ((y > j) ? g * ir : g);
       const double rx = __shfl(g, j + x * nb, 64), ry = __shfl(g, j + y * nb, 64);
       if (in && x > j && x <= y) g -= rx * ry;
     }
@@ -420,7 +420,7 @@ __device__ __forceinline__ int cqr_small(EigLDS &s, int nb, double shift_coef) {
 #pragma unroll
         for (int q = a + 1; q < 8; ++q)
           if (q <= c) v = fma(-s.H[min(a, nb - 1) + min(q, nb - 1) * B_], ri[q], v);
-        ri[a] = (a <= c && a < nb) ? v / s.H[min(a, nb - 1) + min(a, nb - 1) * B_] : 0.0;
+        ri[a] = (a <= c && a < nb) ? v * rcp_nr(s.H[min(a, nb - 1) + min(a, nb - 1) * B_]) : 0.0;
       }
 #pragma unroll
       for (int a = 0; a < 8; ++a)

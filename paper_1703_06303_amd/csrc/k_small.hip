@@ -124,8 +124,8 @@ __device__ __forceinline__ void coef_body(const SmallArgs &a, int wg, int nwg) {
           if (t == 0) fail = 1;
           p = gmax > 0 ? gmax : 1.0;
         }
-        const double rjj = sqrt(p);
-        g[j] = (t == j) ? rjj : g[j] / rjj;
+        const double ir = rsq_nr(p), rjj = p * ir;
+        g[j] = (t == j) ? rjj : g[j] * ir;
         sRow[j & 1][t] = g[j];
         wave_sync();
 #pragma unroll
@@ -163,7 +163,7 @@ __device__ __forceinline__ void coef_body(const SmallArgs &a, int wg, int nwg) {
         double s = x[i];
 #pragma unroll
         for (int q = 0; q < i; ++q) s -= sR[q + i * 64] * x[q];
-        x[i] = s / sR[i + i * 64];
+        x[i] = s * rcp_nr(sR[i + i * 64]);
       }
       // keep the reads of R inside their row (unrolled, the compiler would
       // otherwise hoist all of R into registers)
@@ -183,7 +183,7 @@ __device__ __forceinline__ void coef_body(const SmallArgs &a, int wg, int nwg) {
         double s = x[i];
 #pragma unroll
         for (int q = i + 1; q < KMAX; ++q) s -= sR[i + q * 64] * x[q];
-        x[i] = s / sR[i + i * 64];
+        x[i] = s * rcp_nr(sR[i + i * 64]);
       }
       asm volatile("" ::: "memory");
     }
