@@ -68,7 +68,7 @@ PLAIN_TOLS = (1e-7, 1e-6, 1e-5, 1e-4, 1e-3)
 # the mixed schedules' stopping rules: below 1e-5 they all run the BF16 sweeps
 # to 1e-5 and one exact sweep, so the grid starts there (named without suffix)
 MIXED_TOLS = (1e-7, 1e-4, 1e-3)
-STREAMING = ("update", "gram_X1A2", "change", "gram_A2", "gram_X1X1", "validate")
+STREAMING = ("update", "gram_X1", "change", "gram_A2", "validate")
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by
 # the same counters read for a plain copy of known size (reads x2.0, writes

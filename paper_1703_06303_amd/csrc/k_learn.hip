@@ -46,10 +46,28 @@ __global__ __launch_bounds__(256) void k_sketch_finish(int n, const double *__re
   for (int j0 = 0; j0 < n; j0 += CH) {
     const int nj = min(CH, n - j0);
     __syncthreads();
-    for (int e = threadIdx.x; e < LEARN_SK_ROWS * nj; e += 256) sP[e] = P1[(int64_t)j0 * LEARN_SK_ROWS + e];
-    for (int e = threadIdx.x; e < nj * LEARN_SK_COLS; e += 256) {
-      const int jj = e % nj, b = e / nj;
-      sQ[jj * LEARN_SK_COLS + b] = (double)Ps[j0 + jj + (int64_t)b * n];
+    // eight clamped reads in flight per thread
+    const int np = LEARN_SK_ROWS * nj, nq = nj * LEARN_SK_COLS;
+    for (int e0 = threadIdx.x; e0 < np; e0 += 8 * 256) {
+      double v8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v8[u] = P1[(int64_t)j0 * LEARN_SK_ROWS + min(e0 + 256 * u, np - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + 256 * u < np) sP[e0 + 256 * u] = v8[u];
+    }
+    for (int e0 = threadIdx.x; e0 < nq; e0 += 8 * 256) {
+      T q8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(e0 + 256 * u, nq - 1), jj = e % nj, b = e / nj;
+        q8[u] = Ps[j0 + jj + (int64_t)b * n];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u, jj = e % nj, b = e / nj;
+        if (e < nq) sQ[jj * LEARN_SK_COLS + b] = (double)q8[u];
+      }
     }
     __syncthreads();
 #pragma unroll

@@ -102,14 +102,17 @@ __global__ __launch_bounds__(256) void k_init_x1(int64_t m, int64_t k, int mode,
 // in double).  Row chunks of 32 are staged through LDS as double
 // (column-major, padded), the next chunk being loaded into registers while
 // the current one multiplies.  `sym` computes only the tiles on or above the
-// diagonal (X == Y).  Fragment layouts (lane l): A[l % 16][l / 16],
-// B[l / 16][l % 16], accumulator v holds D[l / 16 + 4 v][l % 16].
+// diagonal (X == Y).  With Y2 given, Y's columns ky1 .. k2 - 1 are Y2's
+// columns 0 .. k2 - ky1 - 1 (ld ldy2): one product X^T [Y Y2].  Fragment
+// layouts (lane l): A[l % 16][l / 16], B[l / 16][l % 16], accumulator v
+// holds D[l / 16 + 4 v][l % 16].
 typedef double ts_d4 __attribute__((ext_vector_type(4)));
 template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict__ X, int64_t ldx,
                                                 int k1, const TY *__restrict__ Y, int64_t ldy,
                                                 int k2, int sym, int64_t rows_per_split,
-                                                double *__restrict__ part, const int *skip) {
+                                                double *__restrict__ part, const int *skip,
+                                                const TY *__restrict__ Y2, int64_t ldy2, int ky1) {
   if (skip != nullptr && *skip) return;
   const int ti = blockIdx.x, tj = blockIdx.y, s = blockIdx.z;
   if (sym && ti > tj) return;
@@ -132,7 +135,9 @@ __global__ __launch_bounds__(256) void k_tsgemm(int64_t m, const TX *__restrict_
       const int rr = e & 31, cc = e >> 5;
       const int64_t rowc = min(rb + rr, r1 - 1);
       px[u] = X[rowc + (int64_t)min(i0 + cc, k1 - 1) * ldx];
-      py[u] = Y[rowc + (int64_t)min(j0 + cc, k2 - 1) * ldy];
+      const int jc = min(j0 + cc, k2 - 1);
+      const TY *yc = jc < ky1 ? Y + (int64_t)jc * ldy : Y2 + (int64_t)(jc - ky1) * ldy2;
+      py[u] = yc[rowc];
     }
   };
   ts_d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -1542,10 +1547,11 @@ void launch_init_x1(hipStream_t s, int64_t m, int64_t k, int mode, uint64_t seed
 template <typename TX, typename TY>
 void launch_tsgemm(hipStream_t s, int64_t m, const TX *X, int64_t ldx, int k1, const TY *Y,
                    int64_t ldy, int k2, int sym, int splits, int64_t rows_per_split, double *part,
-                   double *out, const int *skip) {
+                   double *out, const int *skip, const TY *Y2, int64_t ldy2, int ky1) {
   const int ti = (k1 + 31) / 32, tj = (k2 + 31) / 32;
+  if (Y2 == nullptr) ky1 = k2;
   hipLaunchKernelGGL((k_tsgemm<TX, TY>), dim3(ti, tj, splits), dim3(256), 0, s, m, X, ldx, k1, Y,
-                     ldy, k2, sym, rows_per_split, part, skip);
+                     ldy, k2, sym, rows_per_split, part, skip, Y2, ldy2, ky1);
   const int64_t total = (int64_t)k1 * k2;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 31) / 32, 4096));
   hipLaunchKernelGGL(k_reduce_parts, dim3(g), dim3(256), 0, s, k1, k2, splits, sym, part, out, skip);
@@ -1788,7 +1794,7 @@ void launch_copy_out(hipStream_t s, int64_t m, int64_t k, const T *src, T *dst, 
                                   int64_t, T *, int *, const int *);                              \
   template void launch_tsgemm<T, T>(hipStream_t, int64_t, const T *, int64_t, int, const T *,     \
                                     int64_t, int, int, int, int64_t, double *, double *,          \
-                                    const int *);                                                 \
+                                    const int *, const T *, int64_t, int);                        \
   template void launch_f1<T>(hipStream_t, int64_t, int, const T *, int64_t, const T *, int64_t,   \
                              double, const T *, double *, int);                                   \
   template void launch_update<T>(hipStream_t, const UpdateArgs<T> &);                             \

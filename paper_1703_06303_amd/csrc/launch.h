@@ -38,10 +38,13 @@ void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t ld
 template <typename T>
 void launch_init_x1(hipStream_t s, int64_t m, int64_t k, int mode, uint64_t seed, const T *src,
                     int64_t lds, T *X1, int *flags, const int *gate = nullptr);
+// part[split] = X[rows]^T Y[rows] (k1 x k2), then out = the sum of the
+// splits in order.  With Y2, Y's columns from ky1 on are Y2's (ld ldy2).
 template <typename TX, typename TY>
 void launch_tsgemm(hipStream_t s, int64_t m, const TX *X, int64_t ldx, int k1, const TY *Y,
                    int64_t ldy, int k2, int sym, int splits, int64_t rows_per_split, double *part,
-                   double *out, const int *skip);
+                   double *out, const int *skip, const TY *Y2 = nullptr, int64_t ldy2 = 0,
+                   int ky1 = 0);
 template <typename T>
 void launch_f1(hipStream_t s, int64_t m, int k, const T *A, int64_t lda, const T *W1, int64_t ldw,
                double wc, const T *X1, double *part, int nwg);

@@ -59,11 +59,11 @@ static void *scratch_ptr(int device) {
 }
 
 enum KernelKind {
-  KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_XTX, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
+  KK_VALIDATE, KK_INIT, KK_GRAM, KK_GAST, KK_XTA, KK_F1, KK_COEF, KK_FORMM, KK_EIG,
   KK_POST, KK_CHANGE, KK_DECIDE, KK_UPDATE, KK_X2, KK_COPY, KK_LEARN, KK_CHGQR, KK_COUNT
 };
 static const char *kKernelNames[KK_COUNT] = {
-    "validate", "init_x1", "gram_A2", "gram_stats", "gram_X1A2", "gram_X1X1", "objective_f1",
+    "validate", "init_x1", "gram_A2", "gram_stats", "gram_X1", "objective_f1",
     "coef", "form_M", "eig", "post", "change", "decide", "update", "x2_out", "copy_out",
     "learned_init", "change_qr"};
 
@@ -208,8 +208,6 @@ struct Sizes {
   bool colw;  // column weights of the unweighted block: A staged scaled
   int splits_l1;  // Om^T A of the learned start's sketch
   int64_t rows_l1;
-  int splits_g1;  // X1^T X1
-  int64_t rows_g1;
 };
 
 struct Ptrs {
@@ -264,10 +262,6 @@ Sizes make_sizes(int64_t m, int64_t n, int64_t k, int64_t r, size_t elt, bool mi
     z.splits_ga_max = std::max(z.splits_ga, choose_splits(m, z.tiles_ga, &rr, TUNE_TARGET_MAX));
     z.splits_p_max = std::max(z.splits_p, choose_splits(m, z.tiles_p, &rr, TUNE_TARGET_MAX));
   }
-  {
-    const int tk1 = (int)((std::max<int64_t>(k, 1) + 31) / 32);
-    z.splits_g1 = choose_splits(m, tk1 * tk1, &z.rows_g1);
-  }
   z.splits_l1 = choose_splits(m, (int)((n + 31) / 32), &z.rows_l1);
   z.nwg_upd = (int)((m + 63) / 64);
   z.nwg_f1 = 256;
@@ -285,10 +279,8 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
   const size_t d = sizeof(double);
   const int64_t m = z.m, k = z.k, n2 = z.n2, l = z.l;
   const int64_t kk = std::max<int64_t>(k, 1), ll = std::max<int64_t>(l, 1);
-  const size_t part = std::max<size_t>(
-      std::max<size_t>((size_t)z.splits_ga_max * n2 * n2,
-                       (size_t)z.splits_p_max * std::max<int64_t>(kk * n2, kk * kk)),
-      (size_t)z.splits_g1 * kk * kk);
+  const size_t part = std::max<size_t>((size_t)z.splits_ga_max * n2 * n2,
+                                       (size_t)z.splits_p_max * kk * (kk + n2));
   struct Item { void **dst; size_t bytes; };
   Ptrs p{};
   Item items[] = {
@@ -296,8 +288,9 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
       {&p.X1[1], (size_t)(m * kk) * z.elt},
       {(void **)&p.part, part * d},
       {(void **)&p.GA, (size_t)(n2 * n2) * d},
-      {(void **)&p.P, (size_t)(kk * n2) * d},
-      {(void **)&p.G1, (size_t)(kk * kk) * d},
+      // X1^T [X1 A2] = [G1 P]: G1 (k x k) and P (k x n2), both ld k, in one
+      // block (one product forms both)
+      {(void **)&p.G1, (size_t)(kk * (kk + n2)) * d},
       {(void **)&p.R, (size_t)(kk * kk) * d},
       {(void **)&p.B, (size_t)(kk * n2) * d},
       {(void **)&p.C, (size_t)(kk * n2) * d},
@@ -348,6 +341,7 @@ Layout make_layout(const Sizes &z, Ptrs *P, char *base) {
     const size_t off = L.add(it.bytes);
     *it.dst = (base && it.bytes) ? (void *)(base + off) : nullptr;
   }
+  p.P = p.G1 ? p.G1 + kk * kk : nullptr;
   if (P) *P = p;
   return L;
 }
@@ -608,10 +602,7 @@ struct Run {
     // eig_floor is relative to ||A2^T A2||_F; k_gastats scales it.
     PROFWS(h, s, KK_GAST, 0, 0, launch_gastats(s, (int)n2, P.GA, P.st));
     if (k > 0) {
-      gram_X1A2(X1c);
-      PROFWS(h, s, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
-             (launch_tsgemm<T, T>(s, m, X1c, m, (int)k, X1c, m, (int)k, 0, z.splits_g1,
-                                  z.rows_g1, P.part, P.G1, nullptr)));
+      gram_X1(X1c);
       PROFWS(h, s, KK_F1, 0, 0,
              launch_f1<T>(s, m, (int)k, A, lda, W1, pr->ldw, wc, X1c, P.upd_part, z.nwg_f1));
       nparts = z.nwg_f1;
@@ -705,11 +696,12 @@ struct Run {
            (launch_tsgemm<T, T>(s, m, A2, lda, (int)n2, A2, lda, (int)n2, 1, z.splits_ga,
                                 z.rows_ga, P.part, P.GA, nullptr)));
   }
-  // X1^T A2 (k x n2) for the coefficients of the next small step.
-  void gram_X1A2(const T *X1) {
-    PROFWS(h, s, KK_XTA, md * (kd + n2d) * es, 2.0 * md * kd * n2d,
-           (launch_tsgemm<T, T>(s, m, X1, m, (int)k, A2, lda, (int)n2, 0, z.splits_p, z.rows_p,
-                                P.part, P.P, nullptr)));
+  // X1^T [X1 A2] = [G1 P] (k x (k + n2)) for the next small step: one
+  // product over the rows of X1 and A2 (X1 read once for both).
+  void gram_X1(const T *X1) {
+    PROFWS(h, s, KK_XTA, md * (kd + n2d) * es, 2.0 * md * kd * (kd + n2d),
+           (launch_tsgemm<T, T>(s, m, X1, m, (int)k, X1, m, (int)(k + n2), 0, z.splits_p,
+                                z.rows_p, P.part, P.G1, nullptr, A2, lda, (int)k)));
   }
 
   // Arguments of sweep p's small step.
@@ -809,10 +801,7 @@ struct Run {
            2.0 * md * ((double)pr->n + kd) * kd +
                (constw ? 0.0 : md * (kd * kd * kd / 3.0 + 2.0 * kd * kd)),
            launch_update<T>(s, ua));
-    gram_X1A2(X1n);
-    PROFWS(h, s, KK_XTX, md * kd * es, 2.0 * md * kd * kd,
-           (launch_tsgemm<T, T>(s, m, X1n, m, (int)k, X1n, m, (int)k, 0, z.splits_g1, z.rows_g1,
-                                P.part, P.G1, nullptr)));
+    gram_X1(X1n);
     nparts = z.nwg_upd;
     cur ^= 1;
     X1c = X1n;
