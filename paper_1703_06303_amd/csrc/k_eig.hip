@@ -621,9 +621,9 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
     }
     const double sigma = h / (top - e0), tau = 2.0 / sigma;
     double s1 = sigma;
-    Blk<RES> P0 = F0, P1 = F1, P2 = F2;
-    for (int e = t; e < n2 * act; e += ET) P0.at(s, e) = Ya.at(s, e);
-    __syncthreads();
+    // the recurrence's three blocks rotate through Ya (the filter's input,
+    // not needed once the first step has read it), F1 and F2
+    Blk<RES> P0 = Ya, P1 = F1, P2 = F2;
     {
       const double f1 = s1 / h;
       blk_op<RES>(s, cx, P0, act, P1, [&](int f, double v) { return (v - e0 * P0.at(s, f)) * f1; });
@@ -641,8 +641,10 @@ __device__ __forceinline__ void eig_body(EigLDS &s, const SmallArgs &a, const Ei
       P2 = tmp;
       s1 = s2;
     }
-    for (int e = t; e < n2 * act; e += ET) Ya.at(s, e) = P1.at(s, e);
-    __syncthreads();
+    if (!P1.same(Ya)) {
+      for (int e = t; e < n2 * act; e += ET) Ya.at(s, e) = P1.at(s, e);
+      __syncthreads();
+    }
     blk_orth<RES>(s, cx, Ya, act, Y, locked, a.flags);
     // W (active columns) in F0: free once the filter is done
     const Blk<RES> Wa = W.plus(locked * n2);
