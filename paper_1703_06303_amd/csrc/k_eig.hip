@@ -480,25 +480,85 @@ __device__ __forceinline__ void blk_jacobi(EigLDS &s, int nb) {
   small_jacobi_wave(s.H, s.S, s.G, s.pool + PART_OFF, s.th, s.rc, s.rs, s.rp, s.rq, nb);
 }
 
+// X (n2 x nb) <- X S - L F (S nb x nb, F locked x nb, both ld B_, in LDS;
+// L n2 x locked): X's and L's rows staged column-major in LDS scratch by
+// chunks, then one output entry per thread.
+template <bool RES>
+__device__ __forceinline__ void blk_rot_proj(EigLDS &s, int n2, Blk<RES> X, int nb,
+                                             const double *S, Blk<RES> L, int locked,
+                                             const double *F) {
+  const int t = threadIdx.x;
+  const int tmp = RES ? PART_OFF : STAGE_OFF;
+  const int cap = RES ? EIG_PART : 8192;
+  const int wd = nb + locked;
+  const int rows = max(1, cap / wd);
+  for (int r0 = 0; r0 < n2; r0 += rows) {
+    const int nr = min(rows, n2 - r0);
+    for (int e = t; e < nr * wd; e += ET) {
+      const int i = e % nr, c = e / nr;
+      s.pool[tmp + e] = c < nb ? X.at(s, r0 + i + c * n2) : L.at(s, r0 + i + (c - nb) * n2);
+    }
+    __syncthreads();
+    for (int e = t; e < nr * nb; e += ET) {
+      const int i = e % nr, c = e / nr;
+      double v = 0.0;
+      for (int a = 0; a < nb; ++a) v = fma(s.pool[tmp + i + a * nr], S[a + c * B_], v);
+      for (int q = 0; q < locked; ++q) v = fma(-s.pool[tmp + i + (nb + q) * nr], F[q + c * B_], v);
+      X.at(s, r0 + i + c * n2) = v;
+    }
+    __syncthreads();
+  }
+}
+
+// H = X^T X - G^T G for the Gram of [L X] against X in s.S (rows 0 .. locked-1
+// G = L^T X, rows locked .. X^T X): the Gram of X - L L^T X for orthonormal L.
+__device__ __forceinline__ void proj_gram(EigLDS &s, int locked, int nb) {
+  for (int e = threadIdx.x; e < nb * nb; e += ET) {
+    const int a2 = e % nb, c = e / nb;
+    double v = s.S[locked + a2 + c * B_];
+    for (int q = 0; q < locked; ++q) v = fma(-s.S[q + a2 * B_], s.S[q + c * B_], v);
+    s.H[a2 + c * B_] = v;
+  }
+  __syncthreads();
+}
+
 // Orthonormalise the nb columns of X against the `locked` columns of L and
 // among themselves: CholeskyQR2, shifted CholeskyQR3 if the Gram is not
-// numerically positive definite.
+// numerically positive definite.  With locked columns (which must directly
+// precede X's in the same block) each pass forms one Gram of [L X] against X,
+// takes the projected Gram X^T X - (L^T X)^T (L^T X), and applies
+// X <- (X - L L^T X) R^-1 = X R^-1 - L (L^T X R^-1) in one rotation pass: the
+// filter has shrunk X's components along the locked (deflated) vectors, so
+// the subtraction cancels little.
 template <bool RES>
 __device__ __forceinline__ void blk_orth(EigLDS &s, const EigCtx &cx, Blk<RES> X, int nb,
                                          Blk<RES> L, int locked, int *flags) {
   const int t = threadIdx.x, n2 = cx.n2;
+  const double shift_coef = 11.0 * ((double)n2 * nb + (double)nb * (nb + 1)) * 2.220446049250313e-16;
   int shifted = 0;
   for (int rep = 0; rep < 3; ++rep) {
     if (rep == 2 && !shifted) break;
     if (locked > 0) {
-      blk_gram<RES>(s, cx, L, locked, X, nb, s.G);
-      for (int e = t; e < n2 * nb; e += ET) {
-        const int i = e % n2, c = e / n2;
-        double v = X.at(s, e);
-        for (int a = 0; a < locked; ++a) v -= L.at(s, i + a * n2) * s.G[a + c * B_];
-        X.at(s, e) = v;
+      blk_gram<RES>(s, cx, L, locked + nb, X, nb, s.S);
+      proj_gram(s, locked, nb);
+      if (cqr_small(s, nb, 0.0)) {
+        proj_gram(s, locked, nb);
+        shifted = 1;
+        if (cqr_small(s, nb, shift_coef)) {
+          if (t == 0) atomicOr(flags, DEV_EIG_ORTH);
+          return;
+        }
+      }
+      // F = (L^T X) R^-1 (locked x nb) into s.H, free once R^-1 is formed
+      for (int e = t; e < locked * nb; e += ET) {
+        const int q = e % locked, c = e / locked;
+        double v = 0.0;
+        for (int a2 = 0; a2 <= c; ++a2) v = fma(s.S[q + a2 * B_], s.G[a2 + c * B_], v);
+        s.H[q + c * B_] = v;
       }
       __syncthreads();
+      blk_rot_proj<RES>(s, n2, X, nb, s.G, L, locked, s.H);
+      continue;
     }
     // Gram, scaled to unit diagonal (D^-1/2 G D^-1/2 = R'^T R'), so that
     // X R^-1 = X D^-1/2 R'^-1: the normalisation costs no pass over X
@@ -506,7 +566,7 @@ __device__ __forceinline__ void blk_orth(EigLDS &s, const EigCtx &cx, Blk<RES> X
     if (cqr_small(s, nb, 0.0)) {
       blk_gram<RES>(s, cx, X, nb, X, nb, s.H);
       shifted = 1;
-      if (cqr_small(s, nb, 11.0 * ((double)n2 * nb + (double)nb * (nb + 1)) * 2.220446049250313e-16)) {
+      if (cqr_small(s, nb, shift_coef)) {
         if (t == 0) atomicOr(flags, DEV_EIG_ORTH);
         return;
       }
