@@ -64,6 +64,41 @@ __global__ __launch_bounds__(256) void k_validate(int64_t m, int64_t n, const T 
   }
 }
 
+// The same checks (and BF16 staging) for float storage without column weights
+// when rows come in aligned groups of four (m, lda, ldw multiples of 4,
+// 16-byte aligned A and W1): 16-byte reads of A and W1, 8-byte writes of the
+// BF16 copy, four rows per thread and a column per grid row.
+__global__ __launch_bounds__(256) void k_validate4(int64_t m, int64_t n, const float *__restrict__ A,
+                                                   int64_t lda, int64_t k,
+                                                   const float *__restrict__ W1, int64_t ldw,
+                                                   int *flags, bf16s *__restrict__ A2b) {
+  int bad_a = 0, bad_w = 0;
+  const int64_t m4 = m / 4, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m4; g += stride) {
+      const float4 v = *reinterpret_cast<const float4 *>(A + 4 * g + j * lda);
+      if (!isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w)) bad_a = 1;
+      if (A2b != nullptr && j >= k) {
+        const uint32_t lo = (uint32_t)bf16_rne(v.x).u | ((uint32_t)bf16_rne(v.y).u << 16);
+        const uint32_t hi = (uint32_t)bf16_rne(v.z).u | ((uint32_t)bf16_rne(v.w).u << 16);
+        *reinterpret_cast<uint2 *>(A2b + 4 * g + (j - k) * m) = make_uint2(lo, hi);
+      }
+      if (W1 != nullptr && j < k) {
+        const float4 w = *reinterpret_cast<const float4 *>(W1 + 4 * g + j * ldw);
+        if (!(w.x > 0.f) || !isfinite(w.x) || !(w.y > 0.f) || !isfinite(w.y) ||
+            !(w.z > 0.f) || !isfinite(w.z) || !(w.w > 0.f) || !isfinite(w.w))
+          bad_w = 1;
+      }
+    }
+  }
+  bad_a = __syncthreads_or(bad_a);
+  bad_w = __syncthreads_or(bad_w);
+  if (threadIdx.x == 0) {
+    if (bad_a) atomicOr(flags, DEV_BAD_A);
+    if (bad_w) atomicOr(flags, DEV_BAD_W);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // X1_0: mode 0 = iid N(0,1) (Philox4x32-10 + Box-Muller), 1 = copy of a given
 // matrix, 2 = copy of A1.  Non-finite given entries set DEV_BAD_A.  With a
@@ -1530,6 +1565,16 @@ __global__ __launch_bounds__(256) void k_copy_out(int64_t m, int64_t k, const T 
 template <typename T>
 void launch_validate(hipStream_t s, int64_t m, int64_t n, const T *A, int64_t lda, int64_t k,
                      const T *W1, int64_t ldw, int *flags, bf16s *A2b, const T *W2, T *As) {
+  if constexpr (std::is_same<T, float>::value) {
+    auto al = [](const void *p) { return ((uintptr_t)p & 15u) == 0; };
+    if (W2 == nullptr && m % 4 == 0 && lda % 4 == 0 && al(A) &&
+        (W1 == nullptr || (ldw % 4 == 0 && al(W1)))) {
+      dim3 g4((unsigned)std::max<int64_t>(1, std::min<int64_t>((m / 4 + 255) / 256, 64)),
+              (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 1024)));
+      hipLaunchKernelGGL(k_validate4, g4, dim3(256), 0, s, m, n, A, lda, k, W1, ldw, flags, A2b);
+      return;
+    }
+  }
   dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)std::min<int64_t>(n, 1024));
   hipLaunchKernelGGL(k_validate<T>, grid, dim3(256), 0, s, m, n, A, lda, k, W1, ldw, flags, A2b,
                      W2, As);

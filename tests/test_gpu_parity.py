@@ -204,3 +204,26 @@ def test_error_codes(s64):
     inst_k = video.Instance(A=inst.A, k=inst.k, r=inst.k - 1, W1=inst.W1, w1_const=0.0,
                             X1_0=inst.X1_0, frame_hw=inst.frame_hw, seed=0)
     assert gpu_solve(s64, inst_k, 1e-7, 10)[2]["rc"] == wlra.E_ARG
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("m_hw", [(6, 8), (5, 7)])
+def test_error_codes_float(prec, m_hw):
+    """The float input checks (problem (5) needs finite A and W1 > 0): m = 48
+    takes the four-rows-per-thread path, m = 35 the element path; a bad entry
+    in the last row, in A1 and in A2 each gives its status."""
+    from paper_1703_06303_amd import wlra
+    inst = video.small(m_hw=m_hw, seed=5, dtype=np.float32)
+    m, n = inst.A.shape
+    with wlra.Solver(prec) as s:
+        assert gpu_solve(s, inst, 1e-7, 10)[2]["rc"] >= 0
+        for i, j in ((m - 1, 1), (2, inst.k - 1)):
+            bad = inst.W1.copy()
+            bad[i, j] = 0.0
+            inst_w = video.Instance(A=inst.A, k=inst.k, r=inst.r, W1=bad, w1_const=0.0,
+                                    X1_0=inst.X1_0, frame_hw=inst.frame_hw, seed=0)
+            assert gpu_solve(s, inst_w, 1e-7, 10)[2]["rc"] == wlra.E_WEIGHT
+        for i, j, v in ((m - 1, 0, np.nan), (m - 2, inst.k + 3, np.inf), (1, n - 1, -np.inf)):
+            A = inst.A.copy()
+            A[i, j] = v
+            assert gpu_solve(s, inst, 1e-7, 10, A=A)[2]["rc"] == wlra.E_NONFINITE
