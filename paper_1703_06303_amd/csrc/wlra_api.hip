@@ -574,10 +574,17 @@ struct Run {
         launch_gemm(s, 0, 1, (int)(n * z.r), LEARN_HID, P.lh2, LEARN_HID, W3m, LEARN_HID, P.yv,
                     (int)(n * z.r), b3, 0, nullptr, 0);
         launch_ldecode<T>(s, (int)n, (int)k, (int)z.r, P.yv, Gt, Tt, St, lflag);
-        launch_zero<T>(s, m * k, X1z);
+        // the fit's X1 term multiplies T = 0, so any finite m x k matrix
+        // (ld m) serves as its X1: A1 itself when A's leading dimension is m
+        // (a non-finite A is rejected by the validation pass), zeros else
+        const T *X1fit = X1z;
+        if (lda == m)
+          X1fit = A;
+        else
+          launch_zero<T>(s, m * k, X1z);
         UpdateArgs<T> ua{};
         ua.m = m; ua.k = (int)k; ua.n = (int)n; ua.A = A; ua.lda = lda; ua.W1 = W1;
-        ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1z; ua.X1n = X1c;
+        ua.ldw = pr->ldw; ua.wc = (T)wc; ua.constw = constw; ua.X1o = X1fit; ua.X1n = X1c;
         ua.Gt = Gt; ua.Tt = Tt; ua.St = St; ua.part = P.upd_part; ua.st = P.st;
         ua.Eb = static_cast<T *>(P.Eb);
         ua.A2b = nullptr;
