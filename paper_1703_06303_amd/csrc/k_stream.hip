@@ -1819,8 +1819,11 @@ void launch_change_qr(hipStream_t s, int64_t m, int k, int n2, int l, const T *A
                       const T *X1p, const T *X1q, const double *Hb, const double *Kg,
                       double *part, const SmallState *st) {
   const T *A2 = A + (int64_t)k * lda;
+  // the row pass's per-lane products are unrolled over LMAX >= l
   if (l <= 8)
     launch_change_qr_k<T, 8>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
+  else if (l <= 16)
+    launch_change_qr_k<T, 16>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
   else
     launch_change_qr_k<T, WLRA_BMAX>(s, m, k, n2, l, A2, lda, X1p, X1q, Hb, Kg, part, st);
 }
