@@ -252,30 +252,38 @@ __global__ __launch_bounds__(256) void k_formM_b(const SmallArgs *__restrict__ a
 // inner products.  Small matrices are column-major in the global scratch
 // (CV, S, T, K^-1); the n2-row outputs are left to k_postz.
 
-// In-place Cholesky (upper, K = R^T R) of a k x k matrix in LDS (ld 64).
-__device__ int small_chol64(double *K, int k, int *fail) {
-  if (threadIdx.x == 0) *fail = 0;
+// In-place Cholesky (upper, K = R^T R) of a symmetric k x k matrix in LDS
+// (ld 64) by wavefront 0: at step j lane c forms R_jc = K_cj / R_jj from
+// column j (consecutive words), passes it to every lane through `row` (64
+// doubles of LDS), writes it into row j, and then updates row c of the
+// trailing block, both triangles (for each column the lanes touch
+// consecutive words).  The pivot's reciprocal square root is the refined
+// hardware estimate.
+__device__ int small_chol64(double *K, int k, int *fail, double *row) {
+  const int t = threadIdx.x;
+  if (t == 0) *fail = 0;
   __syncthreads();
-  for (int j = 0; j < k; ++j) {
-    if (threadIdx.x == 0) {
+  if (t < 64) {
+    for (int j = 0; j < k; ++j) {
       double p = K[j + j * 64];
       if (!(p > 0)) {
-        *fail = 1;
+        if (t == 0) *fail = 1;
         p = 1.0;
       }
-      K[j + j * 64] = sqrt(p);
+      const double ir = rsq_nr(p);
+      const bool own = t > j && t < k;
+      const double r = own ? K[t + j * 64] * ir : 0.0;
+      row[t] = r;
+      wave_sync();
+      if (t == j) K[j + j * 64] = p * ir;
+      if (own) {
+        K[j + t * 64] = r;
+        for (int c = j + 1; c < k; ++c) K[t + c * 64] -= r * row[c];
+      }
+      wave_sync();
     }
-    __syncthreads();
-    const double rjj = K[j + j * 64];
-    for (int c = j + 1 + threadIdx.x; c < k; c += blockDim.x) K[j + c * 64] /= rjj;
-    __syncthreads();
-    const int rem = k - j - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-      const int aa = j + 1 + e % rem, cc = j + 1 + e / rem;
-      if (aa <= cc) K[aa + cc * 64] -= K[j + aa * 64] * K[j + cc * 64];
-    }
-    __syncthreads();
   }
+  __syncthreads();
   return *fail;
 }
 
@@ -360,7 +368,7 @@ __device__ __forceinline__ void post_body(const SmallArgs &a, const SmallOut<T> 
       sK[r + c * 64] = S[e] + (r == c ? w2 : 0.0);
     }
     __syncthreads();
-    small_chol64(sK, k, &fail);
+    small_chol64(sK, k, &fail, sKi);  // sKi is free until R^-1
     if (t < k) {
       const int c = t;
       for (int r = 0; r < k; ++r) sKi[r + c * 64] = 0.0;
