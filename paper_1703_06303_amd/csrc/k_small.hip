@@ -308,7 +308,7 @@ __device__ __forceinline__ void post_body(const SmallArgs &a, const SmallOut<T> 
   // ---- CV = C V and S = C C^T ----------------------------------------------
   // on the FP64 matrix cores: 16 x 16 output tiles (S: ceil(k/16)^2, CV:
   // ceil(k/16) x ceil(l/16)), one wavefront per tile, the inner index (the
-  // n2 columns of C) in k-steps of 4, eight steps' reads in flight at once;
+  // n2 columns of C) in k-steps of 4, sixteen steps' reads in flight at once;
   // C (k x n2, ld k) and V (n2 x l, ld n2) are read from L2, clamped and
   // masked by zero factors.
   {
@@ -325,17 +325,17 @@ __device__ __forceinline__ void post_body(const SmallArgs &a, const SmallOut<T> 
       const int cb = isS ? min(c0 + li, max(k - 1, 0)) : min(c0 + li, max(l - 1, 0));
       const double mb = isS ? ((c0 + li < k) ? 1.0 : 0.0) : ((c0 + li < l) ? 1.0 : 0.0);
       pd4 acc = {0.0, 0.0, 0.0, 0.0};
-      for (int j0 = 0; j0 < n2; j0 += 32) {
-        double av[8], bv[8];
+      for (int j0 = 0; j0 < n2; j0 += 64) {
+        double av[16], bv[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
           const int jj = j0 + 4 * u + lk, jc = min(jj, n2 - 1);
           const double mj = (jj < n2) ? 1.0 : 0.0;
           av[u] = a.C[(int64_t)jc * k + ra] * (ma * mj);
           bv[u] = isS ? a.C[(int64_t)jc * k + cb] * mb : V[jc + (int64_t)cb * n2] * mb;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 16; ++u)
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
       }
 #pragma unroll
